@@ -1,0 +1,237 @@
+"""Seeded synthetic inputs: images f and initial level sets phi^0.
+
+This module holds no arithmetic of the segmentation method itself; it only
+draws test images and analytic signed distance functions.  Both the HIP
+library's tests/benchmarks and the FP64 oracle's tests take their inputs from
+here, so the two sides always see identical data (float64 here; the GPU side
+receives a float32 cast).
+
+The paper's own images (two circles, a synthetic hand, cells, wheat grains,
+CT slices) are not available, so these generators stand in for them:
+
+* ``two_disks``      - two unit-intensity disks with a 4 px gap and one
+                       enclosing circular initial contour: the splitting-
+                       prevention set-up of the paper's first experiment.
+* ``ellipses``       - many ellipses with 2-6 px gaps, a low-frequency bias
+                       field and Gaussian noise (the "adhesive cells / grains"
+                       situation: close objects that must not merge).
+* ``annuli``         - annuli and ellipses with holes, some crossed by
+                       occluding bars (large-grid stress case).
+* ``batch_items``    - many uneven-size ``ellipses`` instances.
+
+Geometry conventions: pixel (i, j) has centre (i, j); i is the row index.
+Level sets are negative inside (the paper's sign convention).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+from scipy import ndimage
+
+
+def _rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def _grid(M, N):
+    i = np.arange(M, dtype=np.float64)[:, None]
+    j = np.arange(N, dtype=np.float64)[None, :]
+    return i, j
+
+
+def circle_sdf(M, N, radius, center=None):
+    """Signed distance to a circle (negative inside)."""
+    c = ((M - 1) / 2.0, (N - 1) / 2.0) if center is None else center
+    i, j = _grid(M, N)
+    return np.sqrt((i - c[0]) ** 2 + (j - c[1]) ** 2) - radius
+
+
+def rect_sdf(M, N, inset):
+    """Signed distance to the rectangle [inset, M-1-inset] x [inset, N-1-inset]."""
+    i, j = _grid(M, N)
+    lo_i, hi_i = float(inset), float(M - 1 - inset)
+    lo_j, hi_j = float(inset), float(N - 1 - inset)
+    di = np.maximum(lo_i - i, i - hi_i)          # >0 outside along i
+    dj = np.maximum(lo_j - j, j - hi_j)
+    outside = np.sqrt(np.maximum(di, 0.0) ** 2 + np.maximum(dj, 0.0) ** 2)
+    inside = np.minimum(np.maximum(di, dj), 0.0)  # <=0 inside: -(distance to edge)
+    return outside + inside
+
+
+# --------------------------------------------------------------------------
+# two disks (128 x 128 by default)
+# --------------------------------------------------------------------------
+def two_disks(M=128, N=128, seed=1, radius=20.0, gap=4.0, noise=0.1, phi_radius=60.0):
+    """Two disks of radius `radius`, intensity 1, edge gap `gap`, on 0, plus
+    i.i.d. N(0, noise^2).  phi^0 = circle of radius `phi_radius` about the
+    image centre.  Returns (f, phi0)."""
+    rng = _rng(seed)
+    c = ((M - 1) / 2.0, (N - 1) / 2.0)
+    off = radius + gap / 2.0
+    i, j = _grid(M, N)
+    f = np.zeros((M, N))
+    for s in (-1.0, 1.0):
+        f[(i - c[0]) ** 2 + (j - (c[1] + s * off)) ** 2 <= radius * radius] = 1.0
+    f = f + rng.normal(0.0, noise, size=(M, N))
+    return f, circle_sdf(M, N, phi_radius, c)
+
+
+# --------------------------------------------------------------------------
+# ellipses with small gaps (1024 x 1024 by default)
+# --------------------------------------------------------------------------
+def _ellipse_mask(M, N, ci, cj, a, b, th, box):
+    i0, i1, j0, j1 = box
+    ii = np.arange(i0, i1, dtype=np.float64)[:, None] - ci
+    jj = np.arange(j0, j1, dtype=np.float64)[None, :] - cj
+    ct, st = math.cos(th), math.sin(th)
+    u = ct * ii + st * jj
+    v = -st * ii + ct * jj
+    return (u / a) ** 2 + (v / b) ** 2 <= 1.0
+
+
+def _gap(union, cand, box, margin):
+    """Smallest Euclidean gap (pixel-centre distance minus nothing) between the
+    candidate mask and the union mask, looking `margin` px around the box."""
+    i0, i1, j0, j1 = box
+    M, N = union.shape
+    a0, a1 = max(i0 - margin, 0), min(i1 + margin, M)
+    b0, b1 = max(j0 - margin, 0), min(j1 + margin, N)
+    sub = union[a0:a1, b0:b1]
+    if not sub.any():
+        return math.inf
+    dist = ndimage.distance_transform_edt(~sub)
+    c = np.zeros_like(sub)
+    c[i0 - a0:i1 - a0, j0 - b0:j1 - b0] = cand
+    if (c & sub).any():
+        return 0.0
+    return float(dist[c].min()) - 1.0   # pixels strictly between the two masks
+
+
+def _place_shapes(M, N, n, axis_lo, axis_hi, rng, clearance, gap_lo=2.0, gap_hi=6.0,
+                  max_reject=1000):
+    """Rejection placement: each new ellipse keeps >= gap_lo px to all others and
+    (except the first) lies <= gap_hi px from its nearest neighbour."""
+    union = np.zeros((M, N), dtype=bool)
+    shapes = []
+    scale = 1.0
+    rejects = 0
+    while len(shapes) < n:
+        a = rng.uniform(axis_lo, axis_hi) * scale
+        b = rng.uniform(axis_lo, axis_hi) * scale
+        th = rng.uniform(0.0, math.pi)
+        rmax = max(a, b)
+        lo_i, hi_i = clearance + rmax, M - 1 - clearance - rmax
+        lo_j, hi_j = clearance + rmax, N - 1 - clearance - rmax
+        if lo_i >= hi_i or lo_j >= hi_j:
+            scale *= 0.9
+            continue
+        if shapes:
+            # start next to a random placed shape, along a random direction
+            k = shapes[rng.integers(len(shapes))]
+            ang = rng.uniform(0.0, 2.0 * math.pi)
+            dist = max(k[2], k[3]) + rmax + rng.uniform(0.0, 0.5) * min(a, b)
+            ci = k[0] + dist * math.cos(ang)
+            cj = k[1] + dist * math.sin(ang)
+        else:
+            ci = rng.uniform(lo_i, hi_i)
+            cj = rng.uniform(lo_j, hi_j)
+        ok = lo_i <= ci <= hi_i and lo_j <= cj <= hi_j
+        if ok:
+            box = (int(ci - rmax) - 1, int(ci + rmax) + 3, int(cj - rmax) - 1, int(cj + rmax) + 3)
+            cand = _ellipse_mask(M, N, ci, cj, a, b, th, box)
+            gap = _gap(union, cand, box, int(gap_hi) + 3)
+            ok = gap >= gap_lo and (not shapes or gap <= gap_hi)
+        if ok:
+            union[box[0]:box[1], box[2]:box[3]] |= cand
+            shapes.append((ci, cj, a, b, th))
+            rejects = 0
+        else:
+            rejects += 1
+            if rejects >= max_reject:
+                scale *= 0.9
+                rejects = 0
+    return shapes
+
+
+def ellipses(M=1024, N=1024, seed=2, n_shapes=12, axis_lo=30.0, axis_hi=120.0,
+             noise=0.15, bias=0.2, inset=16):
+    """Ellipses (intensity U[0.6, 1]) with 2-6 px gaps on a U[0, 0.2] background,
+    multiplied by a one-sinusoid bias field of amplitude `bias`, plus
+    N(0, noise^2).  phi^0 = rectangle inset by `inset` px.  Returns (f, phi0)."""
+    rng = _rng(seed)
+    shapes = _place_shapes(M, N, n_shapes, axis_lo, axis_hi, rng, clearance=inset + 8)
+    f = np.full((M, N), rng.uniform(0.0, 0.2))
+    for (ci, cj, a, b, th) in shapes:
+        rmax = max(a, b)
+        box = (max(int(ci - rmax) - 1, 0), min(int(ci + rmax) + 3, M),
+               max(int(cj - rmax) - 1, 0), min(int(cj + rmax) + 3, N))
+        m = _ellipse_mask(M, N, ci, cj, a, b, th, box)
+        f[box[0]:box[1], box[2]:box[3]][m] = rng.uniform(0.6, 1.0)
+    if bias > 0:
+        ang = rng.uniform(0.0, 2.0 * math.pi)
+        psi = rng.uniform(0.0, 2.0 * math.pi)
+        i, j = _grid(M, N)
+        f = f * (1.0 + bias * np.sin(2.0 * math.pi * (math.cos(ang) * i + math.sin(ang) * j) / 1024.0 + psi))
+    f = f + rng.normal(0.0, noise, size=(M, N))
+    return f, rect_sdf(M, N, inset)
+
+
+# --------------------------------------------------------------------------
+# annuli / holed ellipses with occluding bars (4096 x 4096 by default)
+# --------------------------------------------------------------------------
+def annuli(M=4096, N=4096, seed=3, n_shapes=64, axis_lo=60.0, axis_hi=240.0,
+           noise=0.2, bar_frac=0.1, inset=16):
+    """Half annuli, half ellipses with concentric elliptical holes (hole scale
+    q ~ U[0.3, 0.6]); about `bar_frac` of the shapes are crossed by a bar of
+    background intensity (width U[4, 12] px).  Returns (f, phi0)."""
+    rng = _rng(seed)
+    shapes = _place_shapes(M, N, n_shapes, axis_lo, axis_hi, rng, clearance=inset + 8)
+    bg = rng.uniform(0.0, 0.2)
+    f = np.full((M, N), bg)
+    for idx, (ci, cj, a, b, th) in enumerate(shapes):
+        if idx % 2 == 0:   # annulus: circle of the larger axis
+            a = b = max(a, b)
+        q = rng.uniform(0.3, 0.6)
+        rmax = max(a, b)
+        box = (max(int(ci - rmax) - 1, 0), min(int(ci + rmax) + 3, M),
+               max(int(cj - rmax) - 1, 0), min(int(cj + rmax) + 3, N))
+        outer = _ellipse_mask(M, N, ci, cj, a, b, th, box)
+        inner = _ellipse_mask(M, N, ci, cj, q * a, q * b, th, box)
+        sub = f[box[0]:box[1], box[2]:box[3]]
+        sub[outer & ~inner] = rng.uniform(0.6, 1.0)
+        if rng.uniform() < bar_frac:
+            wbar = rng.uniform(4.0, 12.0)
+            ang = rng.uniform(0.0, math.pi)
+            ii = np.arange(box[0], box[1], dtype=np.float64)[:, None] - ci
+            jj = np.arange(box[2], box[3], dtype=np.float64)[None, :] - cj
+            dist = np.abs(-math.sin(ang) * ii + math.cos(ang) * jj)
+            along = np.abs(math.cos(ang) * ii + math.sin(ang) * jj)
+            sub[(dist <= wbar / 2.0) & (along <= rmax)] = bg
+    f = f + rng.normal(0.0, noise, size=(M, N))
+    return f, rect_sdf(M, N, inset)
+
+
+# --------------------------------------------------------------------------
+# many uneven instances
+# --------------------------------------------------------------------------
+BATCH_SIZES = ((128, 128), (256, 256), (512, 512), (256, 512), (512, 1024))
+
+
+def batch_items(count=256, size_seed=4999, seed0=4000):
+    """Instance list: (M, N, R, f, phi0) with sizes drawn uniformly from
+    BATCH_SIZES, R ~ U{3, 4, 5}, and an ``ellipses`` image whose shape count and
+    axes scale with the area."""
+    rs = _rng(size_seed)
+    items = []
+    for k in range(count):
+        M, N = BATCH_SIZES[rs.integers(len(BATCH_SIZES))]
+        R = int(rs.integers(3, 6))
+        area = M * N / (1024.0 * 1024.0)
+        n = max(1, int(round(12 * area)))
+        s = math.sqrt(area)
+        lo = min(max(30.0 * s, 8.0), 0.3 * min(M, N))
+        hi = min(max(120.0 * s, 8.0), 0.3 * min(M, N))
+        f, phi0 = ellipses(M, N, seed=seed0 + k, n_shapes=n, axis_lo=lo, axis_hi=hi)
+        items.append((M, N, R, f, phi0))
+    return items
