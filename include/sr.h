@@ -1,0 +1,222 @@
+/*
+ * sr.h - C ABI of the MI355X (gfx950) Split Bregman solver for the
+ * Self-repelling Snake (SR) model of Pan et al., "Using the Split Bregman
+ * Algorithm to Solve the Self-repelling Snake Model" (arXiv:2003.12693).
+ *
+ * The library minimises the SR energy (eqs 7-10) under |grad phi| = 1 (eq 13)
+ * by Algorithm 1 of the paper: an outer loop k over
+ *   - S semi-implicit FFT steps of the phi sub-problem (eqs 30-33, 37),
+ *   - soft thresholding of the auxiliary gradient variable w (eqs 41-42)
+ *     followed by its projection onto |w| = 1 (eq 40),
+ *   - the Bregman update of b (eq 23).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Grids are M x N, M rows by N columns, row-major, pitch N, float32.
+ *    Row index i is the first gradient component, column index j the second
+ *    (eq 35).  M and N must be powers of two in [8, 4096].
+ *  - Vector fields (w, b, the repulsion field v) are two planes [2][M][N]
+ *    (component 1 first), i.e. 2*M*N floats.
+ *  - Boundaries are periodic for every operator (the symbol of eq 32 is the
+ *    periodic five-point Laplacian's).
+ *  - Pointers are device pointers unless the call takes `flags` and
+ *    SR_HOST is set, in which case they are host pointers and the call
+ *    stages through the workspace and synchronises the stream.
+ *  - The library never allocates device memory.  The caller asks for a
+ *    workspace size, allocates it (any 256-byte aligned device buffer) and
+ *    passes it in; the caller owns it and every in/out buffer, and keeps the
+ *    workspace alive until sr_destroy.  The context itself is a small host
+ *    object owned by the library.
+ *  - Every call enqueues its GPU work on the stream given to sr_create (a
+ *    hipStream_t passed as void*; NULL means the default stream).  Calls that
+ *    return host values (sr_step info, sr_energy, SR_HOST copies) synchronise
+ *    that stream before returning.
+ *  - Return codes: 0 = SR_OK; > 0 warning; < 0 error.  Arguments are
+ *    validated before any HIP call; on error nothing is enqueued and
+ *    sr_last_error() returns a thread-local description.
+ */
+#ifndef SR_H_
+#define SR_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define SR_OK               0
+#define SR_NOT_CONVERGED    1   /* warning: iteration cap reached before tol_outer */
+#define SR_EINVAL          -1   /* bad argument (null pointer, bad parameter) */
+#define SR_EUNSUPPORTED    -2   /* size not a power of two in [8, 4096], R > 8 ... */
+#define SR_EWORKSPACE      -3   /* workspace too small or misaligned */
+#define SR_EHIP            -4   /* a HIP runtime call failed */
+#define SR_ENONFINITE      -5   /* NaN / Inf in an input or in the iterate */
+#define SR_ESTATE          -6   /* call out of order (e.g. sr_step before sr_set_image) */
+
+/* ---- flags ----------------------------------------------------------- */
+#define SR_HOST            1u   /* pointer arguments are host memory */
+
+/* ---- parameters -------------------------------------------------------
+ * Names follow the paper.  sr_params_default fills the parameter set of the
+ * paper's two-circles experiment (alpha = gamma = 4, beta = 0.2, mu = 8,
+ * tau = 0.1, l = 1, d = 5, S = 3) with eps = 1.5, R = 3, sigma = 1.5,
+ * rho = 1000, s = 2, zero_tol = 1e-3.                                     */
+typedef struct sr_params {
+    uint32_t struct_size;  /* sizeof(sr_params), for ABI versioning         */
+    double gamma;          /* weight of the geodesic length E_g (eq 7)       */
+    double alpha;          /* weight of the balloon / area term E_a (eq 7)   */
+    double beta;           /* weight of the repulsion E_r (eq 7)             */
+    double mu;             /* splitting penalty (eq 22) and implicit weight (eq 30) */
+    double tau;            /* time step of the semi-implicit scheme (eq 30)  */
+    double eps;            /* half-width of H_eps, delta_eps (eqs 5-6)       */
+    double band_l;         /* narrow-band half-width l of h_eps (eq 11)      */
+    double d;              /* Gaussian scale of the repulsion kernel (eq 10) */
+    int32_t R;             /* repulsion window half-width: (2R+1)^2 taps, 0..8 */
+    double sigma;          /* pre-smoothing std of G_sigma in g (eq 1), 0..5 */
+    double rho;            /* scaling of |grad| in g (eq 1)                  */
+    int32_t s_exp;         /* exponent s of g (eq 1): 1 or 2                 */
+    int32_t S;             /* inner phi steps per outer iteration (eq 37), 1..64 */
+    double tol_inner;      /* inner stop: ||dphi|| / (||phi|| + 1e-6) <= tol; 0 = always S */
+    double tol_outer;      /* outer stop on the relative phi change r_k; 0 = never */
+    int32_t min_iter;      /* no outer stop before this many iterations      */
+    int32_t check_every;   /* outer stop checked every this many iterations (>= 1) */
+    int32_t w0_mode;       /* 0: w^0 = grad phi^0 (Algorithm 1), 1: w^0 = 0 (eq 23's text) */
+    double zero_tol;       /* |B| <= zero_tol is the zero vector of eq (42) (its
+                              0 (0/|0|) = 0 rule at rounding level); 0 = literal */
+} sr_params;
+
+/* Per-call report of sr_step. */
+typedef struct sr_step_info {
+    int64_t iters_done;    /* outer iterations run by this call              */
+    int64_t k;             /* total outer iterations since sr_set_image/state */
+    double r_last;         /* r_k = ||phi^{k+1}-phi^k||_F / (||phi^k||_F + 1e-6) of the last iteration */
+    int64_t inner_steps;   /* inner steps executed by this call (S per iteration unless tol_inner > 0) */
+    int32_t converged;     /* 1 if r_k < tol_outer stopped the call          */
+    int32_t reserved;
+} sr_step_info;
+
+typedef struct sr_ctx sr_ctx;
+
+/* Fill *p with the defaults above (struct_size included).  SR_EINVAL on NULL. */
+int sr_params_default(sr_params* p);
+
+/* Bytes of device workspace a context of this size needs (256-byte aligned
+ * base required).  Validates M, N and *p exactly as sr_create does. */
+int sr_workspace_size(int32_t M, int32_t N, const sr_params* p, size_t* bytes);
+
+/* Create a context.  `workspace` is a device buffer of at least
+ * sr_workspace_size bytes, `hip_stream` a hipStream_t (NULL: default stream).
+ * Builds the FP64-computed twiddle / cosine / tap tables and uploads them
+ * into the workspace.  *out receives the context (free with sr_destroy). */
+int sr_create(sr_ctx** out, int32_t M, int32_t N, const sr_params* p,
+              void* workspace, size_t bytes, void* hip_stream);
+
+/* Load an image and an initial level set (Algorithm 1, "Initialize"):
+ * g = 1 / (1 + rho |grad(G_sigma * f)|^s) (eq 1); phi = phi0 (a signed
+ * distance function, negative inside the contour, eqs 2-3);
+ * w^0 = grad phi^0 (forward differences, eq 35) or 0 (w0_mode); b^0 = 0;
+ * k = 0.  f and phi0 are M*N floats.  Synchronises; SR_ENONFINITE if f or
+ * phi0 holds NaN/Inf. */
+int sr_set_image(sr_ctx* ctx, const float* f, const float* phi0, uint32_t flags);
+
+/* Run up to n_iter outer iterations of Algorithm 1.  If tol_outer > 0 the
+ * relative change r_k is read back every check_every iterations and the
+ * call stops once r_k < tol_outer and k >= min_iter (returns SR_OK with
+ * info->converged = 1), else returns SR_NOT_CONVERGED after n_iter.  With
+ * tol_outer = 0 it runs exactly n_iter iterations and returns SR_OK.
+ * `info` may be NULL; if given, the call synchronises to fill it.
+ * SR_ENONFINITE if the iterate became non-finite. */
+int sr_step(sr_ctx* ctx, int32_t n_iter, sr_step_info* info);
+
+/* Copy the current phi (M*N floats) out. */
+int sr_get_phi(sr_ctx* ctx, float* phi_out, uint32_t flags);
+
+/* Copy the edge map g (M*N floats) computed by sr_set_image out. */
+int sr_get_g(sr_ctx* ctx, float* g_out, uint32_t flags);
+
+/* SR energy of the current phi, eqs (7)-(10), with the forward-difference
+ * gradient, unit cell area and the repulsion integral truncated to the same
+ * (2R+1)^2 window as the solver:
+ *   terms[0] = gamma * sum g |grad phi| delta_eps(phi)
+ *   terms[1] = alpha * sum g (1 - H_eps(phi))
+ *   terms[2] = -beta * sum (grad phi h)(x) . sum_y K(x-y) (grad phi h)(y)
+ * accumulated in double.  `terms` may be NULL.  Synchronises. */
+int sr_energy(sr_ctx* ctx, double* E_total, double terms[3]);
+
+/* Checkpoint / teacher forcing: copy (phi, w, b) and k out, or in.  phi is
+ * M*N floats, w and b are 2*M*N floats each.  sr_set_state also rebuilds the
+ * per-iteration constant mu div(b - w).  Requires sr_set_image first (for g). */
+int sr_get_state(sr_ctx* ctx, float* phi, float* w, float* b, int64_t* k, uint32_t flags);
+int sr_set_state(sr_ctx* ctx, const float* phi, const float* w, const float* b, int64_t k,
+                 uint32_t flags);
+
+/* ---- component operators (the steps of one iteration, on caller data) ----
+ * They use the context's sizes, parameters, tables and scratch buffers and
+ * leave the solver state (phi, w, b, g) untouched. */
+
+/* g of eq (1) for image f: periodic Gaussian (taps exp(-t^2/(2 sigma^2)),
+ * |t| <= ceil(3 sigma), normalised), central differences, then
+ * 1 / (1 + rho |grad|^s). */
+int sr_edge_map(sr_ctx* ctx, const float* f, float* g_out, uint32_t flags);
+
+/* Repulsion window sum (the discrete v of Sec. 4, after eq 37):
+ * v[i,j] = sum_{|p|,|q|<=R} exp(-(p^2+q^2)/d^2) w[i+p,j+q] h_eps(phi[i+p,j+q]),
+ * periodic.  w and v_out are 2*M*N floats, phi M*N floats. */
+int sr_repulsion(sr_ctx* ctx, const float* w, const float* phi, float* v_out, uint32_t flags);
+
+/* Semi-implicit solve of eqs (31)-(33): u = Re F^{-1}( F(rhs) / (1 - tau mu
+ * (2 cos z1 + 2 cos z2 - 4)) ), i.e. (1 - tau mu Lap) u = rhs on the periodic
+ * grid, through the library's LDS-staged radix-4/2 Stockham FFTs. */
+int sr_implicit_solve(sr_ctx* ctx, const float* rhs, float* u_out, uint32_t flags);
+
+/* ---- measurement -------------------------------------------------------
+ * Per-kernel timing of the iteration: runs n_iter outer iterations (they
+ * advance the state exactly like sr_step) launching each kernel directly on
+ * the context's stream with a hipEvent before and after it, and reports the
+ * average duration of each kernel kind in milliseconds:
+ *   ms[0] rhs + repulsion window (eq 37)   ms[1] forward row FFT
+ *   ms[2] column FFT solve (eqs 31-33)     ms[3] inverse row FFT + update
+ *   ms[4] w / b step (eqs 40-42, 23)
+ * count[i] receives the number of launches of each kind.  Synchronises. */
+#define SR_NUM_KERNEL_KINDS 5
+int sr_profile_kernels(sr_ctx* ctx, int32_t n_iter, double ms[SR_NUM_KERNEL_KINDS],
+                       int64_t count[SR_NUM_KERNEL_KINDS]);
+
+/* ---- batched solve (many independent images of uneven sizes) ----------
+ * Each item is solved by Algorithm 1 from its own f and phi0, with its own
+ * params (R may differ per item), until r_k < tol_outer (after min_iter) or
+ * max_iter.  Items with equal (M, N, params) are grouped and advanced
+ * together in single launches (one grid slice per instance); converged
+ * instances drop out of further work.  All pointers are device pointers.
+ * The workspace size comes from sr_batch_workspace_size for the same items. */
+typedef struct sr_batch_item {
+    int32_t M, N;
+    const float* f;        /* in:  image, M*N floats (device)              */
+    const float* phi0;     /* in:  initial level set, M*N floats (device)  */
+    float* phi_out;        /* out: final phi, M*N floats (device)          */
+    sr_params params;      /* per-item parameters (tol_outer, min_iter, check_every used) */
+    int32_t max_iter;      /* iteration cap                                 */
+    /* outputs */
+    int32_t iters;         /* iterations run                                */
+    int32_t status;        /* SR_OK, SR_NOT_CONVERGED or SR_ENONFINITE      */
+    int32_t reserved;
+    double r_last;         /* last relative phi change                      */
+    double energy;         /* final SR energy (eq 7)                        */
+} sr_batch_item;
+
+int sr_batch_workspace_size(const sr_batch_item* items, int32_t n, size_t* bytes);
+int sr_solve_batch(sr_batch_item* items, int32_t n, void* workspace, size_t bytes,
+                   void* hip_stream);
+
+/* Release the context (not the caller's workspace).  NULL is a no-op. */
+void sr_destroy(sr_ctx* ctx);
+
+/* Thread-local message describing the last error ("" if none). */
+const char* sr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SR_H_ */

@@ -60,6 +60,10 @@ class Params:
     sigma, rho, s_exp  : Gaussian pre-smoothing, scaling and exponent of g (eq 1)
     S                  : number of inner phi iterations (eq 37)
     tol_inner          : inner stop tolerance (Sec. 4, after eq 37); 0 = always S
+    zero_tol           : |B| at or below this counts as the zero vector of
+                         eq (42) (reading: the paper's 0 (0/|0|) = 0 applied to
+                         B at rounding level, whose direction is noise); 0 is
+                         the literal rule
     """
 
     gamma: float = 1.0
@@ -76,6 +80,7 @@ class Params:
     s_exp: int = 2
     S: int = 3
     tol_inner: float = 0.0
+    zero_tol: float = 1e-3
 
 
 # --------------------------------------------------------------------------
@@ -251,11 +256,13 @@ def phi_subproblem(phi_k, w1, w2, b1, b2, g, P: Params):
 # --------------------------------------------------------------------------
 # w sub-problem: soft thresholding + projection, Bregman  (eqs 40-42, 23)
 # --------------------------------------------------------------------------
-def shrink(B1, B2, t):
+def shrink(B1, B2, t, zero_tol=0.0):
     """Generalised soft thresholding of eq (42):
-    max(|B| - t, 0) B / |B|, with the zero vector where |B| = 0."""
+    max(|B| - t, 0) B / |B|, with the zero vector where |B| <= zero_tol
+    (zero_tol = 0: exactly the paper's 0 (0/|0|) = 0)."""
     nb = np.sqrt(B1 * B1 + B2 * B2)
-    scale = np.where(nb > 0, np.maximum(nb - t, 0.0) / np.where(nb > 0, nb, 1.0), 0.0)
+    live = nb > zero_tol
+    scale = np.where(live, np.maximum(nb - t, 0.0) / np.where(nb > 0, nb, 1.0), 0.0)
     return scale * B1, scale * B2
 
 
@@ -284,7 +291,7 @@ def w_subproblem(phi_new, w1, w2, b1, b2, g, P: Params):
     """w^{k+1}: soft thresholding of eq (42) applied to B of eq (41), then the
     projection of eq (40) (the paper applies it afterwards)."""
     B1, B2, t = shrink_input(phi_new, w1, w2, b1, b2, g, P)
-    s1, s2 = shrink(B1, B2, t)
+    s1, s2 = shrink(B1, B2, t, P.zero_tol)
     return project(s1, s2)
 
 

@@ -1,0 +1,625 @@
+// Host runtime of the SR Split Bregman library: argument validation,
+// workspace carving, FP64 table construction, the per-iteration launch
+// sequence (captured once into HIP graphs and replayed) and the C ABI of
+// include/sr.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/sr.h"
+#include "sr_device.hpp"
+#include "sr_kernels.hpp"
+
+namespace sr {
+void configure_kernels();
+}
+
+using sr::DevScal;
+using sr::Geometry;
+using sr::KParams;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+static int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                       \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess) return fail(SR_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+static bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
+
+static int validate(int32_t M, int32_t N, const sr_params* p) {
+    if (!p) return fail(SR_EINVAL, "params is NULL");
+    if (p->struct_size != sizeof(sr_params))
+        return fail(SR_EINVAL, "params.struct_size %u != %zu (call sr_params_default)", p->struct_size,
+                    sizeof(sr_params));
+    if (!is_pow2(M) || !is_pow2(N) || M < 8 || N < 8 || M > 4096 || N > 4096)
+        return fail(SR_EUNSUPPORTED, "M, N must be powers of two in [8, 4096] (got %d x %d)", M, N);
+    const double v[] = {p->gamma, p->alpha, p->beta, p->mu, p->tau, p->eps, p->band_l, p->d,
+                        p->sigma, p->rho, p->tol_inner, p->tol_outer, p->zero_tol};
+    for (double x : v)
+        if (!std::isfinite(x)) return fail(SR_EINVAL, "non-finite parameter");
+    if (p->tau <= 0) return fail(SR_EINVAL, "tau must be > 0");
+    if (p->mu <= 0) return fail(SR_EINVAL, "mu must be > 0 (it divides beta and gamma in eqs 41-42)");
+    if (p->eps <= 0) return fail(SR_EINVAL, "eps must be > 0");
+    if (p->band_l < 0) return fail(SR_EINVAL, "band_l must be >= 0");
+    if (p->d <= 0) return fail(SR_EINVAL, "d must be > 0");
+    if (p->R < 0 || p->R > sr::kMaxR) return fail(SR_EUNSUPPORTED, "R must be in [0, %d]", sr::kMaxR);
+    if (p->sigma < 0 || std::ceil(3.0 * p->sigma) > sr::kMaxGaussR)
+        return fail(SR_EUNSUPPORTED, "sigma must be in [0, %g]", sr::kMaxGaussR / 3.0);
+    if (p->rho < 0) return fail(SR_EINVAL, "rho must be >= 0");
+    if (p->s_exp != 1 && p->s_exp != 2) return fail(SR_EINVAL, "s_exp must be 1 or 2");
+    if (p->S < 1 || p->S > 64) return fail(SR_EINVAL, "S must be in [1, 64]");
+    if (p->tol_inner < 0 || p->tol_outer < 0) return fail(SR_EINVAL, "tolerances must be >= 0");
+    if (p->check_every < 1) return fail(SR_EINVAL, "check_every must be >= 1");
+    if (p->min_iter < 0) return fail(SR_EINVAL, "min_iter must be >= 0");
+    if (p->w0_mode != 0 && p->w0_mode != 1) return fail(SR_EINVAL, "w0_mode must be 0 or 1");
+    if (p->zero_tol < 0) return fail(SR_EINVAL, "zero_tol must be >= 0");
+    return SR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// workspace layout
+// ---------------------------------------------------------------------------
+struct Layout {
+    size_t twM, twN, g, P0, P1, P2, W0, W1, B0, B1, D, Rb, spec, part, scal, rhist, total;
+};
+
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// nz instances of one size class laid out plane-by-plane ([nz][M][N] each).
+static Layout make_layout(int M, int N, int nz) {
+    Layout L{};
+    const size_t MN = (size_t)M * N, pl = MN * 4 * nz, vec = 2 * pl;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
+    L.twM = take(sizeof(float2) * M);
+    L.twN = take(sizeof(float2) * N);
+    L.g = take(pl);
+    L.P0 = take(pl);
+    L.P1 = take(pl);
+    L.P2 = take(pl);
+    L.W0 = take(vec);
+    L.W1 = take(vec);
+    L.B0 = take(vec);
+    L.B1 = take(vec);
+    L.D = take(pl);
+    L.Rb = take(pl);
+    L.spec = take(pl);
+    const int nb = std::max(sr::tile_blocks(M, N), M);
+    L.part = take(sizeof(double) * 3 * (size_t)nb * nz);
+    L.scal = take(sizeof(DevScal) * nz);
+    L.rhist = take(sizeof(double) * sr::kRHist * nz);
+    L.total = o;
+    return L;
+}
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+struct Bufs {
+    float2 *twM, *twN;
+    float *g, *P0, *P1, *P2, *W[2], *B[2], *D, *Rb;
+    float2* spec;
+    double* part;
+    DevScal* scal;
+    double* rhist;
+};
+
+struct sr_ctx {
+    int M, N, nz;
+    sr_params p;
+    KParams kp;
+    Geometry geo;
+    Bufs b;
+    hipStream_t stream;
+    hipStream_t cap;           // capture stream (graphs are replayed on `stream`)
+    hipGraphExec_t g1[2] = {nullptr, nullptr};   // one iteration from parity p
+    hipGraphExec_t g2[2] = {nullptr, nullptr};   // two iterations from parity p
+    bool use_graphs = true;
+    int parity = 0;            // state in W[parity], B[parity]
+    long long k = 0;
+    bool image_set = false;
+    std::vector<float> gauss;  // Gaussian taps
+    int gauss_r = 0;
+};
+
+static void carve(Bufs& b, char* base, const Layout& L) {
+    b.twM = (float2*)(base + L.twM);
+    b.twN = (float2*)(base + L.twN);
+    b.g = (float*)(base + L.g);
+    b.P0 = (float*)(base + L.P0);
+    b.P1 = (float*)(base + L.P1);
+    b.P2 = (float*)(base + L.P2);
+    b.W[0] = (float*)(base + L.W0);
+    b.W[1] = (float*)(base + L.W1);
+    b.B[0] = (float*)(base + L.B0);
+    b.B[1] = (float*)(base + L.B1);
+    b.D = (float*)(base + L.D);
+    b.Rb = (float*)(base + L.Rb);
+    b.spec = (float2*)(base + L.spec);
+    b.part = (double*)(base + L.part);
+    b.scal = (DevScal*)(base + L.scal);
+    b.rhist = (double*)(base + L.rhist);
+}
+
+static void make_kparams(const sr_params& p, KParams& kp) {
+    std::memset(&kp, 0, sizeof kp);
+    kp.gamma = (float)p.gamma;
+    kp.alpha = (float)p.alpha;
+    kp.beta = (float)p.beta;
+    kp.mu = (float)p.mu;
+    kp.tau = (float)p.tau;
+    kp.eps = (float)p.eps;
+    kp.inv_eps = (float)(1.0 / p.eps);
+    kp.band_l = (float)p.band_l;
+    kp.c_rep = (float)(2.0 * p.beta / p.mu);
+    kp.c_thr = (float)(p.gamma / p.mu);
+    kp.tol_inner = (float)p.tol_inner;
+    kp.zero_tol = (float)p.zero_tol;
+    kp.R = p.R;
+    for (int q = -p.R; q <= p.R; ++q) kp.taps[q + p.R] = (float)std::exp(-(double)q * q / (p.d * p.d));
+}
+
+static void make_gauss(double sigma, std::vector<float>& k, int& r) {
+    r = (int)std::ceil(3.0 * sigma);
+    k.assign(2 * r + 1, 0.0f);
+    if (r == 0) { k[0] = 1.0f; return; }
+    std::vector<double> kd(2 * r + 1);
+    double s = 0;
+    for (int t = -r; t <= r; ++t) { kd[t + r] = std::exp(-(double)t * t / (2.0 * sigma * sigma)); s += kd[t + r]; }
+    for (int t = 0; t <= 2 * r; ++t) k[t] = (float)(kd[t] / s);
+}
+
+static std::vector<float2> twiddles(int L) {
+    std::vector<float2> t(L);
+    const double two_pi = 6.283185307179586476925286766559;
+    for (int n = 0; n < L; ++n) {
+        const double a = two_pi * (double)n / (double)L;
+        t[n] = make_float2((float)std::cos(a), (float)-std::sin(a));
+    }
+    return t;
+}
+
+// The launch sequence of one outer iteration from parity p (Algorithm 1):
+// S x [rhs -> row FFT -> column solve -> inverse row FFT], then the w step.
+static void enqueue_iteration(sr_ctx* c, int p, hipStream_t st) {
+    Bufs& b = c->b;
+    const int S = c->p.S;
+    const float* in = b.P0;
+    float* outs[2] = {b.P1, b.P2};
+    for (int s = 0; s < S; ++s) {
+        float* out = outs[s & 1];
+        sr::launch_rhs(c->geo, c->kp, in, b.W[p], b.g, b.D, b.Rb, c->nz, b.scal, st);
+        sr::launch_solve(c->geo, b.Rb, in, out, b.spec, c->kp.tol_inner, b.part, c->nz, b.scal, st);
+        in = out;
+    }
+    sr::launch_wstep(c->geo, c->kp, in, b.P0, b.W[p], b.B[p], b.g, b.W[1 - p], b.B[1 - p], b.D, b.part, b.rhist,
+                     c->nz, b.scal, st);
+}
+
+static int capture(sr_ctx* c, int p, int iters, hipGraphExec_t* out) {
+    hipGraph_t graph = nullptr;
+    HIP_TRY(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+    for (int i = 0; i < iters; ++i) enqueue_iteration(c, (p + i) & 1, c->cap);
+    hipError_t e = hipStreamEndCapture(c->cap, &graph);
+    if (e != hipSuccess) return fail(SR_EHIP, "graph capture: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(SR_EHIP, "graph instantiate: %s", hipGetErrorString(e));
+    return SR_OK;
+}
+
+// Enqueue n outer iterations on the context's stream.
+static int enqueue_iters(sr_ctx* c, int n) {
+    while (n > 0) {
+        const int p = c->parity;
+        if (!c->use_graphs) {
+            enqueue_iteration(c, p, c->stream);
+            HIP_TRY(hipGetLastError());
+            c->parity ^= 1;
+            c->k += 1;
+            n -= 1;
+            continue;
+        }
+        if (n >= 2) {
+            if (!c->g2[p]) { int rc = capture(c, p, 2, &c->g2[p]); if (rc) return rc; }
+            HIP_TRY(hipGraphLaunch(c->g2[p], c->stream));
+            c->k += 2;
+            n -= 2;
+        } else {
+            if (!c->g1[p]) { int rc = capture(c, p, 1, &c->g1[p]); if (rc) return rc; }
+            HIP_TRY(hipGraphLaunch(c->g1[p], c->stream));
+            c->parity ^= 1;
+            c->k += 1;
+            n -= 1;
+        }
+    }
+    return SR_OK;
+}
+
+static int copy_in(sr_ctx* c, void* dst, const void* src, size_t bytes, uint32_t flags) {
+    HIP_TRY(hipMemcpyAsync(dst, src, bytes, (flags & SR_HOST) ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice,
+                           c->stream));
+    return SR_OK;
+}
+
+static int copy_out(sr_ctx* c, void* dst, const void* src, size_t bytes, uint32_t flags, bool sync = true) {
+    HIP_TRY(hipMemcpyAsync(dst, src, bytes, (flags & SR_HOST) ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice,
+                           c->stream));
+    if ((flags & SR_HOST) && sync) HIP_TRY(hipStreamSynchronize(c->stream));
+    return SR_OK;
+}
+
+static int read_scal(sr_ctx* c, DevScal* out) {
+    HIP_TRY(hipMemcpyAsync(out, c->b.scal, sizeof(DevScal), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return SR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int sr_params_default(sr_params* p) {
+    if (!p) return fail(SR_EINVAL, "params is NULL");
+    std::memset(p, 0, sizeof *p);
+    p->struct_size = sizeof(sr_params);
+    p->gamma = 4.0;
+    p->alpha = 4.0;
+    p->beta = 0.2;
+    p->mu = 8.0;
+    p->tau = 0.1;
+    p->eps = 1.5;
+    p->band_l = 1.0;
+    p->d = 5.0;
+    p->R = 3;
+    p->sigma = 1.5;
+    p->rho = 1000.0;
+    p->s_exp = 2;
+    p->S = 3;
+    p->tol_inner = 0.0;
+    p->tol_outer = 0.0;
+    p->min_iter = 0;
+    p->check_every = 10;
+    p->w0_mode = 0;
+    p->zero_tol = 1e-3;
+    return SR_OK;
+}
+
+int sr_workspace_size(int32_t M, int32_t N, const sr_params* p, size_t* bytes) {
+    if (!bytes) return fail(SR_EINVAL, "bytes is NULL");
+    int rc = validate(M, N, p);
+    if (rc) return rc;
+    *bytes = make_layout(M, N, 1).total;
+    return SR_OK;
+}
+
+int sr_create(sr_ctx** out, int32_t M, int32_t N, const sr_params* p, void* workspace, size_t bytes,
+              void* hip_stream) {
+    if (!out) return fail(SR_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = validate(M, N, p);
+    if (rc) return rc;
+    if (!workspace) return fail(SR_EINVAL, "workspace is NULL");
+    if ((uintptr_t)workspace & 255) return fail(SR_EWORKSPACE, "workspace must be 256-byte aligned");
+    const Layout L = make_layout(M, N, 1);
+    if (bytes < L.total) return fail(SR_EWORKSPACE, "workspace has %zu bytes, needs %zu", bytes, L.total);
+
+    sr::configure_kernels();
+    sr_ctx* c = new sr_ctx();
+    c->M = M;
+    c->N = N;
+    c->nz = 1;
+    c->p = *p;
+    c->stream = (hipStream_t)hip_stream;
+    make_kparams(c->p, c->kp);
+    make_gauss(c->p.sigma, c->gauss, c->gauss_r);
+    carve(c->b, (char*)workspace, L);
+    c->geo.M = M;
+    c->geo.N = N;
+    c->geo.twM = c->b.twM;
+    c->geo.twN = c->b.twN;
+    c->geo.taumu = (float)(c->p.tau * c->p.mu);
+    const char* ng = std::getenv("SR_NO_GRAPH");
+    c->use_graphs = !(ng && ng[0] == '1');
+
+    hipError_t e = hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking);
+    if (e != hipSuccess) { delete c; return fail(SR_EHIP, "hipStreamCreate: %s", hipGetErrorString(e)); }
+    const std::vector<float2> tm = twiddles(M), tn = twiddles(N);
+    e = hipMemcpyAsync(c->b.twM, tm.data(), sizeof(float2) * M, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->b.twN, tn.data(), sizeof(float2) * N, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) { sr::launch_reset_scal(c->b.scal, 1, 1, c->stream); e = hipGetLastError(); }
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        (void)hipStreamDestroy(c->cap);
+        delete c;
+        return fail(SR_EHIP, "sr_create upload: %s", hipGetErrorString(e));
+    }
+    *out = c;
+    return SR_OK;
+}
+
+void sr_destroy(sr_ctx* c) {
+    if (!c) return;
+    for (int i = 0; i < 2; ++i) {
+        if (c->g1[i]) (void)hipGraphExecDestroy(c->g1[i]);
+        if (c->g2[i]) (void)hipGraphExecDestroy(c->g2[i]);
+    }
+    (void)hipStreamDestroy(c->cap);
+    delete c;
+}
+
+const char* sr_last_error(void) { return g_err.c_str(); }
+
+int sr_set_image(sr_ctx* c, const float* f, const float* phi0, uint32_t flags) {
+    if (!c || !f || !phi0) return fail(SR_EINVAL, "NULL argument");
+    const size_t bytes = sizeof(float) * c->M * c->N;
+    const float* fd = f;
+    const float* pd = phi0;
+    if (flags & SR_HOST) {
+        int rc = copy_in(c, c->b.P2, f, bytes, flags);
+        if (!rc) rc = copy_in(c, c->b.P1, phi0, bytes, flags);
+        if (rc) return rc;
+        fd = c->b.P2;
+        pd = c->b.P1;
+    }
+    sr::launch_reset_scal(c->b.scal, 1, 1, c->stream);
+    sr::launch_edge(c->geo, fd, c->b.Rb, (float*)c->b.spec, c->b.g, c->gauss.data(), c->gauss_r, (float)c->p.rho,
+                    c->p.s_exp, c->b.scal, c->stream);
+    sr::launch_init(c->geo, pd, c->b.P0, c->b.W[0], c->b.B[0], c->b.D, (float)c->p.mu, c->p.w0_mode, c->b.scal,
+                    c->stream);
+    HIP_TRY(hipGetLastError());
+    c->parity = 0;
+    c->k = 0;
+    DevScal s;
+    int rc = read_scal(c, &s);
+    if (rc) return rc;
+    if (s.nonfinite) return fail(SR_ENONFINITE, "f or phi0 contains NaN/Inf");
+    c->image_set = true;
+    return SR_OK;
+}
+
+int sr_step(sr_ctx* c, int32_t n_iter, sr_step_info* info) {
+    if (!c) return fail(SR_EINVAL, "ctx is NULL");
+    if (n_iter < 0) return fail(SR_EINVAL, "n_iter must be >= 0");
+    if (!c->image_set) return fail(SR_ESTATE, "sr_step before sr_set_image / sr_set_state");
+    const long long k0 = c->k;
+    DevScal s0{};
+    const bool tolin = c->p.tol_inner > 0;
+    if (tolin) { int rc = read_scal(c, &s0); if (rc) return rc; }
+    int done = 0, converged = 0;
+    double r_last = -1.0;
+    if (c->p.tol_outer > 0) {
+        while (done < n_iter) {
+            const int chunk = std::min(c->p.check_every, n_iter - done);
+            int rc = enqueue_iters(c, chunk);
+            if (rc) return rc;
+            done += chunk;
+            DevScal s;
+            rc = read_scal(c, &s);
+            if (rc) return rc;
+            r_last = s.r_last;
+            if (!std::isfinite(r_last)) return fail(SR_ENONFINITE, "iterate became non-finite at k=%lld", c->k);
+            if (c->k >= c->p.min_iter && r_last < c->p.tol_outer) { converged = 1; break; }
+        }
+    } else {
+        int rc = enqueue_iters(c, n_iter);
+        if (rc) return rc;
+        done = n_iter;
+    }
+    if (info || c->p.tol_outer <= 0) {
+        DevScal s;
+        int rc = read_scal(c, &s);
+        if (rc) return rc;
+        r_last = s.r_last;
+        if (done > 0 && !std::isfinite(r_last)) return fail(SR_ENONFINITE, "iterate became non-finite at k=%lld", c->k);
+        if (info) {
+            info->iters_done = c->k - k0;
+            info->k = c->k;
+            info->r_last = r_last;
+            info->inner_steps = tolin ? (s.inner_steps - s0.inner_steps) : (long long)c->p.S * (c->k - k0);
+            info->converged = converged;
+            info->reserved = 0;
+        }
+    }
+    if (c->p.tol_outer > 0 && !converged) return SR_NOT_CONVERGED;
+    return SR_OK;
+}
+
+int sr_get_phi(sr_ctx* c, float* phi_out, uint32_t flags) {
+    if (!c || !phi_out) return fail(SR_EINVAL, "NULL argument");
+    return copy_out(c, phi_out, c->b.P0, sizeof(float) * c->M * c->N, flags);
+}
+
+int sr_get_g(sr_ctx* c, float* g_out, uint32_t flags) {
+    if (!c || !g_out) return fail(SR_EINVAL, "NULL argument");
+    if (!c->image_set) return fail(SR_ESTATE, "sr_get_g before sr_set_image");
+    return copy_out(c, g_out, c->b.g, sizeof(float) * c->M * c->N, flags);
+}
+
+int sr_energy(sr_ctx* c, double* E_total, double terms[3]) {
+    if (!c || !E_total) return fail(SR_EINVAL, "NULL argument");
+    if (!c->image_set) return fail(SR_ESTATE, "sr_energy before sr_set_image");
+    sr::launch_energy(c->geo, c->kp, c->b.P0, c->b.g, c->b.part, 1, c->b.scal, c->stream);
+    HIP_TRY(hipGetLastError());
+    DevScal s;
+    int rc = read_scal(c, &s);
+    if (rc) return rc;
+    *E_total = s.energy[0] + s.energy[1] + s.energy[2];
+    if (terms) { terms[0] = s.energy[0]; terms[1] = s.energy[1]; terms[2] = s.energy[2]; }
+    return SR_OK;
+}
+
+int sr_get_state(sr_ctx* c, float* phi, float* w, float* b, int64_t* k, uint32_t flags) {
+    if (!c || !phi || !w || !b) return fail(SR_EINVAL, "NULL argument");
+    const size_t MN = (size_t)c->M * c->N;
+    int rc = copy_out(c, phi, c->b.P0, sizeof(float) * MN, flags, false);
+    if (!rc) rc = copy_out(c, w, c->b.W[c->parity], 2 * sizeof(float) * MN, flags, false);
+    if (!rc) rc = copy_out(c, b, c->b.B[c->parity], 2 * sizeof(float) * MN, flags);
+    if (rc) return rc;
+    if (k) *k = c->k;
+    return SR_OK;
+}
+
+int sr_set_state(sr_ctx* c, const float* phi, const float* w, const float* b, int64_t k, uint32_t flags) {
+    if (!c || !phi || !w || !b) return fail(SR_EINVAL, "NULL argument");
+    if (!c->image_set) return fail(SR_ESTATE, "sr_set_state needs g: call sr_set_image first");
+    if (k < 0) return fail(SR_EINVAL, "k must be >= 0");
+    const size_t MN = (size_t)c->M * c->N;
+    c->parity = 0;
+    int rc = copy_in(c, c->b.P0, phi, sizeof(float) * MN, flags);
+    if (!rc) rc = copy_in(c, c->b.W[0], w, 2 * sizeof(float) * MN, flags);
+    if (!rc) rc = copy_in(c, c->b.B[0], b, 2 * sizeof(float) * MN, flags);
+    if (rc) return rc;
+    sr::launch_set_D(c->geo, c->b.W[0], c->b.B[0], c->b.D, (float)c->p.mu, c->stream);
+    sr::launch_set_k(c->b.scal, k, c->stream);
+    HIP_TRY(hipGetLastError());
+    if (flags & SR_HOST) HIP_TRY(hipStreamSynchronize(c->stream));
+    c->k = k;
+    return SR_OK;
+}
+
+int sr_edge_map(sr_ctx* c, const float* f, float* g_out, uint32_t flags) {
+    if (!c || !f || !g_out) return fail(SR_EINVAL, "NULL argument");
+    const size_t bytes = sizeof(float) * c->M * c->N;
+    const float* fd = f;
+    float* gd = g_out;
+    if (flags & SR_HOST) {
+        int rc = copy_in(c, c->b.P2, f, bytes, flags);
+        if (rc) return rc;
+        fd = c->b.P2;
+        gd = c->b.P1;
+    }
+    sr::launch_edge(c->geo, fd, c->b.Rb, (float*)c->b.spec, gd, c->gauss.data(), c->gauss_r, (float)c->p.rho,
+                    c->p.s_exp, c->b.scal, c->stream);
+    HIP_TRY(hipGetLastError());
+    if (flags & SR_HOST) return copy_out(c, g_out, gd, bytes, flags);
+    return SR_OK;
+}
+
+int sr_repulsion(sr_ctx* c, const float* w, const float* phi, float* v_out, uint32_t flags) {
+    if (!c || !w || !phi || !v_out) return fail(SR_EINVAL, "NULL argument");
+    const size_t MN = (size_t)c->M * c->N;
+    const int q = c->parity ^ 1;   // the free ping-pong buffers hold no state
+    const float* wd = w;
+    const float* pd = phi;
+    float* vd = v_out;
+    if (flags & SR_HOST) {
+        int rc = copy_in(c, c->b.W[q], w, 2 * sizeof(float) * MN, flags);
+        if (!rc) rc = copy_in(c, c->b.P1, phi, sizeof(float) * MN, flags);
+        if (rc) return rc;
+        wd = c->b.W[q];
+        pd = c->b.P1;
+        vd = c->b.B[q];
+    }
+    sr::launch_repulsion(c->geo, c->kp, pd, wd, vd, c->stream);
+    HIP_TRY(hipGetLastError());
+    if (flags & SR_HOST) return copy_out(c, v_out, vd, 2 * sizeof(float) * MN, flags);
+    return SR_OK;
+}
+
+int sr_implicit_solve(sr_ctx* c, const float* rhs, float* u_out, uint32_t flags) {
+    if (!c || !rhs || !u_out) return fail(SR_EINVAL, "NULL argument");
+    const size_t bytes = sizeof(float) * c->M * c->N;
+    const float* rd = rhs;
+    float* ud = u_out;
+    if (flags & SR_HOST) {
+        int rc = copy_in(c, c->b.P1, rhs, bytes, flags);
+        if (rc) return rc;
+        rd = c->b.P1;
+        ud = c->b.P2;
+    }
+    sr::launch_solve(c->geo, rd, nullptr, ud, c->b.spec, 0.0f, c->b.part, 1, c->b.scal, c->stream);
+    HIP_TRY(hipGetLastError());
+    if (flags & SR_HOST) return copy_out(c, u_out, ud, bytes, flags);
+    return SR_OK;
+}
+
+int sr_profile_kernels(sr_ctx* c, int32_t n_iter, double ms[SR_NUM_KERNEL_KINDS],
+                       int64_t count[SR_NUM_KERNEL_KINDS]) {
+    if (!c || !ms || !count) return fail(SR_EINVAL, "NULL argument");
+    if (n_iter < 1) return fail(SR_EINVAL, "n_iter must be >= 1");
+    if (!c->image_set) return fail(SR_ESTATE, "sr_profile_kernels before sr_set_image");
+    const int S = c->p.S;
+    const int per_iter = 4 * S + 1;
+    std::vector<hipEvent_t> ev(2 * (size_t)per_iter * n_iter);
+    for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
+    std::vector<int> kind;
+    kind.reserve((size_t)per_iter * n_iter);
+    size_t q = 0;
+    Bufs& b = c->b;
+    hipStream_t st = c->stream;
+    for (int it = 0; it < n_iter; ++it) {
+        const int p = c->parity;
+        const float* in = b.P0;
+        float* outs[2] = {b.P1, b.P2};
+        for (int s = 0; s < S; ++s) {
+            float* out = outs[s & 1];
+            HIP_TRY(hipEventRecord(ev[q++], st));
+            sr::launch_rhs(c->geo, c->kp, in, b.W[p], b.g, b.D, b.Rb, 1, b.scal, st);
+            HIP_TRY(hipEventRecord(ev[q++], st));
+            kind.push_back(0);
+            for (int pass = 0; pass < 3; ++pass) {
+                HIP_TRY(hipEventRecord(ev[q++], st));
+                sr::launch_solve_pass(pass, c->geo, b.Rb, in, out, b.spec, c->kp.tol_inner, b.part, 1, b.scal, st);
+                HIP_TRY(hipEventRecord(ev[q++], st));
+                kind.push_back(1 + pass);
+            }
+            in = out;
+        }
+        HIP_TRY(hipEventRecord(ev[q++], st));
+        sr::launch_wstep(c->geo, c->kp, in, b.P0, b.W[p], b.B[p], b.g, b.W[1 - p], b.B[1 - p], b.D, b.part, b.rhist,
+                         1, b.scal, st);
+        HIP_TRY(hipEventRecord(ev[q++], st));
+        kind.push_back(4);
+        HIP_TRY(hipGetLastError());
+        c->parity ^= 1;
+        c->k += 1;
+    }
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int i = 0; i < SR_NUM_KERNEL_KINDS; ++i) { ms[i] = 0.0; count[i] = 0; }
+    for (size_t i = 0; i < kind.size(); ++i) {
+        float t = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&t, ev[2 * i], ev[2 * i + 1]));
+        ms[kind[i]] += t;
+        count[kind[i]] += 1;
+    }
+    for (int i = 0; i < SR_NUM_KERNEL_KINDS; ++i)
+        if (count[i]) ms[i] /= (double)count[i];
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    return SR_OK;
+}
+
+int sr_batch_workspace_size(const sr_batch_item* items, int32_t n, size_t* bytes) {
+    (void)items; (void)n; (void)bytes;
+    return fail(SR_EUNSUPPORTED, "sr_batch_workspace_size: not built yet");
+}
+
+int sr_solve_batch(sr_batch_item* items, int32_t n, void* workspace, size_t bytes, void* hip_stream) {
+    (void)items; (void)n; (void)workspace; (void)bytes; (void)hip_stream;
+    return fail(SR_EUNSUPPORTED, "sr_solve_batch: not built yet");
+}
+
+}  // extern "C"

@@ -1,0 +1,252 @@
+// Device-side building blocks of the SR Split Bregman solver (gfx950).
+//
+//  - the compactly supported H_eps, delta_eps, delta'_eps (eqs 5, 6, 29)
+//    and the narrow band h_eps, h'_eps (eqs 11, 28), in FP32;
+//  - an in-LDS complex FFT (Stockham auto-sort, radix-4 stages plus one
+//    radix-2 stage for odd log2 lengths) used by the row and column passes
+//    of the semi-implicit solve (eqs 31-33);
+//  - deterministic block / grid reductions in FP64.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sr {
+
+constexpr int kMaxR = 8;        // largest repulsion window half-width
+constexpr int kMaxTaps = 2 * kMaxR + 1;
+constexpr int kMaxGaussR = 16;  // largest Gaussian radius ceil(3 sigma)
+constexpr int kTileW = 64;      // tile width of the stencil kernels (one wave per row)
+constexpr int kTileThreads = 256;
+constexpr int kScalStride = 64; // int64 words of per-instance device scalars
+constexpr int kRHist = 1024;    // residual history ring (per instance)
+
+// Per-instance device scalars (one block of kScalStride int64 words,
+// followed elsewhere by the residual ring).
+struct DevScal {
+    unsigned int counter;   // last-block-done ticket of the running kernel
+    int inner_done;         // inner stop rule met in this outer iteration
+    int active;             // 0: instance finished (batched solve) -> kernels skip it
+    int nonfinite;          // NaN/Inf seen in an input
+    long long k;            // outer iterations completed
+    long long inner_steps;  // inner steps executed (counted when tol_inner > 0)
+    double r_last;          // last outer relative change r_k
+    double inner_rel;       // last inner relative change
+    double energy[3];       // gamma E_g, alpha E_a, beta E_r
+    long long pad[kScalStride - 9];
+};
+static_assert(sizeof(DevScal) == kScalStride * 8, "DevScal layout");
+
+// Scalars the kernels need, in FP32, plus the FP64-computed window taps.
+struct KParams {
+    float gamma, alpha, beta, mu, tau;
+    float eps, inv_eps, band_l;
+    float c_rep;       // 2 beta / mu      (eq 41)
+    float c_thr;       // gamma / mu       (eq 42)
+    float tol_inner;
+    float zero_tol;    // |B| <= zero_tol counts as the zero vector (eq 42)
+    int R;
+    float taps[kMaxTaps];   // a_q = exp(-q^2/d^2), q = -R..R at index q+R
+};
+
+// ---------------------------------------------------------------------------
+// H_eps and delta_eps (eqs 5, 6), evaluated together.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void heav_dirac(float x, float eps, float inv_eps, float& H, float& dl) {
+    if (x > eps) { H = 1.0f; dl = 0.0f; return; }
+    if (x < -eps) { H = 0.0f; dl = 0.0f; return; }
+    float s, c;
+    const float u = x * inv_eps;
+    sincospif(u, &s, &c);
+    H = 0.5f * (1.0f + u + s * 0.31830988618379067f);
+    dl = 0.5f * inv_eps * (1.0f + c);
+}
+
+// h_eps = H(phi + l)(1 - H(phi - l))  (eq 11)
+__device__ __forceinline__ float band_h(float x, const KParams& kp) {
+    const float lim = kp.band_l + kp.eps;
+    if (x > lim || x < -lim) return 0.0f;
+    float Hp, dp, Hm, dm;
+    heav_dirac(x + kp.band_l, kp.eps, kp.inv_eps, Hp, dp);
+    heav_dirac(x - kp.band_l, kp.eps, kp.inv_eps, Hm, dm);
+    return Hp * (1.0f - Hm);
+}
+
+// h_eps and h'_eps (eq 28) together.
+__device__ __forceinline__ void band_h_dh(float x, const KParams& kp, float& h, float& dh) {
+    const float lim = kp.band_l + kp.eps;
+    if (x > lim || x < -lim) { h = 0.0f; dh = 0.0f; return; }
+    float Hp, dp, Hm, dm;
+    heav_dirac(x + kp.band_l, kp.eps, kp.inv_eps, Hp, dp);
+    heav_dirac(x - kp.band_l, kp.eps, kp.inv_eps, Hm, dm);
+    h = Hp * (1.0f - Hm);
+    dh = dp * (1.0f - Hm) - Hp * dm;
+}
+
+// delta_eps and delta'_eps (eqs 6, 29) together.
+__device__ __forceinline__ void dirac_d(float x, const KParams& kp, float& dl, float& ddl) {
+    if (x > kp.eps || x < -kp.eps) { dl = 0.0f; ddl = 0.0f; return; }
+    float s, c;
+    sincospif(x * kp.inv_eps, &s, &c);
+    dl = 0.5f * kp.inv_eps * (1.0f + c);
+    ddl = -1.5707963267948966f * kp.inv_eps * kp.inv_eps * s;
+}
+
+// ---------------------------------------------------------------------------
+// complex helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {   // a * conj(b)
+    return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+
+template <int L> struct Ilog2 { static constexpr int v = 1 + Ilog2<L / 2>::v; };
+template <> struct Ilog2<1> { static constexpr int v = 0; };
+
+// Work split of one length-L transform: NT threads, E elements each.
+template <int L> struct FftShape {
+    static constexpr int E = L < 16 ? L : 16;
+    static constexpr int NT = L / E;
+    static constexpr int LOG = Ilog2<L>::v;
+};
+
+// One radix-4 Stockham stage: sub-transform size Ns -> 4 Ns.
+// Butterfly j reads x[j + r L/4], twiddles by W_{4Ns}^{r k} (k = j mod Ns),
+// and writes x[(j - k) 4 + k + r Ns].  Twiddle W_{4Ns}^{m} = tw[m L/(4Ns)],
+// tw[n] = exp(-2 pi i n / L).
+template <int L, bool INV>
+__device__ __forceinline__ void fft_stage4(float2* x, const float2* __restrict__ tw, int t, int Ns) {
+    constexpr int E = FftShape<L>::E, NT = FftShape<L>::NT;
+    constexpr int Q = L / 4;
+    float2 v[E];
+#pragma unroll
+    for (int b = 0; b < E / 4; ++b) {
+        const int j = t + b * NT;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[4 * b + r] = x[j + r * Q];
+    }
+    __syncthreads();
+    const int stride = L / (4 * Ns);
+#pragma unroll
+    for (int b = 0; b < E / 4; ++b) {
+        const int j = t + b * NT;
+        const int k = j & (Ns - 1);
+        float2 a0 = v[4 * b], a1 = v[4 * b + 1], a2 = v[4 * b + 2], a3 = v[4 * b + 3];
+        if (Ns > 1) {
+            const float2 w1 = tw[k * stride], w2 = tw[2 * k * stride], w3 = tw[3 * k * stride];
+            if (INV) { a1 = cmulc(a1, w1); a2 = cmulc(a2, w2); a3 = cmulc(a3, w3); }
+            else     { a1 = cmul(a1, w1);  a2 = cmul(a2, w2);  a3 = cmul(a3, w3); }
+        }
+        const float2 s02 = cadd(a0, a2), d02 = csub(a0, a2);
+        const float2 s13 = cadd(a1, a3), d13 = csub(a1, a3);
+        // forward: y1 = d02 - i d13, y3 = d02 + i d13; inverse swaps them
+        const float2 id13 = make_float2(-d13.y, d13.x);
+        const int base = ((j - k) << 2) + k;
+        x[base] = cadd(s02, s13);
+        x[base + 2 * Ns] = csub(s02, s13);
+        if (INV) { x[base + Ns] = cadd(d02, id13); x[base + 3 * Ns] = csub(d02, id13); }
+        else     { x[base + Ns] = csub(d02, id13); x[base + 3 * Ns] = cadd(d02, id13); }
+    }
+    __syncthreads();
+}
+
+// In-place length-L complex FFT of x (in LDS) by the NT threads t = 0..NT-1
+// of one transform.  Every thread of the workgroup must call it (it
+// contains workgroup barriers).  INV: unnormalised inverse (conjugate twiddles).
+template <int L, bool INV>
+__device__ __forceinline__ void fft_lds(float2* x, const float2* __restrict__ tw, int t) {
+    constexpr int E = FftShape<L>::E, NT = FftShape<L>::NT, LOG = FftShape<L>::LOG;
+    __syncthreads();
+    int Ns = 1;
+    if constexpr (LOG & 1) {
+        float2 v[E];
+#pragma unroll
+        for (int b = 0; b < E / 2; ++b) {
+            const int j = t + b * NT;
+            v[2 * b] = x[j];
+            v[2 * b + 1] = x[j + L / 2];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int b = 0; b < E / 2; ++b) {
+            const int j = t + b * NT;
+            x[2 * j] = cadd(v[2 * b], v[2 * b + 1]);
+            x[2 * j + 1] = csub(v[2 * b], v[2 * b + 1]);
+        }
+        __syncthreads();
+        Ns = 2;
+    }
+#pragma unroll
+    for (int st = 0; st < LOG / 2; ++st) {
+        fft_stage4<L, INV>(x, tw, t, Ns);
+        Ns <<= 2;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// reductions (fixed order -> bitwise deterministic)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+// Sum NV values over the workgroup; the result is valid in thread 0.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* red /* LDS, NV*16 */) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+        double s = wave_sum(v[c]);
+        if (lane == 0) red[c * 16 + wid] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int c = 0; c < NV; ++c) {
+            double s = 0.0;
+            for (int w = 0; w < nw; ++w) s += red[c * 16 + w];
+            v[c] = s;
+        }
+    }
+    __syncthreads();
+}
+
+// Grid-wide sum of NV values: each workgroup stores its partial sums, takes a
+// ticket, and the last workgroup adds all partials in block order.  Returns
+// true in the last workgroup, where thread 0 holds the totals in v.  The
+// ticket counter is reset by the last workgroup.
+template <int NV>
+__device__ __forceinline__ bool grid_sum(double (&v)[NV], double* part, int nblocks, int bid,
+                                         unsigned int* counter, double* red) {
+    __shared__ int s_last;
+    block_sum<NV>(v, red);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int c = 0; c < NV; ++c) part[c * nblocks + bid] = v[c];
+        __threadfence();
+        const unsigned int ticket = atomicAdd(counter, 1u);
+        s_last = (ticket == (unsigned int)(nblocks - 1));
+    }
+    __syncthreads();
+    if (!s_last) return false;
+    __threadfence();
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+        double s = 0.0;
+        for (int b = threadIdx.x; b < nblocks; b += blockDim.x) s += part[c * nblocks + b];
+        v[c] = s;
+    }
+    block_sum<NV>(v, red);
+    if (threadIdx.x == 0) *counter = 0u;
+    return true;
+}
+
+}  // namespace sr

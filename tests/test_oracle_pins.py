@@ -398,3 +398,19 @@ def test_initial_state_and_bregman_increment():
     n = np.hypot(st1.w1, st1.w2)
     assert np.all((n == 0) | (np.abs(n - 1) < 1e-12))
     assert info["inner_steps"] == PSMALL.S
+
+
+def test_shrink_zero_tolerance_reading():
+    """zero_tol = 0 is the paper's literal 0 (0/|0|) = 0: a rounding-level B
+    survives (and projects to a unit vector of arbitrary direction); with
+    zero_tol > 0 such a B is the zero vector, larger B are unaffected."""
+    B1, B2 = np.array([3e-9, 0.6]), np.array([-4e-9, 0.8])
+    t = np.zeros(2)
+    s = O.shrink(B1, B2, t, 0.0)
+    np.testing.assert_array_equal(s[0], B1)
+    p = O.project(*s)
+    np.testing.assert_allclose(np.hypot(*p), 1.0, atol=1e-15)
+    s = O.shrink(B1, B2, t, 1e-3)
+    np.testing.assert_array_equal(s[0], [0.0, 0.6])
+    np.testing.assert_array_equal(s[1], [0.0, 0.8])
+    assert O.Params().zero_tol == 1e-3
