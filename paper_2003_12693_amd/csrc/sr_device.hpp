@@ -24,7 +24,7 @@ constexpr int kRHist = 1024;    // residual history ring (per instance)
 // Per-instance device scalars (one block of kScalStride int64 words,
 // followed elsewhere by the residual ring).
 struct DevScal {
-    unsigned int counter;   // last-block-done ticket of the running kernel
+    unsigned int counter;   // reserved
     int inner_done;         // inner stop rule met in this outer iteration
     int active;             // 0: instance finished (batched solve) -> kernels skip it
     int nonfinite;          // NaN/Inf seen in an input
@@ -108,12 +108,23 @@ __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2
 template <int L> struct Ilog2 { static constexpr int v = 1 + Ilog2<L / 2>::v; };
 template <> struct Ilog2<1> { static constexpr int v = 0; };
 
-// Work split of one length-L transform: NT threads, E elements each.
+// Work split of one length-L transform: NT threads, E elements each.  Four
+// elements (one radix-4 butterfly per stage) for lengths up to 1024 gives
+// the most waves per CU; 2048 and 4096 points take 8 and 16 so that the
+// four transforms of an 8-row tile still fit one 1024-thread workgroup.
 template <int L> struct FftShape {
-    static constexpr int E = L < 16 ? L : 16;
+    static constexpr int E = L <= 1024 ? 4 : (L == 2048 ? 8 : 16);
     static constexpr int NT = L / E;
     static constexpr int LOG = Ilog2<L>::v;
 };
+
+// LDS skew of the FFT buffers: element i of a transform lives at
+// i + i / 16.  Without it the Stockham write pattern (stride 4 Ns between
+// lanes for small Ns) maps many lanes of a wave onto the same LDS bank.
+__device__ __forceinline__ int sk(int i) { return i + (i >> 4); }
+// float2 slots of one skewed length-L buffer, +4 so that consecutive
+// transforms start on different banks.
+template <int L> struct LdsLen { static constexpr int v = L + L / 16 + 4; };
 
 // One radix-4 Stockham stage: sub-transform size Ns -> 4 Ns.
 // Butterfly j reads x[j + r L/4], twiddles by W_{4Ns}^{r k} (k = j mod Ns),
@@ -128,7 +139,7 @@ __device__ __forceinline__ void fft_stage4(float2* x, const float2* __restrict__
     for (int b = 0; b < E / 4; ++b) {
         const int j = t + b * NT;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) v[4 * b + r] = x[j + r * Q];
+        for (int r = 0; r < 4; ++r) v[4 * b + r] = x[sk(j + r * Q)];
     }
     __syncthreads();
     const int stride = L / (4 * Ns);
@@ -147,15 +158,15 @@ __device__ __forceinline__ void fft_stage4(float2* x, const float2* __restrict__
         // forward: y1 = d02 - i d13, y3 = d02 + i d13; inverse swaps them
         const float2 id13 = make_float2(-d13.y, d13.x);
         const int base = ((j - k) << 2) + k;
-        x[base] = cadd(s02, s13);
-        x[base + 2 * Ns] = csub(s02, s13);
-        if (INV) { x[base + Ns] = cadd(d02, id13); x[base + 3 * Ns] = csub(d02, id13); }
-        else     { x[base + Ns] = csub(d02, id13); x[base + 3 * Ns] = cadd(d02, id13); }
+        x[sk(base)] = cadd(s02, s13);
+        x[sk(base + 2 * Ns)] = csub(s02, s13);
+        if (INV) { x[sk(base + Ns)] = cadd(d02, id13); x[sk(base + 3 * Ns)] = csub(d02, id13); }
+        else     { x[sk(base + Ns)] = csub(d02, id13); x[sk(base + 3 * Ns)] = cadd(d02, id13); }
     }
     __syncthreads();
 }
 
-// In-place length-L complex FFT of x (in LDS) by the NT threads t = 0..NT-1
+// In-place length-L complex FFT of x (in LDS, skewed by sk()) by the NT threads t = 0..NT-1
 // of one transform.  Every thread of the workgroup must call it (it
 // contains workgroup barriers).  INV: unnormalised inverse (conjugate twiddles).
 template <int L, bool INV>
@@ -168,15 +179,15 @@ __device__ __forceinline__ void fft_lds(float2* x, const float2* __restrict__ tw
 #pragma unroll
         for (int b = 0; b < E / 2; ++b) {
             const int j = t + b * NT;
-            v[2 * b] = x[j];
-            v[2 * b + 1] = x[j + L / 2];
+            v[2 * b] = x[sk(j)];
+            v[2 * b + 1] = x[sk(j + L / 2)];
         }
         __syncthreads();
 #pragma unroll
         for (int b = 0; b < E / 2; ++b) {
             const int j = t + b * NT;
-            x[2 * j] = cadd(v[2 * b], v[2 * b + 1]);
-            x[2 * j + 1] = csub(v[2 * b], v[2 * b + 1]);
+            x[sk(2 * j)] = cadd(v[2 * b], v[2 * b + 1]);
+            x[sk(2 * j + 1)] = csub(v[2 * b], v[2 * b + 1]);
         }
         __syncthreads();
         Ns = 2;
@@ -219,25 +230,22 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* red /* LDS, N
     __syncthreads();
 }
 
-// Grid-wide sum of NV values: each workgroup stores its partial sums, takes a
-// ticket, and the last workgroup adds all partials in block order.  Returns
-// true in the last workgroup, where thread 0 holds the totals in v.  The
-// ticket counter is reset by the last workgroup.
+// Store this workgroup's NV partial sums at part[c * nblocks + bid]; a
+// separate finalize kernel adds them in block order (bitwise deterministic).
+// (An in-kernel "last workgroup" reduction would need an agent-scope fence
+// per workgroup, which on gfx950 writes back the whole non-coherent L2.)
 template <int NV>
-__device__ __forceinline__ bool grid_sum(double (&v)[NV], double* part, int nblocks, int bid,
-                                         unsigned int* counter, double* red) {
-    __shared__ int s_last;
+__device__ __forceinline__ void store_partials(double (&v)[NV], double* part, int nblocks, int bid, double* red) {
     block_sum<NV>(v, red);
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int c = 0; c < NV; ++c) part[c * nblocks + bid] = v[c];
-        __threadfence();
-        const unsigned int ticket = atomicAdd(counter, 1u);
-        s_last = (ticket == (unsigned int)(nblocks - 1));
     }
-    __syncthreads();
-    if (!s_last) return false;
-    __threadfence();
+}
+
+// Sum of the NV x nblocks partials in fixed order; valid in thread 0.
+template <int NV>
+__device__ __forceinline__ void sum_partials(const double* part, int nblocks, double (&v)[NV], double* red) {
 #pragma unroll
     for (int c = 0; c < NV; ++c) {
         double s = 0.0;
@@ -245,8 +253,6 @@ __device__ __forceinline__ bool grid_sum(double (&v)[NV], double* part, int nblo
         v[c] = s;
     }
     block_sum<NV>(v, red);
-    if (threadIdx.x == 0) *counter = 0u;
-    return true;
 }
 
 }  // namespace sr

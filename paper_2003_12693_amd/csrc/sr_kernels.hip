@@ -154,70 +154,132 @@ __device__ __forceinline__ void window_col(const float* sh1, const float* sh2, i
 //   r = tau ( -gamma g |w| delta'(phi) + alpha g delta(phi)
 //             + 2 beta h'(phi) w . v + D + mu Lap phi ),   D = mu div(b - w)
 // ---------------------------------------------------------------------------
-template <int TH>
+// Tile placement: workgroups are dealt to the 8 XCDs round-robin by linear
+// id, so linear id b is remapped to tile (b % 8) * (nb / 8) + b / 8.  Each
+// XCD then owns a horizontal band of tiles and the halo rows two vertically
+// adjacent tiles share are fetched into the same L2.
+__device__ __forceinline__ void xcd_tile(int& tx, int& ty) {
+    const int gx = gridDim.x, nb = gridDim.x * gridDim.y;
+    int b = blockIdx.y * gx + blockIdx.x;
+    if ((nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);
+    ty = b / gx;
+    tx = b - ty * gx;
+}
+
+template <int TH, int R>
+struct RhsTile {
+    static constexpr int TW = kTileW, T = kTileThreads;
+    static constexpr int EH = TH + 2 * R, EW = TW + 2 * R, NEXT = EH * EW;
+    static constexpr int PH = TH + 2, PW = TW + 2;
+    static constexpr int NE = (NEXT + T - 1) / T, NHZ = (EH * TW + T - 1) / T, NO = TH * TW / T;
+    static constexpr size_t lds_floats = 2 * NEXT + 2 * EH * TW + PH * PW;
+};
+
+template <int TH, int R>
 __global__ __launch_bounds__(kTileThreads) void k_rhs(KParams kp, int M, int N,
                                                       const float* __restrict__ phi_s,
                                                       const float* __restrict__ W,
                                                       const float* __restrict__ g,
                                                       const float* __restrict__ D,
                                                       float* __restrict__ out, DevScal* sc) {
-    constexpr int TW = kTileW;
+    using C = RhsTile<TH, R>;
+    constexpr int TW = C::TW, T = C::T, EH = C::EH, EW = C::EW, NEXT = C::NEXT, PW = C::PW, PH = C::PH;
     const int z = blockIdx.z;
     if (!sc[z].active || sc[z].inner_done) return;
     const size_t MN = (size_t)M * N;
     phi_s += z * MN; W += 2 * z * MN; g += z * MN; D += z * MN; out += z * MN;
 
     extern __shared__ float lds[];
-    const int R = kp.R;
-    const int eh = TH + 2 * R, ew = TW + 2 * R;
     float* su1 = lds;
-    float* su2 = su1 + eh * ew;
-    float* sh1 = su2 + eh * ew;
-    float* sh2 = sh1 + eh * TW;
-    float* sphi = sh2 + eh * TW;               // (TH+2) x (TW+2)
-    const int i0 = blockIdx.y * TH, j0 = blockIdx.x * TW;
+    float* su2 = su1 + NEXT;
+    float* sh1 = su2 + NEXT;
+    float* sh2 = sh1 + EH * TW;
+    float* sphi = sh2 + EH * TW;
+    int tx, ty;
+    xcd_tile(tx, ty);
+    const int i0 = ty * TH, j0 = tx * TW;
+    const int tid = threadIdx.x;
 
-    for (int e = threadIdx.x; e < eh * ew; e += blockDim.x) {
-        const int ei = e / ew, ej = e - ei * ew;
-        const int gi = (i0 - R + ei) & (M - 1), gj = (j0 - R + ej) & (N - 1);
-        const size_t o = (size_t)gi * N + gj;
-        const float p = phi_s[o];
-        const float h = band_h(p, kp);
-        su1[e] = W[o] * h;
-        su2[e] = W[MN + o] * h;
-        const int si = ei - R + 1, sj = ej - R + 1;
-        if ((unsigned)si < (unsigned)(TH + 2) && (unsigned)sj < (unsigned)(TW + 2)) sphi[si * (TW + 2) + sj] = p;
+    // phase 1: all loads of the extended tile first, then u = w h(phi)
+    float lp[C::NE], l1[C::NE], l2[C::NE];
+#pragma unroll
+    for (int u = 0; u < C::NE; ++u) {
+        const int e = tid + u * T;
+        if (e < NEXT) {
+            const int ei = e / EW, ej = e - ei * EW;
+            const size_t o = (size_t)((i0 - R + ei) & (M - 1)) * N + ((j0 - R + ej) & (N - 1));
+            lp[u] = phi_s[o];
+            l1[u] = W[o];
+            l2[u] = W[MN + o];
+        }
     }
-    // R = 0 still needs the one-pixel halo of phi for the Laplacian
-    if (R == 0) {
-        for (int e = threadIdx.x; e < (TH + 2) * (TW + 2); e += blockDim.x) {
-            const int si = e / (TW + 2), sj = e - si * (TW + 2);
-            const int gi = (i0 - 1 + si) & (M - 1), gj = (j0 - 1 + sj) & (N - 1);
-            sphi[e] = phi_s[(size_t)gi * N + gj];
+#pragma unroll
+    for (int u = 0; u < C::NE; ++u) {
+        const int e = tid + u * T;
+        if (e < NEXT) {
+            const int ei = e / EW, ej = e - ei * EW;
+            const float h = band_h(lp[u], kp);
+            su1[e] = l1[u] * h;
+            su2[e] = l2[u] * h;
+            const int si = ei - R + 1, sj = ej - R + 1;
+            if ((unsigned)si < (unsigned)PH && (unsigned)sj < (unsigned)PW) sphi[si * PW + sj] = lp[u];
+        }
+    }
+    if constexpr (R == 0) {
+        for (int e = tid; e < PH * PW; e += T) {
+            const int si = e / PW, sj = e - si * PW;
+            sphi[e] = phi_s[(size_t)((i0 - 1 + si) & (M - 1)) * N + ((j0 - 1 + sj) & (N - 1))];
+        }
+    }
+    // the pointwise inputs of phase 3, issued before the barrier
+    float w1v[C::NO], w2v[C::NO], gv[C::NO], dv[C::NO];
+#pragma unroll
+    for (int u = 0; u < C::NO; ++u) {
+        const int e = tid + u * T;
+        const int gi = i0 + e / TW, gj = j0 + (e % TW);
+        const size_t o = (size_t)(gi & (M - 1)) * N + (gj & (N - 1));
+        w1v[u] = W[o]; w2v[u] = W[MN + o]; gv[u] = g[o]; dv[u] = D[o];
+    }
+    __syncthreads();
+    // phase 2: row pass of the separable window
+#pragma unroll
+    for (int u = 0; u < C::NHZ; ++u) {
+        const int e = tid + u * T;
+        if (e < EH * TW) {
+            const int ei = e / TW, j = e - ei * TW;
+            const float* r1 = su1 + ei * EW + j;
+            const float* r2 = su2 + ei * EW + j;
+            float a1 = 0.0f, a2 = 0.0f;
+#pragma unroll
+            for (int q = 0; q <= 2 * R; ++q) { a1 += kp.taps[q] * r1[q]; a2 += kp.taps[q] * r2[q]; }
+            sh1[e] = a1;
+            sh2[e] = a2;
         }
     }
     __syncthreads();
-    window_rows(su1, su2, sh1, sh2, eh, ew, TW, kp);
-    __syncthreads();
-    for (int e = threadIdx.x; e < TH * TW; e += blockDim.x) {
+    // phase 3: column pass and the pointwise rhs
+#pragma unroll
+    for (int u = 0; u < C::NO; ++u) {
+        const int e = tid + u * T;
         const int i = e / TW, j = e - i * TW;
         const int gi = i0 + i, gj = j0 + j;
-        if (gi >= M || gj >= N) continue;
-        float v1, v2;
-        window_col(sh1, sh2, i, j, TW, kp, v1, v2);
-        const float* sp = sphi + (i + 1) * (TW + 2) + (j + 1);
+        float v1 = 0.0f, v2 = 0.0f;
+#pragma unroll
+        for (int pp = 0; pp <= 2 * R; ++pp) {
+            v1 += kp.taps[pp] * sh1[(i + pp) * TW + j];
+            v2 += kp.taps[pp] * sh2[(i + pp) * TW + j];
+        }
+        const float* sp = sphi + (i + 1) * PW + (j + 1);
         const float p = sp[0];
-        const float lap = (sp[-(TW + 2)] + sp[TW + 2]) + (sp[-1] + sp[1]) - 4.0f * p;
-        const size_t o = (size_t)gi * N + gj;
-        const float w1 = W[o], w2 = W[MN + o];
-        const float gg = g[o];
+        const float lap = (sp[-PW] + sp[PW]) + (sp[-1] + sp[1]) - 4.0f * p;
         float dl, ddl, h, dh;
         dirac_d(p, kp, dl, ddl);
         band_h_dh(p, kp, h, dh);
+        const float w1 = w1v[u], w2 = w2v[u], gg = gv[u];
         const float wn = sqrtf(w1 * w1 + w2 * w2);
         const float force = -kp.gamma * gg * wn * ddl + kp.alpha * gg * dl
                             + 2.0f * kp.beta * dh * (w1 * v1 + w2 * v2);
-        out[o] = kp.tau * (force + D[o] + kp.mu * lap);
+        if (gi < M && gj < N) out[(size_t)gi * N + gj] = kp.tau * (force + dv[u] + kp.mu * lap);
     }
 }
 
@@ -266,43 +328,85 @@ __global__ __launch_bounds__(kTileThreads) void k_repulsion(KParams kp, int M, i
 // FFT passes of the semi-implicit solve (eqs 31-33)
 // ---------------------------------------------------------------------------
 // Rows 2m and 2m+1 of the real field r are transformed together as one
-// complex row z = r_a + i r_b.  The half spectrum of each row (N/2 complex,
-// the DC slot carrying (X[0], X[N/2]) as its real and imaginary parts) is
-// stored row-major: spec[i][k], k < N/2.
+// complex row z = r_a + i r_b.  Each row's half spectrum X[k], k < N/2 (the
+// DC slot carrying (X[0], X[N/2]) as its real and imaginary parts) is stored
+// in 8-row tiles: element (row i, k) at ((i / 8) * (N/2) + k) * 8 + i % 8.
+// Row passes then write / read 64-byte runs (8 rows of one frequency) and
+// the column pass reads 128-byte runs (2 adjacent columns x 8 rows).
+constexpr int kSpecTile = 8;
+
+// Twiddle tables up to 2048 points are staged in LDS; 4096-point tables are
+// read from global memory (L1/L2 resident) to leave LDS for the data.
+template <int L> struct TwInLds { static constexpr bool v = L <= 2048; };
+
+template <int L>
+__device__ __forceinline__ const float2* stage_twiddles(float2* tws, const float2* __restrict__ tw) {
+    if constexpr (TwInLds<L>::v) {
+        // up to 8 loads in flight per thread before the LDS stores
+        constexpr int CH = 8;
+        for (int base = threadIdx.x; base < L; base += CH * blockDim.x) {
+            float2 tv[CH];
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                const int n = base + c * blockDim.x;
+                if (n < L) tv[c] = tw[n];
+            }
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                const int n = base + c * blockDim.x;
+                if (n < L) tws[n] = tv[c];
+            }
+        }
+        return tws;   // made visible by the barrier at the start of fft_lds
+    } else {
+        return tw;
+    }
+}
+
+// RT tiles (8 RT rows, 4 RT complex transforms) per workgroup.
 template <int N>
-__global__ __launch_bounds__(256) void k_row_fwd(const float* __restrict__ src, float2* __restrict__ spec,
-                                                 const float2* __restrict__ twN, int M, int G, DevScal* sc) {
+__global__ __launch_bounds__(1024) void k_row_fwd(const float* __restrict__ src, float2* __restrict__ spec,
+                                                  const float2* __restrict__ twN, int M, int RT, DevScal* sc) {
     constexpr int NT = FftShape<N>::NT, E = FftShape<N>::E, H = N / 2;
     const int z = blockIdx.z;
     if (!sc[z].active || sc[z].inner_done) return;
     src += (size_t)z * M * N;
     spec += (size_t)z * M * H;
-    extern __shared__ float2 xs[];
+    extern __shared__ float2 lds2[];
+    float2* xs = lds2 + (TwInLds<N>::v ? N : 0);
+    const float2* tw = stage_twiddles<N>(lds2, twN);
     const int g = threadIdx.x / NT, t = threadIdx.x - g * NT;
-    const int m = blockIdx.x * G + g;
-    const size_t ra = (size_t)(2 * m) * N, rb = ra + N;
-    float2* x = xs + g * N;
+    const int row0 = blockIdx.x * (kSpecTile * RT);
+    const size_t ra = (size_t)(row0 + 2 * g) * N, rb = ra + N;
+    constexpr int LX = LdsLen<N>::v;
+    float2* x = xs + g * LX;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int n = t + e * NT;
-        x[n] = make_float2(src[ra + n], src[rb + n]);
+        x[sk(n)] = make_float2(src[ra + n], src[rb + n]);
     }
-    fft_lds<N, false>(x, twN, t);
-    float2* sa = spec + (size_t)(2 * m) * H;
-    float2* sb = sa + H;
+    fft_lds<N, false>(x, tw, t);
+    // The workgroup's tiles are one contiguous run of RT * 4N float2.
+    float2* dst = spec + (size_t)row0 * H;
+    const int nthr = blockDim.x;
 #pragma unroll
-    for (int e = 0; e < E / 2; ++e) {
-        const int k = t + e * NT;
-        const float2 Zk = x[k];
-        if (k == 0) {
-            const float2 ZH = x[H];
-            sa[0] = make_float2(Zk.x, ZH.x);
-            sb[0] = make_float2(Zk.y, ZH.y);
+    for (int e = 0; e < E; ++e) {
+        const int o = threadIdx.x + e * nthr;
+        const int r = o & 7;
+        const int kk = (o >> 3) & (H - 1);
+        const int tile = (o >> 3) / H;
+        const float2* xz = xs + (tile * 4 + (r >> 1)) * LX;
+        const float2 Zk = xz[sk(kk)];
+        float2 out;
+        if (kk == 0) {
+            const float2 ZH = xz[sk(H)];
+            out = (r & 1) ? make_float2(Zk.y, ZH.y) : make_float2(Zk.x, ZH.x);
         } else {
-            const float2 Zm = x[N - k];
-            sa[k] = make_float2(0.5f * (Zk.x + Zm.x), 0.5f * (Zk.y - Zm.y));
-            sb[k] = make_float2(0.5f * (Zk.y + Zm.y), -0.5f * (Zk.x - Zm.x));
+            const float2 Zm = xz[sk(N - kk)];
+            out = (r & 1) ? make_float2(0.5f * (Zk.y + Zm.y), -0.5f * (Zk.x - Zm.x))
+                          : make_float2(0.5f * (Zk.x + Zm.x), 0.5f * (Zk.y - Zm.y));
         }
+        dst[o] = out;
     }
 }
 
@@ -311,65 +415,82 @@ __global__ __launch_bounds__(256) void k_row_fwd(const float* __restrict__ src, 
 // Column 0 holds two real-signal spectra (l2 = 0 and l2 = N/2) packed as
 // a + i b; they are separated, scaled by their own symbols and re-packed.
 template <int M>
-__global__ __launch_bounds__(256) void k_col_solve(float2* __restrict__ spec, const float2* __restrict__ twM,
-                                                   const float2* __restrict__ twN, int N, int G,
-                                                   float taumu, float inv_mn, DevScal* sc) {
+__global__ __launch_bounds__(1024) void k_col_solve(float2* __restrict__ spec, const float2* __restrict__ twM,
+                                                    const float2* __restrict__ twN, int N, int G, int lrun,
+                                                    float taumu, float inv_mn, DevScal* sc) {
     constexpr int NT = FftShape<M>::NT, E = FftShape<M>::E;
-    constexpr int LD = M + 1;
+    constexpr int LD = LdsLen<M>::v;
     const int z = blockIdx.z;
     if (!sc[z].active || sc[z].inner_done) return;
     const int H = N / 2;
     spec += (size_t)z * M * H;
-    extern __shared__ float2 xs[];
+    extern __shared__ float2 lds2[];
+    float2* xs = lds2 + (TwInLds<M>::v ? M : 0);
+    const float2* tw = stage_twiddles<M>(lds2, twM);
     const int k0 = blockIdx.x * G;
-    for (int e = threadIdx.x; e < G * M; e += blockDim.x) {
-        const int c = e % G, l = e / G;
-        xs[c * LD + l] = spec[(size_t)l * H + k0 + c];
+    const int run = kSpecTile * G;                 // contiguous float2 per row tile (2^lrun)
+    float2* base = spec + (size_t)k0 * kSpecTile;
+    // M * G elements over NT * G threads: exactly E per thread, all loads first
+    {
+        float2 ld[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int idx = threadIdx.x + e * blockDim.x;
+            ld[e] = base[(size_t)(idx >> lrun) * H * kSpecTile + (idx & (run - 1))];
+        }
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int idx = threadIdx.x + e * blockDim.x;
+            const int rem = idx & (run - 1);
+            xs[(rem >> 3) * LD + sk((idx >> lrun) * kSpecTile + (rem & 7))] = ld[e];
+        }
     }
     const int g = threadIdx.x / NT, t = threadIdx.x - g * NT;
     const int col = k0 + g;
     float2* x = xs + g * LD;
-    fft_lds<M, false>(x, twM, t);
+    fft_lds<M, false>(x, tw, t);
     float2 vz[E], vm[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int l = t + e * NT;
-        vz[e] = x[l];
-        vm[e] = x[(M - l) & (M - 1)];
+        vz[e] = x[sk(l)];
+        vm[e] = x[sk((M - l) & (M - 1))];
     }
     __syncthreads();
     const float cn = 2.0f * twN[col].x;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int l = t + e * NT;
-        const float cm = 2.0f * twM[l].x;
+        const float cm = 2.0f * tw[l].x;
         if (col != 0) {
-            const float s = inv_mn / (1.0f + taumu * (4.0f - cm - cn));
-            x[l] = cscale(vz[e], s);
+            const float sc_ = inv_mn / (1.0f + taumu * (4.0f - cm - cn));
+            x[sk(l)] = cscale(vz[e], sc_);
         } else {
             const float p = inv_mn / (1.0f + taumu * (2.0f - cm));   // l2 = 0
             const float q = inv_mn / (1.0f + taumu * (6.0f - cm));   // l2 = N/2
             const float hp = 0.5f * (p + q), hm = 0.5f * (p - q);
-            x[l] = make_float2(hp * vz[e].x + hm * vm[e].x, hp * vz[e].y - hm * vm[e].y);
+            x[sk(l)] = make_float2(hp * vz[e].x + hm * vm[e].x, hp * vz[e].y - hm * vm[e].y);
         }
     }
-    fft_lds<M, true>(x, twM, t);
+    fft_lds<M, true>(x, tw, t);
     __syncthreads();
-    for (int e = threadIdx.x; e < G * M; e += blockDim.x) {
-        const int c = e % G, l = e / G;
-        spec[(size_t)l * H + k0 + c] = xs[c * LD + l];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int idx = threadIdx.x + e * blockDim.x;
+        const int q = idx >> lrun, rem = idx & (run - 1);
+        base[(size_t)q * H * kSpecTile + rem] = xs[(rem >> 3) * LD + sk(q * kSpecTile + (rem & 7))];
     }
 }
 
-// Inverse row FFTs of two rows at once and phi_{s+1} = phi_s + dphi.  With
-// tol_inner > 0, also the inner stop rule ||dphi|| / (||phi_s|| + 1e-6) <= tol
-// (grid-wide sum, last workgroup decides).  Once the rule has fired, the
-// remaining inner steps of the outer iteration copy phi_s through.
+// Inverse row FFTs (two rows per complex FFT) and phi_{s+1} = phi_s + dphi.
+// With tol_inner > 0, also the inner stop rule ||dphi|| / (||phi_s|| + 1e-6)
+// <= tol (grid-wide sum, last workgroup decides).  Once the rule has fired,
+// the remaining inner steps of the outer iteration copy phi_s through.
 template <int N>
-__global__ __launch_bounds__(256) void k_row_inv(const float2* __restrict__ spec, const float* __restrict__ phi_in,
-                                                 float* __restrict__ phi_out, const float2* __restrict__ twN,
-                                                 int M, int G, float tol_inner, double* __restrict__ part,
-                                                 DevScal* sc) {
+__global__ __launch_bounds__(1024) void k_row_inv(const float2* __restrict__ spec, const float* __restrict__ phi_in,
+                                                  float* __restrict__ phi_out, const float2* __restrict__ twN,
+                                                  int M, int RT, float tol_inner, double* __restrict__ part,
+                                                  DevScal* sc) {
     constexpr int NT = FftShape<N>::NT, E = FftShape<N>::E, H = N / 2;
     const int z = blockIdx.z;
     DevScal& S = sc[z];
@@ -378,57 +499,87 @@ __global__ __launch_bounds__(256) void k_row_inv(const float2* __restrict__ spec
     spec += (size_t)z * M * H;
     if (phi_in) phi_in += z * MN;
     phi_out += z * MN;
-    const int g = threadIdx.x / NT, t = threadIdx.x - g * NT;
-    const int m = blockIdx.x * G + g;
-    const size_t ra = (size_t)(2 * m) * N, rb = ra + N;
+    const int row0 = blockIdx.x * (kSpecTile * RT);
     if (S.inner_done) {
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const int n = t + e * NT;
-            phi_out[ra + n] = phi_in ? phi_in[ra + n] : 0.0f;
-            phi_out[rb + n] = phi_in ? phi_in[rb + n] : 0.0f;
-        }
+        const size_t base = (size_t)row0 * N;
+        for (int idx = threadIdx.x; idx < kSpecTile * RT * N; idx += blockDim.x)
+            phi_out[base + idx] = phi_in ? phi_in[base + idx] : 0.0f;
         return;
     }
-    extern __shared__ float2 xs[];
+    extern __shared__ float2 lds2[];
     __shared__ double red[2 * 16];
-    float2* x = xs + g * N;
-    const float2* sa = spec + (size_t)(2 * m) * H;
-    const float2* sb = sa + H;
+    constexpr int LX = LdsLen<N>::v;
+    float2* xs = lds2 + (TwInLds<N>::v ? N : 0);
+    const float2* tw = stage_twiddles<N>(lds2, twN);
+    const int nthr = blockDim.x;
+    const float2* srcb = spec + (size_t)row0 * H;
+    // stage the half spectra: row a of transform gg at x[k], row b at x[H + k]
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int o = threadIdx.x + e * nthr;
+        const int r = o & 7;
+        const int kk = (o >> 3) & (H - 1);
+        const int tile = (o >> 3) / H;
+        xs[(tile * 4 + (r >> 1)) * LX + sk((r & 1) * H + kk)] = srcb[o];
+    }
+    __syncthreads();
+    const int g = threadIdx.x / NT, t = threadIdx.x - g * NT;
+    float2* x = xs + g * LX;
+    float2 va[E / 2], vb[E / 2];
 #pragma unroll
     for (int e = 0; e < E / 2; ++e) {
         const int k = t + e * NT;
-        const float2 Xa = sa[k], Xb = sb[k];
+        va[e] = x[sk(k)];
+        vb[e] = x[sk(H + k)];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E / 2; ++e) {
+        const int k = t + e * NT;
+        const float2 Xa = va[e], Xb = vb[e];
         if (k == 0) {
-            x[0] = make_float2(Xa.x, Xb.x);
-            x[H] = make_float2(Xa.y, Xb.y);
+            x[sk(0)] = make_float2(Xa.x, Xb.x);
+            x[sk(H)] = make_float2(Xa.y, Xb.y);
         } else {
-            x[k] = make_float2(Xa.x - Xb.y, Xa.y + Xb.x);
-            x[N - k] = make_float2(Xa.x + Xb.y, Xb.x - Xa.y);
+            x[sk(k)] = make_float2(Xa.x - Xb.y, Xa.y + Xb.x);
+            x[sk(N - k)] = make_float2(Xa.x + Xb.y, Xb.x - Xa.y);
         }
     }
-    fft_lds<N, true>(x, twN, t);
+    fft_lds<N, true>(x, tw, t);
+    const size_t ra = (size_t)(row0 + 2 * g) * N, rb = ra + N;
     double sd = 0.0, sp = 0.0;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int n = t + e * NT;
-        const float2 Z = x[n];
+        const float2 Zv = x[sk(n)];
         const float pa = phi_in ? phi_in[ra + n] : 0.0f;
         const float pb = phi_in ? phi_in[rb + n] : 0.0f;
-        phi_out[ra + n] = pa + Z.x;
-        phi_out[rb + n] = pb + Z.y;
-        sd += (double)Z.x * Z.x + (double)Z.y * Z.y;
+        phi_out[ra + n] = pa + Zv.x;
+        phi_out[rb + n] = pb + Zv.y;
+        sd += (double)Zv.x * Zv.x + (double)Zv.y * Zv.y;
         sp += (double)pa * pa + (double)pb * pb;
     }
     if (tol_inner > 0.0f) {
         double v[2] = {sd, sp};
         const int nb = gridDim.x;
-        if (grid_sum<2>(v, part + (size_t)z * 2 * nb, nb, blockIdx.x, &S.counter, red) && threadIdx.x == 0) {
-            const double rel = sqrt(v[0]) / (sqrt(v[1]) + 1e-6);
-            S.inner_rel = rel;
-            S.inner_steps += 1;
-            if (rel <= (double)tol_inner) S.inner_done = 1;
-        }
+        store_partials<2>(v, part + (size_t)z * 2 * nb, nb, blockIdx.x, red);
+    }
+}
+
+// Inner stop rule after an executed inner step: ||dphi|| / (||phi_s|| + 1e-6) <= tol.
+__global__ __launch_bounds__(256) void k_fin_inner(const double* __restrict__ part, int nb, float tol_inner,
+                                                   DevScal* sc) {
+    __shared__ double red[2 * 16];
+    const int z = blockIdx.x;
+    DevScal& S = sc[z];
+    if (!S.active || S.inner_done) return;
+    double v[2];
+    sum_partials<2>(part + (size_t)z * 2 * nb, nb, v, red);
+    if (threadIdx.x == 0) {
+        const double rel = sqrt(v[0]) / (sqrt(v[1]) + 1e-6);
+        S.inner_rel = rel;
+        S.inner_steps += 1;
+        if (rel <= (double)tol_inner) S.inner_done = 1;
     }
 }
 
@@ -438,7 +589,19 @@ __global__ __launch_bounds__(256) void k_row_inv(const float2* __restrict__ spec
 // The tile computes w, b on one extra row above and column left so that the
 // backward divergence of its own pixels is local.
 // ---------------------------------------------------------------------------
-template <int TH>
+template <int TH, int R>
+struct WTile {
+    static constexpr int TW = kTileW, T = kTileThreads;
+    static constexpr int CH = TH + 1, CW = TW + 1;           // computed region (one extra row / column)
+    static constexpr int EH = CH + 2 * R, EW = CW + 2 * R, NEXT = EH * EW;
+    static constexpr int PH = TH + 2, PW = TW + 2;
+    static constexpr int NE = (NEXT + T - 1) / T, NHZ = (EH * CW + T - 1) / T;
+    static constexpr int NC = (CH * CW + T - 1) / T, NO = TH * TW / T;
+    static constexpr size_t su_floats = (2 * NEXT > 2 * CH * CW) ? 2 * NEXT : 2 * CH * CW;
+    static constexpr size_t lds_floats = su_floats + 2 * EH * CW + PH * PW;
+};
+
+template <int TH, int R>
 __global__ __launch_bounds__(kTileThreads) void k_wstep(KParams kp, int M, int N,
                                                         const float* __restrict__ phin,
                                                         float* __restrict__ P0,
@@ -448,8 +611,9 @@ __global__ __launch_bounds__(kTileThreads) void k_wstep(KParams kp, int M, int N
                                                         float* __restrict__ Wnew, float* __restrict__ Bnew,
                                                         float* __restrict__ D, double* __restrict__ part,
                                                         double* __restrict__ rhist, DevScal* sc) {
-    constexpr int TW = kTileW;
-    constexpr int CH = TH + 1, CW = TW + 1;
+    using C = WTile<TH, R>;
+    constexpr int TW = C::TW, T = C::T, CH = C::CH, CW = C::CW, EH = C::EH, EW = C::EW, NEXT = C::NEXT;
+    constexpr int PH = C::PH, PW = C::PW;
     const int z = blockIdx.z;
     DevScal& S = sc[z];
     if (!S.active) return;
@@ -459,86 +623,151 @@ __global__ __launch_bounds__(kTileThreads) void k_wstep(KParams kp, int M, int N
 
     extern __shared__ float lds[];
     __shared__ double red[2 * 16];
-    const int R = kp.R;
-    const int eh = CH + 2 * R, ew = CW + 2 * R;
     float* su1 = lds;
-    float* su2 = su1 + eh * ew;
-    float* sh1 = su2 + eh * ew;
-    float* sh2 = sh1 + eh * CW;
-    float* sphi = sh2 + eh * CW;          // (TH+2) x (TW+2), origin (i0-1, j0-1)
-    float* sd1 = su1;                     // (b - w) after the row pass, aliases su
-    float* sd2 = su1 + CH * CW;
-    const int i0 = blockIdx.y * TH, j0 = blockIdx.x * TW;
+    float* su2 = su1 + NEXT;
+    float* sh1 = lds + C::su_floats;
+    float* sh2 = sh1 + EH * CW;
+    float* sphi = sh2 + EH * CW;          // PH x PW, origin (i0-1, j0-1)
+    float* sd1 = lds;                     // (b - w) after the row pass, aliases su
+    float* sd2 = lds + CH * CW;
+    int tx, ty;
+    xcd_tile(tx, ty);
+    const int i0 = ty * TH, j0 = tx * TW;
+    const int tid = threadIdx.x;
 
-    for (int e = threadIdx.x; e < eh * ew; e += blockDim.x) {
-        const int ei = e / ew, ej = e - ei * ew;
-        const int gi = (i0 - 1 - R + ei) & (M - 1), gj = (j0 - 1 - R + ej) & (N - 1);
-        const size_t o = (size_t)gi * N + gj;
-        const float p = phin[o];
-        const float h = band_h(p, kp);
-        su1[e] = Wold[o] * h;
-        su2[e] = Wold[MN + o] * h;
-        const int si = ei - R, sj = ej - R;
-        if ((unsigned)si < (unsigned)(TH + 2) && (unsigned)sj < (unsigned)(TW + 2)) sphi[si * (TW + 2) + sj] = p;
+    float lp[C::NE], l1[C::NE], l2[C::NE];
+#pragma unroll
+    for (int u = 0; u < C::NE; ++u) {
+        const int e = tid + u * T;
+        if (e < NEXT) {
+            const int ei = e / EW, ej = e - ei * EW;
+            const size_t o = (size_t)((i0 - 1 - R + ei) & (M - 1)) * N + ((j0 - 1 - R + ej) & (N - 1));
+            lp[u] = phin[o];
+            l1[u] = Wold[o];
+            l2[u] = Wold[MN + o];
+        }
     }
-    if (R == 0) {
-        for (int e = threadIdx.x; e < (TH + 2) * (TW + 2); e += blockDim.x) {
-            const int si = e / (TW + 2), sj = e - si * (TW + 2);
-            const int gi = (i0 - 1 + si) & (M - 1), gj = (j0 - 1 + sj) & (N - 1);
-            sphi[e] = phin[(size_t)gi * N + gj];
+#pragma unroll
+    for (int u = 0; u < C::NE; ++u) {
+        const int e = tid + u * T;
+        if (e < NEXT) {
+            const int ei = e / EW, ej = e - ei * EW;
+            const float h = band_h(lp[u], kp);
+            su1[e] = l1[u] * h;
+            su2[e] = l2[u] * h;
+            const int si = ei - R, sj = ej - R;
+            if ((unsigned)si < (unsigned)PH && (unsigned)sj < (unsigned)PW) sphi[si * PW + sj] = lp[u];
+        }
+    }
+    if constexpr (R == 0) {
+        for (int e = tid; e < PH * PW; e += T) {
+            const int si = e / PW, sj = e - si * PW;
+            sphi[e] = phin[(size_t)((i0 - 1 + si) & (M - 1)) * N + ((j0 - 1 + sj) & (N - 1))];
+        }
+    }
+    // inputs of the computed region, issued before the barrier
+    float b1v[C::NC], b2v[C::NC], gv[C::NC];
+#pragma unroll
+    for (int u = 0; u < C::NC; ++u) {
+        const int e = tid + u * T;
+        if (e < CH * CW) {
+            const int ci = e / CW, cj = e - ci * CW;
+            const size_t o = (size_t)((i0 - 1 + ci) & (M - 1)) * N + ((j0 - 1 + cj) & (N - 1));
+            b1v[u] = Bold[o]; b2v[u] = Bold[MN + o]; gv[u] = g[o];
         }
     }
     __syncthreads();
-    window_rows(su1, su2, sh1, sh2, eh, ew, CW, kp);
+#pragma unroll
+    for (int u = 0; u < C::NHZ; ++u) {
+        const int e = tid + u * T;
+        if (e < EH * CW) {
+            const int ei = e / CW, j = e - ei * CW;
+            const float* r1 = su1 + ei * EW + j;
+            const float* r2 = su2 + ei * EW + j;
+            float a1 = 0.0f, a2 = 0.0f;
+#pragma unroll
+            for (int q = 0; q <= 2 * R; ++q) { a1 += kp.taps[q] * r1[q]; a2 += kp.taps[q] * r2[q]; }
+            sh1[e] = a1;
+            sh2[e] = a2;
+        }
+    }
     __syncthreads();
-    for (int e = threadIdx.x; e < CH * CW; e += blockDim.x) {
-        const int ci = e / CW, cj = e - ci * CW;
-        const int gi = (i0 - 1 + ci) & (M - 1), gj = (j0 - 1 + cj) & (N - 1);
-        float v1, v2;
-        window_col(sh1, sh2, ci, cj, CW, kp, v1, v2);
-        const float* sp = sphi + ci * (TW + 2) + cj;
-        const float p = sp[0];
-        const float G1 = sp[TW + 2] - p, G2 = sp[1] - p;
-        const size_t o = (size_t)gi * N + gj;
-        const float b1 = Bold[o], b2 = Bold[MN + o];
-        const float h = band_h(p, kp);
-        float H_, dl;
-        heav_dirac(p, kp.eps, kp.inv_eps, H_, dl);
-        const float B1 = G1 + b1 + kp.c_rep * h * v1;
-        const float B2 = G2 + b2 + kp.c_rep * h * v2;
-        const float thr = kp.c_thr * g[o] * dl;
-        const float nb = sqrtf(B1 * B1 + B2 * B2);
-        float w1 = 0.0f, w2 = 0.0f;
-        if (nb > thr && nb > kp.zero_tol) { w1 = B1 / nb; w2 = B2 / nb; }
-        const float bn1 = b1 + G1 - w1, bn2 = b2 + G2 - w2;
-        sd1[e] = bn1 - w1;
-        sd2[e] = bn2 - w2;
-        if (ci >= 1 && cj >= 1 && i0 - 1 + ci < M && j0 - 1 + cj < N) {
-            Wnew[o] = w1; Wnew[MN + o] = w2;
-            Bnew[o] = bn1; Bnew[MN + o] = bn2;
+    float pold[C::NO];
+#pragma unroll
+    for (int u = 0; u < C::NO; ++u) {
+        const int e = tid + u * T;
+        const int gi = i0 + e / TW, gj = j0 + (e % TW);
+        pold[u] = P0[(size_t)(gi & (M - 1)) * N + (gj & (N - 1))];
+    }
+#pragma unroll
+    for (int u = 0; u < C::NC; ++u) {
+        const int e = tid + u * T;
+        if (e < CH * CW) {
+            const int ci = e / CW, cj = e - ci * CW;
+            float v1 = 0.0f, v2 = 0.0f;
+#pragma unroll
+            for (int pp = 0; pp <= 2 * R; ++pp) {
+                v1 += kp.taps[pp] * sh1[(ci + pp) * CW + cj];
+                v2 += kp.taps[pp] * sh2[(ci + pp) * CW + cj];
+            }
+            const float* sp = sphi + ci * PW + cj;
+            const float p = sp[0];
+            const float G1 = sp[PW] - p, G2 = sp[1] - p;
+            const float b1 = b1v[u], b2 = b2v[u];
+            const float h = band_h(p, kp);
+            float H_, dl;
+            heav_dirac(p, kp.eps, kp.inv_eps, H_, dl);
+            const float B1 = G1 + b1 + kp.c_rep * h * v1;
+            const float B2 = G2 + b2 + kp.c_rep * h * v2;
+            const float thr = kp.c_thr * gv[u] * dl;
+            const float nb = sqrtf(B1 * B1 + B2 * B2);
+            float w1 = 0.0f, w2 = 0.0f;
+            if (nb > thr && nb > kp.zero_tol) { w1 = B1 / nb; w2 = B2 / nb; }
+            const float bn1 = b1 + G1 - w1, bn2 = b2 + G2 - w2;
+            sd1[e] = bn1 - w1;
+            sd2[e] = bn2 - w2;
+            if (ci >= 1 && cj >= 1 && i0 - 1 + ci < M && j0 - 1 + cj < N) {
+                const size_t o = (size_t)(i0 - 1 + ci) * N + (j0 - 1 + cj);
+                Wnew[o] = w1; Wnew[MN + o] = w2;
+                Bnew[o] = bn1; Bnew[MN + o] = bn2;
+            }
         }
     }
     __syncthreads();
     double sdiff = 0.0, sold = 0.0;
-    for (int e = threadIdx.x; e < TH * TW; e += blockDim.x) {
+#pragma unroll
+    for (int u = 0; u < C::NO; ++u) {
+        const int e = tid + u * T;
         const int i = e / TW, j = e - i * TW;
         const int gi = i0 + i, gj = j0 + j;
-        if (gi >= M || gj >= N) continue;
-        const int c = (i + 1) * CW + (j + 1);
-        const float dv = (sd1[c] - sd1[c - CW]) + (sd2[c] - sd2[c - 1]);
-        const size_t o = (size_t)gi * N + gj;
-        D[o] = kp.mu * dv;
-        const float pn = sphi[(i + 1) * (TW + 2) + (j + 1)];
-        const float po = P0[o];
-        P0[o] = pn;
-        const double df = (double)pn - (double)po;
-        sdiff += df * df;
-        sold += (double)po * po;
+        if (gi < M && gj < N) {
+            const int c = (i + 1) * CW + (j + 1);
+            const float dvv = (sd1[c] - sd1[c - CW]) + (sd2[c] - sd2[c - 1]);
+            const size_t o = (size_t)gi * N + gj;
+            D[o] = kp.mu * dvv;
+            const float pn = sphi[(i + 1) * PW + (j + 1)];
+            const float po = pold[u];
+            P0[o] = pn;
+            const double df = (double)pn - (double)po;
+            sdiff += df * df;
+            sold += (double)po * po;
+        }
     }
     double v[2] = {sdiff, sold};
     const int nb = gridDim.x * gridDim.y;
-    if (grid_sum<2>(v, part + (size_t)z * 2 * nb, nb, blockIdx.y * gridDim.x + blockIdx.x, &S.counter, red) &&
-        threadIdx.x == 0) {
+    store_partials<2>(v, part + (size_t)z * 2 * nb, nb, blockIdx.y * gridDim.x + blockIdx.x, red);
+}
+
+// End of an outer iteration: r_k = ||phi^{k+1} - phi^k||_F / (||phi^k||_F + 1e-6).
+__global__ __launch_bounds__(256) void k_fin_outer(const double* __restrict__ part, int nb,
+                                                   double* __restrict__ rhist, DevScal* sc) {
+    __shared__ double red[2 * 16];
+    const int z = blockIdx.x;
+    DevScal& S = sc[z];
+    if (!S.active) return;
+    double v[2];
+    sum_partials<2>(part + (size_t)z * 2 * nb, nb, v, red);
+    if (threadIdx.x == 0) {
         const double r = sqrt(v[0]) / (sqrt(v[1]) + 1e-6);
         S.r_last = r;
         rhist[(size_t)z * kRHist + (S.k % kRHist)] = r;
@@ -604,8 +833,17 @@ __global__ __launch_bounds__(kTileThreads) void k_energy(KParams kp, int M, int 
     }
     double v[3] = {eg, ea, er};
     const int nb = gridDim.x * gridDim.y;
-    if (grid_sum<3>(v, part + (size_t)z * 3 * nb, nb, blockIdx.y * gridDim.x + blockIdx.x, &S.counter, red) &&
-        threadIdx.x == 0) {
+    store_partials<3>(v, part + (size_t)z * 3 * nb, nb, blockIdx.y * gridDim.x + blockIdx.x, red);
+}
+
+__global__ __launch_bounds__(256) void k_fin_energy(const double* __restrict__ part, int nb, KParams kp,
+                                                    DevScal* sc) {
+    __shared__ double red[3 * 16];
+    const int z = blockIdx.x;
+    DevScal& S = sc[z];
+    double v[3];
+    sum_partials<3>(part + (size_t)z * 3 * nb, nb, v, red);
+    if (threadIdx.x == 0) {
         S.energy[0] = (double)kp.gamma * v[0];
         S.energy[1] = (double)kp.alpha * v[1];
         S.energy[2] = -(double)kp.beta * v[2];
@@ -621,39 +859,42 @@ constexpr int kTH = 32;   // tile height of the stencil kernels
 inline dim3 tile_grid(int M, int N, int TH, int nz) {
     return dim3((N + kTileW - 1) / kTileW, (M + TH - 1) / TH, nz);
 }
-inline size_t lds_rhs(int TH, int R) {
-    const int eh = TH + 2 * R, ew = kTileW + 2 * R;
-    return sizeof(float) * (2 * eh * ew + 2 * eh * kTileW + (TH + 2) * (kTileW + 2));
-}
-inline size_t lds_wstep(int TH, int R) {
-    const int CH = TH + 1, CW = kTileW + 1;
-    const int eh = CH + 2 * R, ew = CW + 2 * R;
-    size_t su = 2 * eh * ew;
-    if (su < (size_t)(2 * CH * CW)) su = 2 * CH * CW;
-    return sizeof(float) * (su + 2 * eh * CW + (TH + 2) * (kTileW + 2));
-}
 inline size_t lds_energy(int TH, int R) {
     const int eh = TH + 2 * R, ew = kTileW + 2 * R;
     return sizeof(float) * (2 * eh * ew + 2 * eh * kTileW);
 }
 }  // namespace
 
-int tile_blocks(int M, int N) { return ((N + kTileW - 1) / kTileW) * ((M + kTH - 1) / kTH); }
+int tile_blocks(int M, int N) { return ((N + kTileW - 1) / kTileW) * ((M + 15) / 16); }
 
-// Transforms per workgroup: as many as fit 256 threads, fewer when that
-// would leave less than ~2 workgroups per CU.
-int fft_group(int count, int L) {
-    const int E = L < 16 ? L : 16;
-    const int NT = L / E;
-    int G = 256 / NT;
-    const int Gmin = NT >= 64 ? 1 : 64 / NT;   // keep at least one full wave
-    if (G < 1) G = 1;
-    while (G > Gmin && count / G < 512) G >>= 1;
-    if (G > count) G = count;
+// Row-tile count per workgroup of the row passes: enough rows for at least
+// one full wave (each 8-row tile is 4 transforms of NT threads).
+template <int L> int fft_nt() { return FftShape<L>::NT; }
+static int fft_nt_rt(int L) {
+    switch (L) {
+        case 8: return fft_nt<8>(); case 16: return fft_nt<16>(); case 32: return fft_nt<32>();
+        case 64: return fft_nt<64>(); case 128: return fft_nt<128>(); case 256: return fft_nt<256>();
+        case 512: return fft_nt<512>(); case 1024: return fft_nt<1024>(); case 2048: return fft_nt<2048>();
+        default: return fft_nt<4096>();
+    }
+}
+int fft_row_tiles(int M, int N) {
+    const int NT = fft_nt_rt(N);
+    int RT = 1;
+    while (4 * RT * NT < 64 && RT * 8 * 2 <= M) RT <<= 1;
+    return RT;
+}
+// Columns per workgroup of the column pass: 2 (128-byte runs), more for short
+// columns so a workgroup holds at least one wave.
+int fft_col_group(int M, int N) {
+    const int NT = fft_nt_rt(M);
+    int G = 2;
+    while (G * NT < 64 && G * 2 <= N / 2) G <<= 1;
+    if (G > N / 2) G = N / 2;
     return G;
 }
 
-template <int L> struct Dispatch;
+template <int L> constexpr size_t tw_lds_bytes() { return TwInLds<L>::v ? sizeof(float2) * L : 0; }
 
 #define SR_FFT_DISPATCH(FN, LEN, ...)                                   \
     switch (LEN) {                                                      \
@@ -674,25 +915,40 @@ template <int N>
 static void launch_row_fwd_t(const float* src, float2* spec, const float2* twN, int M, int nz, DevScal* sc,
                              hipStream_t st) {
     const int NT = FftShape<N>::NT;
-    const int G = fft_group(M / 2, N);
-    hipLaunchKernelGGL(k_row_fwd<N>, dim3(M / 2 / G, 1, nz), dim3(NT * G), sizeof(float2) * G * N, st,
-                       src, spec, twN, M, G, sc);
+    const int RT = fft_row_tiles(M, N);
+    const size_t lds = tw_lds_bytes<N>() + sizeof(float2) * 4 * RT * LdsLen<N>::v;
+    hipLaunchKernelGGL(k_row_fwd<N>, dim3(M / (8 * RT), 1, nz), dim3(4 * RT * NT), lds, st, src, spec, twN, M, RT,
+                       sc);
 }
 template <int M>
 static void launch_col_t(float2* spec, const float2* twM, const float2* twN, int N, float taumu, float inv_mn,
                          int nz, DevScal* sc, hipStream_t st) {
     const int NT = FftShape<M>::NT;
-    const int G = fft_group(N / 2, M);
-    hipLaunchKernelGGL(k_col_solve<M>, dim3(N / 2 / G, 1, nz), dim3(NT * G), sizeof(float2) * G * (M + 1), st,
-                       spec, twM, twN, N, G, taumu, inv_mn, sc);
+    const int G = fft_col_group(M, N);
+    const size_t lds = tw_lds_bytes<M>() + sizeof(float2) * G * LdsLen<M>::v;
+    int lrun = 0;
+    while ((1 << lrun) < kSpecTile * G) ++lrun;
+    hipLaunchKernelGGL(k_col_solve<M>, dim3(N / 2 / G, 1, nz), dim3(NT * G), lds, st, spec, twM, twN, N, G, lrun,
+                       taumu, inv_mn, sc);
 }
 template <int N>
 static void launch_row_inv_t(const float2* spec, const float* phi_in, float* phi_out, const float2* twN, int M,
                              float tol, double* part, int nz, DevScal* sc, hipStream_t st) {
     const int NT = FftShape<N>::NT;
-    const int G = fft_group(M / 2, N);
-    hipLaunchKernelGGL(k_row_inv<N>, dim3(M / 2 / G, 1, nz), dim3(NT * G), sizeof(float2) * G * N, st,
-                       spec, phi_in, phi_out, twN, M, G, tol, part, sc);
+    const int RT = fft_row_tiles(M, N);
+    const size_t lds = tw_lds_bytes<N>() + sizeof(float2) * 4 * RT * LdsLen<N>::v;
+    const int nb = M / (8 * RT);
+    hipLaunchKernelGGL(k_row_inv<N>, dim3(nb, 1, nz), dim3(4 * RT * NT), lds, st, spec, phi_in, phi_out,
+                       twN, M, RT, tol, part, sc);
+    if (tol > 0.0f) hipLaunchKernelGGL(k_fin_inner, dim3(nz), dim3(256), 0, st, part, nb, tol, sc);
+}
+
+template <int L>
+static void set_fft_attrs() {
+    const int bytes = 160 * 1024 - 1024;
+    (void)hipFuncSetAttribute((const void*)k_row_fwd<L>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    (void)hipFuncSetAttribute((const void*)k_col_solve<L>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    (void)hipFuncSetAttribute((const void*)k_row_inv<L>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
 void launch_solve_pass(int pass, const Geometry& geo, const float* rhs, const float* phi_in, float* phi_out,
@@ -714,23 +970,83 @@ void launch_solve(const Geometry& geo, const float* rhs, const float* phi_in, fl
         launch_solve_pass(pass, geo, rhs, phi_in, phi_out, spec, tol_inner, part, nz, sc, st);
 }
 
+// Tile height: 32 rows unless that leaves fewer than ~4 workgroups per CU.
+static int tile_height(int M, int N, int nz) {
+    const long tiles32 = (long)((N + kTileW - 1) / kTileW) * ((M + 31) / 32) * nz;
+    return tiles32 >= 1024 ? 32 : 16;
+}
+
+template <int TH, int R>
+static void launch_rhs_t(const Geometry& geo, const KParams& kp, const float* phi_s, const float* W, const float* g,
+                         const float* D, float* out, int nz, DevScal* sc, hipStream_t st) {
+    k_rhs<TH, R><<<tile_grid(geo.M, geo.N, TH, nz), dim3(kTileThreads), sizeof(float) * RhsTile<TH, R>::lds_floats,
+                   st>>>(kp, geo.M, geo.N, phi_s, W, g, D, out, sc);
+}
+template <int TH, int R>
+static void launch_wstep_t(const Geometry& geo, const KParams& kp, const float* phin, float* P0, const float* Wold,
+                           const float* Bold, const float* g, float* Wnew, float* Bnew, float* D, double* part,
+                           double* rhist, int nz, DevScal* sc, hipStream_t st) {
+    k_wstep<TH, R><<<tile_grid(geo.M, geo.N, TH, nz), dim3(kTileThreads), sizeof(float) * WTile<TH, R>::lds_floats,
+                     st>>>(kp, geo.M, geo.N, phin, P0, Wold, Bold, g, Wnew, Bnew, D, part, rhist, sc);
+}
+
+#define SR_R_DISPATCH(FN, TH, R, ...)                                                          \
+    switch (R) {                                                                               \
+        case 0: FN<TH, 0>(__VA_ARGS__); break;                                                 \
+        case 1: FN<TH, 1>(__VA_ARGS__); break;                                                 \
+        case 2: FN<TH, 2>(__VA_ARGS__); break;                                                 \
+        case 3: FN<TH, 3>(__VA_ARGS__); break;                                                 \
+        case 4: FN<TH, 4>(__VA_ARGS__); break;                                                 \
+        case 5: FN<TH, 5>(__VA_ARGS__); break;                                                 \
+        case 6: FN<TH, 6>(__VA_ARGS__); break;                                                 \
+        case 7: FN<TH, 7>(__VA_ARGS__); break;                                                 \
+        case 8: FN<TH, 8>(__VA_ARGS__); break;                                                 \
+        default: break;                                                                        \
+    }
+
 void launch_rhs(const Geometry& geo, const KParams& kp, const float* phi_s, const float* W, const float* g,
                 const float* D, float* out, int nz, DevScal* sc, hipStream_t st) {
-    hipLaunchKernelGGL(k_rhs<kTH>, tile_grid(geo.M, geo.N, kTH, nz), dim3(kTileThreads), lds_rhs(kTH, kp.R), st,
-                       kp, geo.M, geo.N, phi_s, W, g, D, out, sc);
+    if (tile_height(geo.M, geo.N, nz) == 32) {
+        SR_R_DISPATCH(launch_rhs_t, 32, kp.R, geo, kp, phi_s, W, g, D, out, nz, sc, st);
+    } else {
+        SR_R_DISPATCH(launch_rhs_t, 16, kp.R, geo, kp, phi_s, W, g, D, out, nz, sc, st);
+    }
 }
 
 void launch_wstep(const Geometry& geo, const KParams& kp, const float* phin, float* P0, const float* Wold,
                   const float* Bold, const float* g, float* Wnew, float* Bnew, float* D, double* part,
                   double* rhist, int nz, DevScal* sc, hipStream_t st) {
-    hipLaunchKernelGGL(k_wstep<kTH>, tile_grid(geo.M, geo.N, kTH, nz), dim3(kTileThreads), lds_wstep(kTH, kp.R),
-                       st, kp, geo.M, geo.N, phin, P0, Wold, Bold, g, Wnew, Bnew, D, part, rhist, sc);
+    const int TH = tile_height(geo.M, geo.N, nz);
+    if (TH == 32) {
+        SR_R_DISPATCH(launch_wstep_t, 32, kp.R, geo, kp, phin, P0, Wold, Bold, g, Wnew, Bnew, D, part, rhist, nz, sc,
+                      st);
+    } else {
+        SR_R_DISPATCH(launch_wstep_t, 16, kp.R, geo, kp, phin, P0, Wold, Bold, g, Wnew, Bnew, D, part, rhist, nz, sc,
+                      st);
+    }
+    const int nb = ((geo.N + kTileW - 1) / kTileW) * ((geo.M + TH - 1) / TH);
+    hipLaunchKernelGGL(k_fin_outer, dim3(nz), dim3(256), 0, st, part, nb, rhist, sc);
+}
+
+template <int TH, int R>
+static void set_tile_attrs_one() {
+    const int bytes = 160 * 1024 - 1024;
+    (void)hipFuncSetAttribute((const void*)k_rhs<TH, R>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    (void)hipFuncSetAttribute((const void*)k_wstep<TH, R>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+template <int TH>
+static void set_tile_attrs() {
+    set_tile_attrs_one<TH, 0>(); set_tile_attrs_one<TH, 1>(); set_tile_attrs_one<TH, 2>();
+    set_tile_attrs_one<TH, 3>(); set_tile_attrs_one<TH, 4>(); set_tile_attrs_one<TH, 5>();
+    set_tile_attrs_one<TH, 6>(); set_tile_attrs_one<TH, 7>(); set_tile_attrs_one<TH, 8>();
 }
 
 void launch_energy(const Geometry& geo, const KParams& kp, const float* phi, const float* g, double* part,
                    int nz, DevScal* sc, hipStream_t st) {
     hipLaunchKernelGGL(k_energy<kTH>, tile_grid(geo.M, geo.N, kTH, nz), dim3(kTileThreads), lds_energy(kTH, kp.R),
                        st, kp, geo.M, geo.N, phi, g, part, sc);
+    const int nb = ((geo.N + kTileW - 1) / kTileW) * ((geo.M + kTH - 1) / kTH);
+    hipLaunchKernelGGL(k_fin_energy, dim3(nz), dim3(256), 0, st, part, nb, kp, sc);
 }
 
 void launch_repulsion(const Geometry& geo, const KParams& kp, const float* phi, const float* W, float* V,
@@ -769,10 +1085,6 @@ void launch_set_k(DevScal* sc, long long k, hipStream_t st) {
     hipLaunchKernelGGL(k_set_k, dim3(1), dim3(64), 0, st, sc, k);
 }
 
-size_t lds_max_needed(int R) {
-    size_t a = lds_rhs(kTH, R), b = lds_wstep(kTH, R), c = lds_energy(kTH, R);
-    return a > b ? (a > c ? a : c) : (b > c ? b : c);
-}
 
 }  // namespace sr
 
@@ -783,10 +1095,12 @@ void configure_kernels() {
     static bool done = false;
     if (done) return;
     const int bytes = 160 * 1024 - 1024;
-    (void)hipFuncSetAttribute((const void*)k_rhs<kTH>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    (void)hipFuncSetAttribute((const void*)k_wstep<kTH>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    set_tile_attrs<16>();
+    set_tile_attrs<32>();
     (void)hipFuncSetAttribute((const void*)k_energy<kTH>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     (void)hipFuncSetAttribute((const void*)k_repulsion<kTH>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    set_fft_attrs<8>(); set_fft_attrs<16>(); set_fft_attrs<32>(); set_fft_attrs<64>(); set_fft_attrs<128>();
+    set_fft_attrs<256>(); set_fft_attrs<512>(); set_fft_attrs<1024>(); set_fft_attrs<2048>(); set_fft_attrs<4096>();
     done = true;
 }
 }  // namespace sr

@@ -18,8 +18,6 @@ struct Geometry {
 };
 
 int tile_blocks(int M, int N);
-int fft_group(int count, int L);
-size_t lds_max_needed(int R);
 
 void launch_edge(const Geometry& geo, const float* f, float* tmp, float* fs, float* g, const float* taps, int r,
                  float rho, int s_exp, DevScal* sc, hipStream_t st);
