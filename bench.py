@@ -1,16 +1,22 @@
 """Benchmark of the Split Bregman SR solver on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload ellipses-1024|annuli-4096]
 
 A step is one outer iteration of Algorithm 1 (S inner FFT solves with the
-fused repulsion window, then shrink / projection / Bregman) over the
-1024 x 1024 synthetic ellipses workload, inputs resident in HBM.  Prints one
-JSON line with the throughput in megapixel-iterations per second, the
-roofline position of the dominant kernel (HIP-event timing of each kernel
-kind, algorithmic bytes per launch), and the FP64 oracle timed on the host
+fused repulsion window, then shrink / projection / Bregman) over one
+synthetic image, with the inputs resident in HBM.  Prints one JSON line with
+the throughput in megapixel-iterations per second, the roofline position of
+the dominant kernel (HIP-event timing of each kernel kind on the solver's
+stream, algorithmic bytes per launch), and the FP64 oracle timed on the host
 on a bounded sample of the same workload.
+
+    python bench.py --copy-probe 256
+
+runs a plain 256 MiB device-to-device copy ten times and exits; profiled
+with rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE it calibrates those counters.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -29,18 +35,57 @@ HBM_PEAK_GBS = 8000.0
 #   w step: read phi^{k+1}, phi^k, w(2), b(2), g = 28, write phi, w(2), b(2), D = 24
 BYTES_PER_PX = {"rhs_repulsion": 24, "row_fft_fwd": 8, "col_fft_solve": 8, "row_fft_inv": 12, "w_step": 52}
 
-WORKLOAD = dict(M=1024, N=1024, R=3, eps=1.5, d=5.0, S=3)
+# The paper's two-circles weights (alpha = gamma = 4, beta = 0.2, mu = 8,
+# tau = 0.1, l = 1, d = 5, S = 3) with each workload's eps / R.
+WORKLOADS = {
+    "ellipses-1024": dict(M=1024, N=1024, R=3, eps=1.5, d=5.0, S=3, default_steps=2000,
+                          text="ellipses-1024x1024: 12 ellipses with 2-6 px gaps, bias 0.2, noise 0.15; "
+                               "rectangle phi0; R=3, eps=1.5, d=5, S=3, paper two-circles weights"),
+    "annuli-4096": dict(M=4096, N=4096, R=5, eps=2.0, d=5.0, S=3, default_steps=300,
+                        text="annuli-4096x4096: 64 annuli / holed ellipses, 10% crossed by bars, noise 0.2; "
+                             "rectangle phi0; R=5, eps=2, d=5, S=3, paper two-circles weights"),
+}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_2003_12693_amd", "csrc", "sr_kernels.hip")
 
 
-def params_kw():
-    return dict(gamma=4.0, alpha=4.0, beta=0.2, mu=8.0, tau=0.1, eps=WORKLOAD["eps"], band_l=1.0,
-                d=WORKLOAD["d"], R=WORKLOAD["R"], sigma=1.5, rho=1000.0, s_exp=2, S=WORKLOAD["S"],
+def params_kw(wl):
+    return dict(gamma=4.0, alpha=4.0, beta=0.2, mu=8.0, tau=0.1, eps=wl["eps"], band_l=1.0,
+                d=wl["d"], R=wl["R"], sigma=1.5, rho=1000.0, s_exp=2, S=wl["S"],
                 tol_inner=0.0, zero_tol=1e-3)
 
 
-def cpu_baseline(f, phi0, iters):
+def make_input(name):
+    from paper_2003_12693_amd import synth
+    if name == "ellipses-1024":
+        return synth.ellipses(1024, 1024, seed=2)
+    return synth.annuli(4096, 4096, seed=3)
+
+
+def source_sha():
+    h = hashlib.sha256()
+    for fn in (KERNEL_SRC, os.path.join(ROOT, "paper_2003_12693_amd", "csrc", "sr_device.hpp")):
+        with open(fn, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch from the committed rocprofv3 counter summary,
+    or None if it was taken on different kernel sources."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    sha = source_sha()
+    for line in open(TRAFFIC_FILE):
+        parts = line.split("#", 1)[0].split()
+        if len(parts) == 4 and parts[0] == workload and parts[1] == kernel and parts[3] == sha:
+            return int(parts[2])
+    return None
+
+
+def cpu_baseline(f, phi0, wl, iters):
     from oracle import sr_oracle as O
-    P = O.Params(**params_kw())
+    P = O.Params(**params_kw(wl))
     t0 = time.perf_counter()
     g = O.edge_map(f, P.sigma, P.rho, P.s_exp)
     st = O.initial_state(phi0)
@@ -50,30 +95,48 @@ def cpu_baseline(f, phi0, iters):
     t2 = time.perf_counter()
     M, N = f.shape
     return {"value": M * N * iters / 1e6 / (t2 - t1), "unit": "MPix-it/s", "cores": 1, "kind": "oracle",
-            "sample": f"{iters} outer iterations of the FP64 NumPy oracle on the same 1024x1024 input "
-                      f"({t2 - t1:.1f} s; setup {t1 - t0:.1f} s excluded)"}
+            "sample": f"{iters} outer iterations of the FP64 NumPy oracle on the same {M}x{N} input "
+                      f"({t2 - t1:.1f} s; edge map and initialisation excluded)"}
+
+
+def copy_probe(mib):
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(10):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_mib": mib, "bytes_read_per_copy": n * 4, "bytes_written_per_copy": n * 4}))
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="ellipses-1024", choices=sorted(WORKLOADS))
     ap.add_argument("--profile-iters", type=int, default=20)
-    ap.add_argument("--cpu-iters", type=int, default=5)
+    ap.add_argument("--cpu-iters", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the solver runs on a single "
               "device; see the sharding notes in the design document)", file=sys.stderr)
         sys.exit(2)
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
 
     import torch
-    from paper_2003_12693_amd import sr, synth
+    from paper_2003_12693_amd import sr
 
-    M, N = WORKLOAD["M"], WORKLOAD["N"]
-    f, phi0 = synth.ellipses(M, N, seed=2)
-    s = sr.Solver(M, N, device="cuda:0", **params_kw())
+    wl = WORKLOADS[args.workload]
+    steps = args.steps if args.steps is not None else wl["default_steps"]
+    M, N = wl["M"], wl["N"]
+    f, phi0 = make_input(args.workload)
+    s = sr.Solver(M, N, device="cuda:0", **params_kw(wl))
     ft = torch.from_numpy(f.astype(np.float32)).cuda()
     pt = torch.from_numpy(phi0.astype(np.float32)).cuda()
     s.set_image(ft, pt)
@@ -85,49 +148,49 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     e0.record(stream)
-    rc, info = sr.sr_step(s.ctx, args.steps)
+    rc, info = sr.sr_step(s.ctx, steps)
     e1.record(stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    ms_events = e0.elapsed_time(e1)
-    wall_ms = (t1 - t0) * 1e3
-    ms = max(ms_events, wall_ms)
-    value = M * N * args.steps / 1e6 / (ms / 1e3)
+    ms = max(e0.elapsed_time(e1), (t1 - t0) * 1e3)
+    value = M * N * steps / 1e6 / (ms / 1e3)
 
-    # per-kernel timing (HIP events around each launch, same stream)
+    # per-kernel timing (HIP events around each launch, on the solver's stream)
     prof = sr.sr_profile_kernels(s.ctx, args.profile_iters)
     per_iter_ms = {k: v[0] * v[1] / args.profile_iters for k, v in prof.items()}
     dom = max(per_iter_ms, key=per_iter_ms.get)
     dom_ms = prof[dom][0]
-    achieved = BYTES_PER_PX[dom] * M * N / (dom_ms * 1e-3) / 1e9
+    alg_bytes = BYTES_PER_PX[dom] * M * N
+    achieved = alg_bytes / (dom_ms * 1e-3) / 1e9
     E, terms = s.energy()
 
     out = {
-        "metric": "SB megapixel-iters/s at 1024^2",
+        "metric": f"SB megapixel-iters/s at {M}^2" if M == N else f"SB megapixel-iters/s at {M}x{N}",
         "value": round(value, 2),
         "unit": "MPix-it/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms / args.steps, 6),
+        "ms_per_step": round(ms / steps, 6),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "ellipses-1024x1024: 12 ellipses with 2-6 px gaps, bias 0.2, noise 0.15; "
-                               "rectangle phi0; R=3, eps=1.5, d=5, S=3, paper two-circles weights",
-                   "M": M, "N": N, "R": WORKLOAD["R"], "S": WORKLOAD["S"],
+        "config": {"workload": wl["text"], "M": M, "N": N, "R": wl["R"], "S": wl["S"],
                    "bytes_per_px_iter": sum(BYTES_PER_PX[k] * prof[k][1] for k in prof) / args.profile_iters},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(args.workload, dom), "alg_bytes_per_launch": alg_bytes},
         "kernels_ms": {k: round(v[0], 5) for k, v in prof.items()},
         "iteration_ms_sum_of_kernels": round(sum(per_iter_ms.values()), 5),
         "energy_after": E,
         "r_last": info.r_last,
+        "kernel_source_sha": source_sha(),
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(f, phi0, args.cpu_iters)
+        iters = args.cpu_iters if args.cpu_iters is not None else (5 if M * N <= 1 << 20 else 1)
+        out["cpu_baseline"] = cpu_baseline(f, phi0, wl, iters)
     print(json.dumps(out), flush=True)
 
 

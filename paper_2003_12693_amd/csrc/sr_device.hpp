@@ -1,7 +1,8 @@
 // Device-side building blocks of the SR Split Bregman solver (gfx950).
 //
 //  - the compactly supported H_eps, delta_eps, delta'_eps (eqs 5, 6, 29)
-//    and the narrow band h_eps, h'_eps (eqs 11, 28), in FP32;
+//    and the narrow band h_eps, h'_eps (eqs 11, 28), in FP32 from a
+//    half-angle Taylor evaluation of sin / cos on the support;
 //  - an in-LDS complex FFT (Stockham auto-sort, radix-4 stages plus one
 //    radix-2 stage for odd log2 lengths) used by the row and column passes
 //    of the semi-implicit solve (eqs 31-33);
@@ -50,16 +51,46 @@ struct KParams {
 };
 
 // ---------------------------------------------------------------------------
-// H_eps and delta_eps (eqs 5, 6), evaluated together.
+// sin and cos of the half angle t = pi u / 2 for |u| <= 1, i.e. |t| <= pi/2,
+// by the Taylor series of sin and cos truncated after t^11 and t^12 (the
+// first omitted terms are below 6e-8 and 7e-9 on that interval).  The
+// smoothed Heaviside / Dirac only ever need |u| = |phi / eps| <= 1, so no
+// range reduction is required, and every quantity below is built from
+// (sin t, cos t) without cancellation:
+//   sin(pi u) = 2 sin t cos t,   1 + cos(pi u) = 2 cos^2 t.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ void half_sincos(float u, float& sh, float& ch) {
+    const float t = 1.5707963267948966f * u;
+    const float t2 = t * t;
+    float ps = -2.505210838544172e-08f;
+    ps = fmaf(ps, t2, 2.7557319223985893e-06f);
+    ps = fmaf(ps, t2, -0.0001984126984126984f);
+    ps = fmaf(ps, t2, 0.008333333333333333f);
+    ps = fmaf(ps, t2, -0.16666666666666666f);
+    ps = fmaf(ps, t2, 1.0f);
+    float pc = 2.08767569878681e-09f;
+    pc = fmaf(pc, t2, -2.755731922398589e-07f);
+    pc = fmaf(pc, t2, 2.48015873015873e-05f);
+    pc = fmaf(pc, t2, -0.001388888888888889f);
+    pc = fmaf(pc, t2, 0.041666666666666664f);
+    pc = fmaf(pc, t2, -0.5f);
+    pc = fmaf(pc, t2, 1.0f);
+    sh = t * ps;
+    ch = pc;
+}
+
+constexpr float kInvPi = 0.31830988618379067f;
+
+// H_eps and delta_eps (eqs 5, 6), evaluated together:
+//   H = (1 + u + sin(pi u)/pi) / 2,   delta = (1 + cos(pi u)) / (2 eps),   u = x / eps.
 __device__ __forceinline__ void heav_dirac(float x, float eps, float inv_eps, float& H, float& dl) {
     if (x > eps) { H = 1.0f; dl = 0.0f; return; }
     if (x < -eps) { H = 0.0f; dl = 0.0f; return; }
-    float s, c;
     const float u = x * inv_eps;
-    sincospif(u, &s, &c);
-    H = 0.5f * (1.0f + u + s * 0.31830988618379067f);
-    dl = 0.5f * inv_eps * (1.0f + c);
+    float sh, ch;
+    half_sincos(u, sh, ch);
+    H = 0.5f * (1.0f + u) + kInvPi * sh * ch;
+    dl = inv_eps * ch * ch;
 }
 
 // h_eps = H(phi + l)(1 - H(phi - l))  (eq 11)
@@ -83,13 +114,14 @@ __device__ __forceinline__ void band_h_dh(float x, const KParams& kp, float& h, 
     dh = dp * (1.0f - Hm) - Hp * dm;
 }
 
-// delta_eps and delta'_eps (eqs 6, 29) together.
+// delta_eps and delta'_eps (eqs 6, 29) together:
+//   delta' = -(pi / (2 eps^2)) sin(pi u) = -(pi / eps^2) sin t cos t.
 __device__ __forceinline__ void dirac_d(float x, const KParams& kp, float& dl, float& ddl) {
     if (x > kp.eps || x < -kp.eps) { dl = 0.0f; ddl = 0.0f; return; }
-    float s, c;
-    sincospif(x * kp.inv_eps, &s, &c);
-    dl = 0.5f * kp.inv_eps * (1.0f + c);
-    ddl = -1.5707963267948966f * kp.inv_eps * kp.inv_eps * s;
+    float sh, ch;
+    half_sincos(x * kp.inv_eps, sh, ch);
+    dl = kp.inv_eps * ch * ch;
+    ddl = -3.141592653589793f * kp.inv_eps * kp.inv_eps * sh * ch;
 }
 
 // ---------------------------------------------------------------------------
@@ -112,8 +144,12 @@ template <> struct Ilog2<1> { static constexpr int v = 0; };
 // elements (one radix-4 butterfly per stage) for lengths up to 1024 gives
 // the most waves per CU; 2048 and 4096 points take 8 and 16 so that the
 // four transforms of an 8-row tile still fit one 1024-thread workgroup.
-template <int L> struct FftShape {
-    static constexpr int E = L <= 1024 ? 4 : (L == 2048 ? 8 : 16);
+template <int L> struct RowE { static constexpr int v = L <= 1024 ? 4 : (L == 2048 ? 8 : 16); };
+// The column pass runs two transforms per workgroup, so it can afford more
+// threads per transform (fewer registers per thread) at 4096 points.
+template <int L> struct ColE { static constexpr int v = L <= 2048 ? 4 : 8; };
+template <int L, int EE = RowE<L>::v> struct FftShape {
+    static constexpr int E = EE;
     static constexpr int NT = L / E;
     static constexpr int LOG = Ilog2<L>::v;
 };
@@ -130,9 +166,9 @@ template <int L> struct LdsLen { static constexpr int v = L + L / 16 + 4; };
 // Butterfly j reads x[j + r L/4], twiddles by W_{4Ns}^{r k} (k = j mod Ns),
 // and writes x[(j - k) 4 + k + r Ns].  Twiddle W_{4Ns}^{m} = tw[m L/(4Ns)],
 // tw[n] = exp(-2 pi i n / L).
-template <int L, bool INV>
+template <int L, int EE, bool INV>
 __device__ __forceinline__ void fft_stage4(float2* x, const float2* __restrict__ tw, int t, int Ns) {
-    constexpr int E = FftShape<L>::E, NT = FftShape<L>::NT;
+    constexpr int E = FftShape<L, EE>::E, NT = FftShape<L, EE>::NT;
     constexpr int Q = L / 4;
     float2 v[E];
 #pragma unroll
@@ -169,9 +205,9 @@ __device__ __forceinline__ void fft_stage4(float2* x, const float2* __restrict__
 // In-place length-L complex FFT of x (in LDS, skewed by sk()) by the NT threads t = 0..NT-1
 // of one transform.  Every thread of the workgroup must call it (it
 // contains workgroup barriers).  INV: unnormalised inverse (conjugate twiddles).
-template <int L, bool INV>
+template <int L, int EE, bool INV>
 __device__ __forceinline__ void fft_lds(float2* x, const float2* __restrict__ tw, int t) {
-    constexpr int E = FftShape<L>::E, NT = FftShape<L>::NT, LOG = FftShape<L>::LOG;
+    constexpr int E = FftShape<L, EE>::E, NT = FftShape<L, EE>::NT, LOG = FftShape<L, EE>::LOG;
     __syncthreads();
     int Ns = 1;
     if constexpr (LOG & 1) {
@@ -194,7 +230,7 @@ __device__ __forceinline__ void fft_lds(float2* x, const float2* __restrict__ tw
     }
 #pragma unroll
     for (int st = 0; st < LOG / 2; ++st) {
-        fft_stage4<L, INV>(x, tw, t, Ns);
+        fft_stage4<L, EE, INV>(x, tw, t, Ns);
         Ns <<= 2;
     }
 }

@@ -385,7 +385,7 @@ __global__ __launch_bounds__(1024) void k_row_fwd(const float* __restrict__ src,
         const int n = t + e * NT;
         x[sk(n)] = make_float2(src[ra + n], src[rb + n]);
     }
-    fft_lds<N, false>(x, tw, t);
+    fft_lds<N, RowE<N>::v, false>(x, tw, t);
     // The workgroup's tiles are one contiguous run of RT * 4N float2.
     float2* dst = spec + (size_t)row0 * H;
     const int nthr = blockDim.x;
@@ -418,7 +418,7 @@ template <int M>
 __global__ __launch_bounds__(1024) void k_col_solve(float2* __restrict__ spec, const float2* __restrict__ twM,
                                                     const float2* __restrict__ twN, int N, int G, int lrun,
                                                     float taumu, float inv_mn, DevScal* sc) {
-    constexpr int NT = FftShape<M>::NT, E = FftShape<M>::E;
+    constexpr int NT = FftShape<M, ColE<M>::v>::NT, E = FftShape<M, ColE<M>::v>::E;
     constexpr int LD = LdsLen<M>::v;
     const int z = blockIdx.z;
     if (!sc[z].active || sc[z].inner_done) return;
@@ -448,31 +448,32 @@ __global__ __launch_bounds__(1024) void k_col_solve(float2* __restrict__ spec, c
     const int g = threadIdx.x / NT, t = threadIdx.x - g * NT;
     const int col = k0 + g;
     float2* x = xs + g * LD;
-    fft_lds<M, false>(x, tw, t);
-    float2 vz[E], vm[E];
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int l = t + e * NT;
-        vz[e] = x[sk(l)];
-        vm[e] = x[sk((M - l) & (M - 1))];
-    }
-    __syncthreads();
+    fft_lds<M, ColE<M>::v, false>(x, tw, t);
+    // Divide by the symbol.  The symbol is even in l1, so each thread owns the
+    // mirror pair (l, M - l): column 0's two packed real spectra mix Z[l]
+    // with conj(Z[M - l]), every other column scales pointwise.
     const float cn = 2.0f * twN[col].x;
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int l = t + e * NT;
+    auto scale_pair = [&](int l) {
+        const int m = (M - l) & (M - 1);
         const float cm = 2.0f * tw[l].x;
+        float hp, hm;
         if (col != 0) {
-            const float sc_ = inv_mn / (1.0f + taumu * (4.0f - cm - cn));
-            x[sk(l)] = cscale(vz[e], sc_);
+            hp = inv_mn / (1.0f + taumu * (4.0f - cm - cn));
+            hm = 0.0f;
         } else {
             const float p = inv_mn / (1.0f + taumu * (2.0f - cm));   // l2 = 0
             const float q = inv_mn / (1.0f + taumu * (6.0f - cm));   // l2 = N/2
-            const float hp = 0.5f * (p + q), hm = 0.5f * (p - q);
-            x[sk(l)] = make_float2(hp * vz[e].x + hm * vm[e].x, hp * vz[e].y - hm * vm[e].y);
+            hp = 0.5f * (p + q);
+            hm = 0.5f * (p - q);
         }
-    }
-    fft_lds<M, true>(x, tw, t);
+        const float2 zl = x[sk(l)], zm = x[sk(m)];
+        x[sk(l)] = make_float2(hp * zl.x + hm * zm.x, hp * zl.y - hm * zm.y);
+        if (m != l) x[sk(m)] = make_float2(hp * zm.x + hm * zl.x, hp * zm.y - hm * zl.y);
+    };
+#pragma unroll
+    for (int e = 0; e < E / 2; ++e) scale_pair(t + e * NT);   // l in [0, M/2)
+    if (t == 0) scale_pair(M / 2);
+    fft_lds<M, ColE<M>::v, true>(x, tw, t);
     __syncthreads();
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -545,7 +546,7 @@ __global__ __launch_bounds__(1024) void k_row_inv(const float2* __restrict__ spe
             x[sk(N - k)] = make_float2(Xa.x + Xb.y, Xb.x - Xa.y);
         }
     }
-    fft_lds<N, true>(x, tw, t);
+    fft_lds<N, RowE<N>::v, true>(x, tw, t);
     const size_t ra = (size_t)(row0 + 2 * g) * N, rb = ra + N;
     double sd = 0.0, sp = 0.0;
 #pragma unroll
@@ -869,17 +870,12 @@ int tile_blocks(int M, int N) { return ((N + kTileW - 1) / kTileW) * ((M + 15) /
 
 // Row-tile count per workgroup of the row passes: enough rows for at least
 // one full wave (each 8-row tile is 4 transforms of NT threads).
-template <int L> int fft_nt() { return FftShape<L>::NT; }
-static int fft_nt_rt(int L) {
-    switch (L) {
-        case 8: return fft_nt<8>(); case 16: return fft_nt<16>(); case 32: return fft_nt<32>();
-        case 64: return fft_nt<64>(); case 128: return fft_nt<128>(); case 256: return fft_nt<256>();
-        case 512: return fft_nt<512>(); case 1024: return fft_nt<1024>(); case 2048: return fft_nt<2048>();
-        default: return fft_nt<4096>();
-    }
+static int fft_nt_rt(int L, bool col) {
+    const int E = col ? (L <= 2048 ? 4 : 8) : (L <= 1024 ? 4 : (L == 2048 ? 8 : 16));
+    return L / E;
 }
 int fft_row_tiles(int M, int N) {
-    const int NT = fft_nt_rt(N);
+    const int NT = fft_nt_rt(N, false);
     int RT = 1;
     while (4 * RT * NT < 64 && RT * 8 * 2 <= M) RT <<= 1;
     return RT;
@@ -887,7 +883,7 @@ int fft_row_tiles(int M, int N) {
 // Columns per workgroup of the column pass: 2 (128-byte runs), more for short
 // columns so a workgroup holds at least one wave.
 int fft_col_group(int M, int N) {
-    const int NT = fft_nt_rt(M);
+    const int NT = fft_nt_rt(M, true);
     int G = 2;
     while (G * NT < 64 && G * 2 <= N / 2) G <<= 1;
     if (G > N / 2) G = N / 2;
@@ -923,7 +919,7 @@ static void launch_row_fwd_t(const float* src, float2* spec, const float2* twN, 
 template <int M>
 static void launch_col_t(float2* spec, const float2* twM, const float2* twN, int N, float taumu, float inv_mn,
                          int nz, DevScal* sc, hipStream_t st) {
-    const int NT = FftShape<M>::NT;
+    const int NT = FftShape<M, ColE<M>::v>::NT;
     const int G = fft_col_group(M, N);
     const size_t lds = tw_lds_bytes<M>() + sizeof(float2) * G * LdsLen<M>::v;
     int lrun = 0;

@@ -90,32 +90,43 @@ def _ellipse_mask(M, N, ci, cj, a, b, th, box):
     return (u / a) ** 2 + (v / b) ** 2 <= 1.0
 
 
-def _gap(union, cand, box, margin):
-    """Smallest Euclidean gap (pixel-centre distance minus nothing) between the
-    candidate mask and the union mask, looking `margin` px around the box."""
-    i0, i1, j0, j1 = box
-    M, N = union.shape
-    a0, a1 = max(i0 - margin, 0), min(i1 + margin, M)
-    b0, b1 = max(j0 - margin, 0), min(j1 + margin, N)
-    sub = union[a0:a1, b0:b1]
-    if not sub.any():
-        return math.inf
-    dist = ndimage.distance_transform_edt(~sub)
-    c = np.zeros_like(sub)
-    c[i0 - a0:i1 - a0, j0 - b0:j1 - b0] = cand
-    if (c & sub).any():
-        return 0.0
-    return float(dist[c].min()) - 1.0   # pixels strictly between the two masks
-
-
 def _place_shapes(M, N, n, axis_lo, axis_hi, rng, clearance, gap_lo=2.0, gap_hi=6.0,
                   max_reject=1000):
-    """Rejection placement: each new ellipse keeps >= gap_lo px to all others and
-    (except the first) lies <= gap_hi px from its nearest neighbour."""
-    union = np.zeros((M, N), dtype=bool)
+    """Rejection placement of n ellipses: each new ellipse keeps >= gap_lo px
+    (pixels strictly between the masks) to all placed ones and, except the
+    first, lies <= gap_hi px from its nearest neighbour.  A new shape is
+    proposed next to a random placed one, along a random direction, at the
+    distance where its gap is about the middle of [gap_lo, gap_hi]
+    (bisection).  Gaps are tested against masks of the placed shapes grown
+    by Euclidean distance (one distance transform per placed shape)."""
+    d_lo, d_mid, d_hi = gap_lo + 1.0, 0.5 * (gap_lo + gap_hi) + 1.0, gap_hi + 1.0
+    near_lo = np.zeros((M, N), dtype=bool)   # distance to placed shapes < d_lo
+    near_mid = np.zeros((M, N), dtype=bool)  # < d_mid
+    near_hi = np.zeros((M, N), dtype=bool)   # <= d_hi
     shapes = []
     scale = 1.0
     rejects = 0
+    grow = int(math.ceil(d_hi)) + 1
+
+    def box_of(ci, cj, rmax):
+        box = (int(ci - rmax) - 1, int(ci + rmax) + 3, int(cj - rmax) - 1, int(cj + rmax) + 3)
+        if box[0] < 0 or box[2] < 0 or box[1] > M or box[3] > N:
+            return None
+        return box
+
+    def hits(mask, box, cand):
+        return bool((mask[box[0]:box[1], box[2]:box[3]] & cand).any())
+
+    def add(box, cand):
+        a0, a1 = max(box[0] - grow, 0), min(box[1] + grow, M)
+        b0, b1 = max(box[2] - grow, 0), min(box[3] + grow, N)
+        c = np.zeros((a1 - a0, b1 - b0), dtype=bool)
+        c[box[0] - a0:box[1] - a0, box[2] - b0:box[3] - b0] = cand
+        dist = ndimage.distance_transform_edt(~c)
+        near_lo[a0:a1, b0:b1] |= dist < d_lo
+        near_mid[a0:a1, b0:b1] |= dist < d_mid
+        near_hi[a0:a1, b0:b1] |= dist <= d_hi
+
     while len(shapes) < n:
         a = rng.uniform(axis_lo, axis_hi) * scale
         b = rng.uniform(axis_lo, axis_hi) * scale
@@ -126,24 +137,36 @@ def _place_shapes(M, N, n, axis_lo, axis_hi, rng, clearance, gap_lo=2.0, gap_hi=
         if lo_i >= hi_i or lo_j >= hi_j:
             scale *= 0.9
             continue
+        ok = False
         if shapes:
-            # start next to a random placed shape, along a random direction
             k = shapes[rng.integers(len(shapes))]
             ang = rng.uniform(0.0, 2.0 * math.pi)
-            dist = max(k[2], k[3]) + rmax + rng.uniform(0.0, 0.5) * min(a, b)
-            ci = k[0] + dist * math.cos(ang)
-            cj = k[1] + dist * math.sin(ang)
+            di, dj = math.cos(ang), math.sin(ang)
+            t_lo, t_hi = 0.0, max(k[2], k[3]) + rmax + gap_hi + 4.0
+            for _ in range(12):
+                t = 0.5 * (t_lo + t_hi)
+                bx = box_of(k[0] + t * di, k[1] + t * dj, rmax)
+                if bx is None:
+                    break
+                cand = _ellipse_mask(M, N, k[0] + t * di, k[1] + t * dj, a, b, th, bx)
+                if hits(near_mid, bx, cand):
+                    t_lo = t
+                else:
+                    t_hi = t
+            ci, cj = k[0] + t_hi * di, k[1] + t_hi * dj
+            box = box_of(ci, cj, rmax)
+            if box is not None and lo_i <= ci <= hi_i and lo_j <= cj <= hi_j:
+                cand = _ellipse_mask(M, N, ci, cj, a, b, th, box)
+                ok = (not hits(near_lo, box, cand)) and hits(near_hi, box, cand)
         else:
             ci = rng.uniform(lo_i, hi_i)
             cj = rng.uniform(lo_j, hi_j)
-        ok = lo_i <= ci <= hi_i and lo_j <= cj <= hi_j
+            box = box_of(ci, cj, rmax)
+            if box is not None:
+                cand = _ellipse_mask(M, N, ci, cj, a, b, th, box)
+                ok = True
         if ok:
-            box = (int(ci - rmax) - 1, int(ci + rmax) + 3, int(cj - rmax) - 1, int(cj + rmax) + 3)
-            cand = _ellipse_mask(M, N, ci, cj, a, b, th, box)
-            gap = _gap(union, cand, box, int(gap_hi) + 3)
-            ok = gap >= gap_lo and (not shapes or gap <= gap_hi)
-        if ok:
-            union[box[0]:box[1], box[2]:box[3]] |= cand
+            add(box, cand)
             shapes.append((ci, cj, a, b, th))
             rejects = 0
         else:
