@@ -99,6 +99,54 @@ def cpu_baseline(f, phi0, wl, iters):
                       f"({t2 - t1:.1f} s; edge map and initialisation excluded)"}
 
 
+def batch_bench(count, cap, tol):
+    """Time-to-converge of `count` uneven instances: one sr_solve_batch call
+    against sequential plain solves (sr_step with the same stop rule)."""
+    import torch
+    from paper_2003_12693_amd import sr, synth
+    insts = synth.batch_items(count=count)
+    dev = []
+    for (M, N, R, f, phi0) in insts:
+        kw = dict(params_kw(dict(eps=1.5, d=float(R), R=R, S=3)), tol_outer=tol, min_iter=20, check_every=10)
+        dev.append((M, N, R, torch.from_numpy(f.astype(np.float32)).cuda(),
+                    torch.from_numpy(phi0.astype(np.float32)).cuda(), kw))
+    items = [dict(f=f, phi0=p, max_iter=cap, params=sr.sr_params_default(**kw)) for (M, N, R, f, p, kw) in dev]
+    sr.solve_batch(items[:4])          # warm-up: code objects, graph machinery
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, res = sr.solve_batch(items)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    # sequential plain solves of the same instances
+    t_plain = 0.0
+    agree = []
+    px_it = 0
+    for (M, N, R, f, p, kw), r in zip(dev, res):
+        s = sr.Solver(M, N, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.set_image(f, p)
+        info = s.step(cap)
+        torch.cuda.synchronize()
+        t_plain += time.perf_counter() - t0
+        px_it += M * N * r["iters"]
+        same_iters = info["k"] == r["iters"]
+        rel = float(torch.linalg.norm(s.phi() - r["phi"]) / torch.linalg.norm(s.phi()))
+        agree.append((same_iters, rel))
+        s.close()
+    conv = sum(1 for r in res if r["status"] == 0)
+    return {
+        "metric": f"time-to-converge, {count} uneven instances (sizes 128^2..512x1024, R 3-5, cap {cap}, r_k<{tol})",
+        "value": round(t_batch, 4), "unit": "s", "higher_is_better": False,
+        "plain_sequential_s": round(t_plain, 4), "speedup_vs_plain": round(t_plain / t_batch, 2),
+        "batched_mpix_it_per_s": round(px_it / 1e6 / t_batch, 1),
+        "converged": conv, "instances": count,
+        "iters_equal_to_plain": sum(1 for a in agree if a[0]),
+        "max_rel_phi_diff_vs_plain_when_iters_equal": max([a[1] for a in agree if a[0]] or [0.0]),
+        "n_gpus": 1, "dtype": "f32", "data": "synthetic",
+    }
+
+
 def copy_probe(mib):
     import torch
     n = mib * (1 << 20) // 4
@@ -120,6 +168,8 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB")
+    ap.add_argument("--batch", type=int, default=0, metavar="COUNT",
+                    help="time-to-converge of COUNT uneven instances, batched vs plain")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the solver runs on a single "
@@ -127,6 +177,9 @@ def main():
         sys.exit(2)
     if args.copy_probe:
         copy_probe(args.copy_probe)
+        return
+    if args.batch:
+        print(json.dumps(batch_bench(args.batch, 500, 1e-4)), flush=True)
         return
 
     import torch

@@ -612,14 +612,183 @@ int sr_profile_kernels(sr_ctx* c, int32_t n_iter, double ms[SR_NUM_KERNEL_KINDS]
     return SR_OK;
 }
 
+}  // extern "C"
+
+// ---- batched solve --------------------------------------------------------
+// Items are grouped by (M, N, model / solver parameters); each group is one
+// sr_ctx whose planes hold nz instances ([nz][M][N]).  All groups' launches
+// for a chunk of outer iterations are captured into one HIP graph; instances
+// retire on the device (cap, tolerance, NaN) and are skipped by every kernel
+// afterwards, so the host only polls the per-instance scalars between chunks.
+static bool same_class(const sr_batch_item& a, const sr_batch_item& b) {
+    const sr_params &x = a.params, &y = b.params;
+    return a.M == b.M && a.N == b.N && x.gamma == y.gamma && x.alpha == y.alpha && x.beta == y.beta &&
+           x.mu == y.mu && x.tau == y.tau && x.eps == y.eps && x.band_l == y.band_l && x.d == y.d && x.R == y.R &&
+           x.sigma == y.sigma && x.rho == y.rho && x.s_exp == y.s_exp && x.S == y.S &&
+           x.tol_inner == y.tol_inner && x.w0_mode == y.w0_mode && x.zero_tol == y.zero_tol;
+}
+
+struct BatchPlan {
+    std::vector<std::vector<int>> groups;   // item indices per group
+    std::vector<size_t> offset;             // workspace offset per group
+    size_t total = 0;
+};
+
+static int plan_batch(const sr_batch_item* items, int32_t n, BatchPlan& plan) {
+    if (!items || n < 1) return fail(SR_EINVAL, "items is NULL or n < 1");
+    for (int i = 0; i < n; ++i) {
+        const sr_batch_item& it = items[i];
+        int rc = validate(it.M, it.N, &it.params);
+        if (rc) return fail(rc, "item %d: %s", i, g_err.c_str());
+        if (it.max_iter < 1) return fail(SR_EINVAL, "item %d: max_iter must be >= 1", i);
+        bool placed = false;
+        for (auto& g : plan.groups)
+            if (same_class(items[g[0]], it)) { g.push_back(i); placed = true; break; }
+        if (!placed) plan.groups.push_back({i});
+    }
+    size_t o = 0;
+    for (auto& g : plan.groups) {
+        plan.offset.push_back(o);
+        o += align256(make_layout(items[g[0]].M, items[g[0]].N, (int)g.size()).total);
+    }
+    plan.total = o;
+    return SR_OK;
+}
+
+extern "C" {
+
 int sr_batch_workspace_size(const sr_batch_item* items, int32_t n, size_t* bytes) {
-    (void)items; (void)n; (void)bytes;
-    return fail(SR_EUNSUPPORTED, "sr_batch_workspace_size: not built yet");
+    if (!bytes) return fail(SR_EINVAL, "bytes is NULL");
+    BatchPlan plan;
+    int rc = plan_batch(items, n, plan);
+    if (rc) return rc;
+    *bytes = plan.total;
+    return SR_OK;
 }
 
 int sr_solve_batch(sr_batch_item* items, int32_t n, void* workspace, size_t bytes, void* hip_stream) {
-    (void)items; (void)n; (void)workspace; (void)bytes; (void)hip_stream;
-    return fail(SR_EUNSUPPORTED, "sr_solve_batch: not built yet");
+    BatchPlan plan;
+    int rc = plan_batch(items, n, plan);
+    if (rc) return rc;
+    for (int i = 0; i < n; ++i)
+        if (!items[i].f || !items[i].phi0 || !items[i].phi_out) return fail(SR_EINVAL, "item %d: NULL buffer", i);
+    if (!workspace) return fail(SR_EINVAL, "workspace is NULL");
+    if ((uintptr_t)workspace & 255) return fail(SR_EWORKSPACE, "workspace must be 256-byte aligned");
+    if (bytes < plan.total) return fail(SR_EWORKSPACE, "workspace has %zu bytes, needs %zu", bytes, plan.total);
+    sr::configure_kernels();
+    hipStream_t st = (hipStream_t)hip_stream;
+    const int G = (int)plan.groups.size();
+    std::vector<sr_ctx> ctx(G);
+    std::vector<std::vector<DevScal>> hs(G);
+    int max_cap = 0;
+    for (int gi = 0; gi < G; ++gi) {
+        const auto& idx = plan.groups[gi];
+        const sr_batch_item& it0 = items[idx[0]];
+        sr_ctx& c = ctx[gi];
+        c.M = it0.M; c.N = it0.N; c.nz = (int)idx.size();
+        c.p = it0.params;
+        c.stream = st;
+        make_kparams(c.p, c.kp);
+        make_gauss(c.p.sigma, c.gauss, c.gauss_r);
+        carve(c.b, (char*)workspace + plan.offset[gi], make_layout(c.M, c.N, c.nz));
+        c.geo.M = c.M; c.geo.N = c.N; c.geo.twM = c.b.twM; c.geo.twN = c.b.twN;
+        c.geo.taumu = (float)(c.p.tau * c.p.mu);
+        const std::vector<float2> tm = twiddles(c.M), tn = twiddles(c.N);
+        HIP_TRY(hipMemcpy(c.b.twM, tm.data(), sizeof(float2) * c.M, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(c.b.twN, tn.data(), sizeof(float2) * c.N, hipMemcpyHostToDevice));
+        hs[gi].assign(c.nz, DevScal{});
+        for (int z = 0; z < c.nz; ++z) {
+            const sr_batch_item& it = items[idx[z]];
+            DevScal& d = hs[gi][z];
+            std::memset(&d, 0, sizeof d);
+            d.active = 1;
+            d.r_last = -1.0;
+            d.max_iter = it.max_iter;
+            d.min_iter = it.params.min_iter;
+            d.tol_outer = it.params.tol_outer;
+            max_cap = std::max(max_cap, it.max_iter);
+        }
+        HIP_TRY(hipMemcpy(c.b.scal, hs[gi].data(), sizeof(DevScal) * c.nz, hipMemcpyHostToDevice));
+        const size_t MN = (size_t)c.M * c.N;
+        for (int z = 0; z < c.nz; ++z) {
+            HIP_TRY(hipMemcpyAsync(c.b.P2 + z * MN, items[idx[z]].f, MN * 4, hipMemcpyDeviceToDevice, st));
+            HIP_TRY(hipMemcpyAsync(c.b.P1 + z * MN, items[idx[z]].phi0, MN * 4, hipMemcpyDeviceToDevice, st));
+        }
+        sr::launch_edge(c.geo, c.b.P2, c.b.Rb, (float*)c.b.spec, c.b.g, c.gauss.data(), c.gauss_r, (float)c.p.rho,
+                        c.p.s_exp, c.b.scal, st, c.nz);
+        sr::launch_init(c.geo, c.b.P1, c.b.P0, c.b.W[0], c.b.B[0], c.b.D, (float)c.p.mu, c.p.w0_mode, c.b.scal, st,
+                        c.nz);
+        HIP_TRY(hipGetLastError());
+    }
+    HIP_TRY(hipStreamSynchronize(st));
+    // instances with non-finite inputs are retired before the first iteration
+    for (int gi = 0; gi < G; ++gi) {
+        sr_ctx& c = ctx[gi];
+        HIP_TRY(hipMemcpy(hs[gi].data(), c.b.scal, sizeof(DevScal) * c.nz, hipMemcpyDeviceToHost));
+        bool any = false;
+        for (auto& d : hs[gi]) if (d.nonfinite) { d.active = 0; any = true; }
+        if (any) HIP_TRY(hipMemcpy(c.b.scal, hs[gi].data(), sizeof(DevScal) * c.nz, hipMemcpyHostToDevice));
+    }
+    // one graph: a chunk of outer iterations of every group
+    const int chunk = 10;
+    hipStream_t cap = nullptr;
+    HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        for (int it = 0; it < chunk; ++it)
+            for (int gi = 0; gi < G; ++gi) enqueue_iteration(&ctx[gi], it & 1, cap);
+        e = hipStreamEndCapture(cap, &graph);
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        (void)hipStreamDestroy(cap);
+        return fail(SR_EHIP, "batch graph: %s", hipGetErrorString(e));
+    }
+    int done = 0;
+    while (done < max_cap) {
+        e = hipGraphLaunch(exec, st);
+        if (e != hipSuccess) break;
+        done += chunk;
+        bool any_active = false;
+        for (int gi = 0; gi < G && e == hipSuccess; ++gi) {
+            e = hipMemcpyAsync(hs[gi].data(), ctx[gi].b.scal, sizeof(DevScal) * ctx[gi].nz, hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            for (auto& d : hs[gi]) any_active |= d.active != 0;
+        }
+        if (!any_active) break;
+    }
+    (void)hipGraphExecDestroy(exec);
+    (void)hipStreamDestroy(cap);
+    if (e != hipSuccess) return fail(SR_EHIP, "batch iterations: %s", hipGetErrorString(e));
+    // energies and outputs
+    int worst = SR_OK;
+    for (int gi = 0; gi < G; ++gi) {
+        sr_ctx& c = ctx[gi];
+        sr::launch_energy(c.geo, c.kp, c.b.P0, c.b.g, c.b.part, c.nz, c.b.scal, st);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(hs[gi].data(), c.b.scal, sizeof(DevScal) * c.nz, hipMemcpyDeviceToHost, st));
+        const size_t MN = (size_t)c.M * c.N;
+        const auto& idx = plan.groups[gi];
+        for (int z = 0; z < c.nz; ++z)
+            HIP_TRY(hipMemcpyAsync(items[idx[z]].phi_out, c.b.P0 + z * MN, MN * 4, hipMemcpyDeviceToDevice, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        for (int z = 0; z < c.nz; ++z) {
+            sr_batch_item& it = items[idx[z]];
+            const DevScal& d = hs[gi][z];
+            it.iters = (int32_t)d.k;
+            it.r_last = d.r_last;
+            it.energy = d.energy[0] + d.energy[1] + d.energy[2];
+            if (d.nonfinite) it.status = SR_ENONFINITE;
+            else if (d.converged || it.params.tol_outer <= 0) it.status = SR_OK;
+            else it.status = SR_NOT_CONVERGED;
+            it.reserved = 0;
+            if (it.status == SR_NOT_CONVERGED && worst == SR_OK) worst = SR_NOT_CONVERGED;
+        }
+    }
+    return worst;
 }
 
 }  // extern "C"

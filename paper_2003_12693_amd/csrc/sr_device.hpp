@@ -34,7 +34,13 @@ struct DevScal {
     double r_last;          // last outer relative change r_k
     double inner_rel;       // last inner relative change
     double energy[3];       // gamma E_g, alpha E_a, beta E_r
-    long long pad[kScalStride - 9];
+    // per-instance stop rule of the batched solve (0 = host decides)
+    int max_iter;           // retire when k reaches this
+    int min_iter;           // no tolerance stop before this
+    double tol_outer;       // retire when r_k < tol_outer
+    int converged;          // set when retired by the tolerance
+    int spare;
+    long long pad[kScalStride - 12];
 };
 static_assert(sizeof(DevScal) == kScalStride * 8, "DevScal layout");
 

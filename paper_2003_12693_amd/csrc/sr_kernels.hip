@@ -29,12 +29,13 @@ __global__ __launch_bounds__(256) void k_blur_rows(const float* __restrict__ src
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     const int i = blockIdx.y;
     if (j >= N) return;
-    const float* row = src + (size_t)i * N;
+    const size_t zo = (size_t)blockIdx.z * M * N;
+    const float* row = src + zo + (size_t)i * N;
     float acc = 0.0f;
     for (int t = -gt.r; t <= gt.r; ++t) acc += gt.k[t + gt.r] * row[(j + t) & (N - 1)];
     const float c = row[j];
-    if (!isfinite(c)) sc->nonfinite = 1;
-    dst[(size_t)i * N + j] = acc;
+    if (!isfinite(c)) sc[blockIdx.z].nonfinite = 1;
+    dst[zo + (size_t)i * N + j] = acc;
 }
 
 __global__ __launch_bounds__(256) void k_blur_cols(const float* __restrict__ src, float* __restrict__ dst,
@@ -42,9 +43,11 @@ __global__ __launch_bounds__(256) void k_blur_cols(const float* __restrict__ src
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     const int i = blockIdx.y;
     if (j >= N) return;
+    const size_t zo = (size_t)blockIdx.z * M * N;
+    src += zo;
     float acc = 0.0f;
     for (int t = -gt.r; t <= gt.r; ++t) acc += gt.k[t + gt.r] * src[(size_t)((i + t) & (M - 1)) * N + j];
-    dst[(size_t)i * N + j] = acc;
+    dst[zo + (size_t)i * N + j] = acc;
 }
 
 // g = 1 / (1 + rho |grad fs|^s), central differences.
@@ -53,6 +56,9 @@ __global__ __launch_bounds__(256) void k_edge(const float* __restrict__ fs, floa
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     const int i = blockIdx.y;
     if (j >= N) return;
+    const size_t zo = (size_t)blockIdx.z * M * N;
+    fs += zo;
+    g += zo;
     const float gx = 0.5f * (fs[(size_t)((i + 1) & (M - 1)) * N + j] - fs[(size_t)((i - 1) & (M - 1)) * N + j]);
     const float gy = 0.5f * (fs[(size_t)i * N + ((j + 1) & (N - 1))] - fs[(size_t)i * N + ((j - 1) & (N - 1))]);
     const float m2 = gx * gx + gy * gy;
@@ -70,8 +76,10 @@ __global__ __launch_bounds__(256) void k_init(const float* __restrict__ phi0, fl
     const int i = blockIdx.y;
     if (j >= N) return;
     const size_t MN = (size_t)M * N, o = (size_t)i * N + j;
+    const size_t z = blockIdx.z;
+    phi0 += z * MN; P0 += z * MN; W += 2 * z * MN; B += 2 * z * MN; D += z * MN;
     const float p = phi0[o];
-    if (!isfinite(p)) sc->nonfinite = 1;
+    if (!isfinite(p)) sc[z].nonfinite = 1;
     const float pd = phi0[(size_t)((i + 1) & (M - 1)) * N + j];
     const float pr = phi0[(size_t)i * N + ((j + 1) & (N - 1))];
     const float pu = phi0[(size_t)((i - 1) & (M - 1)) * N + j];
@@ -111,6 +119,7 @@ __global__ void k_reset_scal(DevScal* sc, int n, int active) {
     s.counter = 0u; s.inner_done = 0; s.active = active; s.nonfinite = 0;
     s.k = 0; s.inner_steps = 0; s.r_last = -1.0; s.inner_rel = -1.0;
     s.energy[0] = s.energy[1] = s.energy[2] = 0.0;
+    s.max_iter = 0; s.min_iter = 0; s.tol_outer = 0.0; s.converged = 0; s.spare = 0;
 }
 
 __global__ void k_set_k(DevScal* sc, long long k) {
@@ -774,6 +783,10 @@ __global__ __launch_bounds__(256) void k_fin_outer(const double* __restrict__ pa
         rhist[(size_t)z * kRHist + (S.k % kRHist)] = r;
         S.k += 1;
         S.inner_done = 0;
+        // batched solves retire an instance on the device: cap, tolerance, NaN
+        if (!(r == r) || r > 1e30) { S.nonfinite = 1; S.active = 0; }
+        else if (S.tol_outer > 0.0 && S.k >= S.min_iter && r < S.tol_outer) { S.converged = 1; S.active = 0; }
+        else if (S.max_iter > 0 && S.k >= S.max_iter) S.active = 0;
     }
 }
 
@@ -1052,19 +1065,19 @@ void launch_repulsion(const Geometry& geo, const KParams& kp, const float* phi, 
 }
 
 void launch_edge(const Geometry& geo, const float* f, float* tmp, float* fs, float* g, const float* taps, int r,
-                 float rho, int s_exp, DevScal* sc, hipStream_t st) {
+                 float rho, int s_exp, DevScal* sc, hipStream_t st, int nz) {
     GaussTaps gt;
     gt.r = r;
     for (int t = 0; t <= 2 * r; ++t) gt.k[t] = taps[t];
-    const dim3 blk(256), grd((geo.N + 255) / 256, geo.M);
+    const dim3 blk(256), grd((geo.N + 255) / 256, geo.M, nz);
     hipLaunchKernelGGL(k_blur_rows, grd, blk, 0, st, f, tmp, geo.M, geo.N, gt, sc);
     hipLaunchKernelGGL(k_blur_cols, grd, blk, 0, st, tmp, fs, geo.M, geo.N, gt);
     hipLaunchKernelGGL(k_edge, grd, blk, 0, st, fs, g, geo.M, geo.N, rho, s_exp);
 }
 
 void launch_init(const Geometry& geo, const float* phi0, float* P0, float* W, float* B, float* D, float mu,
-                 int w0_mode, DevScal* sc, hipStream_t st) {
-    const dim3 blk(256), grd((geo.N + 255) / 256, geo.M);
+                 int w0_mode, DevScal* sc, hipStream_t st, int nz) {
+    const dim3 blk(256), grd((geo.N + 255) / 256, geo.M, nz);
     hipLaunchKernelGGL(k_init, grd, blk, 0, st, phi0, P0, W, B, D, geo.M, geo.N, mu, w0_mode, sc);
 }
 

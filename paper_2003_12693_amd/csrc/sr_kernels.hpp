@@ -20,9 +20,9 @@ struct Geometry {
 int tile_blocks(int M, int N);
 
 void launch_edge(const Geometry& geo, const float* f, float* tmp, float* fs, float* g, const float* taps, int r,
-                 float rho, int s_exp, DevScal* sc, hipStream_t st);
+                 float rho, int s_exp, DevScal* sc, hipStream_t st, int nz = 1);
 void launch_init(const Geometry& geo, const float* phi0, float* P0, float* W, float* B, float* D, float mu,
-                 int w0_mode, DevScal* sc, hipStream_t st);
+                 int w0_mode, DevScal* sc, hipStream_t st, int nz = 1);
 void launch_set_D(const Geometry& geo, const float* W, const float* B, float* D, float mu, hipStream_t st);
 void launch_reset_scal(DevScal* sc, int n, int active, hipStream_t st);
 void launch_set_k(DevScal* sc, long long k, hipStream_t st);

@@ -338,3 +338,32 @@ class Solver:
 
     def implicit_solve(self, rhs):
         return sr_implicit_solve(self.ctx, rhs, self._empty(self.M, self.N))
+
+
+def solve_batch(items, stream=None):
+    """Batched solve.  `items` is a list of dicts with keys f, phi0 (contiguous
+    float32 GPU tensors), max_iter, and optional params (an sr_params) or
+    parameter overrides under "params_kw".  Returns a list of dicts with
+    phi (tensor), iters, status, r_last, energy."""
+    import torch
+    cs = []
+    outs = []
+    for it in items:
+        f, phi0 = it["f"], it["phi0"]
+        M, N = f.shape
+        p = it.get("params") or sr_params_default(**it.get("params_kw", {}))
+        out = torch.empty_like(f)
+        outs.append(out)
+        bi = sr_batch_item()
+        bi.M, bi.N = M, N
+        bi.f, bi.phi0, bi.phi_out = _ptr(f, False)[0], _ptr(phi0, False)[0], out.data_ptr()
+        bi.params = p
+        bi.max_iter = int(it["max_iter"])
+        cs.append(bi)
+    nbytes = sr_batch_workspace_size(cs)
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=items[0]["f"].device)
+    off = (-ws.data_ptr()) % 256
+    rc = sr_solve_batch(cs, ws[off:off + nbytes], stream)
+    res = [{"phi": outs[i], "iters": cs[i].iters, "status": cs[i].status, "r_last": cs[i].r_last,
+            "energy": cs[i].energy} for i in range(len(cs))]
+    return rc, res

@@ -110,3 +110,24 @@ def test_workspace_size_scales(sr):
     b = sr.sr_workspace_size(4096, 4096, p)
     assert 13 * 4 * 1024 * 1024 <= a < 20 * 4 * 1024 * 1024
     assert 15.5 < b / a < 16.5
+
+
+def test_batch_validation_before_hip(sr):
+    lib = sr.load()
+    items = (sr.sr_batch_item * 2)()
+    for it in items:
+        it.M, it.N, it.max_iter = 64, 64, 10
+        it.params = sr.sr_params_default()
+    n = C.c_size_t()
+    assert lib.sr_batch_workspace_size(items, 2, C.byref(n)) == sr.SR_OK and n.value > 0
+    one = (sr.sr_batch_item * 1)(items[0])
+    n1 = C.c_size_t()
+    lib.sr_batch_workspace_size(one, 1, C.byref(n1))
+    assert n.value < 2 * n1.value          # equal classes share one group layout
+    items[1].M = 100
+    assert lib.sr_batch_workspace_size(items, 2, C.byref(n)) == sr.SR_EUNSUPPORTED
+    items[1].M = 64
+    items[1].max_iter = 0
+    assert lib.sr_batch_workspace_size(items, 2, C.byref(n)) == sr.SR_EINVAL
+    items[1].max_iter = 10
+    assert lib.sr_solve_batch(items, 2, None, 0, None) == sr.SR_EINVAL     # NULL buffers

@@ -1,0 +1,110 @@
+"""GPU tests of the batched solve (sr_solve_batch) through the C ABI."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import sr_oracle as O
+from paper_2003_12693_amd import synth
+from tests.helpers import as64, f32, gpu_params, oracle_params, rel_l2
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def sr():
+    from paper_2003_12693_amd import sr as srmod
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    srmod.load()
+    return srmod
+
+
+def _cuda(x):
+    return torch.from_numpy(f32(x)).cuda()
+
+
+def _instances():
+    out = []
+    for k, (M, N, R) in enumerate([(64, 64, 3), (64, 128, 3), (128, 128, 4), (64, 64, 5), (64, 128, 3),
+                                   (128, 64, 4)]):
+        f, phi0 = synth.ellipses(M, N, seed=100 + k, n_shapes=2, axis_lo=6.0, axis_hi=14.0, inset=8)
+        out.append((M, N, R, f, phi0))
+    return out
+
+
+def test_batch_matches_single_instance_solves(sr):
+    _note("batch vs single")
+    inst = _instances()
+    items = [dict(f=_cuda(f), phi0=_cuda(p), max_iter=7, params=gpu_params(R=R, d=float(R)))
+             for (M, N, R, f, p) in inst]
+    rc, res = sr.solve_batch(items)
+    assert rc == 0
+    for (M, N, R, f, p), r in zip(inst, res):
+        assert r["iters"] == 7 and r["status"] == 0
+        s = sr.Solver(M, N, gpu_params(R=R, d=float(R)))
+        s.set_image(_cuda(f), _cuda(p))
+        s.step(7)
+        ref = s.phi().cpu().numpy()
+        got = r["phi"].cpu().numpy()
+        assert rel_l2(got, ref) <= 1e-6
+        E, _ = s.energy()
+        assert abs(r["energy"] - E) <= 1e-6 * abs(E)
+
+
+def test_batch_against_oracle(sr):
+    _note("batch vs oracle")
+    inst = _instances()[:3]
+    items = [dict(f=_cuda(f), phi0=_cuda(p), max_iter=3, params=gpu_params(R=R, d=float(R)))
+             for (M, N, R, f, p) in inst]
+    rc, res = sr.solve_batch(items)
+    for (M, N, R, f, p), r in zip(inst, res):
+        P = oracle_params(R=R, d=float(R))
+        st, g, _ = O.solve(as64(f), as64(p), P, 3)
+        assert rel_l2(r["phi"].cpu().numpy(), st.phi) <= 1e-5
+        Eo = O.energy(st.phi, g, P)
+        assert abs(r["energy"] - Eo) <= 1e-4 * abs(Eo)
+
+
+def test_batch_tolerance_and_caps(sr):
+    _note("batch tolerance")
+    inst = _instances()
+    items = []
+    for k, (M, N, R, f, p) in enumerate(inst):
+        params = gpu_params(R=R, d=float(R), tol_outer=3e-3 if k % 2 == 0 else 0.0, min_iter=4)
+        items.append(dict(f=_cuda(f), phi0=_cuda(p), max_iter=25 + k, params=params))
+    rc, res = sr.solve_batch(items)
+    for k, r in enumerate(res):
+        if k % 2 == 0:
+            assert r["status"] in (0, 1)
+            if r["status"] == 0:
+                assert r["r_last"] < 3e-3 and 4 <= r["iters"] <= 25 + k
+            else:
+                assert r["iters"] == 25 + k
+        else:
+            assert r["status"] == 0 and r["iters"] == 25 + k
+    # the same instance solved alone for the reported iteration count agrees
+    M, N, R, f, p = inst[0]
+    s = sr.Solver(M, N, gpu_params(R=R, d=float(R)))
+    s.set_image(_cuda(f), _cuda(p))
+    s.step(res[0]["iters"])
+    assert rel_l2(res[0]["phi"].cpu().numpy(), s.phi().cpu().numpy()) <= 1e-6
+
+
+def test_batch_nonfinite_instance_isolated(sr):
+    _note("batch nonfinite")
+    inst = _instances()[:3]
+    items = [dict(f=_cuda(f), phi0=_cuda(p), max_iter=5, params=gpu_params(R=R, d=float(R)))
+             for (M, N, R, f, p) in inst]
+    bad = inst[1][3].copy()
+    bad[3, 3] = np.nan
+    items[1]["f"] = _cuda(bad)
+    rc, res = sr.solve_batch(items)
+    assert res[1]["status"] == sr.SR_ENONFINITE
+    assert res[0]["status"] == 0 and res[0]["iters"] == 5
+    assert res[2]["status"] == 0 and res[2]["iters"] == 5
