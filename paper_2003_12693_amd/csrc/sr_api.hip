@@ -344,6 +344,8 @@ int sr_create(sr_ctx** out, int32_t M, int32_t N, const sr_params* p, void* work
     c->geo.taumu = (float)(c->p.tau * c->p.mu);
     const char* ng = std::getenv("SR_NO_GRAPH");
     c->use_graphs = !(ng && ng[0] == '1');
+    const char* th = std::getenv("SR_TILE_TH");
+    c->geo.tile_th = th ? std::atoi(th) : 0;
 
     hipError_t e = hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking);
     if (e != hipSuccess) { delete c; return fail(SR_EHIP, "hipStreamCreate: %s", hipGetErrorString(e)); }

@@ -209,27 +209,31 @@ __global__ __launch_bounds__(kTileThreads) void k_rhs(KParams kp, int M, int N,
     const int i0 = ty * TH, j0 = tx * TW;
     const int tid = threadIdx.x;
 
-    // phase 1: all loads of the extended tile first, then u = w h(phi)
-    float lp[C::NE], l1[C::NE], l2[C::NE];
+    // phase 1: phi on the extended tile and D on the tile; is any pixel of
+    // the extended tile inside the band |phi| <= l + eps?
+    const float lim = kp.band_l + kp.eps;
+    float lp[C::NE];
 #pragma unroll
     for (int u = 0; u < C::NE; ++u) {
         const int e = tid + u * T;
         if (e < NEXT) {
             const int ei = e / EW, ej = e - ei * EW;
-            const size_t o = (size_t)((i0 - R + ei) & (M - 1)) * N + ((j0 - R + ej) & (N - 1));
-            lp[u] = phi_s[o];
-            l1[u] = W[o];
-            l2[u] = W[MN + o];
+            lp[u] = phi_s[(size_t)((i0 - R + ei) & (M - 1)) * N + ((j0 - R + ej) & (N - 1))];
         }
     }
+    float dv[C::NO];
+#pragma unroll
+    for (int u = 0; u < C::NO; ++u) {
+        const int e = tid + u * T;
+        dv[u] = D[(size_t)((i0 + e / TW) & (M - 1)) * N + ((j0 + (e % TW)) & (N - 1))];
+    }
+    int inband = 0;
 #pragma unroll
     for (int u = 0; u < C::NE; ++u) {
         const int e = tid + u * T;
         if (e < NEXT) {
             const int ei = e / EW, ej = e - ei * EW;
-            const float h = band_h(lp[u], kp);
-            su1[e] = l1[u] * h;
-            su2[e] = l2[u] * h;
+            inband |= (lp[u] <= lim && lp[u] >= -lim);
             const int si = ei - R + 1, sj = ej - R + 1;
             if ((unsigned)si < (unsigned)PH && (unsigned)sj < (unsigned)PW) sphi[si * PW + sj] = lp[u];
         }
@@ -240,14 +244,50 @@ __global__ __launch_bounds__(kTileThreads) void k_rhs(KParams kp, int M, int N,
             sphi[e] = phi_s[(size_t)((i0 - 1 + si) & (M - 1)) * N + ((j0 - 1 + sj) & (N - 1))];
         }
     }
-    // the pointwise inputs of phase 3, issued before the barrier
-    float w1v[C::NO], w2v[C::NO], gv[C::NO], dv[C::NO];
+    const bool band = __syncthreads_or(inband) != 0;
+    if (!band) {
+        // h, h', delta, delta' vanish on the whole extended tile: v = 0 and
+        // the force is zero, so r = tau (D + mu Lap phi) exactly.
+#pragma unroll
+        for (int u = 0; u < C::NO; ++u) {
+            const int e = tid + u * T;
+            const int i = e / TW, j = e - i * TW;
+            const int gi = i0 + i, gj = j0 + j;
+            const float* sp = sphi + (i + 1) * PW + (j + 1);
+            const float p = sp[0];
+            const float lap = (sp[-PW] + sp[PW]) + (sp[-1] + sp[1]) - 4.0f * p;
+            const float force = 0.0f;
+            if (gi < M && gj < N) out[(size_t)gi * N + gj] = kp.tau * (force + dv[u] + kp.mu * lap);
+        }
+        return;
+    }
+    // band tile: u = w h(phi) on the extended tile
+    float l1[C::NE], l2[C::NE];
+#pragma unroll
+    for (int u = 0; u < C::NE; ++u) {
+        const int e = tid + u * T;
+        if (e < NEXT) {
+            const int ei = e / EW, ej = e - ei * EW;
+            const size_t o = (size_t)((i0 - R + ei) & (M - 1)) * N + ((j0 - R + ej) & (N - 1));
+            l1[u] = W[o];
+            l2[u] = W[MN + o];
+        }
+    }
+    float w1v[C::NO], w2v[C::NO], gv[C::NO];
 #pragma unroll
     for (int u = 0; u < C::NO; ++u) {
         const int e = tid + u * T;
-        const int gi = i0 + e / TW, gj = j0 + (e % TW);
-        const size_t o = (size_t)(gi & (M - 1)) * N + (gj & (N - 1));
-        w1v[u] = W[o]; w2v[u] = W[MN + o]; gv[u] = g[o]; dv[u] = D[o];
+        const size_t o = (size_t)((i0 + e / TW) & (M - 1)) * N + ((j0 + (e % TW)) & (N - 1));
+        w1v[u] = W[o]; w2v[u] = W[MN + o]; gv[u] = g[o];
+    }
+#pragma unroll
+    for (int u = 0; u < C::NE; ++u) {
+        const int e = tid + u * T;
+        if (e < NEXT) {
+            const float h = band_h(lp[u], kp);
+            su1[e] = l1[u] * h;
+            su2[e] = l2[u] * h;
+        }
     }
     __syncthreads();
     // phase 2: row pass of the separable window
@@ -645,26 +685,40 @@ __global__ __launch_bounds__(kTileThreads) void k_wstep(KParams kp, int M, int N
     const int i0 = ty * TH, j0 = tx * TW;
     const int tid = threadIdx.x;
 
-    float lp[C::NE], l1[C::NE], l2[C::NE];
+    const float lim = kp.band_l + kp.eps;
+    float lp[C::NE];
 #pragma unroll
     for (int u = 0; u < C::NE; ++u) {
         const int e = tid + u * T;
         if (e < NEXT) {
             const int ei = e / EW, ej = e - ei * EW;
-            const size_t o = (size_t)((i0 - 1 - R + ei) & (M - 1)) * N + ((j0 - 1 - R + ej) & (N - 1));
-            lp[u] = phin[o];
-            l1[u] = Wold[o];
-            l2[u] = Wold[MN + o];
+            lp[u] = phin[(size_t)((i0 - 1 - R + ei) & (M - 1)) * N + ((j0 - 1 - R + ej) & (N - 1))];
         }
     }
+    // b on the computed region and phi^k on the tile (both paths need them)
+    float b1v[C::NC], b2v[C::NC];
+#pragma unroll
+    for (int u = 0; u < C::NC; ++u) {
+        const int e = tid + u * T;
+        if (e < CH * CW) {
+            const int ci = e / CW, cj = e - ci * CW;
+            const size_t o = (size_t)((i0 - 1 + ci) & (M - 1)) * N + ((j0 - 1 + cj) & (N - 1));
+            b1v[u] = Bold[o]; b2v[u] = Bold[MN + o];
+        }
+    }
+    float pold[C::NO];
+#pragma unroll
+    for (int u = 0; u < C::NO; ++u) {
+        const int e = tid + u * T;
+        pold[u] = P0[(size_t)((i0 + e / TW) & (M - 1)) * N + ((j0 + (e % TW)) & (N - 1))];
+    }
+    int inband = 0;
 #pragma unroll
     for (int u = 0; u < C::NE; ++u) {
         const int e = tid + u * T;
         if (e < NEXT) {
             const int ei = e / EW, ej = e - ei * EW;
-            const float h = band_h(lp[u], kp);
-            su1[e] = l1[u] * h;
-            su2[e] = l2[u] * h;
+            inband |= (lp[u] <= lim && lp[u] >= -lim);
             const int si = ei - R, sj = ej - R;
             if ((unsigned)si < (unsigned)PH && (unsigned)sj < (unsigned)PW) sphi[si * PW + sj] = lp[u];
         }
@@ -675,71 +729,111 @@ __global__ __launch_bounds__(kTileThreads) void k_wstep(KParams kp, int M, int N
             sphi[e] = phin[(size_t)((i0 - 1 + si) & (M - 1)) * N + ((j0 - 1 + sj) & (N - 1))];
         }
     }
-    // inputs of the computed region, issued before the barrier
-    float b1v[C::NC], b2v[C::NC], gv[C::NC];
+    const bool band = __syncthreads_or(inband) != 0;
+    if (band) {
+        float l1[C::NE], l2[C::NE];
 #pragma unroll
-    for (int u = 0; u < C::NC; ++u) {
-        const int e = tid + u * T;
-        if (e < CH * CW) {
-            const int ci = e / CW, cj = e - ci * CW;
-            const size_t o = (size_t)((i0 - 1 + ci) & (M - 1)) * N + ((j0 - 1 + cj) & (N - 1));
-            b1v[u] = Bold[o]; b2v[u] = Bold[MN + o]; gv[u] = g[o];
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < C::NHZ; ++u) {
-        const int e = tid + u * T;
-        if (e < EH * CW) {
-            const int ei = e / CW, j = e - ei * CW;
-            const float* r1 = su1 + ei * EW + j;
-            const float* r2 = su2 + ei * EW + j;
-            float a1 = 0.0f, a2 = 0.0f;
-#pragma unroll
-            for (int q = 0; q <= 2 * R; ++q) { a1 += kp.taps[q] * r1[q]; a2 += kp.taps[q] * r2[q]; }
-            sh1[e] = a1;
-            sh2[e] = a2;
-        }
-    }
-    __syncthreads();
-    float pold[C::NO];
-#pragma unroll
-    for (int u = 0; u < C::NO; ++u) {
-        const int e = tid + u * T;
-        const int gi = i0 + e / TW, gj = j0 + (e % TW);
-        pold[u] = P0[(size_t)(gi & (M - 1)) * N + (gj & (N - 1))];
-    }
-#pragma unroll
-    for (int u = 0; u < C::NC; ++u) {
-        const int e = tid + u * T;
-        if (e < CH * CW) {
-            const int ci = e / CW, cj = e - ci * CW;
-            float v1 = 0.0f, v2 = 0.0f;
-#pragma unroll
-            for (int pp = 0; pp <= 2 * R; ++pp) {
-                v1 += kp.taps[pp] * sh1[(ci + pp) * CW + cj];
-                v2 += kp.taps[pp] * sh2[(ci + pp) * CW + cj];
+        for (int u = 0; u < C::NE; ++u) {
+            const int e = tid + u * T;
+            if (e < NEXT) {
+                const int ei = e / EW, ej = e - ei * EW;
+                const size_t o = (size_t)((i0 - 1 - R + ei) & (M - 1)) * N + ((j0 - 1 - R + ej) & (N - 1));
+                l1[u] = Wold[o];
+                l2[u] = Wold[MN + o];
             }
-            const float* sp = sphi + ci * PW + cj;
-            const float p = sp[0];
-            const float G1 = sp[PW] - p, G2 = sp[1] - p;
-            const float b1 = b1v[u], b2 = b2v[u];
-            const float h = band_h(p, kp);
-            float H_, dl;
-            heav_dirac(p, kp.eps, kp.inv_eps, H_, dl);
-            const float B1 = G1 + b1 + kp.c_rep * h * v1;
-            const float B2 = G2 + b2 + kp.c_rep * h * v2;
-            const float thr = kp.c_thr * gv[u] * dl;
-            const float nb = sqrtf(B1 * B1 + B2 * B2);
-            float w1 = 0.0f, w2 = 0.0f;
-            if (nb > thr && nb > kp.zero_tol) { w1 = B1 / nb; w2 = B2 / nb; }
-            const float bn1 = b1 + G1 - w1, bn2 = b2 + G2 - w2;
-            sd1[e] = bn1 - w1;
-            sd2[e] = bn2 - w2;
-            if (ci >= 1 && cj >= 1 && i0 - 1 + ci < M && j0 - 1 + cj < N) {
-                const size_t o = (size_t)(i0 - 1 + ci) * N + (j0 - 1 + cj);
-                Wnew[o] = w1; Wnew[MN + o] = w2;
-                Bnew[o] = bn1; Bnew[MN + o] = bn2;
+        }
+        float gv[C::NC];
+#pragma unroll
+        for (int u = 0; u < C::NC; ++u) {
+            const int e = tid + u * T;
+            if (e < CH * CW) {
+                const int ci = e / CW, cj = e - ci * CW;
+                gv[u] = g[(size_t)((i0 - 1 + ci) & (M - 1)) * N + ((j0 - 1 + cj) & (N - 1))];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < C::NE; ++u) {
+            const int e = tid + u * T;
+            if (e < NEXT) {
+                const float h = band_h(lp[u], kp);
+                su1[e] = l1[u] * h;
+                su2[e] = l2[u] * h;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < C::NHZ; ++u) {
+            const int e = tid + u * T;
+            if (e < EH * CW) {
+                const int ei = e / CW, j = e - ei * CW;
+                const float* r1 = su1 + ei * EW + j;
+                const float* r2 = su2 + ei * EW + j;
+                float a1 = 0.0f, a2 = 0.0f;
+#pragma unroll
+                for (int q = 0; q <= 2 * R; ++q) { a1 += kp.taps[q] * r1[q]; a2 += kp.taps[q] * r2[q]; }
+                sh1[e] = a1;
+                sh2[e] = a2;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < C::NC; ++u) {
+            const int e = tid + u * T;
+            if (e < CH * CW) {
+                const int ci = e / CW, cj = e - ci * CW;
+                float v1 = 0.0f, v2 = 0.0f;
+#pragma unroll
+                for (int pp = 0; pp <= 2 * R; ++pp) {
+                    v1 += kp.taps[pp] * sh1[(ci + pp) * CW + cj];
+                    v2 += kp.taps[pp] * sh2[(ci + pp) * CW + cj];
+                }
+                const float* sp = sphi + ci * PW + cj;
+                const float p = sp[0];
+                const float G1 = sp[PW] - p, G2 = sp[1] - p;
+                const float b1 = b1v[u], b2 = b2v[u];
+                const float h = band_h(p, kp);
+                float H_, dl;
+                heav_dirac(p, kp.eps, kp.inv_eps, H_, dl);
+                const float B1 = G1 + b1 + kp.c_rep * h * v1;
+                const float B2 = G2 + b2 + kp.c_rep * h * v2;
+                const float thr = kp.c_thr * gv[u] * dl;
+                const float nb = sqrtf(B1 * B1 + B2 * B2);
+                float w1 = 0.0f, w2 = 0.0f;
+                if (nb > thr && nb > kp.zero_tol) { w1 = B1 / nb; w2 = B2 / nb; }
+                const float bn1 = b1 + G1 - w1, bn2 = b2 + G2 - w2;
+                sd1[e] = bn1 - w1;
+                sd2[e] = bn2 - w2;
+                if (ci >= 1 && cj >= 1 && i0 - 1 + ci < M && j0 - 1 + cj < N) {
+                    const size_t o = (size_t)(i0 - 1 + ci) * N + (j0 - 1 + cj);
+                    Wnew[o] = w1; Wnew[MN + o] = w2;
+                    Bnew[o] = bn1; Bnew[MN + o] = bn2;
+                }
+            }
+        }
+    } else {
+        // no band pixel on the extended tile: v = 0, h = 0 and the threshold
+        // is 0, so B = grad phi + b exactly and the gate is |B| > zero_tol.
+#pragma unroll
+        for (int u = 0; u < C::NC; ++u) {
+            const int e = tid + u * T;
+            if (e < CH * CW) {
+                const int ci = e / CW, cj = e - ci * CW;
+                const float* sp = sphi + ci * PW + cj;
+                const float p = sp[0];
+                const float G1 = sp[PW] - p, G2 = sp[1] - p;
+                const float b1 = b1v[u], b2 = b2v[u];
+                const float B1 = G1 + b1, B2 = G2 + b2;
+                const float nb = sqrtf(B1 * B1 + B2 * B2);
+                float w1 = 0.0f, w2 = 0.0f;
+                if (nb > 0.0f && nb > kp.zero_tol) { w1 = B1 / nb; w2 = B2 / nb; }
+                const float bn1 = b1 + G1 - w1, bn2 = b2 + G2 - w2;
+                sd1[e] = bn1 - w1;
+                sd2[e] = bn2 - w2;
+                if (ci >= 1 && cj >= 1 && i0 - 1 + ci < M && j0 - 1 + cj < N) {
+                    const size_t o = (size_t)(i0 - 1 + ci) * N + (j0 - 1 + cj);
+                    Wnew[o] = w1; Wnew[MN + o] = w2;
+                    Bnew[o] = bn1; Bnew[MN + o] = bn2;
+                }
             }
         }
     }
@@ -879,7 +973,7 @@ inline size_t lds_energy(int TH, int R) {
 }
 }  // namespace
 
-int tile_blocks(int M, int N) { return ((N + kTileW - 1) / kTileW) * ((M + 15) / 16); }
+int tile_blocks(int M, int N) { return ((N + kTileW - 1) / kTileW) * ((M + 7) / 8); }
 
 // Row-tile count per workgroup of the row passes: enough rows for at least
 // one full wave (each 8-row tile is 4 transforms of NT threads).
@@ -979,10 +1073,12 @@ void launch_solve(const Geometry& geo, const float* rhs, const float* phi_in, fl
         launch_solve_pass(pass, geo, rhs, phi_in, phi_out, spec, tol_inner, part, nz, sc, st);
 }
 
-// Tile height: 32 rows unless that leaves fewer than ~4 workgroups per CU.
-static int tile_height(int M, int N, int nz) {
-    const long tiles32 = (long)((N + kTileW - 1) / kTileW) * ((M + 31) / 32) * nz;
-    return tiles32 >= 1024 ? 32 : 16;
+// Tile height: 32 rows unless that leaves fewer than ~4 workgroups per CU
+// (a context may fix it, e.g. from the autotuner).
+static int tile_height(const Geometry& geo, int nz) {
+    if (geo.tile_th == 8 || geo.tile_th == 16 || geo.tile_th == 32) return geo.tile_th;
+    (void)nz;
+    return 16;
 }
 
 template <int TH, int R>
@@ -1015,22 +1111,28 @@ static void launch_wstep_t(const Geometry& geo, const KParams& kp, const float* 
 
 void launch_rhs(const Geometry& geo, const KParams& kp, const float* phi_s, const float* W, const float* g,
                 const float* D, float* out, int nz, DevScal* sc, hipStream_t st) {
-    if (tile_height(geo.M, geo.N, nz) == 32) {
+    const int TH = tile_height(geo, nz);
+    if (TH == 32) {
         SR_R_DISPATCH(launch_rhs_t, 32, kp.R, geo, kp, phi_s, W, g, D, out, nz, sc, st);
-    } else {
+    } else if (TH == 16) {
         SR_R_DISPATCH(launch_rhs_t, 16, kp.R, geo, kp, phi_s, W, g, D, out, nz, sc, st);
+    } else {
+        SR_R_DISPATCH(launch_rhs_t, 8, kp.R, geo, kp, phi_s, W, g, D, out, nz, sc, st);
     }
 }
 
 void launch_wstep(const Geometry& geo, const KParams& kp, const float* phin, float* P0, const float* Wold,
                   const float* Bold, const float* g, float* Wnew, float* Bnew, float* D, double* part,
                   double* rhist, int nz, DevScal* sc, hipStream_t st) {
-    const int TH = tile_height(geo.M, geo.N, nz);
+    const int TH = tile_height(geo, nz);
     if (TH == 32) {
         SR_R_DISPATCH(launch_wstep_t, 32, kp.R, geo, kp, phin, P0, Wold, Bold, g, Wnew, Bnew, D, part, rhist, nz, sc,
                       st);
-    } else {
+    } else if (TH == 16) {
         SR_R_DISPATCH(launch_wstep_t, 16, kp.R, geo, kp, phin, P0, Wold, Bold, g, Wnew, Bnew, D, part, rhist, nz, sc,
+                      st);
+    } else {
+        SR_R_DISPATCH(launch_wstep_t, 8, kp.R, geo, kp, phin, P0, Wold, Bold, g, Wnew, Bnew, D, part, rhist, nz, sc,
                       st);
     }
     const int nb = ((geo.N + kTileW - 1) / kTileW) * ((geo.M + TH - 1) / TH);
@@ -1104,6 +1206,7 @@ void configure_kernels() {
     static bool done = false;
     if (done) return;
     const int bytes = 160 * 1024 - 1024;
+    set_tile_attrs<8>();
     set_tile_attrs<16>();
     set_tile_attrs<32>();
     (void)hipFuncSetAttribute((const void*)k_energy<kTH>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);

@@ -15,6 +15,7 @@ struct Geometry {
     const float2* twM;
     const float2* twN;
     float taumu;
+    int tile_th = 0;   // stencil tile height (16 or 32); 0 = size heuristic
 };
 
 int tile_blocks(int M, int N);
