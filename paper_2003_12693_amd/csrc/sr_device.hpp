@@ -150,10 +150,21 @@ template <> struct Ilog2<1> { static constexpr int v = 0; };
 // elements (one radix-4 butterfly per stage) for lengths up to 1024 gives
 // the most waves per CU; 2048 and 4096 points take 8 and 16 so that the
 // four transforms of an 8-row tile still fit one 1024-thread workgroup.
-template <int L> struct RowE { static constexpr int v = L <= 1024 ? 4 : (L == 2048 ? 8 : 16); };
+#ifndef SR_ROW_E
+#define SR_ROW_E 4
+#endif
+#ifndef SR_COL_E
+#define SR_COL_E 4
+#endif
+template <int L> struct RowE {
+    static constexpr int v = L <= 1024 ? (SR_ROW_E < L ? SR_ROW_E : L)
+                                       : (L == 2048 ? (SR_ROW_E > 8 ? SR_ROW_E : 8) : 16);
+};
 // The column pass runs two transforms per workgroup, so it can afford more
 // threads per transform (fewer registers per thread) at 4096 points.
-template <int L> struct ColE { static constexpr int v = L <= 2048 ? 4 : 8; };
+template <int L> struct ColE {
+    static constexpr int v = L <= 2048 ? (SR_COL_E < L ? SR_COL_E : L) : (SR_COL_E > 8 ? SR_COL_E : 8);
+};
 template <int L, int EE = RowE<L>::v> struct FftShape {
     static constexpr int E = EE;
     static constexpr int NT = L / E;
@@ -168,77 +179,139 @@ __device__ __forceinline__ int sk(int i) { return i + (i >> 4); }
 // transforms start on different banks.
 template <int L> struct LdsLen { static constexpr int v = L + L / 16 + 4; };
 
-// One radix-4 Stockham stage: sub-transform size Ns -> 4 Ns.
-// Butterfly j reads x[j + r L/4], twiddles by W_{4Ns}^{r k} (k = j mod Ns),
-// and writes x[(j - k) 4 + k + r Ns].  Twiddle W_{4Ns}^{m} = tw[m L/(4Ns)],
-// tw[n] = exp(-2 pi i n / L).
-template <int L, int EE, bool INV>
-__device__ __forceinline__ void fft_stage4(float2* x, const float2* __restrict__ tw, int t, int Ns) {
-    constexpr int E = FftShape<L, EE>::E, NT = FftShape<L, EE>::NT;
-    constexpr int Q = L / 4;
+// Twiddle W_L^n = exp(-2 pi i n / L) for 0 <= n < L from the quarter table
+// Q[m] = W_L^m, m < L/4 (lq = log2(L/4)): W_L^n = (-i)^(n / (L/4)) Q[n mod L/4].
+__device__ __forceinline__ float2 twq(const float2* Q, int n, int lq) {
+    const int q = n >> lq;
+    const float2 t = Q[n & ((1 << lq) - 1)];
+    // q = 1: (y, -x); q = 2: (-x, -y); q = 3: (-y, x)
+    return make_float2(q == 0 ? t.x : (q == 2 ? -t.x : (q == 1 ? t.y : -t.y)),
+                       q == 0 ? t.y : (q == 2 ? -t.y : (q == 1 ? -t.x : t.x)));
+}
+
+// Multiplication by the constant W_16^m = exp(-2 pi i m / 16) (forward) or
+// its conjugate (inverse); m = 0 and m = 4 (= -i) are exact.
+template <int m, bool INV>
+__device__ __forceinline__ float2 w16(float2 a) {
+    if constexpr (m == 0) return a;
+    else if constexpr (m == 4) return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+    else {
+        constexpr float cs[10] = {1.0f, 0.9238795325112867f, 0.7071067811865476f, 0.38268343236508984f, 6.123233995736766e-17f, -0.3826834323650897f, -0.7071067811865475f, -0.9238795325112867f, -1.0f, -0.9238795325112868f};
+        constexpr float sn[10] = {0.0f, 0.3826834323650898f, 0.7071067811865475f, 0.9238795325112867f, 1.0f, 0.9238795325112867f, 0.7071067811865476f, 0.3826834323650899f, 1.2246467991473532e-16f, -0.38268343236508967f};
+        const float2 w = make_float2(cs[m], INV ? sn[m] : -sn[m]);
+        return cmul(a, w);
+    }
+}
+
+// In-register DFTs of 2, 4, 8, 16 points (outputs in natural order).
+template <bool INV>
+__device__ __forceinline__ void dft4(float2& a0, float2& a1, float2& a2, float2& a3) {
+    const float2 s02 = cadd(a0, a2), d02 = csub(a0, a2);
+    const float2 s13 = cadd(a1, a3), d13 = csub(a1, a3);
+    const float2 id13 = make_float2(-d13.y, d13.x);
+    a0 = cadd(s02, s13);
+    a2 = csub(s02, s13);
+    if (INV) { a1 = cadd(d02, id13); a3 = csub(d02, id13); }
+    else     { a1 = csub(d02, id13); a3 = cadd(d02, id13); }
+}
+
+template <int R, bool INV>
+__device__ __forceinline__ void dft(float2 (&u)[R]) {
+    if constexpr (R == 2) {
+        const float2 a = u[0], b = u[1];
+        u[0] = cadd(a, b);
+        u[1] = csub(a, b);
+    } else if constexpr (R == 4) {
+        dft4<INV>(u[0], u[1], u[2], u[3]);
+    } else if constexpr (R == 8) {
+        // n = 2 n1 + n2, k = k1 + 4 k2: two DFT4 over n1, twiddle W_8^{n2 k1}, DFT2 over n2
+        float2 a0 = u[0], a1 = u[2], a2 = u[4], a3 = u[6];
+        float2 b0 = u[1], b1 = u[3], b2 = u[5], b3 = u[7];
+        dft4<INV>(a0, a1, a2, a3);
+        dft4<INV>(b0, b1, b2, b3);
+        b1 = w16<2, INV>(b1);
+        b2 = w16<4, INV>(b2);
+        b3 = w16<6, INV>(b3);
+        u[0] = cadd(a0, b0); u[4] = csub(a0, b0);
+        u[1] = cadd(a1, b1); u[5] = csub(a1, b1);
+        u[2] = cadd(a2, b2); u[6] = csub(a2, b2);
+        u[3] = cadd(a3, b3); u[7] = csub(a3, b3);
+    } else {
+        static_assert(R == 16, "radix");
+        // n = 4 n1 + n2, k = k1 + 4 k2: DFT4 over n1, twiddle W_16^{n2 k1}, DFT4 over n2
+        float2 A[4][4];
+#pragma unroll
+        for (int n2 = 0; n2 < 4; ++n2) {
+            A[n2][0] = u[n2]; A[n2][1] = u[4 + n2]; A[n2][2] = u[8 + n2]; A[n2][3] = u[12 + n2];
+            dft4<INV>(A[n2][0], A[n2][1], A[n2][2], A[n2][3]);
+        }
+        A[1][1] = w16<1, INV>(A[1][1]); A[1][2] = w16<2, INV>(A[1][2]); A[1][3] = w16<3, INV>(A[1][3]);
+        A[2][1] = w16<2, INV>(A[2][1]); A[2][2] = w16<4, INV>(A[2][2]); A[2][3] = w16<6, INV>(A[2][3]);
+        A[3][1] = w16<3, INV>(A[3][1]); A[3][2] = w16<6, INV>(A[3][2]); A[3][3] = w16<9, INV>(A[3][3]);
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1) {
+            float2 b0 = A[0][k1], b1 = A[1][k1], b2 = A[2][k1], b3 = A[3][k1];
+            dft4<INV>(b0, b1, b2, b3);
+            u[k1] = b0; u[k1 + 4] = b1; u[k1 + 8] = b2; u[k1 + 12] = b3;
+        }
+    }
+}
+
+// One radix-R Stockham stage: sub-transform size Ns -> R Ns.  Butterfly j
+// reads x[j + r L/R], twiddles by W_{R Ns}^{r k} (k = j mod Ns), applies the
+// R-point DFT and writes x[(j - k) R + k + r Ns].  W_{R Ns}^m = W_L^{m L/(R Ns)}
+// comes from the quarter table tw (see twq).
+template <int L, int EE, int R, int Ns, bool INV>
+__device__ __forceinline__ void fft_stage(float2* x, const float2* __restrict__ tw, int t) {
+    constexpr int E = EE, NT = L / E, NB = E / R, Q = L / R, LQ = Ilog2<L>::v - 2;
+    constexpr int stride = L / (R * Ns);
     float2 v[E];
 #pragma unroll
-    for (int b = 0; b < E / 4; ++b) {
+    for (int b = 0; b < NB; ++b) {
         const int j = t + b * NT;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) v[4 * b + r] = x[sk(j + r * Q)];
+        for (int r = 0; r < R; ++r) v[b * R + r] = x[sk(j + r * Q)];
     }
     __syncthreads();
-    const int stride = L / (4 * Ns);
 #pragma unroll
-    for (int b = 0; b < E / 4; ++b) {
+    for (int b = 0; b < NB; ++b) {
         const int j = t + b * NT;
         const int k = j & (Ns - 1);
-        float2 a0 = v[4 * b], a1 = v[4 * b + 1], a2 = v[4 * b + 2], a3 = v[4 * b + 3];
-        if (Ns > 1) {
-            const float2 w1 = tw[k * stride], w2 = tw[2 * k * stride], w3 = tw[3 * k * stride];
-            if (INV) { a1 = cmulc(a1, w1); a2 = cmulc(a2, w2); a3 = cmulc(a3, w3); }
-            else     { a1 = cmul(a1, w1);  a2 = cmul(a2, w2);  a3 = cmul(a3, w3); }
+        float2 u[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) u[r] = v[b * R + r];
+        if constexpr (Ns > 1) {
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                const float2 w = twq(tw, r * k * stride, LQ);
+                u[r] = INV ? cmulc(u[r], w) : cmul(u[r], w);
+            }
         }
-        const float2 s02 = cadd(a0, a2), d02 = csub(a0, a2);
-        const float2 s13 = cadd(a1, a3), d13 = csub(a1, a3);
-        // forward: y1 = d02 - i d13, y3 = d02 + i d13; inverse swaps them
-        const float2 id13 = make_float2(-d13.y, d13.x);
-        const int base = ((j - k) << 2) + k;
-        x[sk(base)] = cadd(s02, s13);
-        x[sk(base + 2 * Ns)] = csub(s02, s13);
-        if (INV) { x[sk(base + Ns)] = cadd(d02, id13); x[sk(base + 3 * Ns)] = csub(d02, id13); }
-        else     { x[sk(base + Ns)] = csub(d02, id13); x[sk(base + 3 * Ns)] = cadd(d02, id13); }
+        dft<R, INV>(u);
+        const int base = (j - k) * R + k;
+#pragma unroll
+        for (int r = 0; r < R; ++r) x[sk(base + r * Ns)] = u[r];
     }
     __syncthreads();
 }
 
-// In-place length-L complex FFT of x (in LDS, skewed by sk()) by the NT threads t = 0..NT-1
-// of one transform.  Every thread of the workgroup must call it (it
-// contains workgroup barriers).  INV: unnormalised inverse (conjugate twiddles).
+template <int L, int EE, bool INV, int Ns>
+__device__ __forceinline__ void fft_stages(float2* x, const float2* __restrict__ tw, int t) {
+    if constexpr (Ns < L) {
+        constexpr int R = (EE < L / Ns) ? EE : L / Ns;
+        fft_stage<L, EE, R, Ns, INV>(x, tw, t);
+        fft_stages<L, EE, INV, Ns * R>(x, tw, t);
+    }
+}
+
+// In-place length-L complex FFT of x (in LDS, skewed by sk()) by the NT = L/EE
+// threads t = 0..NT-1 of one transform: mixed-radix Stockham stages of radix
+// min(EE, remaining length).  Every thread of the workgroup must call it (it
+// contains workgroup barriers).  INV: unnormalised inverse.
 template <int L, int EE, bool INV>
 __device__ __forceinline__ void fft_lds(float2* x, const float2* __restrict__ tw, int t) {
-    constexpr int E = FftShape<L, EE>::E, NT = FftShape<L, EE>::NT, LOG = FftShape<L, EE>::LOG;
     __syncthreads();
-    int Ns = 1;
-    if constexpr (LOG & 1) {
-        float2 v[E];
-#pragma unroll
-        for (int b = 0; b < E / 2; ++b) {
-            const int j = t + b * NT;
-            v[2 * b] = x[sk(j)];
-            v[2 * b + 1] = x[sk(j + L / 2)];
-        }
-        __syncthreads();
-#pragma unroll
-        for (int b = 0; b < E / 2; ++b) {
-            const int j = t + b * NT;
-            x[sk(2 * j)] = cadd(v[2 * b], v[2 * b + 1]);
-            x[sk(2 * j + 1)] = csub(v[2 * b], v[2 * b + 1]);
-        }
-        __syncthreads();
-        Ns = 2;
-    }
-#pragma unroll
-    for (int st = 0; st < LOG / 2; ++st) {
-        fft_stage4<L, EE, INV>(x, tw, t, Ns);
-        Ns <<= 2;
-    }
+    fft_stages<L, EE, INV, 1>(x, tw, t);
 }
 
 // ---------------------------------------------------------------------------

@@ -384,32 +384,27 @@ __global__ __launch_bounds__(kTileThreads) void k_repulsion(KParams kp, int M, i
 // the column pass reads 128-byte runs (2 adjacent columns x 8 rows).
 constexpr int kSpecTile = 8;
 
-// Twiddle tables up to 2048 points are staged in LDS; 4096-point tables are
-// read from global memory (L1/L2 resident) to leave LDS for the data.
-template <int L> struct TwInLds { static constexpr bool v = L <= 2048; };
+// The quarter twiddle table W_L^m, m < L/4, is staged in LDS by every FFT
+// workgroup (at most 8 KiB); other quadrants follow from powers of -i.
+template <int L> struct TwQ { static constexpr int n = L / 4; };
 
 template <int L>
 __device__ __forceinline__ const float2* stage_twiddles(float2* tws, const float2* __restrict__ tw) {
-    if constexpr (TwInLds<L>::v) {
-        // up to 8 loads in flight per thread before the LDS stores
-        constexpr int CH = 8;
-        for (int base = threadIdx.x; base < L; base += CH * blockDim.x) {
-            float2 tv[CH];
+    constexpr int NQ = TwQ<L>::n;
+    for (int base = threadIdx.x; base < NQ; base += 4 * blockDim.x) {
+        float2 tv[4];
 #pragma unroll
-            for (int c = 0; c < CH; ++c) {
-                const int n = base + c * blockDim.x;
-                if (n < L) tv[c] = tw[n];
-            }
-#pragma unroll
-            for (int c = 0; c < CH; ++c) {
-                const int n = base + c * blockDim.x;
-                if (n < L) tws[n] = tv[c];
-            }
+        for (int c = 0; c < 4; ++c) {
+            const int n = base + c * blockDim.x;
+            if (n < NQ) tv[c] = tw[n];
         }
-        return tws;   // made visible by the barrier at the start of fft_lds
-    } else {
-        return tw;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int n = base + c * blockDim.x;
+            if (n < NQ) tws[n] = tv[c];
+        }
     }
+    return tws;   // made visible by the barrier at the start of fft_lds
 }
 
 // RT tiles (8 RT rows, 4 RT complex transforms) per workgroup.
@@ -422,7 +417,7 @@ __global__ __launch_bounds__(1024) void k_row_fwd(const float* __restrict__ src,
     src += (size_t)z * M * N;
     spec += (size_t)z * M * H;
     extern __shared__ float2 lds2[];
-    float2* xs = lds2 + (TwInLds<N>::v ? N : 0);
+    float2* xs = lds2 + TwQ<N>::n;
     const float2* tw = stage_twiddles<N>(lds2, twN);
     const int g = threadIdx.x / NT, t = threadIdx.x - g * NT;
     const int row0 = blockIdx.x * (kSpecTile * RT);
@@ -474,7 +469,7 @@ __global__ __launch_bounds__(1024) void k_col_solve(float2* __restrict__ spec, c
     const int H = N / 2;
     spec += (size_t)z * M * H;
     extern __shared__ float2 lds2[];
-    float2* xs = lds2 + (TwInLds<M>::v ? M : 0);
+    float2* xs = lds2 + TwQ<M>::n;
     const float2* tw = stage_twiddles<M>(lds2, twM);
     const int k0 = blockIdx.x * G;
     const int run = kSpecTile * G;                 // contiguous float2 per row tile (2^lrun)
@@ -504,7 +499,7 @@ __global__ __launch_bounds__(1024) void k_col_solve(float2* __restrict__ spec, c
     const float cn = 2.0f * twN[col].x;
     auto scale_pair = [&](int l) {
         const int m = (M - l) & (M - 1);
-        const float cm = 2.0f * tw[l].x;
+        const float cm = 2.0f * twq(tw, l, Ilog2<M>::v - 2).x;
         float hp, hm;
         if (col != 0) {
             hp = inv_mn / (1.0f + taumu * (4.0f - cm - cn));
@@ -559,7 +554,7 @@ __global__ __launch_bounds__(1024) void k_row_inv(const float2* __restrict__ spe
     extern __shared__ float2 lds2[];
     __shared__ double red[2 * 16];
     constexpr int LX = LdsLen<N>::v;
-    float2* xs = lds2 + (TwInLds<N>::v ? N : 0);
+    float2* xs = lds2 + TwQ<N>::n;
     const float2* tw = stage_twiddles<N>(lds2, twN);
     const int nthr = blockDim.x;
     const float2* srcb = spec + (size_t)row0 * H;
@@ -978,8 +973,18 @@ int tile_blocks(int M, int N) { return ((N + kTileW - 1) / kTileW) * ((M + 7) / 
 // Row-tile count per workgroup of the row passes: enough rows for at least
 // one full wave (each 8-row tile is 4 transforms of NT threads).
 static int fft_nt_rt(int L, bool col) {
-    const int E = col ? (L <= 2048 ? 4 : 8) : (L <= 1024 ? 4 : (L == 2048 ? 8 : 16));
-    return L / E;
+    switch (L) {
+        case 8: return col ? FftShape<8, ColE<8>::v>::NT : FftShape<8>::NT;
+        case 16: return col ? FftShape<16, ColE<16>::v>::NT : FftShape<16>::NT;
+        case 32: return col ? FftShape<32, ColE<32>::v>::NT : FftShape<32>::NT;
+        case 64: return col ? FftShape<64, ColE<64>::v>::NT : FftShape<64>::NT;
+        case 128: return col ? FftShape<128, ColE<128>::v>::NT : FftShape<128>::NT;
+        case 256: return col ? FftShape<256, ColE<256>::v>::NT : FftShape<256>::NT;
+        case 512: return col ? FftShape<512, ColE<512>::v>::NT : FftShape<512>::NT;
+        case 1024: return col ? FftShape<1024, ColE<1024>::v>::NT : FftShape<1024>::NT;
+        case 2048: return col ? FftShape<2048, ColE<2048>::v>::NT : FftShape<2048>::NT;
+        default: return col ? FftShape<4096, ColE<4096>::v>::NT : FftShape<4096>::NT;
+    }
 }
 int fft_row_tiles(int M, int N) {
     const int NT = fft_nt_rt(N, false);
@@ -997,7 +1002,7 @@ int fft_col_group(int M, int N) {
     return G;
 }
 
-template <int L> constexpr size_t tw_lds_bytes() { return TwInLds<L>::v ? sizeof(float2) * L : 0; }
+template <int L> constexpr size_t tw_lds_bytes() { return sizeof(float2) * TwQ<L>::n; }
 
 #define SR_FFT_DISPATCH(FN, LEN, ...)                                   \
     switch (LEN) {                                                      \

@@ -17,7 +17,7 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libsr.so")
+LIB_PATH = os.environ.get("SR_LIB") or os.path.join(_HERE, "libsr.so")
 
 SR_OK = 0
 SR_NOT_CONVERGED = 1
