@@ -123,24 +123,46 @@ def upsample_backward(dy):
 
 
 # --------------------------------------------------------------------------
+# storage precision
+# --------------------------------------------------------------------------
+def bf16(x):
+    """Round to bfloat16 (8 significant bits, float32 exponent range) to
+    nearest, ties to even, via float32; returned as float64."""
+    u = np.asarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16 << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _ident(x):
+    return x
+
+
+# --------------------------------------------------------------------------
 # network
 # --------------------------------------------------------------------------
-def forward(params, x):
-    """x: (N, H, W, 3) -> (prediction (N, H, W), cache of activations)."""
+def forward(params, x, q=None):
+    """x: (N, H, W, 3) -> (prediction (N, H, W), cache of activations).
+
+    q is the storage rounding of the network's tensors (None: exact FP64;
+    bf16: the network as specified, with BF16 input, 3x3 weights and stored
+    activations, every sum taken exactly).  The head weights and all biases
+    stay unrounded."""
+    q = q or _ident
     w, b = params["w"], params["b"]
     a = {}
 
     def cr(name, inp):
         a[name + ".in"] = inp
-        z = conv3x3(inp, w[name], b[name])
-        out = relu(z)
+        z = conv3x3(inp, q(w[name]), b[name])
+        out = q(relu(z))
         a[name] = out
         return out
 
+    x = q(x)
     s0 = cr("L0b", cr("L0a", x))
-    s1 = cr("L1b", cr("L1a", pool(s0)))
-    s2 = cr("L2b", cr("L2a", pool(s1)))
-    bott = cr("L3b", cr("L3a", pool(s2)))
+    s1 = cr("L1b", cr("L1a", q(pool(s0))))
+    s2 = cr("L2b", cr("L2a", q(pool(s1))))
+    bott = cr("L3b", cr("L3a", q(pool(s2))))
     d2 = cr("D2", np.concatenate([cr("U2", upsample(bott)), s2], axis=3))
     d1 = cr("D1", np.concatenate([cr("U1", upsample(d2)), s1], axis=3))
     d0 = cr("D0", np.concatenate([cr("U0", upsample(d1)), s0], axis=3))
@@ -149,11 +171,13 @@ def forward(params, x):
     return y[..., 0], a
 
 
-def loss_and_grad(params, x, target):
+def loss_and_grad(params, x, target, q=None):
     """Mean squared error of the prediction against `target` (N, H, W) and its
-    gradient w.r.t. every parameter (same dict layout)."""
+    gradient w.r.t. every parameter (same dict layout).  With q, the masked
+    output gradient of every 3x3 layer is stored rounded by q as well."""
+    qq = q or _ident
     w, b = params["w"], params["b"]
-    y, a = forward(params, x)
+    y, a = forward(params, x, q)
     n = y.size
     diff = y - target
     loss = float(np.mean(diff * diff))
@@ -164,8 +188,8 @@ def loss_and_grad(params, x, target):
     dd0 = np.einsum("nijo,oc->nijc", dy, w["head"])
 
     def back(name, dout):
-        dz = dout * (a[name] > 0)
-        dx, gw[name], gb[name] = conv3x3_backward(a[name + ".in"], w[name], dz)
+        dz = qq(dout * (a[name] > 0))
+        dx, gw[name], gb[name] = conv3x3_backward(a[name + ".in"], qq(w[name]), dz)
         return dx
 
     # decoder, level 0 -> 2
@@ -192,3 +216,13 @@ def loss_and_grad(params, x, target):
 def make_input(f, g, phi0, clip):
     """Network input channels (image, edge map, clipped / scaled phi^0)."""
     return np.stack([f, g, np.clip(phi0, -clip, clip) / clip], axis=-1)
+
+
+def adam_step(p, m, v, g, t, lr, beta1, beta2, eps):
+    """One Adam update (Kingma and Ba, 2015) with bias-corrected moments, on
+    flat FP64 vectors; returns (p, m, v) after step number t (t >= 1)."""
+    m = beta1 * m + (1.0 - beta1) * g
+    v = beta2 * v + (1.0 - beta2) * g * g
+    mh = m / (1.0 - beta1 ** t)
+    vh = v / (1.0 - beta2 ** t)
+    return p - lr * mh / (np.sqrt(vh) + eps), m, v

@@ -69,3 +69,46 @@ def test_parameter_count():
     n = sum(int(np.prod(ws)) + int(np.prod(bs)) for _, ws, bs in C.param_shapes())
     assert n == len(C.flatten(C.init_params(0)))
     assert 400_000 < n < 700_000
+
+
+def test_adam_first_step_is_signed_learning_rate():
+    # from zero moments the bias-corrected first step is lr*g/(|g|+eps)
+    rng = np.random.default_rng(3)
+    g = rng.normal(size=50)
+    p0 = rng.normal(size=50)
+    p1, m, v = C.adam_step(p0, np.zeros(50), np.zeros(50), g, 1, 1e-3, 0.9, 0.999, 1e-8)
+    np.testing.assert_allclose(p0 - p1, 1e-3 * g / (np.abs(g) + 1e-8), rtol=1e-12)
+    np.testing.assert_allclose(m, 0.1 * g)
+    np.testing.assert_allclose(v, 0.001 * g * g)
+
+
+def test_adam_constant_gradient_keeps_unit_steps():
+    # a constant gradient keeps the corrected ratio m_hat/sqrt(v_hat) at sign(g)
+    g = np.array([2.0, -0.5, 1e-3])
+    p, m, v = np.zeros(3), np.zeros(3), np.zeros(3)
+    for t in range(1, 30):
+        q, m, v = C.adam_step(p, m, v, g, t, 0.01, 0.9, 0.999, 0.0)
+        np.testing.assert_allclose(p - q, 0.01 * np.sign(g), rtol=1e-10)
+        p = q
+
+
+def test_bf16_rounding_matches_torch():
+    import torch
+    rng = np.random.default_rng(11)
+    x = np.concatenate([rng.normal(size=4000) * 10.0 ** rng.integers(-30, 30, size=4000),
+                        1.0 + np.arange(64) * 2.0 ** -9,          # halfway cases
+                        [0.0, -0.0, 1e-40, -3.0e38, 65504.0]])
+    want = torch.tensor(x, dtype=torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
+    np.testing.assert_array_equal(C.bf16(x), want)
+
+
+def test_bf16_network_close_to_exact_network():
+    # storage rounding perturbs the prediction at the level of the bf16 unit
+    # roundoff (2^-9) times the depth, not more
+    rng = np.random.default_rng(5)
+    params = C.init_params(2)
+    x = rng.normal(size=(1, 16, 16, 3))
+    y, _ = C.forward(params, x)
+    yq, _ = C.forward(params, x, C.bf16)
+    rel = np.linalg.norm(yq - y) / np.linalg.norm(y)
+    assert 1e-4 < rel < 15 * 2.0 ** -9

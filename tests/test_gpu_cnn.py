@@ -1,0 +1,366 @@
+"""GPU parity of the warm-start network (forward, loss, backward, Adam)
+through the cnn_* C ABI against the FP64 reference network.
+
+The tight checks are teacher-forced, layer by layer: each stored tensor of
+the library (BF16 activations, BF16 masked output gradients) against the
+reference layer applied to the library's own stored inputs, and each weight
+gradient against the exact sum over the library's own operands.  A stored
+tensor then equals the reference's except where the FP32 accumulation error
+(<= 2^-14 of the sum of |terms| for <= 1152 terms, the FP32 bound)
+moves a value across a bf16 rounding boundary: one rounding step, on a
+small fraction of elements.
+
+End to end, the network is compared with the reference at BF16 storage and
+with the exact FP64 network.  Rounding to the bf16 grid turns a perturbation
+d below one rounding step u into one of size about sqrt(d*u), so end to end
+the two BF16 computations agree only to the scale of the storage rounding
+itself (unit roundoff 2^-9 per stored tensor, about 15 in a row); those bars
+are set at that scale.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import cnn_reference as R
+from tests.helpers import f32, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+CLIP = 8.0
+FWD_TOL = 15 * 2.0 ** -9       # prediction, end to end (bf16-storage and exact references)
+GRAD_TOL = 0.1                 # per-layer gradient, end to end
+ACC_REL = 2.0 ** -14           # FP32 accumulation error bound relative to sum|terms|
+FLIP_FRAC = 2e-3               # largest fraction of bf16 values one rounding step apart
+
+
+def _note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def cnn():
+    from paper_2003_12693_amd import cnn as cnnmod
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    cnnmod.load()
+    return cnnmod
+
+
+def _params(seed):
+    """He-normal weights and small random biases (every bias path is used),
+    rounded to float32 as the library stores them."""
+    p = R.init_params(seed)
+    rng = np.random.default_rng(seed + 100)
+    for name in p["b"]:
+        p["b"][name] = rng.normal(0.0, 0.05, size=p["b"][name].shape)
+    return R.unflatten(f32(R.flatten(p)).astype(np.float64))
+
+
+def _inputs(n, H, W, seed):
+    rng = np.random.default_rng(seed)
+    f = f32(rng.uniform(0.0, 1.0, (n, H, W)))
+    g = f32(rng.uniform(0.05, 1.0, (n, H, W)))
+    phi0 = f32(rng.normal(0.0, 6.0, (n, H, W)))       # partly beyond the clip
+    target = f32(rng.normal(0.0, 6.0, (n, H, W)))
+    return f, g, phi0, target
+
+
+def _cuda(x):
+    return torch.from_numpy(f32(x)).cuda()
+
+
+def _np(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def _x(f, g, phi0):
+    return R.make_input(f.astype(np.float64), g.astype(np.float64), phi0.astype(np.float64), CLIP)
+
+
+CASES = [(2, 64, 96), (1, 32, 32), (3, 32, 64)]
+
+
+@pytest.mark.parametrize("n,H,W", CASES)
+def test_forward_matches_reference(cnn, n, H, W):
+    _note(f"cnn forward n={n} {H}x{W}")
+    params = _params(1)
+    f, g, phi0, _ = _inputs(n, H, W, 2)
+    net = cnn.Network(n, H, W, R.flatten(params))
+    out = _np(net.forward(_cuda(f), _cuda(g), _cuda(phi0), CLIP)) / CLIP
+    x = _x(f, g, phi0)
+    yq, _ = R.forward(params, x, R.bf16)
+    y, _ = R.forward(params, x)
+    e_q, e = rel_l2(out, yq), rel_l2(out, y)
+    border = np.zeros((H, W), bool)
+    border[[0, -1], :] = border[:, [0, -1]] = True
+    e_border = rel_l2(out[:, border], yq[:, border])
+    _note(f"  rel L2 vs bf16-storage ref {e_q:.2e} (border {e_border:.2e}), vs exact {e:.2e}")
+    assert e_q <= FWD_TOL and e_border <= FWD_TOL
+    assert e <= FWD_TOL
+
+
+def _ulp_compare(got, ref, name):
+    """got: the library's bf16 tensor; ref = (bf16 result, exact pre-activation
+    z, sum of |terms|).  Equal, except where the FP32 accumulation error
+    (bounded by ACC_REL * sum|terms|) moves z across a bf16 rounding boundary
+    or across zero; then the values differ by one rounding step of z."""
+    want, z, za = ref
+    d = np.abs(got - want)
+    allowed = 2.0 ** -7 * np.maximum(np.abs(got), np.abs(want)) + ACC_REL * za
+    bad = d > allowed
+    frac = float(np.mean(got != want))
+    if bad.any() or frac > FLIP_FRAC:
+        idx = np.argsort((d - allowed).ravel())[-3:]
+        for i in idx:
+            _note(f"  {name}: got {got.ravel()[i]:.6e} want {want.ravel()[i]:.6e} z {z.ravel()[i]:.6e} "
+                  f"sum|terms| {za.ravel()[i]:.3e}")
+    assert not bad.any(), (name, int(bad.sum()), float(d.max()))
+    assert frac <= FLIP_FRAC, (name, frac)
+    return frac
+
+
+@pytest.mark.parametrize("n,H,W", CASES[:2])
+def test_forward_layers_teacher_forced(cnn, n, H, W):
+    """Each stored tensor against the reference layer applied to the
+    library's own stored input tensors (bf16 values, so the reference sees
+    exactly what the kernel saw)."""
+    _note(f"cnn layers n={n} {H}x{W}")
+    params = _params(12)
+    f, g, phi0, _ = _inputs(n, H, W, 13)
+    net = cnn.Network(n, H, W, R.flatten(params))
+    net.forward(_cuda(f), _cuda(g), _cuda(phi0), CLIP, want_output=False)
+    A = {k: _np(net.activation(k, n)) for k in range(19)}
+    np.testing.assert_array_equal(A[14][..., :3], R.bf16(_x(f, g, phi0)))
+    assert not A[14][..., 3].any()
+    w, b = params["w"], params["b"]
+    names = [l[0] for l in R.LAYERS]
+
+    def layer(name, inp):
+        z = R.conv3x3(inp, R.bf16(w[name]), b[name])
+        za = R.conv3x3(np.abs(inp), np.abs(R.bf16(w[name])), np.abs(b[name]))
+        return R.bf16(R.relu(z)), z, za
+
+    def pooled(x):
+        p = R.pool(x)
+        return R.bf16(p), p, R.pool(np.abs(x))
+
+    fr = {}
+    fr["L0a"] = _ulp_compare(A[0], layer("L0a", A[14][..., :3]), "L0a")
+    fr["L0b"] = _ulp_compare(A[1], layer("L0b", A[0]), "L0b")
+    _ulp_compare(A[16], pooled(A[1]), "pool0")
+    fr["L1a"] = _ulp_compare(A[2], layer("L1a", A[16]), "L1a")
+    fr["L1b"] = _ulp_compare(A[3], layer("L1b", A[2]), "L1b")
+    _ulp_compare(A[17], pooled(A[3]), "pool1")
+    fr["L2a"] = _ulp_compare(A[4], layer("L2a", A[17]), "L2a")
+    fr["L2b"] = _ulp_compare(A[5], layer("L2b", A[4]), "L2b")
+    _ulp_compare(A[18], pooled(A[5]), "pool2")
+    fr["L3a"] = _ulp_compare(A[6], layer("L3a", A[18]), "L3a")
+    fr["L3b"] = _ulp_compare(A[7], layer("L3b", A[6]), "L3b")
+    fr["U2"] = _ulp_compare(A[8], layer("U2", R.upsample(A[7])), "U2")
+    fr["D2"] = _ulp_compare(A[9], layer("D2", np.concatenate([A[8], A[5]], axis=3)), "D2")
+    fr["U1"] = _ulp_compare(A[10], layer("U1", R.upsample(A[9])), "U1")
+    fr["D1"] = _ulp_compare(A[11], layer("D1", np.concatenate([A[10], A[3]], axis=3)), "D1")
+    fr["U0"] = _ulp_compare(A[12], layer("U0", R.upsample(A[11])), "U0")
+    fr["D0"] = _ulp_compare(A[13], layer("D0", np.concatenate([A[12], A[1]], axis=3)), "D0")
+    head = np.einsum("nijc,oc->nijo", A[13], w["head"]) + b["head"]
+    assert rel_l2(A[15], head) <= 1e-6
+    assert sorted(fr) == sorted(names)
+    _note("  bf16 rounding flips per layer: " + " ".join(f"{k}:{v:.1e}" for k, v in fr.items()))
+
+
+@pytest.mark.parametrize("n,H,W", CASES[:2])
+def test_backward_matches_reference(cnn, n, H, W):
+    _note(f"cnn backward n={n} {H}x{W}")
+    params = _params(3)
+    f, g, phi0, target = _inputs(n, H, W, 4)
+    net = cnn.Network(n, H, W, R.flatten(params))
+    net.forward(_cuda(f), _cuda(g), _cuda(phi0), CLIP, want_output=False)
+    loss, grad = net.backward(_cuda(target), CLIP, want_grad=True)
+    grad = _np(grad)
+    t = np.clip(target.astype(np.float64), -CLIP, CLIP) / CLIP
+    lq, gq = R.loss_and_grad(params, _x(f, g, phi0), t, R.bf16)
+    assert abs(loss - lq) <= 1e-3 * lq
+    ref = R.flatten(gq)
+    o = 0
+    worst = 0.0
+    for name, ws, bs in R.param_shapes():
+        for part, shape in (("w", ws), ("b", bs)):
+            k = int(np.prod(shape))
+            e = rel_l2(grad[o:o + k], ref[o:o + k])
+            worst = max(worst, e)
+            assert e <= GRAD_TOL, (name, part, e)
+            o += k
+    _, g64 = R.loss_and_grad(params, _x(f, g, phi0), t)
+    e64 = rel_l2(grad, R.flatten(g64))
+    _note(f"  loss {loss:.6f} (ref {lq:.6f}); worst per-layer gradient rel L2 {worst:.2e}; "
+          f"whole gradient vs exact network {e64:.2e}")
+    assert e64 <= GRAD_TOL
+
+
+@pytest.mark.parametrize("n,H,W", CASES)
+def test_backward_layers_teacher_forced(cnn, n, H, W):
+    """Masked output gradients, weight and bias gradients of every layer from
+    the library's own stored activations and downstream gradients."""
+    _note(f"cnn backward layers n={n} {H}x{W}")
+    params = _params(14)
+    f, g, phi0, target = _inputs(n, H, W, 15)
+    net = cnn.Network(n, H, W, R.flatten(params))
+    net.forward(_cuda(f), _cuda(g), _cuda(phi0), CLIP, want_output=False)
+    loss, grad = net.backward(_cuda(target), CLIP, want_grad=True)
+    grad = _np(grad)
+    A = {k: _np(net.activation(k, n)) for k in range(19)}
+    names = [l[0] for l in R.LAYERS]
+    DZ = {name: _np(net.activation(19 + i, n)) for i, name in enumerate(names)}
+    w = {k: R.bf16(v) for k, v in params["w"].items()}
+    t = np.clip(target.astype(np.float64), -CLIP, CLIP) / CLIP
+    P = n * H * W
+    y = A[15][..., 0]
+    assert abs(loss - np.mean((y - t) ** 2)) <= 1e-5 * loss
+
+    # head and the last layer's masked gradient
+    dy = (2.0 / P) * (y - t)
+    dd0 = dy[..., None] * params["w"]["head"][0]
+    flips = {"D0": _ulp_compare(DZ["D0"], (R.bf16(dd0 * (A[13] > 0)), dd0, np.abs(dd0)), "dz D0")}
+    off = {}
+    o = 0
+    for name, ws, bs in R.param_shapes():
+        off[name] = (o, o + int(np.prod(ws)), o + int(np.prod(ws)) + int(np.prod(bs)))
+        o = off[name][2]
+    hw = np.einsum("nijc,nij->c", A[13], dy)
+    hb = dy.sum()
+    a0, a1, a2 = off["head"]
+    habs = np.einsum("nijc,nij->c", np.abs(A[13]), np.abs(dy))
+    assert np.all(np.abs(grad[a0:a1] - hw) <= ACC_REL * habs + 1e-12)
+    assert abs(grad[a1] - hb) <= ACC_REL * np.abs(dy).sum() + 1e-12
+
+    inputs = {
+        "D0": np.concatenate([A[12], A[1]], axis=3), "U0": R.upsample(A[11]),
+        "D1": np.concatenate([A[10], A[3]], axis=3), "U1": R.upsample(A[9]),
+        "D2": np.concatenate([A[8], A[5]], axis=3), "U2": R.upsample(A[7]),
+        "L3b": A[6], "L3a": A[18], "L2b": A[4], "L2a": A[17], "L1b": A[2], "L1a": A[16],
+        "L0b": A[0], "L0a": A[14][..., :3],
+    }
+    outputs = {"D0": A[13], "U0": A[12], "D1": A[11], "U1": A[10], "D2": A[9], "U2": A[8], "L3b": A[7],
+               "L3a": A[6], "L2b": A[5], "L2a": A[4], "L1b": A[3], "L1a": A[2], "L0b": A[1], "L0a": A[0]}
+    dx, dxa = {}, {}
+
+    def grads_of(name):
+        """weight / bias gradient check, then the input gradient (exact, FP64)."""
+        x, dz = inputs[name], DZ[name]
+        gx, gw_, gb_ = R.conv3x3_backward(x, w[name], dz)
+        ax, aw, ab = R.conv3x3_backward(np.abs(x), np.abs(w[name]), np.abs(dz))
+        a0, a1, a2 = off[name]
+        gw_got = grad[a0:a1].reshape(gw_.shape)
+        assert np.all(np.abs(gw_got - gw_) <= ACC_REL * aw + 1e-12), (name, float(np.abs(gw_got - gw_).max()))
+        assert np.all(np.abs(grad[a1:a2] - gb_) <= ACC_REL * ab + 1e-12), name
+        dx[name], dxa[name] = gx, ax
+
+    def check_mask(name, up_src=None, cat=None, pooled=None):
+        """dz of `name` from the downstream gradients: a slice of a concat
+        gradient, or the 2x2 sum of an upsampled input's gradient, plus the
+        pooled path's gradient."""
+        if up_src is not None:
+            g_, ga = R.upsample_backward(dx[up_src]), R.upsample_backward(dxa[up_src])
+        else:
+            src, sl = cat
+            g_, ga = dx[src][..., sl], dxa[src][..., sl]
+        if pooled is not None:
+            g_ = g_ + R.pool_backward(dx[pooled])
+            ga = ga + R.pool_backward(dxa[pooled])
+        want = R.bf16(g_ * (outputs[name] > 0))
+        flips[name] = _ulp_compare(DZ[name], (want, g_, ga), "dz " + name)
+
+    grads_of("D0")
+    check_mask("U0", cat=("D0", slice(0, 16)))
+    grads_of("U0")
+    check_mask("D1", up_src="U0")
+    grads_of("D1")
+    check_mask("U1", cat=("D1", slice(0, 32)))
+    grads_of("U1")
+    check_mask("D2", up_src="U1")
+    grads_of("D2")
+    check_mask("U2", cat=("D2", slice(0, 64)))
+    grads_of("U2")
+    check_mask("L3b", up_src="U2")
+    grads_of("L3b")
+    check_mask("L3a", cat=("L3b", slice(None)))
+    grads_of("L3a")
+    check_mask("L2b", cat=("D2", slice(64, 128)), pooled="L3a")
+    grads_of("L2b")
+    check_mask("L2a", cat=("L2b", slice(None)))
+    grads_of("L2a")
+    check_mask("L1b", cat=("D1", slice(32, 64)), pooled="L2a")
+    grads_of("L1b")
+    check_mask("L1a", cat=("L1b", slice(None)))
+    grads_of("L1a")
+    check_mask("L0b", cat=("D0", slice(16, 32)), pooled="L1a")
+    grads_of("L0b")
+    check_mask("L0a", cat=("L0b", slice(None)))
+    grads_of("L0a")
+    assert sorted(flips) == sorted(names)
+    _note("  dz rounding flips per layer: " + " ".join(f"{k}:{v:.1e}" for k, v in flips.items()))
+
+
+def test_adam_matches_reference(cnn):
+    _note("cnn adam")
+    n, H, W = 1, 32, 32
+    params = _params(5)
+    f, g, phi0, target = _inputs(n, H, W, 6)
+    net = cnn.Network(n, H, W, R.flatten(params))
+    p = R.flatten(params)
+    m = np.zeros_like(p)
+    v = np.zeros_like(p)
+    for step in (1, 2, 3):
+        net.forward(_cuda(f), _cuda(g), _cuda(phi0), CLIP, want_output=False)
+        _, grad = net.backward(_cuda(target), CLIP, want_grad=True)
+        net.adam_step(lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8)
+        p, m, v = R.adam_step(p, m, v, _np(grad), step, 1e-3, 0.9, 0.999, 1e-8)
+        got = _np(net.get_params())
+        np.testing.assert_allclose(got, p, rtol=2e-6, atol=2e-8)
+        p = got  # continue from the library's float32 parameters
+
+
+def test_training_reduces_loss_and_is_deterministic(cnn):
+    _note("cnn training")
+    n, H, W = 2, 64, 64
+    f, g, phi0, _ = _inputs(n, H, W, 8)
+    target = np.clip(phi0, -CLIP, CLIP) * 0.5          # a map the network can learn from phi0
+    net = cnn.Network(n, H, W, R.flatten(_params(9)))
+    tf, tg, tp, tt = _cuda(f), _cuda(g), _cuda(phi0), _cuda(target)
+    a = _np(net.forward(tf, tg, tp, CLIP))
+    b = _np(net.forward(tf, tg, tp, CLIP))
+    assert np.array_equal(a, b)
+    _, g1 = net.backward(tt, CLIP, want_grad=True)
+    net.forward(tf, tg, tp, CLIP, want_output=False)
+    _, g2 = net.backward(tt, CLIP, want_grad=True)
+    assert torch.equal(g1, g2)
+    losses = []
+    for _ in range(40):
+        net.forward(tf, tg, tp, CLIP, want_output=False)
+        losses.append(net.backward(tt, CLIP)[0])
+        net.adam_step(lr=2e-3)
+    _note(f"  loss {losses[0]:.4f} -> {losses[-1]:.4f}")
+    assert np.all(np.isfinite(losses))
+    assert losses[-1] < 0.3 * losses[0]
+
+
+def test_partial_batch_and_errors(cnn):
+    _note("cnn partial batch / errors")
+    params = _params(10)
+    f, g, phi0, target = _inputs(3, 32, 32, 11)
+    net = cnn.Network(3, 32, 32, R.flatten(params))
+    from paper_2003_12693_amd.sr import SRError
+    with pytest.raises(SRError) as e:
+        cnn.cnn_backward(net.ctx, _cuda(target), CLIP)           # before any forward
+    assert e.value.code == -6
+    full = _np(net.forward(_cuda(f), _cuda(g), _cuda(phi0), CLIP))
+    one = _np(net.forward(_cuda(f[1:2]), _cuda(g[1:2]), _cuda(phi0[1:2]), CLIP))
+    np.testing.assert_array_equal(one[0], full[1])                # images are independent
+    four = np.concatenate([f, f[:1]])
+    with pytest.raises(SRError) as e:
+        net.forward(_cuda(four), _cuda(np.concatenate([g, g[:1]])), _cuda(np.concatenate([phi0, phi0[:1]])), CLIP)
+    assert e.value.code == -1
