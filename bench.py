@@ -147,6 +147,121 @@ def batch_bench(count, cap, tol):
     }
 
 
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+
+
+def cnn_bench(batch, H, steps, warmup, train_batch, cpu):
+    """Warm-start network throughput on H x H inputs: inference (forward on
+    `batch` images) and training (forward + backward + Adam on `train_batch`
+    images), with inputs resident in HBM; MFMA utilisation against the dense
+    BF16 peak."""
+    import torch
+    from paper_2003_12693_amd import cnn
+    rng = np.random.default_rng(0)
+
+    def inputs(n):
+        f = torch.from_numpy(rng.uniform(0, 1, (n, H, H)).astype(np.float32)).cuda()
+        g = torch.from_numpy(rng.uniform(0.05, 1, (n, H, H)).astype(np.float32)).cuda()
+        p = torch.from_numpy(rng.normal(0, 6, (n, H, H)).astype(np.float32)).cuda()
+        return f, g, p
+
+    params = cnn.he_init(1)
+    res = {}
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    # inference
+    net = cnn.Network(batch, H, H, params)
+    f, g, p = inputs(batch)
+    out = torch.empty_like(f)
+    for _ in range(warmup):
+        cnn.cnn_forward(net.ctx, f, g, p, batch, 8.0, out)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(steps):
+        cnn.cnn_forward(net.ctx, f, g, p, batch, 8.0, out)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_fwd = e0.elapsed_time(e1) / steps
+    fl_fwd, _ = cnn.flops(batch, H, H)
+    net.close()
+    del net
+    # training
+    net = cnn.Network(train_batch, H, H, params)
+    f, g, p = inputs(train_batch)
+    t = torch.from_numpy(rng.normal(0, 6, (train_batch, H, H)).astype(np.float32)).cuda()
+    for _ in range(warmup):
+        cnn.cnn_forward(net.ctx, f, g, p, train_batch, 8.0)
+        cnn.cnn_backward(net.ctx, t, 8.0, want_loss=False)
+        cnn.cnn_adam_step(net.ctx, 1e-4)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(steps):
+        cnn.cnn_forward(net.ctx, f, g, p, train_batch, 8.0)
+        cnn.cnn_backward(net.ctx, t, 8.0, want_loss=False)
+        cnn.cnn_adam_step(net.ctx, 1e-4)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_train = e0.elapsed_time(e1) / steps
+    _, fl_train = cnn.flops(train_batch, H, H)
+    net.close()
+    tf_fwd = fl_fwd / (ms_fwd * 1e-3) / 1e12
+    tf_train = fl_train / (ms_train * 1e-3) / 1e12
+    out = {
+        "metric": f"CNN warm-start inference images/s at {H}^2",
+        "value": round(batch / (ms_fwd * 1e-3), 2), "unit": "images/s", "higher_is_better": True,
+        "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": round(ms_fwd, 4),
+        "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": f"warm-start encoder-decoder (3x3 convs 16-32-64-128, BF16 storage, FP32 "
+                               f"accumulate) on {batch} x 3 x {H}x{H} inputs",
+                   "gflop_per_image_forward": round(fl_fwd / batch / 1e9, 3),
+                   "gflop_per_image_train_step": round(fl_train / train_batch / 1e9, 3)},
+        "roofline": {"bound": "mfma", "kernel": "whole forward pass", "achieved": round(tf_fwd, 2),
+                     "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(tf_fwd / MFMA_BF16_PEAK_TFLOPS, 4), "traffic": None},
+        "training": {"batch": train_batch, "ms_per_step": round(ms_train, 3),
+                     "images_per_s": round(train_batch / (ms_train * 1e-3), 2),
+                     "tflops": round(tf_train, 2), "frac": round(tf_train / MFMA_BF16_PEAK_TFLOPS, 4)},
+    }
+    if cpu:
+        from oracle import cnn_reference as R
+        from paper_2003_12693_amd.cnn import he_init
+        pr = R.unflatten(he_init(1).astype(np.float64))
+        hs = 256
+        x = rng.normal(size=(1, hs, hs, 3))
+        t0 = time.perf_counter()
+        R.forward(pr, x)
+        dt = time.perf_counter() - t0
+        fl, _ = cnn.flops(1, hs, hs)
+        out["cpu_baseline"] = {"value": round(fl / dt / (fl_fwd / batch), 4), "unit": "images/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"FP64 NumPy reference forward of one {hs}x{hs} image ({dt:.1f} s), "
+                                         f"scaled to {H}x{H} by the FLOP count"}
+    return out
+
+
+def warmstart_bench(n):
+    """Time-to-solve on n held-out 512^2 instances: the plain solver's
+    fixed-budget solve against the committed warm-start network's start
+    refined by Split Bregman to the same energy (inference, refinement and
+    fallbacks included)."""
+    from paper_2003_12693_amd import warmstart as W
+    params = np.load(W.WEIGHTS)
+    W.evaluate(params, [W.EVAL_SEED0 + 999], k_plain=200, log=lambda m: None)     # warm-up
+    summary, rows = W.evaluate(params, list(range(W.EVAL_SEED0, W.EVAL_SEED0 + n)), log=lambda m: None)
+    return {
+        "metric": f"time-to-solve at {W.SIZE}^2, plain ({W.K_PLAIN} iterations) vs CNN warm start",
+        "value": round(summary["mean_s_warm_incl_inference_and_fallback"], 5), "unit": "s",
+        "higher_is_better": False, "plain_s": round(summary["mean_s_plain"], 5),
+        "speedup_vs_plain": round(summary["mean_s_plain"] / summary["mean_s_warm_incl_inference_and_fallback"], 2),
+        "iters_saved_frac": round(summary["iters_saved_frac"], 4), "accepted": summary["accepted"],
+        "instances": summary["instances"], "fallback_rate": summary["fallback_rate"],
+        "within_window": summary["within_window"], "max_abs_rel_dE_accepted": summary["max_abs_rel_dE_accepted"],
+        "n_gpus": 1, "dtype": "f32 solver, bf16 network", "data": "synthetic",
+        "config": {"workload": f"{n} held-out 512^2 ellipse images (3 ellipses, semi-axes 15-60 px, noise 0.15, "
+                               f"bias 0.2), rectangle phi0, paper two-circles weights, R=3, eps=1.5"},
+    }
+
+
 def copy_probe(mib):
     import torch
     n = mib * (1 << 20) // 4
@@ -170,6 +285,12 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB")
     ap.add_argument("--batch", type=int, default=0, metavar="COUNT",
                     help="time-to-converge of COUNT uneven instances, batched vs plain")
+    ap.add_argument("--cnn", type=int, default=0, metavar="BATCH",
+                    help="warm-start network throughput: inference on BATCH images, training on --train-batch")
+    ap.add_argument("--train-batch", type=int, default=16)
+    ap.add_argument("--warmstart", type=int, default=0, metavar="N",
+                    help="time-to-solve of N held-out instances, plain vs CNN warm start")
+    ap.add_argument("--cnn-size", type=int, default=512)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the solver runs on a single "
@@ -180,6 +301,14 @@ def main():
         return
     if args.batch:
         print(json.dumps(batch_bench(args.batch, 500, 1e-4)), flush=True)
+        return
+    if args.warmstart:
+        print(json.dumps(warmstart_bench(args.warmstart)), flush=True)
+        return
+    if args.cnn:
+        steps = args.steps if args.steps is not None else 20
+        print(json.dumps(cnn_bench(args.cnn, args.cnn_size, steps, min(args.warmup, 5), args.train_batch,
+                                   not args.no_cpu_baseline)), flush=True)
         return
 
     import torch

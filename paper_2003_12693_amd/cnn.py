@@ -117,6 +117,41 @@ def cnn_destroy(ctx):
     load().cnn_destroy(ctx)
 
 
+# (name, cin, cout, level) of the 3x3 layers in parameter order, then the
+# 1x1 head (16 -> 1); the library's flat parameter vector follows this order
+# with each layer's weights [cout][cin][3][3] before its biases.
+LAYERS = [("L0a", 3, 16, 0), ("L0b", 16, 16, 0), ("L1a", 16, 32, 1), ("L1b", 32, 32, 1),
+          ("L2a", 32, 64, 2), ("L2b", 64, 64, 2), ("L3a", 64, 128, 3), ("L3b", 128, 128, 3),
+          ("U2", 128, 64, 2), ("D2", 128, 64, 2), ("U1", 64, 32, 1), ("D1", 64, 32, 1),
+          ("U0", 32, 16, 0), ("D0", 32, 16, 0)]
+
+
+def he_init(seed):
+    """Flat FP32 parameter vector: He-normal weights, zero biases."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    parts = []
+    for _, cin, cout, _ in LAYERS:
+        parts += [rng.normal(0.0, np.sqrt(2.0 / (9 * cin)), cout * cin * 9), np.zeros(cout)]
+    parts += [rng.normal(0.0, np.sqrt(2.0 / 16), 16), np.zeros(1)]
+    return np.concatenate(parts).astype(np.float32)
+
+
+def flops(n, H, W):
+    """(forward, training step) floating-point operations of the network on n
+    images of H x W: 2 per multiply-add of every 3x3 layer and the head; a
+    training step adds each layer's data gradient (not the first layer's)
+    and weight gradient."""
+    fwd = train = 0
+    for i, (_, cin, cout, lev) in enumerate(LAYERS):
+        px = n * (H >> lev) * (W >> lev)
+        f = 2 * px * 9 * cin * cout
+        fwd += f
+        train += f * (3 if i else 2)
+    head = 2 * n * H * W * 16
+    return fwd + head, train + 3 * head
+
+
 # channels and level of the tensors cnn_get_activation returns
 ACT_SHAPE = {0: (16, 0), 1: (16, 0), 2: (32, 1), 3: (32, 1), 4: (64, 2), 5: (64, 2), 6: (128, 3),
              7: (128, 3), 8: (64, 2), 9: (64, 2), 10: (32, 1), 11: (32, 1), 12: (16, 0), 13: (16, 0),

@@ -596,7 +596,10 @@ static const Net& net() {
     return n;
 }
 
-constexpr int kMaxSlabs = 128;
+// Weight-gradient grids aim at kWgBlocks blocks (k blocks x channel blocks x
+// pixel slabs); the partial tiles of one layer then take at most
+// kWgBlocks * 64 * 64 floats.
+constexpr int kWgBlocks = 2048;
 
 struct Carve {
     char* base;
@@ -663,8 +666,8 @@ static size_t carve_all(cnn_ctx* c, char* base, int B, int H, int W) {
     c->dcat2 = k.take<float>(P2 * 128);
     c->T0 = k.take<float>(P0 * 32);
     c->T1 = k.take<float>(P0 * 16);
-    c->part = k.take<float>((size_t)kMaxSlabs * N.max_part);
-    c->bpart = k.take<float>((size_t)kMaxSlabs * 128);
+    c->part = k.take<float>((size_t)kWgBlocks * 64 * 64);
+    c->bpart = k.take<float>((size_t)kWgBlocks * 128);
     c->hpart = k.take<float>((P0 + 255) / 256 * kHeadPart);
     c->loss = k.take<float>(1);
     return k.off;
@@ -770,7 +773,7 @@ static void conv_wgrad(cnn_ctx* c, int li, Act in, bool up, int n) {
     const int OT = std::min(d.cout, 64);
     const int kb = (d.kpad + 63) / 64, ob = d.cout / OT;
     const int chunks = (a.P + 63) / 64;
-    int S = std::max(1, std::min(std::min(chunks, kMaxSlabs), 2048 / (kb * ob)));
+    int S = std::max(1, std::min(chunks, kWgBlocks / (kb * ob)));
     const int per = (chunks + S - 1) / S;
     a.slab = per * 64;
     S = (a.P + a.slab - 1) / a.slab;

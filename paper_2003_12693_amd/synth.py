@@ -178,19 +178,19 @@ def _place_shapes(M, N, n, axis_lo, axis_hi, rng, clearance, gap_lo=2.0, gap_hi=
 
 
 def ellipses(M=1024, N=1024, seed=2, n_shapes=12, axis_lo=30.0, axis_hi=120.0,
-             noise=0.15, bias=0.2, inset=16):
-    """Ellipses (intensity U[0.6, 1]) with 2-6 px gaps on a U[0, 0.2] background,
+             noise=0.15, bias=0.2, inset=16, fg=(0.6, 1.0), bg=(0.0, 0.2)):
+    """Ellipses (intensity U[fg]) with 2-6 px gaps on a U[bg] background,
     multiplied by a one-sinusoid bias field of amplitude `bias`, plus
     N(0, noise^2).  phi^0 = rectangle inset by `inset` px.  Returns (f, phi0)."""
     rng = _rng(seed)
     shapes = _place_shapes(M, N, n_shapes, axis_lo, axis_hi, rng, clearance=inset + 8)
-    f = np.full((M, N), rng.uniform(0.0, 0.2))
+    f = np.full((M, N), rng.uniform(*bg))
     for (ci, cj, a, b, th) in shapes:
         rmax = max(a, b)
         box = (max(int(ci - rmax) - 1, 0), min(int(ci + rmax) + 3, M),
                max(int(cj - rmax) - 1, 0), min(int(cj + rmax) + 3, N))
         m = _ellipse_mask(M, N, ci, cj, a, b, th, box)
-        f[box[0]:box[1], box[2]:box[3]][m] = rng.uniform(0.6, 1.0)
+        f[box[0]:box[1], box[2]:box[3]][m] = rng.uniform(*fg)
     if bias > 0:
         ang = rng.uniform(0.0, 2.0 * math.pi)
         psi = rng.uniform(0.0, 2.0 * math.pi)

@@ -68,3 +68,14 @@ def test_create_validates_before_any_hip_call(lib):
     assert lib.cnn_backward(None, None, 8.0, None, None) == -1
     assert lib.cnn_adam_step(None, 1e-3, 0.9, 0.999, 1e-8) == -1
     lib.cnn_destroy(None)
+
+
+def test_binding_layer_table_matches_reference():
+    from paper_2003_12693_amd import cnn
+    assert [(a, b, c) for a, b, c, _ in cnn.LAYERS] == R.LAYERS
+    assert cnn.he_init(0).size == R.flatten(R.init_params(0)).size
+    fwd, train = cnn.flops(1, 512, 512)
+    # per pixel: sum over levels of 9*cin*cout*2 / 4^level, plus the head
+    per_px = sum(2 * 9 * cin * cout / 4 ** lev for _, cin, cout, lev in cnn.LAYERS) + 2 * 16
+    assert fwd == pytest.approx(per_px * 512 * 512)
+    assert 2.9 < train / fwd < 3.0
