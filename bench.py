@@ -322,6 +322,7 @@ def main():
     ft = torch.from_numpy(f.astype(np.float32)).cuda()
     pt = torch.from_numpy(phi0.astype(np.float32)).cuda()
     s.set_image(ft, pt)
+    tile_th, tune_us = s.autotune(5)
     s.step(args.warmup)
     torch.cuda.synchronize()
 
@@ -359,7 +360,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": wl["text"], "M": M, "N": N, "R": wl["R"], "S": wl["S"],
+        "config": {"workload": wl["text"], "M": M, "N": N, "R": wl["R"], "S": wl["S"], "tile_rows": tile_th,
                    "bytes_per_px_iter": sum(BYTES_PER_PX[k] * prof[k][1] for k in prof) / args.profile_iters},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),

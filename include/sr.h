@@ -184,6 +184,22 @@ int sr_implicit_solve(sr_ctx* ctx, const float* rhs, float* u_out, uint32_t flag
 int sr_profile_kernels(sr_ctx* ctx, int32_t n_iter, double ms[SR_NUM_KERNEL_KINDS],
                        int64_t count[SR_NUM_KERNEL_KINDS]);
 
+/* ---- autotuner ----------------------------------------------------------
+ * Chooses the row height of the stencil tiles (8, 16 or 32 rows of 64
+ * columns) of the two window kernels (eq 37 right-hand side; eqs 40-42 w
+ * step).  Each candidate is timed on the context's current state by
+ * launching the right-hand-side kernel, which reads the state and writes
+ * only its own scratch plane, so the iterate is unchanged and so is every
+ * later result (the per-pixel arithmetic does not depend on the tile
+ * height).  The fastest is kept for the context and recorded process-wide
+ * for its size class (M, N, R); sr_create and every size-class group of
+ * sr_solve_batch take a recorded choice, and sr_solve_batch tunes classes
+ * it has not seen.  reps >= 1 timed launches per candidate after one warm-
+ * up; us_out (nullable, host) receives the mean duration of each candidate
+ * in microseconds, *tile_th (nullable) the choice.  Requires sr_set_image;
+ * synchronises; SR_EINVAL / SR_ESTATE / SR_EHIP on error. */
+int sr_autotune(sr_ctx* ctx, int32_t reps, int32_t* tile_th, double us_out[3]);
+
 /* ---- batched solve (many independent images of uneven sizes) ----------
  * Each item is solved by Algorithm 1 from its own f and phi0, with its own
  * params (R may differ per item), until r_k < tol_outer (after min_iter) or

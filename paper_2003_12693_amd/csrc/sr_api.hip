@@ -10,7 +10,10 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/sr.h"
@@ -45,6 +48,20 @@ static int fail(int code, const char* fmt, ...) {
         hipError_t e_ = (expr);                                                             \
         if (e_ != hipSuccess) return fail(SR_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
     } while (0)
+
+// ---------------------------------------------------------------------------
+// autotuner of the stencil tile height, with a process-wide record per size
+// class (M, N, R, batch depth)
+// ---------------------------------------------------------------------------
+static std::mutex g_tune_mu;
+static std::map<std::tuple<int, int, int, int>, int> g_tuned;
+static const int kTileHeights[3] = {8, 16, 32};
+
+static int tuned_tile_height(int M, int N, int R, int nz) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(std::make_tuple(M, N, R, nz));
+    return it == g_tuned.end() ? 0 : it->second;
+}
 
 static bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
 
@@ -230,6 +247,52 @@ static int capture(sr_ctx* c, int p, int iters, hipGraphExec_t* out) {
     return SR_OK;
 }
 
+// Time the right-hand-side kernel for each tile height on the current state
+// (it writes only the scratch plane Rb) and keep the fastest.
+static int tune_tiles(sr_ctx* c, int reps, double us_out[3]) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    const int p = c->parity;
+    Bufs& b = c->b;
+    int best = 16;
+    double best_us = 1e300;
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < 3 && e == hipSuccess; ++i) {
+        c->geo.tile_th = kTileHeights[i];
+        sr::launch_rhs(c->geo, c->kp, b.P0, b.W[p], b.g, b.D, b.Rb, c->nz, b.scal, c->stream);
+        e = hipEventRecord(e0, c->stream);
+        for (int r = 0; r < reps && e == hipSuccess; ++r)
+            sr::launch_rhs(c->geo, c->kp, b.P0, b.W[p], b.g, b.D, b.Rb, c->nz, b.scal, c->stream);
+        if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        const double us = 1e3 * ms / reps;
+        if (us_out) us_out[i] = us;
+        if (us < best_us) {
+            best_us = us;
+            best = kTileHeights[i];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return fail(SR_EHIP, "autotune: %s", hipGetErrorString(e));
+    HIP_TRY(hipGetLastError());
+    c->geo.tile_th = best;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[std::make_tuple(c->M, c->N, c->kp.R, c->nz)] = best;
+    return SR_OK;
+}
+
+static void drop_graphs(sr_ctx* c) {
+    for (int p = 0; p < 2; ++p) {
+        if (c->g1[p]) (void)hipGraphExecDestroy(c->g1[p]);
+        if (c->g2[p]) (void)hipGraphExecDestroy(c->g2[p]);
+        c->g1[p] = c->g2[p] = nullptr;
+    }
+}
+
 // Enqueue n outer iterations on the context's stream.
 static int enqueue_iters(sr_ctx* c, int n) {
     while (n > 0) {
@@ -345,7 +408,7 @@ int sr_create(sr_ctx** out, int32_t M, int32_t N, const sr_params* p, void* work
     const char* ng = std::getenv("SR_NO_GRAPH");
     c->use_graphs = !(ng && ng[0] == '1');
     const char* th = std::getenv("SR_TILE_TH");
-    c->geo.tile_th = th ? std::atoi(th) : 0;
+    c->geo.tile_th = th ? std::atoi(th) : tuned_tile_height(M, N, c->kp.R, 1);
 
     hipError_t e = hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking);
     if (e != hipSuccess) { delete c; return fail(SR_EHIP, "hipStreamCreate: %s", hipGetErrorString(e)); }
@@ -559,6 +622,18 @@ int sr_implicit_solve(sr_ctx* c, const float* rhs, float* u_out, uint32_t flags)
     return SR_OK;
 }
 
+int sr_autotune(sr_ctx* c, int32_t reps, int32_t* tile_th, double us_out[3]) {
+    if (!c) return fail(SR_EINVAL, "NULL context");
+    if (reps < 1) return fail(SR_EINVAL, "reps must be >= 1");
+    if (!c->image_set) return fail(SR_ESTATE, "sr_autotune before sr_set_image");
+    const int before = c->geo.tile_th;
+    int rc = tune_tiles(c, reps, us_out);
+    if (rc) return rc;
+    if (c->geo.tile_th != before) drop_graphs(c);   // graphs hold the old launch shapes
+    if (tile_th) *tile_th = c->geo.tile_th;
+    return SR_OK;
+}
+
 int sr_profile_kernels(sr_ctx* c, int32_t n_iter, double ms[SR_NUM_KERNEL_KINDS],
                        int64_t count[SR_NUM_KERNEL_KINDS]) {
     if (!c || !ms || !count) return fail(SR_EINVAL, "NULL argument");
@@ -730,6 +805,16 @@ int sr_solve_batch(sr_batch_item* items, int32_t n, void* workspace, size_t byte
         bool any = false;
         for (auto& d : hs[gi]) if (d.nonfinite) { d.active = 0; any = true; }
         if (any) HIP_TRY(hipMemcpy(c.b.scal, hs[gi].data(), sizeof(DevScal) * c.nz, hipMemcpyHostToDevice));
+    }
+    // stencil tile height per size class: a recorded choice, else tuned on
+    // the group's initial state (state unchanged)
+    for (int gi = 0; gi < G; ++gi) {
+        sr_ctx& c = ctx[gi];
+        c.geo.tile_th = tuned_tile_height(c.M, c.N, c.kp.R, c.nz);
+        if (!c.geo.tile_th) {
+            rc = tune_tiles(&c, 3, nullptr);
+            if (rc) return rc;
+        }
     }
     // one graph: a chunk of outer iterations of every group
     const int chunk = 10;

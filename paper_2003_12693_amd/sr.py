@@ -101,6 +101,7 @@ def load(path=LIB_PATH):
         "sr_batch_workspace_size": (C.c_int, [C.POINTER(sr_batch_item), I, C.POINTER(C.c_size_t)]),
         "sr_solve_batch": (C.c_int, [C.POINTER(sr_batch_item), I, P, C.c_size_t, P]),
         "sr_profile_kernels": (C.c_int, [P, I, C.POINTER(D), C.POINTER(C.c_int64)]),
+        "sr_autotune": (C.c_int, [P, I, C.POINTER(I), C.POINTER(D)]),
         "sr_destroy": (None, [P]),
         "sr_last_error": (C.c_char_p, []),
     }
@@ -249,6 +250,14 @@ def sr_profile_kernels(ctx, n_iter):
     return {k: (ms[i], cnt[i]) for i, k in enumerate(KERNEL_KINDS)}
 
 
+def sr_autotune(ctx, reps=5):
+    """Stencil tile height chosen for the context: (rows, {rows: mean us})."""
+    th = C.c_int32()
+    us = (C.c_double * 3)()
+    _check(load().sr_autotune(ctx, reps, C.byref(th), us))
+    return th.value, {8: us[0], 16: us[1], 32: us[2]}
+
+
 def sr_destroy(ctx):
     if ctx:
         load().sr_destroy(ctx)
@@ -329,6 +338,9 @@ class Solver:
 
     def set_state(self, phi, w, b, k=0):
         sr_set_state(self.ctx, phi, w, b, k)
+
+    def autotune(self, reps=5):
+        return sr_autotune(self.ctx, reps)
 
     def edge_map(self, f):
         return sr_edge_map(self.ctx, f, self._empty(self.M, self.N))

@@ -123,3 +123,35 @@ def test_batch_nonfinite_instance_isolated(sr):
     assert res[1]["status"] == sr.SR_ENONFINITE
     assert res[0]["status"] == 0 and res[0]["iters"] == 5
     assert res[2]["status"] == 0 and res[2]["iters"] == 5
+
+
+def test_autotune_leaves_state_and_results_unchanged(sr):
+    """The tuner times the rhs kernel on the live state: the iterate is
+    untouched, and the per-pixel arithmetic does not depend on the tile
+    height, so every later iterate is bitwise the same."""
+    _note("autotune")
+    import os
+    f, p = synth.ellipses(256, 256, seed=7, n_shapes=3, axis_lo=10.0, axis_hi=30.0, inset=8)
+    kw = gpu_params(R=4, d=4.0)
+    ref = sr.Solver(256, 256, kw)
+    ref.set_image(_cuda(f), _cuda(p))
+    ref.step(5)
+    want = ref.phi().cpu().numpy()
+    s = sr.Solver(256, 256, kw)
+    s.set_image(_cuda(f), _cuda(p))
+    before = s.phi().cpu().numpy()
+    th, us = s.autotune(3)
+    _note(f"  chose {th} rows; mean us per candidate {us}")
+    assert th in (8, 16, 32) and all(v > 0 for v in us.values())
+    assert np.array_equal(s.phi().cpu().numpy(), before)
+    s.step(5)
+    assert np.array_equal(s.phi().cpu().numpy(), want)
+    for forced in ("8", "32"):
+        os.environ["SR_TILE_TH"] = forced
+        try:
+            t = sr.Solver(256, 256, kw)
+        finally:
+            del os.environ["SR_TILE_TH"]
+        t.set_image(_cuda(f), _cuda(p))
+        t.step(5)
+        assert np.array_equal(t.phi().cpu().numpy(), want), forced
