@@ -30,6 +30,7 @@
 namespace cnn {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // fp32 -> bf16 bits, round to nearest even.
@@ -54,6 +55,11 @@ __device__ __forceinline__ void transpose4(const uint2 v[4], uint2 o[4]) {
 __device__ __forceinline__ bf16x4 as_bf16x4(uint2 v) {
     bf16x4 r;
     __builtin_memcpy(&r, &v, 8);
+    return r;
+}
+__device__ __forceinline__ bf16x8 as_bf16x8(uint4 v) {
+    bf16x8 r;
+    __builtin_memcpy(&r, &v, 16);
     return r;
 }
 
@@ -151,6 +157,115 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
                     ((float*)a.y)[off] = acc[m][t][i];
                 } else {
                     const float v = fmaxf(acc[m][t][i] + bo, 0.f);
+                    ((uint16_t*)a.y)[off] = (uint16_t)f2bf(v);
+                }
+            }
+        }
+    }
+}
+
+// Spatially tiled form (level widths that are multiples of 16, >= 16 input
+// channels): a block owns a 16 x 16 output tile of one image and NT x 16
+// output channels.  For each chunk of KC input channels it stages the tile
+// plus a one-pixel halo (18 x 18 pixels, zeros outside the image, nearest
+// upsampling folded into the staging) in LDS; the nine taps then read their
+// MFMA A fragments from LDS (8 consecutive channels of one pixel per lane,
+// one ds_read_b128) without bounds checks.  v_mfma_f32_16x16x32_bf16: lane l
+// holds A[l%16][8(l/16)+i], B[8(l/16)+i][l%16]; D row 4(l/16)+i, column l%16.
+// Wave w computes tile rows 4w..4w+3 (four 16-pixel row tiles).
+constexpr int kTileR = 16, kTileC = 16;
+
+template <int NT, int KC, bool UP, bool F32OUT>
+__global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a) {
+    constexpr int SR = kTileR + 2, SC = kTileC + 2, PITCH = KC + 8, G8 = KC / 8;
+    constexpr int NKS = (9 * KC + 31) / 32;
+    __shared__ __attribute__((aligned(16))) uint16_t tile[SR * SC * PITCH];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int g = lane >> 4, r = lane & 15;
+    const int tiles_w = a.W / kTileC, tiles_h = (a.H + kTileR - 1) / kTileR;
+    int b = blockIdx.x;
+    const int tx = b % tiles_w;
+    b /= tiles_w;
+    const int ty = b % tiles_h;
+    const int n = b / tiles_h;
+    const int i0 = ty * kTileR, j0 = tx * kTileC;
+    const int cbase = blockIdx.y * (16 * NT);
+    const int cin = 1 << a.lcin;
+    const size_t img = (size_t)n * a.Hin * a.Win;
+    const int row0 = 4 * wave;
+    const bool active = i0 + row0 < a.H;
+
+    f32x4 acc[4][NT];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int u = 0; u < NT; ++u) acc[m][u] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const uint16_t* wrow[NT];
+#pragma unroll
+    for (int u = 0; u < NT; ++u) wrow[u] = a.w + (size_t)(cbase + u * 16 + r) * a.kpad;
+
+    for (int c0 = 0; c0 < cin; c0 += KC) {
+        for (int e = t; e < SR * SC * G8; e += 256) {
+            const int px = e / G8, cg = e - px * G8;
+            const int si = px / SC, sj = px - si * SC;
+            int ii = i0 + si - 1, jj = j0 + sj - 1;
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (ii >= 0 && ii < a.H && jj >= 0 && jj < a.W) {
+                if (UP) {
+                    ii >>= 1;
+                    jj >>= 1;
+                }
+                v = *(const uint4*)(a.x + (img + (size_t)ii * a.Win + jj) * a.xstride + a.xoff + c0 + 8 * cg);
+            }
+            *(uint4*)&tile[px * PITCH + 8 * cg] = v;
+        }
+        __syncthreads();
+        if (active) {
+#pragma unroll 3
+            for (int ks = 0; ks < NKS; ++ks) {
+                const int kk = ks * 32 + 8 * g;
+                const int tap = kk / KC, cc = kk - tap * KC;
+                const bool tv = tap < 9;
+                const int ty3 = tap / 3, tx3 = tap - 3 * ty3;
+                bf16x8 bv[NT], av[4];
+#pragma unroll
+                for (int u = 0; u < NT; ++u) {
+                    uint4 w = make_uint4(0u, 0u, 0u, 0u);
+                    if (tv) w = *(const uint4*)(wrow[u] + tap * cin + c0 + cc);
+                    bv[u] = as_bf16x8(w);
+                }
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    uint4 v = make_uint4(0u, 0u, 0u, 0u);
+                    if (tv) v = *(const uint4*)&tile[((row0 + m + ty3) * SC + r + tx3) * PITCH + cc];
+                    av[m] = as_bf16x8(v);
+                }
+#pragma unroll
+                for (int m = 0; m < 4; ++m)
+#pragma unroll
+                    for (int u = 0; u < NT; ++u)
+                        acc[m][u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[m], bv[u], acc[m][u], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+
+#pragma unroll
+    for (int u = 0; u < NT; ++u) {
+        const int o = cbase + u * 16 + r;
+        const float bo = F32OUT ? 0.f : a.bias[o];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int row = i0 + row0 + m;
+            if (row >= a.H) continue;
+            const size_t pbase = ((size_t)n * a.H + row) * a.W + j0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const size_t off = (pbase + 4 * g + i) * a.ystride + a.yoff + o;
+                if (F32OUT) {
+                    ((float*)a.y)[off] = acc[m][u][i];
+                } else {
+                    const float v = fmaxf(acc[m][u][i] + bo, 0.f);
                     ((uint16_t*)a.y)[off] = (uint16_t)f2bf(v);
                 }
             }
@@ -264,6 +379,138 @@ __global__ __launch_bounds__(256) void k_wgrad(WgArgs a) {
                 a.part[((size_t)blockIdx.z * a.cout + obase + 16 * o + 4 * g + i) * a.kpad + k] = acc[o][i];
     }
     if (blockIdx.x == 0 && t < OT) a.bpart[(size_t)blockIdx.z * a.cout + obase + t] = bsum;
+}
+
+// Spatially tiled weight gradient (level widths that are multiples of 16,
+// >= 16 input channels).  A block owns OT output channels and 16 input
+// channels and walks a slab of 16 x 16 output tiles.  Per tile it stages the
+// masked gradient transposed (dzT[o][pixel]) and the input tile plus halo
+// transposed in three column-shifted copies (xT[dx][ci][row][col] = input at
+// (row - 1, col + dx - 1) of the tile), so that both MFMA operands of every
+// tap are aligned 8-pixel runs: dW[o][tap, ci] += sum over 32-pixel steps of
+// dzT[o][px] * xT[dx][ci][row + dy][col].  v_mfma_f32_16x16x32_bf16 with the
+// pixels as the reduction; the MFMA tiles (OT/16 channel tiles x 9 taps) are
+// dealt to the 4 waves.
+constexpr int kWgTiles = 9 * 2;   // max MFMA tiles per block (OT = 32)
+
+template <int OT, bool UP>
+__global__ __launch_bounds__(256) void k_wgrad_sp(WgArgs a, int tiles_per_slab) {
+    constexpr int DZP = 256 + 8;              // dzT row pitch (pixels)
+    constexpr int XR = kTileR + 2;            // staged rows
+    constexpr int XP = XR * kTileC + 8;       // xT pitch per (dx, ci)
+    constexpr int NTILE = (OT / 16) * 9;
+    constexpr int PER_WAVE = (NTILE + 3) / 4;
+    __shared__ __attribute__((aligned(16))) uint16_t dzT[OT * DZP];
+    __shared__ __attribute__((aligned(16))) uint16_t xT[3 * 16 * XP];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int g = lane >> 4, r = lane & 15;
+    const int obase = blockIdx.y * OT, c0 = blockIdx.z * 16;
+    const int cin = 1 << a.lcin;
+    const int tiles_w = a.W / kTileC, tiles_h = (a.H + kTileR - 1) / kTileR;
+    const int n_tiles = (a.P / (a.H * a.W)) * tiles_h * tiles_w;
+    const int tile0 = blockIdx.x * tiles_per_slab;
+    const int tile1 = min(tile0 + tiles_per_slab, n_tiles);
+
+    f32x4 acc[PER_WAVE];
+#pragma unroll
+    for (int q = 0; q < PER_WAVE; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float bsum = 0.f;
+
+    for (int tl = tile0; tl < tile1; ++tl) {
+        int b = tl;
+        const int tx = b % tiles_w;
+        b /= tiles_w;
+        const int ty = b % tiles_h;
+        const int n = b / tiles_h;
+        const int i0 = ty * kTileR, j0 = tx * kTileC;
+        // masked gradient, 4 pixels x 4 channels per step, transposed
+        for (int e = t; e < (256 / 4) * (OT / 4); e += 256) {
+            const int pg = e % 64, cg = e / 64;
+            const int row = pg >> 2, col = (pg & 3) * 4;
+            uint2 v[4], o[4];
+            const bool ok = i0 + row < a.H;
+            const size_t p = ((size_t)n * a.H + i0 + row) * a.W + j0 + col;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                v[q] = ok ? *(const uint2*)(a.dz + (p + q) * a.cout + obase + 4 * cg) : make_uint2(0u, 0u);
+            transpose4(v, o);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) *(uint2*)&dzT[(4 * cg + c) * DZP + row * kTileC + col] = o[c];
+        }
+        // input tile + halo, 16 channels, into the three shifted copies
+        for (int e = t; e < XR * (kTileC + 2) * 2; e += 256) {
+            const int px = e >> 1, h8 = (e & 1) * 8;
+            const int sr = px / (kTileC + 2), sc = px - sr * (kTileC + 2);
+            int ii = i0 + sr - 1, jj = j0 + sc - 1;
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (ii >= 0 && ii < a.H && jj >= 0 && jj < a.W) {
+                if (UP) {
+                    ii >>= 1;
+                    jj >>= 1;
+                }
+                v = *(const uint4*)(a.x + ((size_t)n * a.Hin * a.Win + (size_t)ii * a.Win + jj) * a.xstride + a.xoff +
+                                    c0 + h8);
+            }
+            const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx) {
+                const int col = sc - dx;
+                if (col < 0 || col >= kTileC) continue;
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    xT[(dx * 16 + h8 + q) * XP + sr * kTileC + col] =
+                        (uint16_t)((q & 1) ? (w[q >> 1] >> 16) : (w[q >> 1] & 0xffffu));
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < PER_WAVE; ++q) {
+            const int tile = wave + 4 * q;
+            if (tile >= NTILE) break;
+            const int ot = tile / 9, tap = tile - 9 * ot;
+            const int ty3 = tap / 3, tx3 = tap - 3 * ty3;
+#pragma unroll 4
+            for (int ks = 0; ks < 8; ++ks) {
+                const int px = 32 * ks + 8 * g;               // 8 pixels of one tile row
+                const int row = px >> 4, col = px & 15;
+                const bf16x8 av = as_bf16x8(*(const uint4*)&dzT[(ot * 16 + r) * DZP + px]);
+                const bf16x8 bv = as_bf16x8(*(const uint4*)&xT[(tx3 * 16 + r) * XP + (row + ty3) * kTileC + col]);
+                acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[q], 0, 0, 0);
+            }
+        }
+        if (blockIdx.z == 0 && t < OT) {
+            for (int q = 0; q < 256; q += 8) {
+                const uint4 v = *(const uint4*)&dzT[t * DZP + q];
+                const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int h = 0; h < 4; ++h) bsum += bf2f(w[h] & 0xffffu) + bf2f(w[h] >> 16);
+            }
+        }
+        __syncthreads();
+    }
+    // D tile: row (output channel) 4g+i, column (input channel) r
+#pragma unroll
+    for (int q = 0; q < PER_WAVE; ++q) {
+        const int tile = wave + 4 * q;
+        if (tile >= NTILE) break;
+        const int ot = tile / 9, tap = tile - 9 * ot;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            a.part[((size_t)blockIdx.x * a.cout + obase + ot * 16 + 4 * g + i) * a.kpad + tap * cin + c0 + r] =
+                acc[q][i];
+    }
+    if (blockIdx.z == 0 && t < OT) a.bpart[(size_t)blockIdx.x * a.cout + obase + t] = bsum;
+}
+
+// First level of the slab sum: out[y][e] = sum of in[z][e] over the 32 slabs
+// z of group y (fixed order).
+__global__ void k_sum_slabs(const float* in, int S, int n, float* out) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const int z0 = blockIdx.y * 32, z1 = min(z0 + 32, S);
+    float s = 0.f;
+    for (int z = z0; z < z1; ++z) s += in[(size_t)z * n + e];
+    out[(size_t)blockIdx.y * n + e] = s;
 }
 
 // Sum the slabs and scatter into the flat gradient ([cout][cin][3][3], then bias).
@@ -495,15 +742,15 @@ __global__ void k_pack_fwd(const float* w, int cin, int lcin_s, int cout, int kp
     wf[idx] = (uint16_t)f2bf(v);
 }
 
-// Flat weights -> data-gradient layout [cin][9*cout], k = tap*cout + o, the
-// stencil turned by 180 degrees (tap (ky,kx) reads weight (2-ky, 2-kx)).
-__global__ void k_pack_dgrad(const float* w, int cin, int cout, uint16_t* wd) {
-    const int kd = 9 * cout;
+// Flat weights -> data-gradient layout [cin][kdpad], k = tap*cout + o (zero
+// beyond 9*cout), the stencil turned by 180 degrees (tap (ky,kx) reads
+// weight (2-ky, 2-kx)).
+__global__ void k_pack_dgrad(const float* w, int cin, int cout, int kdpad, uint16_t* wd) {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= cin * kd) return;
-    const int c = idx / kd, k = idx - c * kd;
+    if (idx >= cin * kdpad) return;
+    const int c = idx / kdpad, k = idx - c * kdpad;
     const int tap = k / cout, o = k - tap * cout;
-    wd[idx] = (uint16_t)f2bf(w[(o * cin + c) * 9 + (8 - tap)]);
+    wd[idx] = tap < 9 ? (uint16_t)f2bf(w[(o * cin + c) * 9 + (8 - tap)]) : (uint16_t)0;
 }
 
 }  // namespace cnn
@@ -538,7 +785,8 @@ enum { L0a, L0b, L1a, L1b, L2a, L2b, L3a, L3b, U2, D2, U1, D1, U0, D0, kConv };
 struct LayerDesc {
     const char* name;
     int cin, cout, cin_s, level;
-    int kpad;         // forward reduction length (multiple of 16)
+    int kpad;         // forward reduction length (multiple of 32)
+    int kdpad;        // data-gradient reduction length (multiple of 32)
     size_t pw, pb;    // offsets of weights / bias in the flat parameter vector
     size_t wf, wd;    // offsets (elements) in the packed bf16 weight buffers
 };
@@ -572,7 +820,8 @@ static const Net& net() {
             d.cout = spec[i].cout;
             d.level = spec[i].level;
             d.cin_s = d.cin < 4 ? 4 : d.cin;
-            d.kpad = (9 * d.cin_s + 15) / 16 * 16;
+            d.kpad = (9 * d.cin_s + 31) / 32 * 32;
+            d.kdpad = (9 * d.cout + 31) / 32 * 32;
             d.pw = off;
             off += (size_t)d.cout * d.cin * 9;
             d.pb = off;
@@ -580,7 +829,7 @@ static const Net& net() {
             d.wf = wf;
             wf += (size_t)d.cout * d.kpad;
             d.wd = wd;
-            wd += (size_t)d.cin * 9 * d.cout;
+            wd += (size_t)d.cin * d.kdpad;
             mp = std::max(mp, (size_t)d.cout * d.kpad);
         }
         t.head_w = off;
@@ -600,6 +849,7 @@ static const Net& net() {
 // pixel slabs); the partial tiles of one layer then take at most
 // kWgBlocks * 64 * 64 floats.
 constexpr int kWgBlocks = 2048;
+constexpr size_t kPartFloats = (size_t)kWgBlocks * 64 * 64;
 
 struct Carve {
     char* base;
@@ -628,7 +878,7 @@ struct cnn_ctx {
     // backward: masked output gradient of every 3x3 layer (bf16 [P_l][cout])
     uint16_t* dz[kConv];
     float *dcat0, *dcat1, *dcat2, *T0, *T1;
-    float *part, *bpart, *hpart, *loss;
+    float *part, *bpart, *part2, *bpart2, *hpart, *loss;
     // state of the last forward / backward
     int n_last, n_grad;
     float clip_last;
@@ -666,8 +916,10 @@ static size_t carve_all(cnn_ctx* c, char* base, int B, int H, int W) {
     c->dcat2 = k.take<float>(P2 * 128);
     c->T0 = k.take<float>(P0 * 32);
     c->T1 = k.take<float>(P0 * 16);
-    c->part = k.take<float>((size_t)kWgBlocks * 64 * 64);
+    c->part = k.take<float>(kPartFloats);
     c->bpart = k.take<float>((size_t)kWgBlocks * 128);
+    c->part2 = k.take<float>((size_t)(kWgBlocks / 32) * N.max_part);
+    c->bpart2 = k.take<float>((size_t)(kWgBlocks / 32) * 128);
     c->hpart = k.take<float>((P0 + 255) / 256 * kHeadPart);
     c->loss = k.take<float>(1);
     return k.off;
@@ -690,9 +942,27 @@ struct Act {  // a channels-last bf16 tensor view
     int stride, off;
 };
 
+template <int KC, bool UP, bool F32>
+static void conv_lds_t(const ConvArgs& a, int cout, int nt, hipStream_t st) {
+    const int n = a.P / (a.H * a.W);
+    dim3 grid(n * ((a.H + kTileR - 1) / kTileR) * (a.W / kTileC), cout / (16 * nt));
+    switch (nt) {
+        case 1: k_conv_lds<1, KC, UP, F32><<<grid, 256, 0, st>>>(a); break;
+        case 2: k_conv_lds<2, KC, UP, F32><<<grid, 256, 0, st>>>(a); break;
+        default: k_conv_lds<4, KC, UP, F32><<<grid, 256, 0, st>>>(a); break;
+    }
+}
+
+// Spatially tiled kernel where the level's width is a multiple of 16 and the
+// input has >= 16 channels; the per-pixel-tile kernel otherwise.
 template <bool UP, bool F32>
 static void conv_t(const ConvArgs& a, int cout, hipStream_t st) {
     const int nt = std::min(cout / 16, 4);
+    if (a.W % kTileC == 0 && a.lcin >= 4) {
+        if (a.lcin >= 5) conv_lds_t<32, UP, F32>(a, cout, nt, st);
+        else conv_lds_t<16, UP, F32>(a, cout, nt, st);
+        return;
+    }
     dim3 grid(blocks(a.P, 256), cout / (16 * nt));
     switch (nt) {
         case 1: k_conv<4, 1, UP, F32><<<grid, 256, 0, st>>>(a); break;
@@ -740,14 +1010,31 @@ static void conv_dgrad(cnn_ctx* c, int li, float* out, int n) {
     a.W = W;
     a.P = n * H * W;
     a.lcin = ilog2(d.cout);
-    a.nkb = 9 * d.cout / 16;
+    a.nkb = d.kdpad / 16;
     a.w = c->wd + d.wd;
-    a.kpad = 9 * d.cout;
+    a.kpad = d.kdpad;
     a.bias = nullptr;
     a.y = out;
     a.ystride = d.cin;
     a.yoff = 0;
     conv_t<false, true>(a, d.cin, c->st);
+}
+
+// Slab partials -> flat gradient: a first fixed-order pass over groups of 32
+// slabs when there are more than 32, then the scatter.
+static void reduce_wgrad(cnn_ctx* c, const LayerDesc& d, int S) {
+    const int nw = d.cout * d.kpad;
+    const float *part = c->part, *bpart = c->bpart;
+    if (S > 32) {
+        const int S2 = (S + 31) / 32;
+        k_sum_slabs<<<dim3(blocks(nw), S2), 256, 0, c->st>>>(c->part, S, nw, c->part2);
+        k_sum_slabs<<<dim3(blocks(d.cout), S2), 256, 0, c->st>>>(c->bpart, S, d.cout, c->bpart2);
+        part = c->part2;
+        bpart = c->bpart2;
+        S = S2;
+    }
+    k_reduce_wgrad<<<blocks(nw + d.cout), 256, 0, c->st>>>(part, bpart, S, d.cout, d.kpad, ilog2(d.cin_s), d.cin,
+                                                            c->grad + d.pw, c->grad + d.pb);
 }
 
 static void conv_wgrad(cnn_ctx* c, int li, Act in, bool up, int n) {
@@ -770,10 +1057,30 @@ static void conv_wgrad(cnn_ctx* c, int li, Act in, bool up, int n) {
     a.cout = d.cout;
     a.part = c->part;
     a.bpart = c->bpart;
+    const size_t nw = (size_t)d.cout * d.kpad;
+    const int cap = (int)std::min<size_t>(kWgBlocks, kPartFloats / nw);
+    if (W % kTileC == 0 && d.cin_s >= 16) {
+        const int OT = std::min(d.cout, 32);
+        const int ob = d.cout / OT, nch = d.cin_s / 16;
+        const int n_tiles = n * ((H + kTileR - 1) / kTileR) * (W / kTileC);
+        int S = std::max(1, std::min(std::min(n_tiles, cap), kWgBlocks / (ob * nch)));
+        const int per = (n_tiles + S - 1) / S;
+        S = (n_tiles + per - 1) / per;
+        dim3 grid(S, ob, nch);
+        if (OT == 16) {
+            if (up) k_wgrad_sp<16, true><<<grid, 256, 0, c->st>>>(a, per);
+            else k_wgrad_sp<16, false><<<grid, 256, 0, c->st>>>(a, per);
+        } else {
+            if (up) k_wgrad_sp<32, true><<<grid, 256, 0, c->st>>>(a, per);
+            else k_wgrad_sp<32, false><<<grid, 256, 0, c->st>>>(a, per);
+        }
+        reduce_wgrad(c, d, S);
+        return;
+    }
     const int OT = std::min(d.cout, 64);
     const int kb = (d.kpad + 63) / 64, ob = d.cout / OT;
     const int chunks = (a.P + 63) / 64;
-    int S = std::max(1, std::min(chunks, kWgBlocks / (kb * ob)));
+    int S = std::max(1, std::min(std::min(chunks, cap), kWgBlocks / (kb * ob)));
     const int per = (chunks + S - 1) / S;
     a.slab = per * 64;
     S = (a.P + a.slab - 1) / a.slab;
@@ -788,9 +1095,7 @@ static void conv_wgrad(cnn_ctx* c, int li, Act in, bool up, int n) {
         if (up) k_wgrad<64, true><<<grid, 256, 0, c->st>>>(a);
         else k_wgrad<64, false><<<grid, 256, 0, c->st>>>(a);
     }
-    const int tot = d.cout * d.kpad + d.cout;
-    k_reduce_wgrad<<<blocks(tot), 256, 0, c->st>>>(c->part, c->bpart, S, d.cout, d.kpad, ilog2(d.cin_s), d.cin,
-                                                    c->grad + d.pw, c->grad + d.pb);
+    reduce_wgrad(c, d, S);
 }
 
 static void mask(cnn_ctx* c, int li, const float* A, int astride, int aoff, bool aup, const float* B, Act act,
@@ -826,8 +1131,8 @@ static void pack_weights(cnn_ctx* c) {
         k_pack_fwd<<<blocks((size_t)d.cout * d.kpad), 256, 0, c->st>>>(c->params + d.pw, d.cin, ilog2(d.cin_s), d.cout,
                                                                         d.kpad, c->wf + d.wf);
         if (i != L0a)
-            k_pack_dgrad<<<blocks((size_t)d.cin * 9 * d.cout), 256, 0, c->st>>>(c->params + d.pw, d.cin, d.cout,
-                                                                                 c->wd + d.wd);
+            k_pack_dgrad<<<blocks((size_t)d.cin * d.kdpad), 256, 0, c->st>>>(c->params + d.pw, d.cin, d.cout,
+                                                                              d.kdpad, c->wd + d.wd);
     }
 }
 

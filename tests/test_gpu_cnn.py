@@ -81,7 +81,7 @@ def _x(f, g, phi0):
     return R.make_input(f.astype(np.float64), g.astype(np.float64), phi0.astype(np.float64), CLIP)
 
 
-CASES = [(2, 64, 96), (1, 32, 32), (3, 32, 64)]
+CASES = [(2, 64, 96), (1, 32, 32), (3, 32, 64), (2, 96, 64)]
 
 
 @pytest.mark.parametrize("n,H,W", CASES)
