@@ -176,24 +176,22 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
 constexpr int kTileR = 16, kTileC = 16;
 
 template <int NT, int KC, bool UP, bool F32OUT>
-__global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a) {
+__global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a, int tiles_per_block) {
     constexpr int SR = kTileR + 2, SC = kTileC + 2, PITCH = KC + 8, G8 = KC / 8;
     constexpr int NKS = (9 * KC + 31) / 32;
+    constexpr int ITEMS = (SR * SC * G8 + 255) / 256;   // staged 16-byte items per thread
     __shared__ __attribute__((aligned(16))) uint16_t tile[SR * SC * PITCH];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int g = lane >> 4, r = lane & 15;
     const int tiles_w = a.W / kTileC, tiles_h = (a.H + kTileR - 1) / kTileR;
-    int b = blockIdx.x;
-    const int tx = b % tiles_w;
-    b /= tiles_w;
-    const int ty = b % tiles_h;
-    const int n = b / tiles_h;
-    const int i0 = ty * kTileR, j0 = tx * kTileC;
+    const int n_tiles = (a.P / (a.H * a.W)) * tiles_h * tiles_w;
+    const int tl0 = blockIdx.x * tiles_per_block;
+    const int tl1 = min(tl0 + tiles_per_block, n_tiles);
     const int cbase = blockIdx.y * (16 * NT);
     const int cin = 1 << a.lcin;
-    const size_t img = (size_t)n * a.Hin * a.Win;
+    const int nch = cin / KC;
+    const int nsteps = (tl1 - tl0) * nch;
     const int row0 = 4 * wave;
-    const bool active = i0 + row0 < a.H;
 
     f32x4 acc[4][NT];
 #pragma unroll
@@ -204,23 +202,57 @@ __global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a) {
 #pragma unroll
     for (int u = 0; u < NT; ++u) wrow[u] = a.w + (size_t)(cbase + u * 16 + r) * a.kpad;
 
-    for (int c0 = 0; c0 < cin; c0 += KC) {
-        for (int e = t; e < SR * SC * G8; e += 256) {
-            const int px = e / G8, cg = e - px * G8;
-            const int si = px / SC, sj = px - si * SC;
-            int ii = i0 + si - 1, jj = j0 + sj - 1;
-            uint4 v = make_uint4(0u, 0u, 0u, 0u);
-            if (ii >= 0 && ii < a.H && jj >= 0 && jj < a.W) {
-                if (UP) {
-                    ii >>= 1;
-                    jj >>= 1;
+    // global -> registers for step `step` (tile tl0 + step / nch, channel chunk step % nch)
+    uint4 pre[ITEMS];
+    auto fetch = [&](int step) {
+        int b = tl0 + step / nch;
+        const int c0 = (step % nch) * KC;
+        const int tx = b % tiles_w;
+        b /= tiles_w;
+        const int ty = b % tiles_h;
+        const int n = b / tiles_h;
+        const int i0 = ty * kTileR, j0 = tx * kTileC;
+        const size_t img = (size_t)n * a.Hin * a.Win;
+#pragma unroll
+        for (int it = 0; it < ITEMS; ++it) {
+            const int e = t + 256 * it;
+            pre[it] = make_uint4(0u, 0u, 0u, 0u);
+            if (e < SR * SC * G8) {
+                const int px = e / G8, cg = e - px * G8;
+                const int si = px / SC, sj = px - si * SC;
+                int ii = i0 + si - 1, jj = j0 + sj - 1;
+                if (ii >= 0 && ii < a.H && jj >= 0 && jj < a.W) {
+                    if (UP) {
+                        ii >>= 1;
+                        jj >>= 1;
+                    }
+                    pre[it] = *(const uint4*)(a.x + (img + (size_t)ii * a.Win + jj) * a.xstride + a.xoff + c0 + 8 * cg);
                 }
-                v = *(const uint4*)(a.x + (img + (size_t)ii * a.Win + jj) * a.xstride + a.xoff + c0 + 8 * cg);
             }
-            *(uint4*)&tile[px * PITCH + 8 * cg] = v;
+        }
+    };
+
+    if (nsteps > 0) fetch(0);
+    for (int step = 0; step < nsteps; ++step) {
+        int b = tl0 + step / nch;
+        const int c0 = (step % nch) * KC;
+        const int tx = b % tiles_w;
+        b /= tiles_w;
+        const int ty = b % tiles_h;
+        const int n = b / tiles_h;
+        const int i0 = ty * kTileR, j0 = tx * kTileC;
+        __syncthreads();   // the previous step is done with the LDS tile
+#pragma unroll
+        for (int it = 0; it < ITEMS; ++it) {
+            const int e = t + 256 * it;
+            if (e < SR * SC * G8) {
+                const int px = e / G8, cg = e - px * G8;
+                *(uint4*)&tile[px * PITCH + 8 * cg] = pre[it];
+            }
         }
         __syncthreads();
-        if (active) {
+        if (step + 1 < nsteps) fetch(step + 1);   // in flight during the MFMAs below
+        if (i0 + row0 < a.H) {
 #pragma unroll 3
             for (int ks = 0; ks < NKS; ++ks) {
                 const int kk = ks * 32 + 8 * g;
@@ -247,27 +279,29 @@ __global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a) {
                         acc[m][u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[m], bv[u], acc[m][u], 0, 0, 0);
             }
         }
-        __syncthreads();
-    }
-
+        if (c0 + KC < cin) continue;
+        // last chunk of this tile: D tile row (pixel) 4g+i, column (channel) r
 #pragma unroll
-    for (int u = 0; u < NT; ++u) {
-        const int o = cbase + u * 16 + r;
-        const float bo = F32OUT ? 0.f : a.bias[o];
+        for (int u = 0; u < NT; ++u) {
+            const int o = cbase + u * 16 + r;
+            const float bo = F32OUT ? 0.f : a.bias[o];
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            const int row = i0 + row0 + m;
-            if (row >= a.H) continue;
-            const size_t pbase = ((size_t)n * a.H + row) * a.W + j0;
+            for (int m = 0; m < 4; ++m) {
+                const int row = i0 + row0 + m;
+                if (row < a.H) {
+                    const size_t pbase = ((size_t)n * a.H + row) * a.W + j0;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const size_t off = (pbase + 4 * g + i) * a.ystride + a.yoff + o;
-                if (F32OUT) {
-                    ((float*)a.y)[off] = acc[m][u][i];
-                } else {
-                    const float v = fmaxf(acc[m][u][i] + bo, 0.f);
-                    ((uint16_t*)a.y)[off] = (uint16_t)f2bf(v);
+                    for (int i = 0; i < 4; ++i) {
+                        const size_t off = (pbase + 4 * g + i) * a.ystride + a.yoff + o;
+                        if (F32OUT) {
+                            ((float*)a.y)[off] = acc[m][u][i];
+                        } else {
+                            const float v = fmaxf(acc[m][u][i] + bo, 0.f);
+                            ((uint16_t*)a.y)[off] = (uint16_t)f2bf(v);
+                        }
+                    }
                 }
+                acc[m][u] = f32x4{0.f, 0.f, 0.f, 0.f};
             }
         }
     }
@@ -389,17 +423,16 @@ __global__ __launch_bounds__(256) void k_wgrad(WgArgs a) {
 // (row - 1, col + dx - 1) of the tile), so that both MFMA operands of every
 // tap are aligned 8-pixel runs: dW[o][tap, ci] += sum over 32-pixel steps of
 // dzT[o][px] * xT[dx][ci][row + dy][col].  v_mfma_f32_16x16x32_bf16 with the
-// pixels as the reduction; the MFMA tiles (OT/16 channel tiles x 9 taps) are
-// dealt to the 4 waves.
-constexpr int kWgTiles = 9 * 2;   // max MFMA tiles per block (OT = 32)
+// pixels as the reduction.  Wave w owns taps w and w + 4 for every channel
+// tile, and tap 8 for channel tile w (w < OT/16), so each 32-pixel step reads
+// every masked-gradient fragment once and reuses it across the wave's taps.
 
 template <int OT, bool UP>
 __global__ __launch_bounds__(256) void k_wgrad_sp(WgArgs a, int tiles_per_slab) {
     constexpr int DZP = 256 + 8;              // dzT row pitch (pixels)
     constexpr int XR = kTileR + 2;            // staged rows
     constexpr int XP = XR * kTileC + 8;       // xT pitch per (dx, ci)
-    constexpr int NTILE = (OT / 16) * 9;
-    constexpr int PER_WAVE = (NTILE + 3) / 4;
+    constexpr int NO = OT / 16;
     __shared__ __attribute__((aligned(16))) uint16_t dzT[OT * DZP];
     __shared__ __attribute__((aligned(16))) uint16_t xT[3 * 16 * XP];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -411,9 +444,12 @@ __global__ __launch_bounds__(256) void k_wgrad_sp(WgArgs a, int tiles_per_slab) 
     const int tile0 = blockIdx.x * tiles_per_slab;
     const int tile1 = min(tile0 + tiles_per_slab, n_tiles);
 
-    f32x4 acc[PER_WAVE];
+    f32x4 acc[2][NO], acc8 = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int q = 0; q < PER_WAVE; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int u = 0; u < NO; ++u) acc[j][u] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const bool has8 = wave < NO;
     float bsum = 0.f;
 
     for (int tl = tile0; tl < tile1; ++tl) {
@@ -463,19 +499,29 @@ __global__ __launch_bounds__(256) void k_wgrad_sp(WgArgs a, int tiles_per_slab) 
             }
         }
         __syncthreads();
+#pragma unroll 2
+        for (int ks = 0; ks < 8; ++ks) {
+            const int px = 32 * ks + 8 * g;                   // 8 pixels of one tile row
+            const int row = px >> 4, col = px & 15;
+            bf16x8 av[NO];
 #pragma unroll
-        for (int q = 0; q < PER_WAVE; ++q) {
-            const int tile = wave + 4 * q;
-            if (tile >= NTILE) break;
-            const int ot = tile / 9, tap = tile - 9 * ot;
-            const int ty3 = tap / 3, tx3 = tap - 3 * ty3;
-#pragma unroll 4
-            for (int ks = 0; ks < 8; ++ks) {
-                const int px = 32 * ks + 8 * g;               // 8 pixels of one tile row
-                const int row = px >> 4, col = px & 15;
-                const bf16x8 av = as_bf16x8(*(const uint4*)&dzT[(ot * 16 + r) * DZP + px]);
+            for (int u = 0; u < NO; ++u) av[u] = as_bf16x8(*(const uint4*)&dzT[(u * 16 + r) * DZP + px]);
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int tap = wave + 4 * j;
+                const int ty3 = tap / 3, tx3 = tap - 3 * ty3;
                 const bf16x8 bv = as_bf16x8(*(const uint4*)&xT[(tx3 * 16 + r) * XP + (row + ty3) * kTileC + col]);
-                acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[q], 0, 0, 0);
+#pragma unroll
+                for (int u = 0; u < NO; ++u)
+                    acc[j][u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[u], bv, acc[j][u], 0, 0, 0);
+            }
+            if (has8) {   // tap 8 = (2, 2)
+                const bf16x8 bv = as_bf16x8(*(const uint4*)&xT[(2 * 16 + r) * XP + (row + 2) * kTileC + col]);
+                bf16x8 a8 = av[0];
+#pragma unroll
+                for (int u = 1; u < NO; ++u)
+                    if (u == wave) a8 = av[u];
+                acc8 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a8, bv, acc8, 0, 0, 0);
             }
         }
         if (blockIdx.z == 0 && t < OT) {
@@ -489,16 +535,17 @@ __global__ __launch_bounds__(256) void k_wgrad_sp(WgArgs a, int tiles_per_slab) 
         __syncthreads();
     }
     // D tile: row (output channel) 4g+i, column (input channel) r
+    float* prow = a.part + (size_t)blockIdx.x * a.cout * a.kpad;
 #pragma unroll
-    for (int q = 0; q < PER_WAVE; ++q) {
-        const int tile = wave + 4 * q;
-        if (tile >= NTILE) break;
-        const int ot = tile / 9, tap = tile - 9 * ot;
+    for (int j = 0; j < 2; ++j)
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-            a.part[((size_t)blockIdx.x * a.cout + obase + ot * 16 + 4 * g + i) * a.kpad + tap * cin + c0 + r] =
-                acc[q][i];
-    }
+        for (int u = 0; u < NO; ++u)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                prow[(size_t)(obase + u * 16 + 4 * g + i) * a.kpad + (wave + 4 * j) * cin + c0 + r] = acc[j][u][i];
+    if (has8)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) prow[(size_t)(obase + wave * 16 + 4 * g + i) * a.kpad + 8 * cin + c0 + r] = acc8[i];
     if (blockIdx.z == 0 && t < OT) a.bpart[(size_t)blockIdx.x * a.cout + obase + t] = bsum;
 }
 
@@ -942,14 +989,22 @@ struct Act {  // a channels-last bf16 tensor view
     int stride, off;
 };
 
+// Grids aim at ~6 resident blocks per CU; each block walks consecutive
+// tiles (spatial neighbours) so the staging of the next one overlaps the
+// MFMAs of the current one.
+constexpr int kConvBlocks = 256 * 6;
+
 template <int KC, bool UP, bool F32>
 static void conv_lds_t(const ConvArgs& a, int cout, int nt, hipStream_t st) {
     const int n = a.P / (a.H * a.W);
-    dim3 grid(n * ((a.H + kTileR - 1) / kTileR) * (a.W / kTileC), cout / (16 * nt));
+    const int n_tiles = n * ((a.H + kTileR - 1) / kTileR) * (a.W / kTileC);
+    const int ob = cout / (16 * nt);
+    const int per = std::max(1, n_tiles / std::max(1, kConvBlocks / ob));
+    dim3 grid((n_tiles + per - 1) / per, ob);
     switch (nt) {
-        case 1: k_conv_lds<1, KC, UP, F32><<<grid, 256, 0, st>>>(a); break;
-        case 2: k_conv_lds<2, KC, UP, F32><<<grid, 256, 0, st>>>(a); break;
-        default: k_conv_lds<4, KC, UP, F32><<<grid, 256, 0, st>>>(a); break;
+        case 1: k_conv_lds<1, KC, UP, F32><<<grid, 256, 0, st>>>(a, per); break;
+        case 2: k_conv_lds<2, KC, UP, F32><<<grid, 256, 0, st>>>(a, per); break;
+        default: k_conv_lds<4, KC, UP, F32><<<grid, 256, 0, st>>>(a, per); break;
     }
 }
 
