@@ -358,14 +358,24 @@ __device__ __forceinline__ void store_partials(double (&v)[NV], double* part, in
     }
 }
 
-// Sum of the NV x nblocks partials in fixed order; valid in thread 0.
+// Sum of the NV x nblocks partials in fixed order; valid in thread 0.  Each
+// thread keeps four independent running sums so that its loads overlap.
 template <int NV>
 __device__ __forceinline__ void sum_partials(const double* part, int nblocks, double (&v)[NV], double* red) {
+    const int bd = blockDim.x;
 #pragma unroll
     for (int c = 0; c < NV; ++c) {
-        double s = 0.0;
-        for (int b = threadIdx.x; b < nblocks; b += blockDim.x) s += part[c * nblocks + b];
-        v[c] = s;
+        const double* p = part + (size_t)c * nblocks;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        int b = threadIdx.x;
+        for (; b + 3 * bd < nblocks; b += 4 * bd) {
+            s0 += p[b];
+            s1 += p[b + bd];
+            s2 += p[b + 2 * bd];
+            s3 += p[b + 3 * bd];
+        }
+        for (; b < nblocks; b += bd) s0 += p[b];
+        v[c] = (s0 + s1) + (s2 + s3);
     }
     block_sum<NV>(v, red);
 }

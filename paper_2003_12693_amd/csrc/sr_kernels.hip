@@ -612,7 +612,7 @@ __global__ __launch_bounds__(1024) void k_row_inv(const float2* __restrict__ spe
 }
 
 // Inner stop rule after an executed inner step: ||dphi|| / (||phi_s|| + 1e-6) <= tol.
-__global__ __launch_bounds__(256) void k_fin_inner(const double* __restrict__ part, int nb, float tol_inner,
+__global__ __launch_bounds__(1024) void k_fin_inner(const double* __restrict__ part, int nb, float tol_inner,
                                                    DevScal* sc) {
     __shared__ double red[2 * 16];
     const int z = blockIdx.x;
@@ -858,7 +858,7 @@ __global__ __launch_bounds__(kTileThreads) void k_wstep(KParams kp, int M, int N
 }
 
 // End of an outer iteration: r_k = ||phi^{k+1} - phi^k||_F / (||phi^k||_F + 1e-6).
-__global__ __launch_bounds__(256) void k_fin_outer(const double* __restrict__ part, int nb,
+__global__ __launch_bounds__(1024) void k_fin_outer(const double* __restrict__ part, int nb,
                                                    double* __restrict__ rhist, DevScal* sc) {
     __shared__ double red[2 * 16];
     const int z = blockIdx.x;
@@ -939,7 +939,7 @@ __global__ __launch_bounds__(kTileThreads) void k_energy(KParams kp, int M, int 
     store_partials<3>(v, part + (size_t)z * 3 * nb, nb, blockIdx.y * gridDim.x + blockIdx.x, red);
 }
 
-__global__ __launch_bounds__(256) void k_fin_energy(const double* __restrict__ part, int nb, KParams kp,
+__global__ __launch_bounds__(1024) void k_fin_energy(const double* __restrict__ part, int nb, KParams kp,
                                                     DevScal* sc) {
     __shared__ double red[3 * 16];
     const int z = blockIdx.x;
@@ -1048,7 +1048,7 @@ static void launch_row_inv_t(const float2* spec, const float* phi_in, float* phi
     const int nb = M / (8 * RT);
     hipLaunchKernelGGL(k_row_inv<N>, dim3(nb, 1, nz), dim3(4 * RT * NT), lds, st, spec, phi_in, phi_out,
                        twN, M, RT, tol, part, sc);
-    if (tol > 0.0f) hipLaunchKernelGGL(k_fin_inner, dim3(nz), dim3(256), 0, st, part, nb, tol, sc);
+    if (tol > 0.0f) hipLaunchKernelGGL(k_fin_inner, dim3(nz), dim3(1024), 0, st, part, nb, tol, sc);
 }
 
 template <int L>
@@ -1141,7 +1141,7 @@ void launch_wstep(const Geometry& geo, const KParams& kp, const float* phin, flo
                       st);
     }
     const int nb = ((geo.N + kTileW - 1) / kTileW) * ((geo.M + TH - 1) / TH);
-    hipLaunchKernelGGL(k_fin_outer, dim3(nz), dim3(256), 0, st, part, nb, rhist, sc);
+    hipLaunchKernelGGL(k_fin_outer, dim3(nz), dim3(1024), 0, st, part, nb, rhist, sc);
 }
 
 template <int TH, int R>
@@ -1162,7 +1162,7 @@ void launch_energy(const Geometry& geo, const KParams& kp, const float* phi, con
     hipLaunchKernelGGL(k_energy<kTH>, tile_grid(geo.M, geo.N, kTH, nz), dim3(kTileThreads), lds_energy(kTH, kp.R),
                        st, kp, geo.M, geo.N, phi, g, part, sc);
     const int nb = ((geo.N + kTileW - 1) / kTileW) * ((geo.M + kTH - 1) / kTH);
-    hipLaunchKernelGGL(k_fin_energy, dim3(nz), dim3(256), 0, st, part, nb, kp, sc);
+    hipLaunchKernelGGL(k_fin_energy, dim3(nz), dim3(1024), 0, st, part, nb, kp, sc);
 }
 
 void launch_repulsion(const Geometry& geo, const KParams& kp, const float* phi, const float* W, float* V,
