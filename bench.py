@@ -280,6 +280,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="ellipses-1024", choices=sorted(WORKLOADS))
     ap.add_argument("--profile-iters", type=int, default=20)
+    ap.add_argument("--tile-rows", type=int, default=0, choices=[0, 8, 16, 32],
+                    help="stencil tile height (default: chosen by the autotuner)")
     ap.add_argument("--cpu-iters", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB")
@@ -318,11 +320,13 @@ def main():
     steps = args.steps if args.steps is not None else wl["default_steps"]
     M, N = wl["M"], wl["N"]
     f, phi0 = make_input(args.workload)
+    if args.tile_rows:
+        os.environ["SR_TILE_TH"] = str(args.tile_rows)
     s = sr.Solver(M, N, device="cuda:0", **params_kw(wl))
     ft = torch.from_numpy(f.astype(np.float32)).cuda()
     pt = torch.from_numpy(phi0.astype(np.float32)).cuda()
     s.set_image(ft, pt)
-    tile_th, tune_us = s.autotune(5)
+    tile_th = args.tile_rows or s.autotune(20)[0]
     s.step(args.warmup)
     torch.cuda.synchronize()
 
