@@ -410,7 +410,7 @@ __device__ __forceinline__ const float2* stage_twiddles(float2* tws, const float
 // RT tiles (8 RT rows, 4 RT complex transforms) per workgroup.
 template <int N>
 __global__ __launch_bounds__(1024) void k_row_fwd(const float* __restrict__ src, float2* __restrict__ spec,
-                                                  const float2* __restrict__ twN, int M, int RT, DevScal* sc) {
+                                                  const float2* __restrict__ twN, int M, int lrpw, DevScal* sc) {
     constexpr int NT = FftShape<N>::NT, E = FftShape<N>::E, H = N / 2;
     const int z = blockIdx.z;
     if (!sc[z].active || sc[z].inner_done) return;
@@ -420,7 +420,7 @@ __global__ __launch_bounds__(1024) void k_row_fwd(const float* __restrict__ src,
     float2* xs = lds2 + TwQ<N>::n;
     const float2* tw = stage_twiddles<N>(lds2, twN);
     const int g = threadIdx.x / NT, t = threadIdx.x - g * NT;
-    const int row0 = blockIdx.x * (kSpecTile * RT);
+    const int row0 = blockIdx.x << lrpw;            // 2^lrpw rows (2^(lrpw-1) transforms) per workgroup
     const size_t ra = (size_t)(row0 + 2 * g) * N, rb = ra + N;
     constexpr int LX = LdsLen<N>::v;
     float2* x = xs + g * LX;
@@ -430,16 +430,25 @@ __global__ __launch_bounds__(1024) void k_row_fwd(const float* __restrict__ src,
         x[sk(n)] = make_float2(src[ra + n], src[rb + n]);
     }
     fft_lds<N, RowE<N>::v, false>(x, tw, t);
-    // The workgroup's tiles are one contiguous run of RT * 4N float2.
-    float2* dst = spec + (size_t)row0 * H;
+    // Whole 8-row tiles are one contiguous run of 4N float2 each; with fewer
+    // rows per workgroup it writes its rows of every 8-row run.
     const int nthr = blockDim.x;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int o = threadIdx.x + e * nthr;
-        const int r = o & 7;
-        const int kk = (o >> 3) & (H - 1);
-        const int tile = (o >> 3) / H;
-        const float2* xz = xs + (tile * 4 + (r >> 1)) * LX;
+        int r, kk;
+        size_t di;
+        if (lrpw >= 3) {
+            r = o & 7;
+            kk = (o >> 3) & (H - 1);
+            r += ((o >> 3) / H) * 8;
+            di = (size_t)row0 * H + o;
+        } else {
+            r = o & ((1 << lrpw) - 1);
+            kk = o >> lrpw;
+            di = ((size_t)(row0 >> 3) * H + kk) * 8 + (row0 & 7) + r;
+        }
+        const float2* xz = xs + (r >> 1) * LX;
         const float2 Zk = xz[sk(kk)];
         float2 out;
         if (kk == 0) {
@@ -450,7 +459,7 @@ __global__ __launch_bounds__(1024) void k_row_fwd(const float* __restrict__ src,
             out = (r & 1) ? make_float2(0.5f * (Zk.y + Zm.y), -0.5f * (Zk.x - Zm.x))
                           : make_float2(0.5f * (Zk.x + Zm.x), 0.5f * (Zk.y - Zm.y));
         }
-        dst[o] = out;
+        spec[di] = out;
     }
 }
 
@@ -534,7 +543,7 @@ __global__ __launch_bounds__(1024) void k_col_solve(float2* __restrict__ spec, c
 template <int N>
 __global__ __launch_bounds__(1024) void k_row_inv(const float2* __restrict__ spec, const float* __restrict__ phi_in,
                                                   float* __restrict__ phi_out, const float2* __restrict__ twN,
-                                                  int M, int RT, float tol_inner, double* __restrict__ part,
+                                                  int M, int lrpw, float tol_inner, double* __restrict__ part,
                                                   DevScal* sc) {
     constexpr int NT = FftShape<N>::NT, E = FftShape<N>::E, H = N / 2;
     const int z = blockIdx.z;
@@ -544,10 +553,10 @@ __global__ __launch_bounds__(1024) void k_row_inv(const float2* __restrict__ spe
     spec += (size_t)z * M * H;
     if (phi_in) phi_in += z * MN;
     phi_out += z * MN;
-    const int row0 = blockIdx.x * (kSpecTile * RT);
+    const int row0 = blockIdx.x << lrpw;
     if (S.inner_done) {
         const size_t base = (size_t)row0 * N;
-        for (int idx = threadIdx.x; idx < kSpecTile * RT * N; idx += blockDim.x)
+        for (int idx = threadIdx.x; idx < (N << lrpw); idx += blockDim.x)
             phi_out[base + idx] = phi_in ? phi_in[base + idx] : 0.0f;
         return;
     }
@@ -557,15 +566,23 @@ __global__ __launch_bounds__(1024) void k_row_inv(const float2* __restrict__ spe
     float2* xs = lds2 + TwQ<N>::n;
     const float2* tw = stage_twiddles<N>(lds2, twN);
     const int nthr = blockDim.x;
-    const float2* srcb = spec + (size_t)row0 * H;
     // stage the half spectra: row a of transform gg at x[k], row b at x[H + k]
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int o = threadIdx.x + e * nthr;
-        const int r = o & 7;
-        const int kk = (o >> 3) & (H - 1);
-        const int tile = (o >> 3) / H;
-        xs[(tile * 4 + (r >> 1)) * LX + sk((r & 1) * H + kk)] = srcb[o];
+        int r, kk;
+        size_t si;
+        if (lrpw >= 3) {
+            r = o & 7;
+            kk = (o >> 3) & (H - 1);
+            r += ((o >> 3) / H) * 8;
+            si = (size_t)row0 * H + o;
+        } else {
+            r = o & ((1 << lrpw) - 1);
+            kk = o >> lrpw;
+            si = ((size_t)(row0 >> 3) * H + kk) * 8 + (row0 & 7) + r;
+        }
+        xs[(r >> 1) * LX + sk((r & 1) * H + kk)] = spec[si];
     }
     __syncthreads();
     const int g = threadIdx.x / NT, t = threadIdx.x - g * NT;
@@ -986,19 +1003,37 @@ static int fft_nt_rt(int L, bool col) {
         default: return col ? FftShape<4096, ColE<4096>::v>::NT : FftShape<4096>::NT;
     }
 }
-int fft_row_tiles(int M, int N) {
+// log2 of the rows per workgroup of the row passes: whole 8-row tiles
+// (several for short rows, so a workgroup holds at least one wave), split
+// into 4- or 2-row pieces while the grid would have fewer than min_wg
+// workgroups and a piece still holds a full wave.  Measured at 1024^2: the
+// inverse pass gains from 256 workgroups (11.1 -> 9.8 us), the forward pass
+// does not (9.6 -> 10.5 us), so only the inverse pass splits.
+#ifndef SR_ROW_FWD_MIN_WG
+#define SR_ROW_FWD_MIN_WG 0
+#endif
+#ifndef SR_ROW_INV_MIN_WG
+#define SR_ROW_INV_MIN_WG 256
+#endif
+int fft_row_split(int M, int N, int nz, int min_wg) {
     const int NT = fft_nt_rt(N, false);
-    int RT = 1;
-    while (4 * RT * NT < 64 && RT * 8 * 2 <= M) RT <<= 1;
-    return RT;
+    int lr = 3;
+    while ((1 << lr) * 2 * NT < 64 * 4 && (2 << lr) <= M) ++lr;   // 4 * RT transforms of NT threads >= 64
+    while (lr > 1 && (M >> lr) * nz < min_wg && (1 << (lr - 2)) * NT >= 64) --lr;
+    return lr;
 }
 // Columns per workgroup of the column pass: 2 (128-byte runs), more for short
-// columns so a workgroup holds at least one wave.
-int fft_col_group(int M, int N) {
+// columns so a workgroup holds at least one wave; 1 while the grid would have
+// fewer than SR_COL_MIN_WG workgroups.
+#ifndef SR_COL_MIN_WG
+#define SR_COL_MIN_WG 0
+#endif
+int fft_col_group(int M, int N, int nz) {
     const int NT = fft_nt_rt(M, true);
     int G = 2;
     while (G * NT < 64 && G * 2 <= N / 2) G <<= 1;
     if (G > N / 2) G = N / 2;
+    if (G == 2 && NT >= 64 && (N / 2 / 2) * nz < SR_COL_MIN_WG) G = 1;
     return G;
 }
 
@@ -1023,16 +1058,16 @@ template <int N>
 static void launch_row_fwd_t(const float* src, float2* spec, const float2* twN, int M, int nz, DevScal* sc,
                              hipStream_t st) {
     const int NT = FftShape<N>::NT;
-    const int RT = fft_row_tiles(M, N);
-    const size_t lds = tw_lds_bytes<N>() + sizeof(float2) * 4 * RT * LdsLen<N>::v;
-    hipLaunchKernelGGL(k_row_fwd<N>, dim3(M / (8 * RT), 1, nz), dim3(4 * RT * NT), lds, st, src, spec, twN, M, RT,
-                       sc);
+    const int lr = fft_row_split(M, N, nz, SR_ROW_FWD_MIN_WG);
+    const size_t lds = tw_lds_bytes<N>() + sizeof(float2) * ((1 << lr) / 2) * LdsLen<N>::v;
+    hipLaunchKernelGGL(k_row_fwd<N>, dim3(M >> lr, 1, nz), dim3(((1 << lr) / 2) * NT), lds, st, src, spec, twN, M,
+                       lr, sc);
 }
 template <int M>
 static void launch_col_t(float2* spec, const float2* twM, const float2* twN, int N, float taumu, float inv_mn,
                          int nz, DevScal* sc, hipStream_t st) {
     const int NT = FftShape<M, ColE<M>::v>::NT;
-    const int G = fft_col_group(M, N);
+    const int G = fft_col_group(M, N, nz);
     const size_t lds = tw_lds_bytes<M>() + sizeof(float2) * G * LdsLen<M>::v;
     int lrun = 0;
     while ((1 << lrun) < kSpecTile * G) ++lrun;
@@ -1043,11 +1078,11 @@ template <int N>
 static void launch_row_inv_t(const float2* spec, const float* phi_in, float* phi_out, const float2* twN, int M,
                              float tol, double* part, int nz, DevScal* sc, hipStream_t st) {
     const int NT = FftShape<N>::NT;
-    const int RT = fft_row_tiles(M, N);
-    const size_t lds = tw_lds_bytes<N>() + sizeof(float2) * 4 * RT * LdsLen<N>::v;
-    const int nb = M / (8 * RT);
-    hipLaunchKernelGGL(k_row_inv<N>, dim3(nb, 1, nz), dim3(4 * RT * NT), lds, st, spec, phi_in, phi_out,
-                       twN, M, RT, tol, part, sc);
+    const int lr = fft_row_split(M, N, nz, SR_ROW_INV_MIN_WG);
+    const size_t lds = tw_lds_bytes<N>() + sizeof(float2) * ((1 << lr) / 2) * LdsLen<N>::v;
+    const int nb = M >> lr;
+    hipLaunchKernelGGL(k_row_inv<N>, dim3(nb, 1, nz), dim3(((1 << lr) / 2) * NT), lds, st, spec, phi_in, phi_out,
+                       twN, M, lr, tol, part, sc);
     if (tol > 0.0f) hipLaunchKernelGGL(k_fin_inner, dim3(nz), dim3(1024), 0, st, part, nb, tol, sc);
 }
 
