@@ -1,0 +1,97 @@
+"""The 4096 x 4096 workload in the benchmark's launch configuration (R = 5,
+eps = 2, 16-row stencil tiles), checked on sampled outputs.  The FP64 oracle
+cannot run whole iterations at this size, but every quantity below is local:
+the oracle's own functions are evaluated on a small periodic crop around
+each sampled pixel (the crop reaches every pixel the definition at the
+centre reads) and compared with the library's value there.
+
+With S = 1, one outer iteration solves (1 - tau mu Lap) phi^{k+1} = F^k once
+(eq 30 / 33), so the residual of the five-point operator at a pixel must
+equal F^k there (eq 37, local); w^{k+1} is the gate of eqs 40-42 applied to
+B of eq 41 at that pixel, b^{k+1} the Bregman update of eq 23."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import sr_oracle as O
+from paper_2003_12693_amd import synth
+from tests.helpers import gpu_params, oracle_params
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+M = N = 4096
+KW = dict(R=5, eps=2.0, d=5.0, S=1)
+
+
+def _note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _crop(a, i, j, c):
+    return a[np.ix_((np.arange(i - c, i + c + 1)) % a.shape[0], (np.arange(j - c, j + c + 1)) % a.shape[1])]
+
+
+def _lap_at(a, i, j):
+    return (a[(i + 1) % M, j] + a[(i - 1) % M, j] + a[i, (j + 1) % N] + a[i, (j - 1) % N] - 4.0 * a[i, j])
+
+
+def test_full_size_4096_sampled():
+    _note("full size 4096^2: sampled residual / gate / Bregman checks")
+    from paper_2003_12693_amd import sr
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import os
+    f, phi0 = synth.annuli(M, N, seed=3)
+    os.environ["SR_TILE_TH"] = "16"
+    try:
+        s = sr.Solver(M, N, gpu_params(**KW))
+    finally:
+        del os.environ["SR_TILE_TH"]
+    s.set_image(torch.from_numpy(f.astype(np.float32)).cuda(), torch.from_numpy(phi0.astype(np.float32)).cuda())
+    s.step(3)
+    host = lambda t: t.cpu().numpy().astype(np.float64)
+    phi, w, b, k = s.get_state()
+    phi, w, b = host(phi), host(w), host(b)
+    g = host(s.g())
+    s.step(1)
+    phi1, w1, b1, k1 = s.get_state()
+    phi1, w1, b1 = host(phi1), host(w1), host(b1)
+    assert k1 == k + 1
+    P = oracle_params(**KW)
+    R = P.R
+    c = R + 3
+    rng = np.random.default_rng(0)
+    band = np.argwhere(np.abs(phi) <= P.band_l + P.eps + 1)
+    picks = [(0, 0), (0, N - 1), (M - 1, 0), (M - 1, N - 1), (16, 64), (15, 63), (2047, 2048), (4095, 1)]
+    picks += [tuple(p) for p in band[rng.choice(len(band), 120, replace=False)]]
+    picks += [tuple(p) for p in rng.integers(0, M, size=(40, 2))]
+    taumu = P.tau * P.mu
+    worst_res = worst_b = 0.0
+    skipped = 0
+    for (i, j) in picks:
+        cr = lambda a: _crop(a, i, j, c)
+        F = O.phi_rhs(cr(phi), cr(w[0]), cr(w[1]), cr(b[0]), cr(b[1]), cr(g), P)[c, c]
+        lhs = phi1[i, j] - taumu * _lap_at(phi1, i, j)
+        scale = max(1.0, np.abs(cr(phi1)).max())
+        res = abs(lhs - F) / scale
+        worst_res = max(worst_res, res)
+        assert res <= 2e-6, ((i, j), lhs, F, scale)
+        B1, B2, t = O.shrink_input(cr(phi1), cr(w[0]), cr(w[1]), cr(b[0]), cr(b[1]), cr(g), P)
+        Bn = np.hypot(B1[c, c], B2[c, c])
+        if abs(Bn - t[c, c]) <= 1e-4 * max(1.0, Bn) or abs(Bn) <= 2 * P.zero_tol:
+            skipped += 1          # within rounding of the gate: either side is correct
+        else:
+            s1, s2 = O.shrink(B1[c:c + 1, c:c + 1], B2[c:c + 1, c:c + 1], t[c:c + 1, c:c + 1], P.zero_tol)
+            p1, p2 = O.project(s1, s2)
+            assert abs(w1[0, i, j] - p1[0, 0]) <= 2e-4 and abs(w1[1, i, j] - p2[0, 0]) <= 2e-4, ((i, j), Bn, t[c, c])
+        G1, G2 = O.grad_fwd(cr(phi1))
+        bb1 = b[0, i, j] + G1[c, c] - w1[0, i, j]
+        bb2 = b[1, i, j] + G2[c, c] - w1[1, i, j]
+        eb = max(abs(b1[0, i, j] - bb1), abs(b1[1, i, j] - bb2)) / max(1.0, abs(bb1), abs(bb2))
+        worst_b = max(worst_b, eb)
+        assert eb <= 1e-5, ((i, j), b1[:, i, j], bb1, bb2)
+    _note(f"  {len(picks)} pixels: worst solve residual {worst_res:.2e} (relative to |phi|), worst Bregman "
+          f"{worst_b:.2e}; {skipped} gate decisions within rounding skipped")
+    assert skipped <= len(picks) // 10
