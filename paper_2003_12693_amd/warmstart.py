@@ -280,6 +280,57 @@ def evaluate(params, seeds, k_plain=K_PLAIN, log=print):
     return summary, rows
 
 
+def evaluate_many(params, seeds, k_plain=K_PLAIN, chunk=128, log=print):
+    """Iterations saved and fallback rate over many held-out instances: the
+    plain solves run batched (sr_solve_batch gives every instance bitwise the
+    result of its single solve), each warm start is refined on its own."""
+    import torch
+    kw = solver_kw()
+    params_sr = sr.sr_params_default(**kw)
+    s = sr.Solver(SIZE, SIZE, **kw)
+    p = np.array(params, dtype=np.float32, copy=True)
+    p[-1] -= MARGIN / CLIP
+    net = cnn.Network(1, SIZE, SIZE, p)
+    rows = []
+    t_batch = 0.0
+    for c0 in range(0, len(seeds), chunk):
+        part = seeds[c0:c0 + chunk]
+        insts = [instance(sd) for sd in part]
+        ft = [torch.from_numpy(f).cuda() for f, _ in insts]
+        pt = [torch.from_numpy(q).cuda() for _, q in insts]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, res = sr.solve_batch([dict(f=a, phi0=b, max_iter=k_plain, params=params_sr) for a, b in zip(ft, pt)])
+        torch.cuda.synchronize()
+        t_batch += time.perf_counter() - t0
+        for sd, a, b, r in zip(part, ft, pt, res):
+            s.set_image(a, b)                   # g for the network input
+            ok, it_w, t_w, E_w, why = warm_solve(s, net, a, s.g(), b, k_plain, r["energy"])
+            rows.append({"seed": sd, "accepted": ok, "iters_warm": it_w, "reason": why, "E_plain": r["energy"],
+                         "E_warm": E_w, "rel_dE": None if E_w is None else (E_w - r["energy"]) / abs(r["energy"]),
+                         "t_warm": t_w})
+        acc = sum(1 for r in rows if r["accepted"])
+        log(f"  {len(rows)} instances: {acc} accepted, mean warm iterations "
+            f"{np.mean([r['iters_warm'] for r in rows if r['accepted']] or [0]):.0f}")
+    s.close()
+    net.close()
+    acc = [r for r in rows if r["accepted"]]
+    cost = [r["iters_warm"] if r["accepted"] else r["iters_warm"] + k_plain for r in rows]
+    summary = {
+        "instances": len(rows), "accepted": len(acc), "fallback_rate": 1 - len(acc) / len(rows),
+        "k_plain": k_plain, "e_tol": E_TOL, "margin_px": MARGIN,
+        "mean_iters_warm_accepted": float(np.mean([r["iters_warm"] for r in acc] or [0])),
+        "max_iters_warm_accepted": int(max([r["iters_warm"] for r in acc] or [0])),
+        "within_window": sum(1 for r in rows if r["reason"] == "energy reached"),
+        "max_abs_rel_dE_accepted": float(max([abs(r["rel_dE"]) for r in acc] or [0])),
+        "iters_saved_frac": float(1 - np.sum(cost) / (k_plain * len(rows))),
+        "plain_batched_s_per_instance": t_batch / len(rows),
+        "mean_warm_s_incl_inference": float(np.mean([r["t_warm"] for r in rows])),
+        "reasons": {k: sum(1 for r in rows if r["reason"] == k) for k in sorted({r["reason"] for r in rows})},
+    }
+    return summary, rows
+
+
 # ---------------------------------------------------------------------------
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
@@ -295,6 +346,8 @@ def main(argv=None):
     e = sub.add_parser("eval")
     e.add_argument("--weights", default=WEIGHTS)
     e.add_argument("--n-eval", type=int, default=32)
+    e.add_argument("--n-eval-many", type=int, default=0,
+                   help="also: iterations saved / fallback rate over this many held-out seeds (plain solves batched)")
     e.add_argument("--report", default=None)
     a = ap.parse_args(argv)
 
@@ -323,6 +376,12 @@ def main(argv=None):
     report["eval"] = summary
     report["eval_rows"] = rows
     log(json.dumps(summary))
+    if a.cmd == "eval" and a.n_eval_many:
+        log(f"evaluating iterations saved on {a.n_eval_many} held-out instances")
+        many, mrows = evaluate_many(params, list(range(EVAL_SEED0, EVAL_SEED0 + a.n_eval_many)), log=log)
+        report["eval_many"] = many
+        report["eval_many_rows"] = mrows
+        log(json.dumps(many))
     if a.report:
         with open(a.report, "w") as fh:
             json.dump(report, fh, indent=1)
