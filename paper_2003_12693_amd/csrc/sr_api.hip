@@ -816,22 +816,48 @@ int sr_solve_batch(sr_batch_item* items, int32_t n, void* workspace, size_t byte
             if (rc) return rc;
         }
     }
-    // one graph: a chunk of outer iterations of every group
+    // one graph: a chunk of outer iterations of every group, each group an
+    // independent branch (its own capture stream, forked from and joined to
+    // the origin), so groups of small instances run beside larger ones
     const int chunk = 10;
+    const int NB = std::min(G, 16);
     hipStream_t cap = nullptr;
-    HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    std::vector<hipStream_t> br(NB, nullptr);
+    std::vector<hipEvent_t> evb(NB, nullptr);
+    hipEvent_t fork = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+    for (int i = 0; i < NB && e == hipSuccess; ++i) {
+        e = hipStreamCreateWithFlags(&br[i], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&evb[i], hipEventDisableTiming);
+    }
+    auto release = [&]() {
+        for (int i = 0; i < NB; ++i) {
+            if (evb[i]) (void)hipEventDestroy(evb[i]);
+            if (br[i]) (void)hipStreamDestroy(br[i]);
+        }
+        if (fork) (void)hipEventDestroy(fork);
+        if (cap) (void)hipStreamDestroy(cap);
+    };
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        for (int it = 0; it < chunk; ++it)
-            for (int gi = 0; gi < G; ++gi) enqueue_iteration(&ctx[gi], it & 1, cap);
-        e = hipStreamEndCapture(cap, &graph);
+        e = hipEventRecord(fork, cap);
+        for (int i = 0; i < NB && e == hipSuccess; ++i) e = hipStreamWaitEvent(br[i], fork, 0);
+        for (int gi = 0; gi < G && e == hipSuccess; ++gi)
+            for (int it = 0; it < chunk; ++it) enqueue_iteration(&ctx[gi], it & 1, br[gi % NB]);
+        for (int i = 0; i < NB && e == hipSuccess; ++i) {
+            e = hipEventRecord(evb[i], br[i]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(cap, evb[i], 0);
+        }
+        hipError_t e2 = hipStreamEndCapture(cap, &graph);
+        if (e == hipSuccess) e = e2;
     }
     if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     if (graph) (void)hipGraphDestroy(graph);
     if (e != hipSuccess) {
-        (void)hipStreamDestroy(cap);
+        release();
         return fail(SR_EHIP, "batch graph: %s", hipGetErrorString(e));
     }
     int done = 0;
@@ -848,7 +874,7 @@ int sr_solve_batch(sr_batch_item* items, int32_t n, void* workspace, size_t byte
         if (!any_active) break;
     }
     (void)hipGraphExecDestroy(exec);
-    (void)hipStreamDestroy(cap);
+    release();
     if (e != hipSuccess) return fail(SR_EHIP, "batch iterations: %s", hipGetErrorString(e));
     // energies and outputs
     int worst = SR_OK;
