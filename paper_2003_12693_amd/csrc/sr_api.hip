@@ -639,53 +639,42 @@ int sr_profile_kernels(sr_ctx* c, int32_t n_iter, double ms[SR_NUM_KERNEL_KINDS]
     if (!c || !ms || !count) return fail(SR_EINVAL, "NULL argument");
     if (n_iter < 1) return fail(SR_EINVAL, "n_iter must be >= 1");
     if (!c->image_set) return fail(SR_ESTATE, "sr_profile_kernels before sr_set_image");
-    const int S = c->p.S;
-    const int per_iter = 4 * S + 1;
-    std::vector<hipEvent_t> ev(2 * (size_t)per_iter * n_iter);
-    for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
-    std::vector<int> kind;
-    kind.reserve((size_t)per_iter * n_iter);
-    size_t q = 0;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
     Bufs& b = c->b;
     hipStream_t st = c->stream;
-    for (int it = 0; it < n_iter; ++it) {
-        const int p = c->parity;
-        const float* in = b.P0;
-        float* outs[2] = {b.P1, b.P2};
-        for (int s = 0; s < S; ++s) {
-            float* out = outs[s & 1];
-            HIP_TRY(hipEventRecord(ev[q++], st));
-            sr::launch_rhs(c->geo, c->kp, in, b.W[p], b.g, b.D, b.Rb, 1, b.scal, st);
-            HIP_TRY(hipEventRecord(ev[q++], st));
-            kind.push_back(0);
-            for (int pass = 0; pass < 3; ++pass) {
-                HIP_TRY(hipEventRecord(ev[q++], st));
-                sr::launch_solve_pass(pass, c->geo, b.Rb, in, out, b.spec, c->kp.tol_inner, b.part, 1, b.scal, st);
-                HIP_TRY(hipEventRecord(ev[q++], st));
-                kind.push_back(1 + pass);
-            }
-            in = out;
-        }
-        HIP_TRY(hipEventRecord(ev[q++], st));
-        sr::launch_wstep(c->geo, c->kp, in, b.P0, b.W[p], b.B[p], b.g, b.W[1 - p], b.B[1 - p], b.D, b.part, b.rhist,
-                         1, b.scal, st);
-        HIP_TRY(hipEventRecord(ev[q++], st));
-        kind.push_back(4);
-        HIP_TRY(hipGetLastError());
-        c->parity ^= 1;
-        c->k += 1;
-    }
-    HIP_TRY(hipStreamSynchronize(st));
-    for (int i = 0; i < SR_NUM_KERNEL_KINDS; ++i) { ms[i] = 0.0; count[i] = 0; }
-    for (size_t i = 0; i < kind.size(); ++i) {
+    const int p = c->parity;
+    hipError_t e = hipSuccess;
+    // n_iter back-to-back launches of one kernel kind between one pair of events
+    auto timed = [&](int kind, auto&& launch) {
+        if (e == hipSuccess) e = hipEventRecord(e0, st);
+        for (int r = 0; r < n_iter && e == hipSuccess; ++r) launch();
+        if (e == hipSuccess) e = hipEventRecord(e1, st);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
         float t = 0.0f;
-        HIP_TRY(hipEventElapsedTime(&t, ev[2 * i], ev[2 * i + 1]));
-        ms[kind[i]] += t;
-        count[kind[i]] += 1;
-    }
-    for (int i = 0; i < SR_NUM_KERNEL_KINDS; ++i)
-        if (count[i]) ms[i] /= (double)count[i];
-    for (auto& e : ev) (void)hipEventDestroy(e);
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+        ms[kind] = (double)t / n_iter;
+        count[kind] = n_iter;
+    };
+    // The first inner step of an outer iteration from the current state; each
+    // kind reads valid inputs (the column pass transforms the spectrum in
+    // place, so it is rebuilt before the inverse pass), and the w step takes
+    // the first inner iterate as phi^{k+1} (the same band structure).
+    timed(0, [&] { sr::launch_rhs(c->geo, c->kp, b.P0, b.W[p], b.g, b.D, b.Rb, 1, b.scal, st); });
+    timed(1, [&] { sr::launch_solve_pass(0, c->geo, b.Rb, b.P0, b.P1, b.spec, c->kp.tol_inner, b.part, 1, b.scal, st); });
+    timed(2, [&] { sr::launch_solve_pass(1, c->geo, b.Rb, b.P0, b.P1, b.spec, c->kp.tol_inner, b.part, 1, b.scal, st); });
+    for (int pass = 0; pass < 2; ++pass)
+        sr::launch_solve_pass(pass, c->geo, b.Rb, b.P0, b.P1, b.spec, c->kp.tol_inner, b.part, 1, b.scal, st);
+    timed(3, [&] { sr::launch_solve_pass(2, c->geo, b.Rb, b.P0, b.P1, b.spec, c->kp.tol_inner, b.part, 1, b.scal, st); });
+    timed(4, [&] {
+        sr::launch_wstep(c->geo, c->kp, b.P1, b.P0, b.W[p], b.B[p], b.g, b.W[1 - p], b.B[1 - p], b.D, b.part, b.rhist,
+                         1, b.scal, st, false);
+    });
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return fail(SR_EHIP, "sr_profile_kernels: %s", hipGetErrorString(e));
+    HIP_TRY(hipGetLastError());
     return SR_OK;
 }
 

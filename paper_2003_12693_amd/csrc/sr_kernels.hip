@@ -1163,7 +1163,7 @@ void launch_rhs(const Geometry& geo, const KParams& kp, const float* phi_s, cons
 
 void launch_wstep(const Geometry& geo, const KParams& kp, const float* phin, float* P0, const float* Wold,
                   const float* Bold, const float* g, float* Wnew, float* Bnew, float* D, double* part,
-                  double* rhist, int nz, DevScal* sc, hipStream_t st) {
+                  double* rhist, int nz, DevScal* sc, hipStream_t st, bool finalize) {
     const int TH = tile_height(geo, nz);
     if (TH == 32) {
         SR_R_DISPATCH(launch_wstep_t, 32, kp.R, geo, kp, phin, P0, Wold, Bold, g, Wnew, Bnew, D, part, rhist, nz, sc,
@@ -1175,6 +1175,7 @@ void launch_wstep(const Geometry& geo, const KParams& kp, const float* phin, flo
         SR_R_DISPATCH(launch_wstep_t, 8, kp.R, geo, kp, phin, P0, Wold, Bold, g, Wnew, Bnew, D, part, rhist, nz, sc,
                       st);
     }
+    if (!finalize) return;
     const int nb = ((geo.N + kTileW - 1) / kTileW) * ((geo.M + TH - 1) / TH);
     hipLaunchKernelGGL(k_fin_outer, dim3(nz), dim3(1024), 0, st, part, nb, rhist, sc);
 }

@@ -36,9 +36,11 @@ void launch_solve(const Geometry& geo, const float* rhs, const float* phi_in, fl
 // 1: column solve, 2: inverse rows), for per-kernel timing.
 void launch_solve_pass(int pass, const Geometry& geo, const float* rhs, const float* phi_in, float* phi_out,
                        float2* spec, float tol_inner, double* part, int nz, DevScal* sc, hipStream_t st);
+// finalize = false launches the w step alone (no outer-residual finalize):
+// used by the per-kernel timing.
 void launch_wstep(const Geometry& geo, const KParams& kp, const float* phin, float* P0, const float* Wold,
                   const float* Bold, const float* g, float* Wnew, float* Bnew, float* D, double* part,
-                  double* rhist, int nz, DevScal* sc, hipStream_t st);
+                  double* rhist, int nz, DevScal* sc, hipStream_t st, bool finalize = true);
 void launch_energy(const Geometry& geo, const KParams& kp, const float* phi, const float* g, double* part,
                    int nz, DevScal* sc, hipStream_t st);
 void launch_repulsion(const Geometry& geo, const KParams& kp, const float* phi, const float* W, float* V,

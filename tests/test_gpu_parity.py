@@ -311,6 +311,27 @@ def test_determinism_and_checkpoint(sr):
     assert np.array_equal(d.phi().cpu().numpy(), pa)
 
 
+def test_profile_kernels_then_restore(sr):
+    """Per-kernel timing overwrites the iterate; restoring the saved state
+    makes the continued run bit-identical to an untimed one."""
+    _note("profile kernels / restore")
+    f, phi0 = synth.two_disks(seed=5)
+    a = sr.Solver(128, 128, gpu_params())
+    a.set_image(_cuda(f), _cuda(phi0))
+    a.step(7)
+    pa = a.phi().cpu().numpy()
+    b = sr.Solver(128, 128, gpu_params())
+    b.set_image(_cuda(f), _cuda(phi0))
+    b.step(3)
+    snap = b.get_state()
+    prof = sr.sr_profile_kernels(b.ctx, 4)
+    assert set(prof) == set(sr.KERNEL_KINDS)
+    assert all(ms > 0.0 and n == 4 for ms, n in prof.values()), prof
+    b.set_state(*snap)
+    b.step(4)
+    assert np.array_equal(b.phi().cpu().numpy(), pa)
+
+
 def test_nonfinite_input_rejected(sr):
     _note("nonfinite")
     s = sr.Solver(16, 16, gpu_params())
