@@ -172,17 +172,19 @@ int sr_repulsion(sr_ctx* ctx, const float* w, const float* phi, float* v_out, ui
 int sr_implicit_solve(sr_ctx* ctx, const float* rhs, float* u_out, uint32_t flags);
 
 /* ---- measurement -------------------------------------------------------
- * Per-kernel timing of the iteration: for each kernel kind, n_iter back-to-
- * back launches on the context's stream between one pair of hipEvents, on
- * the inputs of the first inner step of an outer iteration from the current
- * state (the w step takes that inner iterate as phi^{k+1}); reports the
- * average duration of a launch of each kind in milliseconds:
+ * Per-kernel timing of the iteration: runs n_iter outer iterations from the
+ * current state (the iterate advances exactly as under sr_step(ctx, n_iter),
+ * bitwise), launched directly on the context's stream instead of through a
+ * graph, each iteration kernel with its own start / stop hipEvents recorded
+ * at the kernel's own start and end (hipExtLaunchKernel), so every launch is
+ * timed in the cache state the iteration gives it.  Reports the average
+ * duration of a launch of each kind in milliseconds:
  *   ms[0] rhs + repulsion window (eq 37)   ms[1] forward row FFT
  *   ms[2] column FFT solve (eqs 31-33)     ms[3] inverse row FFT + update
  *   ms[4] w / b step (eqs 40-42, 23)
- * count[i] receives the number of launches of each kind.  Synchronises.
- * The iterate is left modified (phi^k, w, b, D of a partial iteration):
- * save it with sr_get_state before and restore it with sr_set_state after. */
+ * count[i] receives the number of launches timed (n_iter S for the first
+ * four kinds, n_iter for the w step).  Synchronises; ignores tol_outer.
+ * Returns SR_EINVAL for n_iter < 1, SR_ESTATE before sr_set_image. */
 #define SR_NUM_KERNEL_KINDS 5
 int sr_profile_kernels(sr_ctx* ctx, int32_t n_iter, double ms[SR_NUM_KERNEL_KINDS],
                        int64_t count[SR_NUM_KERNEL_KINDS]);

@@ -99,7 +99,7 @@ static int validate(int32_t M, int32_t N, const sr_params* p) {
 // workspace layout
 // ---------------------------------------------------------------------------
 struct Layout {
-    size_t twM, twN, g, P0, P1, P2, W0, W1, B0, B1, D, Rb, spec, part, scal, rhist, total;
+    size_t twM, twN, stM, stN, g, P0, P1, P2, W0, W1, B0, B1, D, Rb, spec, part, scal, rhist, total;
 };
 
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -112,6 +112,8 @@ static Layout make_layout(int M, int N, int nz) {
     auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
     L.twM = take(sizeof(float2) * M);
     L.twN = take(sizeof(float2) * N);
+    L.stM = take(sizeof(float2) * sr::fft_stage_table_len(M, true));
+    L.stN = take(sizeof(float2) * sr::fft_stage_table_len(N, false));
     L.g = take(pl);
     L.P0 = take(pl);
     L.P1 = take(pl);
@@ -135,7 +137,7 @@ static Layout make_layout(int M, int N, int nz) {
 // context
 // ---------------------------------------------------------------------------
 struct Bufs {
-    float2 *twM, *twN;
+    float2 *twM, *twN, *stM, *stN;
     float *g, *P0, *P1, *P2, *W[2], *B[2], *D, *Rb;
     float2* spec;
     double* part;
@@ -164,6 +166,8 @@ struct sr_ctx {
 static void carve(Bufs& b, char* base, const Layout& L) {
     b.twM = (float2*)(base + L.twM);
     b.twN = (float2*)(base + L.twN);
+    b.stM = (float2*)(base + L.stM);
+    b.stN = (float2*)(base + L.stN);
     b.g = (float*)(base + L.g);
     b.P0 = (float*)(base + L.P0);
     b.P1 = (float*)(base + L.P1);
@@ -218,19 +222,45 @@ static std::vector<float2> twiddles(int L) {
     return t;
 }
 
+// Twiddle tables of a context (full tables for lengths M and N, stage tables
+// of the column and row transforms), copied from pageable host memory.
+static hipError_t upload_tables(const Bufs& b, int M, int N, hipStream_t st) {
+    const std::vector<float2> tm = twiddles(M), tn = twiddles(N);
+    std::vector<float2> sm(sr::fft_stage_table_len(M, true)), sn(sr::fft_stage_table_len(N, false));
+    sr::fft_stage_table(M, true, sm.data());
+    sr::fft_stage_table(N, false, sn.data());
+    hipError_t e = hipMemcpyAsync(b.twM, tm.data(), sizeof(float2) * M, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(b.twN, tn.data(), sizeof(float2) * N, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && !sm.empty())
+        e = hipMemcpyAsync(b.stM, sm.data(), sizeof(float2) * sm.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && !sn.empty())
+        e = hipMemcpyAsync(b.stN, sn.data(), sizeof(float2) * sn.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);   // the host vectors are released on return
+    return e;
+}
+
 // The launch sequence of one outer iteration from parity p (Algorithm 1):
 // S x [rhs -> row FFT -> column solve -> inverse row FFT], then the w step.
-static void enqueue_iteration(sr_ctx* c, int p, hipStream_t st) {
+// before(kind) runs ahead of each iteration kernel's launch (kinds as in
+// sr_profile_kernels); the per-kernel timing uses it to arm events.
+struct NoHook { void operator()(int) const {} };
+template <typename Hook = NoHook>
+static void enqueue_iteration(sr_ctx* c, int p, hipStream_t st, Hook&& before = Hook{}) {
     Bufs& b = c->b;
     const int S = c->p.S;
     const float* in = b.P0;
     float* outs[2] = {b.P1, b.P2};
     for (int s = 0; s < S; ++s) {
         float* out = outs[s & 1];
+        before(0);
         sr::launch_rhs(c->geo, c->kp, in, b.W[p], b.g, b.D, b.Rb, c->nz, b.scal, st);
-        sr::launch_solve(c->geo, b.Rb, in, out, b.spec, c->kp.tol_inner, b.part, c->nz, b.scal, st);
+        for (int pass = 0; pass < 3; ++pass) {
+            before(1 + pass);
+            sr::launch_solve_pass(pass, c->geo, b.Rb, in, out, b.spec, c->kp.tol_inner, b.part, c->nz, b.scal, st);
+        }
         in = out;
     }
+    before(4);
     sr::launch_wstep(c->geo, c->kp, in, b.P0, b.W[p], b.B[p], b.g, b.W[1 - p], b.B[1 - p], b.D, b.part, b.rhist,
                      c->nz, b.scal, st);
 }
@@ -404,6 +434,8 @@ int sr_create(sr_ctx** out, int32_t M, int32_t N, const sr_params* p, void* work
     c->geo.N = N;
     c->geo.twM = c->b.twM;
     c->geo.twN = c->b.twN;
+    c->geo.stM = c->b.stM;
+    c->geo.stN = c->b.stN;
     c->geo.taumu = (float)(c->p.tau * c->p.mu);
     const char* ng = std::getenv("SR_NO_GRAPH");
     c->use_graphs = !(ng && ng[0] == '1');
@@ -412,9 +444,7 @@ int sr_create(sr_ctx** out, int32_t M, int32_t N, const sr_params* p, void* work
 
     hipError_t e = hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking);
     if (e != hipSuccess) { delete c; return fail(SR_EHIP, "hipStreamCreate: %s", hipGetErrorString(e)); }
-    const std::vector<float2> tm = twiddles(M), tn = twiddles(N);
-    e = hipMemcpyAsync(c->b.twM, tm.data(), sizeof(float2) * M, hipMemcpyHostToDevice, c->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(c->b.twN, tn.data(), sizeof(float2) * N, hipMemcpyHostToDevice, c->stream);
+    e = upload_tables(c->b, M, N, c->stream);
     if (e == hipSuccess) { sr::launch_reset_scal(c->b.scal, 1, 1, c->stream); e = hipGetLastError(); }
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {
@@ -639,42 +669,42 @@ int sr_profile_kernels(sr_ctx* c, int32_t n_iter, double ms[SR_NUM_KERNEL_KINDS]
     if (!c || !ms || !count) return fail(SR_EINVAL, "NULL argument");
     if (n_iter < 1) return fail(SR_EINVAL, "n_iter must be >= 1");
     if (!c->image_set) return fail(SR_ESTATE, "sr_profile_kernels before sr_set_image");
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    HIP_TRY(hipEventCreate(&e0));
-    HIP_TRY(hipEventCreate(&e1));
-    Bufs& b = c->b;
-    hipStream_t st = c->stream;
-    const int p = c->parity;
+    // n_iter outer iterations launched directly on the stream (no graph), the
+    // same kernels in the same order as a graph replay, each iteration kernel
+    // with its own start / stop events; synchronised after every iteration.
+    const int per = 4 * c->p.S + 1;
+    std::vector<hipEvent_t> ev(2 * (size_t)per, nullptr);
+    std::vector<int> kind(per, 0);
     hipError_t e = hipSuccess;
-    // n_iter back-to-back launches of one kernel kind between one pair of events
-    auto timed = [&](int kind, auto&& launch) {
-        if (e == hipSuccess) e = hipEventRecord(e0, st);
-        for (int r = 0; r < n_iter && e == hipSuccess; ++r) launch();
-        if (e == hipSuccess) e = hipEventRecord(e1, st);
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
-        float t = 0.0f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
-        ms[kind] = (double)t / n_iter;
-        count[kind] = n_iter;
-    };
-    // The first inner step of an outer iteration from the current state; each
-    // kind reads valid inputs (the column pass transforms the spectrum in
-    // place, so it is rebuilt before the inverse pass), and the w step takes
-    // the first inner iterate as phi^{k+1} (the same band structure).
-    timed(0, [&] { sr::launch_rhs(c->geo, c->kp, b.P0, b.W[p], b.g, b.D, b.Rb, 1, b.scal, st); });
-    timed(1, [&] { sr::launch_solve_pass(0, c->geo, b.Rb, b.P0, b.P1, b.spec, c->kp.tol_inner, b.part, 1, b.scal, st); });
-    timed(2, [&] { sr::launch_solve_pass(1, c->geo, b.Rb, b.P0, b.P1, b.spec, c->kp.tol_inner, b.part, 1, b.scal, st); });
-    for (int pass = 0; pass < 2; ++pass)
-        sr::launch_solve_pass(pass, c->geo, b.Rb, b.P0, b.P1, b.spec, c->kp.tol_inner, b.part, 1, b.scal, st);
-    timed(3, [&] { sr::launch_solve_pass(2, c->geo, b.Rb, b.P0, b.P1, b.spec, c->kp.tol_inner, b.part, 1, b.scal, st); });
-    timed(4, [&] {
-        sr::launch_wstep(c->geo, c->kp, b.P1, b.P0, b.W[p], b.B[p], b.g, b.W[1 - p], b.B[1 - p], b.D, b.part, b.rhist,
-                         1, b.scal, st, false);
-    });
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    for (auto& x : ev)
+        if (e == hipSuccess) e = hipEventCreate(&x);
+    double tot[SR_NUM_KERNEL_KINDS] = {};
+    int64_t cnt[SR_NUM_KERNEL_KINDS] = {};
+    for (int it = 0; it < n_iter && e == hipSuccess; ++it) {
+        int slot = 0;
+        enqueue_iteration(c, c->parity, c->stream, [&](int k) {
+            sr::set_launch_events(ev[2 * slot], ev[2 * slot + 1]);
+            kind[slot++] = k;
+        });
+        sr::set_launch_events(nullptr, nullptr);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        for (int s = 0; s < slot && e == hipSuccess; ++s) {
+            float t = 0.0f;
+            e = hipEventElapsedTime(&t, ev[2 * s], ev[2 * s + 1]);
+            tot[kind[s]] += t;
+            cnt[kind[s]] += 1;
+        }
+        c->parity ^= 1;
+        c->k += 1;
+    }
+    for (auto& x : ev)
+        if (x) (void)hipEventDestroy(x);
     if (e != hipSuccess) return fail(SR_EHIP, "sr_profile_kernels: %s", hipGetErrorString(e));
-    HIP_TRY(hipGetLastError());
+    for (int k = 0; k < SR_NUM_KERNEL_KINDS; ++k) {
+        ms[k] = cnt[k] ? tot[k] / (double)cnt[k] : 0.0;
+        count[k] = cnt[k];
+    }
     return SR_OK;
 }
 
@@ -758,10 +788,10 @@ int sr_solve_batch(sr_batch_item* items, int32_t n, void* workspace, size_t byte
         make_gauss(c.p.sigma, c.gauss, c.gauss_r);
         carve(c.b, (char*)workspace + plan.offset[gi], make_layout(c.M, c.N, c.nz));
         c.geo.M = c.M; c.geo.N = c.N; c.geo.twM = c.b.twM; c.geo.twN = c.b.twN;
+        c.geo.stM = c.b.stM; c.geo.stN = c.b.stN;
         c.geo.taumu = (float)(c.p.tau * c.p.mu);
-        const std::vector<float2> tm = twiddles(c.M), tn = twiddles(c.N);
-        HIP_TRY(hipMemcpy(c.b.twM, tm.data(), sizeof(float2) * c.M, hipMemcpyHostToDevice));
-        HIP_TRY(hipMemcpy(c.b.twN, tn.data(), sizeof(float2) * c.N, hipMemcpyHostToDevice));
+        HIP_TRY(upload_tables(c.b, c.M, c.N, st));
+        HIP_TRY(hipStreamSynchronize(st));
         hs[gi].assign(c.nz, DevScal{});
         for (int z = 0; z < c.nz; ++z) {
             const sr_batch_item& it = items[idx[z]];

@@ -179,14 +179,17 @@ __device__ __forceinline__ int sk(int i) { return i + (i >> 4); }
 // transforms start on different banks.
 template <int L> struct LdsLen { static constexpr int v = L + L / 16 + 4; };
 
-// Twiddle W_L^n = exp(-2 pi i n / L) for 0 <= n < L from the quarter table
-// Q[m] = W_L^m, m < L/4 (lq = log2(L/4)): W_L^n = (-i)^(n / (L/4)) Q[n mod L/4].
-__device__ __forceinline__ float2 twq(const float2* Q, int n, int lq) {
-    const int q = n >> lq;
-    const float2 t = Q[n & ((1 << lq) - 1)];
-    // q = 1: (y, -x); q = 2: (-x, -y); q = 3: (-y, x)
-    return make_float2(q == 0 ? t.x : (q == 2 ? -t.x : (q == 1 ? t.y : -t.y)),
-                       q == 0 ? t.y : (q == 2 ? -t.y : (q == 1 ? -t.x : t.x)));
+// Twiddle tables of the Stockham stages, one per (length L, elements per
+// thread EE), built on the host in FP64: for every stage with Ns > 1, in
+// stage order, Ns blocks of R float2, block k holding W_{R Ns}^{r k} for
+// r = 0..R-1 (entry 0 is 1, kept so that blocks are 16-byte aligned).  A
+// thread fetches its R - 1 factors with 16-byte global loads (the table is
+// at most ~37 KiB and stays in L1/L2), so no index or quadrant arithmetic
+// is left on the vector ALUs.
+constexpr int fft_radix(int L, int EE, int Ns) { return EE < L / Ns ? EE : L / Ns; }
+constexpr int stage_tab_len(int L, int EE, int Ns = 1) {
+    return Ns >= L ? 0
+                   : (Ns > 1 ? Ns * fft_radix(L, EE, Ns) : 0) + stage_tab_len(L, EE, Ns * fft_radix(L, EE, Ns));
 }
 
 // Multiplication by the constant W_16^m = exp(-2 pi i m / 16) (forward) or
@@ -259,12 +262,25 @@ __device__ __forceinline__ void dft(float2 (&u)[R]) {
 
 // One radix-R Stockham stage: sub-transform size Ns -> R Ns.  Butterfly j
 // reads x[j + r L/R], twiddles by W_{R Ns}^{r k} (k = j mod Ns), applies the
-// R-point DFT and writes x[(j - k) R + k + r Ns].  W_{R Ns}^m = W_L^{m L/(R Ns)}
-// comes from the quarter table tw (see twq).
+// R-point DFT and writes x[(j - k) R + k + r Ns].  tws: this stage's block of
+// the stage twiddle table.
 template <int L, int EE, int R, int Ns, bool INV>
-__device__ __forceinline__ void fft_stage(float2* x, const float2* __restrict__ tw, int t) {
-    constexpr int E = EE, NT = L / E, NB = E / R, Q = L / R, LQ = Ilog2<L>::v - 2;
-    constexpr int stride = L / (R * Ns);
+__device__ __forceinline__ void fft_stage(float2* x, const float2* __restrict__ tws, int t) {
+    constexpr int E = EE, NT = L / E, NB = E / R, Q = L / R;
+    float2 w[NB][R];
+    if constexpr (Ns > 1) {   // issued first: their latency overlaps the LDS reads
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int k = (t + b * NT) & (Ns - 1);
+            const float4* p = reinterpret_cast<const float4*>(tws + (size_t)k * R);
+#pragma unroll
+            for (int h = 0; h < R / 2; ++h) {
+                const float4 q = p[h];
+                w[b][2 * h] = make_float2(q.x, q.y);
+                w[b][2 * h + 1] = make_float2(q.z, q.w);
+            }
+        }
+    }
     float2 v[E];
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
@@ -282,10 +298,7 @@ __device__ __forceinline__ void fft_stage(float2* x, const float2* __restrict__ 
         for (int r = 0; r < R; ++r) u[r] = v[b * R + r];
         if constexpr (Ns > 1) {
 #pragma unroll
-            for (int r = 1; r < R; ++r) {
-                const float2 w = twq(tw, r * k * stride, LQ);
-                u[r] = INV ? cmulc(u[r], w) : cmul(u[r], w);
-            }
+            for (int r = 1; r < R; ++r) u[r] = INV ? cmulc(u[r], w[b][r]) : cmul(u[r], w[b][r]);
         }
         dft<R, INV>(u);
         const int base = (j - k) * R + k;
@@ -295,23 +308,25 @@ __device__ __forceinline__ void fft_stage(float2* x, const float2* __restrict__ 
     __syncthreads();
 }
 
-template <int L, int EE, bool INV, int Ns>
-__device__ __forceinline__ void fft_stages(float2* x, const float2* __restrict__ tw, int t) {
+// OFF: offset of this stage's block in the stage twiddle table.
+template <int L, int EE, bool INV, int Ns, int OFF>
+__device__ __forceinline__ void fft_stages(float2* x, const float2* __restrict__ tab, int t) {
     if constexpr (Ns < L) {
-        constexpr int R = (EE < L / Ns) ? EE : L / Ns;
-        fft_stage<L, EE, R, Ns, INV>(x, tw, t);
-        fft_stages<L, EE, INV, Ns * R>(x, tw, t);
+        constexpr int R = fft_radix(L, EE, Ns);
+        fft_stage<L, EE, R, Ns, INV>(x, tab + OFF, t);
+        fft_stages<L, EE, INV, Ns * R, OFF + (Ns > 1 ? Ns * R : 0)>(x, tab, t);
     }
 }
 
 // In-place length-L complex FFT of x (in LDS, skewed by sk()) by the NT = L/EE
 // threads t = 0..NT-1 of one transform: mixed-radix Stockham stages of radix
-// min(EE, remaining length).  Every thread of the workgroup must call it (it
-// contains workgroup barriers).  INV: unnormalised inverse.
+// min(EE, remaining length); tab: the stage twiddle table of (L, EE).  Every
+// thread of the workgroup must call it (it contains workgroup barriers).
+// INV: unnormalised inverse.
 template <int L, int EE, bool INV>
-__device__ __forceinline__ void fft_lds(float2* x, const float2* __restrict__ tw, int t) {
+__device__ __forceinline__ void fft_lds(float2* x, const float2* __restrict__ tab, int t) {
     __syncthreads();
-    fft_stages<L, EE, INV, 1>(x, tw, t);
+    fft_stages<L, EE, INV, 1, 0>(x, tab, t);
 }
 
 // ---------------------------------------------------------------------------

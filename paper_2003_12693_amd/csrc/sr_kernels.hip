@@ -14,6 +14,11 @@
 // whose planes sit at z * M * N (vector fields at z * 2 M N) from the given
 // base pointers and whose device scalars are sc[z]; an instance with
 // sc[z].active == 0 is skipped.
+#include <cmath>
+#include <cstdint>
+
+#include <hip/hip_ext.h>
+
 #include "sr_device.hpp"
 #include "sr_kernels.hpp"
 
@@ -384,41 +389,16 @@ __global__ __launch_bounds__(kTileThreads) void k_repulsion(KParams kp, int M, i
 // the column pass reads 128-byte runs (2 adjacent columns x 8 rows).
 constexpr int kSpecTile = 8;
 
-// The quarter twiddle table W_L^m, m < L/4, is staged in LDS by every FFT
-// workgroup (at most 8 KiB); other quadrants follow from powers of -i.
-template <int L> struct TwQ { static constexpr int n = L / 4; };
-
-template <int L>
-__device__ __forceinline__ const float2* stage_twiddles(float2* tws, const float2* __restrict__ tw) {
-    constexpr int NQ = TwQ<L>::n;
-    for (int base = threadIdx.x; base < NQ; base += 4 * blockDim.x) {
-        float2 tv[4];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int n = base + c * blockDim.x;
-            if (n < NQ) tv[c] = tw[n];
-        }
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int n = base + c * blockDim.x;
-            if (n < NQ) tws[n] = tv[c];
-        }
-    }
-    return tws;   // made visible by the barrier at the start of fft_lds
-}
-
 // RT tiles (8 RT rows, 4 RT complex transforms) per workgroup.
 template <int N>
 __global__ __launch_bounds__(1024) void k_row_fwd(const float* __restrict__ src, float2* __restrict__ spec,
-                                                  const float2* __restrict__ twN, int M, int lrpw, DevScal* sc) {
+                                                  const float2* __restrict__ stN, int M, int lrpw, DevScal* sc) {
     constexpr int NT = FftShape<N>::NT, E = FftShape<N>::E, H = N / 2;
     const int z = blockIdx.z;
     if (!sc[z].active || sc[z].inner_done) return;
     src += (size_t)z * M * N;
     spec += (size_t)z * M * H;
-    extern __shared__ float2 lds2[];
-    float2* xs = lds2 + TwQ<N>::n;
-    const float2* tw = stage_twiddles<N>(lds2, twN);
+    extern __shared__ float2 xs[];
     const int g = threadIdx.x / NT, t = threadIdx.x - g * NT;
     const int row0 = blockIdx.x << lrpw;            // 2^lrpw rows (2^(lrpw-1) transforms) per workgroup
     const size_t ra = (size_t)(row0 + 2 * g) * N, rb = ra + N;
@@ -429,7 +409,7 @@ __global__ __launch_bounds__(1024) void k_row_fwd(const float* __restrict__ src,
         const int n = t + e * NT;
         x[sk(n)] = make_float2(src[ra + n], src[rb + n]);
     }
-    fft_lds<N, RowE<N>::v, false>(x, tw, t);
+    fft_lds<N, RowE<N>::v, false>(x, stN, t);
     // Whole 8-row tiles are one contiguous run of 4N float2 each; with fewer
     // rows per workgroup it writes its rows of every 8-row run.
     const int nthr = blockDim.x;
@@ -469,17 +449,16 @@ __global__ __launch_bounds__(1024) void k_row_fwd(const float* __restrict__ src,
 // a + i b; they are separated, scaled by their own symbols and re-packed.
 template <int M>
 __global__ __launch_bounds__(1024) void k_col_solve(float2* __restrict__ spec, const float2* __restrict__ twM,
-                                                    const float2* __restrict__ twN, int N, int G, int lrun,
-                                                    float taumu, float inv_mn, DevScal* sc) {
+                                                    const float2* __restrict__ twN, const float2* __restrict__ stM,
+                                                    int N, int G, int lrun, float taumu, float inv_mn,
+                                                    DevScal* sc) {
     constexpr int NT = FftShape<M, ColE<M>::v>::NT, E = FftShape<M, ColE<M>::v>::E;
     constexpr int LD = LdsLen<M>::v;
     const int z = blockIdx.z;
     if (!sc[z].active || sc[z].inner_done) return;
     const int H = N / 2;
     spec += (size_t)z * M * H;
-    extern __shared__ float2 lds2[];
-    float2* xs = lds2 + TwQ<M>::n;
-    const float2* tw = stage_twiddles<M>(lds2, twM);
+    extern __shared__ float2 xs[];
     const int k0 = blockIdx.x * G;
     const int run = kSpecTile * G;                 // contiguous float2 per row tile (2^lrun)
     float2* base = spec + (size_t)k0 * kSpecTile;
@@ -501,21 +480,22 @@ __global__ __launch_bounds__(1024) void k_col_solve(float2* __restrict__ spec, c
     const int g = threadIdx.x / NT, t = threadIdx.x - g * NT;
     const int col = k0 + g;
     float2* x = xs + g * LD;
-    fft_lds<M, ColE<M>::v, false>(x, tw, t);
+    fft_lds<M, ColE<M>::v, false>(x, stM, t);
     // Divide by the symbol.  The symbol is even in l1, so each thread owns the
     // mirror pair (l, M - l): column 0's two packed real spectra mix Z[l]
     // with conj(Z[M - l]), every other column scales pointwise.
     const float cn = 2.0f * twN[col].x;
     auto scale_pair = [&](int l) {
         const int m = (M - l) & (M - 1);
-        const float cm = 2.0f * twq(tw, l, Ilog2<M>::v - 2).x;
+        const float cm = 2.0f * twM[l].x;
         float hp, hm;
+        // v_rcp_f32 (1 ulp) in place of an IEEE division: the symbol is >= 1
         if (col != 0) {
-            hp = inv_mn / (1.0f + taumu * (4.0f - cm - cn));
+            hp = inv_mn * __builtin_amdgcn_rcpf(1.0f + taumu * (4.0f - cm - cn));
             hm = 0.0f;
         } else {
-            const float p = inv_mn / (1.0f + taumu * (2.0f - cm));   // l2 = 0
-            const float q = inv_mn / (1.0f + taumu * (6.0f - cm));   // l2 = N/2
+            const float p = inv_mn * __builtin_amdgcn_rcpf(1.0f + taumu * (2.0f - cm));   // l2 = 0
+            const float q = inv_mn * __builtin_amdgcn_rcpf(1.0f + taumu * (6.0f - cm));   // l2 = N/2
             hp = 0.5f * (p + q);
             hm = 0.5f * (p - q);
         }
@@ -526,7 +506,7 @@ __global__ __launch_bounds__(1024) void k_col_solve(float2* __restrict__ spec, c
 #pragma unroll
     for (int e = 0; e < E / 2; ++e) scale_pair(t + e * NT);   // l in [0, M/2)
     if (t == 0) scale_pair(M / 2);
-    fft_lds<M, ColE<M>::v, true>(x, tw, t);
+    fft_lds<M, ColE<M>::v, true>(x, stM, t);
     __syncthreads();
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -542,7 +522,7 @@ __global__ __launch_bounds__(1024) void k_col_solve(float2* __restrict__ spec, c
 // the remaining inner steps of the outer iteration copy phi_s through.
 template <int N>
 __global__ __launch_bounds__(1024) void k_row_inv(const float2* __restrict__ spec, const float* __restrict__ phi_in,
-                                                  float* __restrict__ phi_out, const float2* __restrict__ twN,
+                                                  float* __restrict__ phi_out, const float2* __restrict__ stN,
                                                   int M, int lrpw, float tol_inner, double* __restrict__ part,
                                                   DevScal* sc) {
     constexpr int NT = FftShape<N>::NT, E = FftShape<N>::E, H = N / 2;
@@ -560,11 +540,9 @@ __global__ __launch_bounds__(1024) void k_row_inv(const float2* __restrict__ spe
             phi_out[base + idx] = phi_in ? phi_in[base + idx] : 0.0f;
         return;
     }
-    extern __shared__ float2 lds2[];
+    extern __shared__ float2 xs[];
     __shared__ double red[2 * 16];
     constexpr int LX = LdsLen<N>::v;
-    float2* xs = lds2 + TwQ<N>::n;
-    const float2* tw = stage_twiddles<N>(lds2, twN);
     const int nthr = blockDim.x;
     // stage the half spectra: row a of transform gg at x[k], row b at x[H + k]
 #pragma unroll
@@ -607,7 +585,7 @@ __global__ __launch_bounds__(1024) void k_row_inv(const float2* __restrict__ spe
             x[sk(N - k)] = make_float2(Xa.x + Xb.y, Xb.x - Xa.y);
         }
     }
-    fft_lds<N, RowE<N>::v, true>(x, tw, t);
+    fft_lds<N, RowE<N>::v, true>(x, stN, t);
     const size_t ra = (size_t)(row0 + 2 * g) * N, rb = ra + N;
     double sd = 0.0, sp = 0.0;
 #pragma unroll
@@ -1037,7 +1015,56 @@ int fft_col_group(int M, int N, int nz) {
     return G;
 }
 
-template <int L> constexpr size_t tw_lds_bytes() { return sizeof(float2) * TwQ<L>::n; }
+
+// Per-launch timing of the iteration kernels: while events are set on the
+// calling host thread, their launches go through hipExtLaunchKernel with
+// those events, which the runtime records at the kernel's own start and end
+// (never used under stream capture).
+static thread_local hipEvent_t t_ev_start = nullptr, t_ev_stop = nullptr;
+void set_launch_events(hipEvent_t start, hipEvent_t stop) {
+    t_ev_start = start;
+    t_ev_stop = stop;
+}
+template <typename... KArgs, typename... Args>
+static void launch_iter(void (*kernel)(KArgs...), dim3 grid, dim3 block, size_t lds, hipStream_t st, Args... args) {
+    if (t_ev_start)
+        hipExtLaunchKernelGGL(kernel, grid, block, (std::uint32_t)lds, st, t_ev_start, t_ev_stop, 0u,
+                              static_cast<KArgs>(args)...);
+    else
+        hipLaunchKernelGGL(kernel, grid, block, lds, st, static_cast<KArgs>(args)...);
+}
+
+// Elements per thread of the row (col = false) or column transforms of length L.
+static int fft_e(int L, bool col) {
+    switch (L) {
+        case 8: return col ? ColE<8>::v : RowE<8>::v;
+        case 16: return col ? ColE<16>::v : RowE<16>::v;
+        case 32: return col ? ColE<32>::v : RowE<32>::v;
+        case 64: return col ? ColE<64>::v : RowE<64>::v;
+        case 128: return col ? ColE<128>::v : RowE<128>::v;
+        case 256: return col ? ColE<256>::v : RowE<256>::v;
+        case 512: return col ? ColE<512>::v : RowE<512>::v;
+        case 1024: return col ? ColE<1024>::v : RowE<1024>::v;
+        case 2048: return col ? ColE<2048>::v : RowE<2048>::v;
+        default: return col ? ColE<4096>::v : RowE<4096>::v;
+    }
+}
+int fft_stage_table_len(int L, bool col) { return stage_tab_len(L, fft_e(L, col)); }
+void fft_stage_table(int L, bool col, float2* out) {
+    const int E = fft_e(L, col);
+    const double two_pi = 6.283185307179586476925286766559;
+    size_t o = 0;
+    for (int Ns = 1; Ns < L;) {
+        const int R = fft_radix(L, E, Ns);
+        if (Ns > 1)
+            for (int k = 0; k < Ns; ++k)
+                for (int r = 0; r < R; ++r) {
+                    const double a = two_pi * (double)(r * k) / (double)(R * Ns);
+                    out[o++] = make_float2((float)std::cos(a), (float)-std::sin(a));
+                }
+        Ns *= R;
+    }
+}
 
 #define SR_FFT_DISPATCH(FN, LEN, ...)                                   \
     switch (LEN) {                                                      \
@@ -1055,34 +1082,33 @@ template <int L> constexpr size_t tw_lds_bytes() { return sizeof(float2) * TwQ<L
     }
 
 template <int N>
-static void launch_row_fwd_t(const float* src, float2* spec, const float2* twN, int M, int nz, DevScal* sc,
+static void launch_row_fwd_t(const float* src, float2* spec, const float2* stN, int M, int nz, DevScal* sc,
                              hipStream_t st) {
     const int NT = FftShape<N>::NT;
     const int lr = fft_row_split(M, N, nz, SR_ROW_FWD_MIN_WG);
-    const size_t lds = tw_lds_bytes<N>() + sizeof(float2) * ((1 << lr) / 2) * LdsLen<N>::v;
-    hipLaunchKernelGGL(k_row_fwd<N>, dim3(M >> lr, 1, nz), dim3(((1 << lr) / 2) * NT), lds, st, src, spec, twN, M,
-                       lr, sc);
+    const size_t lds = sizeof(float2) * ((1 << lr) / 2) * LdsLen<N>::v;
+    launch_iter(k_row_fwd<N>, dim3(M >> lr, 1, nz), dim3(((1 << lr) / 2) * NT), lds, st, src, spec, stN, M, lr, sc);
 }
 template <int M>
-static void launch_col_t(float2* spec, const float2* twM, const float2* twN, int N, float taumu, float inv_mn,
-                         int nz, DevScal* sc, hipStream_t st) {
+static void launch_col_t(float2* spec, const float2* twM, const float2* twN, const float2* stM, int N, float taumu,
+                         float inv_mn, int nz, DevScal* sc, hipStream_t st) {
     const int NT = FftShape<M, ColE<M>::v>::NT;
     const int G = fft_col_group(M, N, nz);
-    const size_t lds = tw_lds_bytes<M>() + sizeof(float2) * G * LdsLen<M>::v;
+    const size_t lds = sizeof(float2) * G * LdsLen<M>::v;
     int lrun = 0;
     while ((1 << lrun) < kSpecTile * G) ++lrun;
-    hipLaunchKernelGGL(k_col_solve<M>, dim3(N / 2 / G, 1, nz), dim3(NT * G), lds, st, spec, twM, twN, N, G, lrun,
-                       taumu, inv_mn, sc);
+    launch_iter(k_col_solve<M>, dim3(N / 2 / G, 1, nz), dim3(NT * G), lds, st, spec, twM, twN, stM, N, G, lrun, taumu,
+                inv_mn, sc);
 }
 template <int N>
-static void launch_row_inv_t(const float2* spec, const float* phi_in, float* phi_out, const float2* twN, int M,
+static void launch_row_inv_t(const float2* spec, const float* phi_in, float* phi_out, const float2* stN, int M,
                              float tol, double* part, int nz, DevScal* sc, hipStream_t st) {
     const int NT = FftShape<N>::NT;
     const int lr = fft_row_split(M, N, nz, SR_ROW_INV_MIN_WG);
-    const size_t lds = tw_lds_bytes<N>() + sizeof(float2) * ((1 << lr) / 2) * LdsLen<N>::v;
+    const size_t lds = sizeof(float2) * ((1 << lr) / 2) * LdsLen<N>::v;
     const int nb = M >> lr;
-    hipLaunchKernelGGL(k_row_inv<N>, dim3(nb, 1, nz), dim3(((1 << lr) / 2) * NT), lds, st, spec, phi_in, phi_out,
-                       twN, M, lr, tol, part, sc);
+    launch_iter(k_row_inv<N>, dim3(nb, 1, nz), dim3(((1 << lr) / 2) * NT), lds, st, spec, phi_in, phi_out, stN, M, lr,
+                tol, part, sc);
     if (tol > 0.0f) hipLaunchKernelGGL(k_fin_inner, dim3(nz), dim3(1024), 0, st, part, nb, tol, sc);
 }
 
@@ -1098,12 +1124,12 @@ void launch_solve_pass(int pass, const Geometry& geo, const float* rhs, const fl
                        float2* spec, float tol_inner, double* part, int nz, DevScal* sc, hipStream_t st) {
     const int M = geo.M, N = geo.N;
     if (pass == 0) {
-        SR_FFT_DISPATCH(launch_row_fwd_t, N, rhs, spec, geo.twN, M, nz, sc, st);
+        SR_FFT_DISPATCH(launch_row_fwd_t, N, rhs, spec, geo.stN, M, nz, sc, st);
     } else if (pass == 1) {
         const float inv_mn = 1.0f / ((float)M * (float)N);
-        SR_FFT_DISPATCH(launch_col_t, M, spec, geo.twM, geo.twN, N, geo.taumu, inv_mn, nz, sc, st);
+        SR_FFT_DISPATCH(launch_col_t, M, spec, geo.twM, geo.twN, geo.stM, N, geo.taumu, inv_mn, nz, sc, st);
     } else {
-        SR_FFT_DISPATCH(launch_row_inv_t, N, spec, phi_in, phi_out, geo.twN, M, tol_inner, part, nz, sc, st);
+        SR_FFT_DISPATCH(launch_row_inv_t, N, spec, phi_in, phi_out, geo.stN, M, tol_inner, part, nz, sc, st);
     }
 }
 
@@ -1124,15 +1150,16 @@ static int tile_height(const Geometry& geo, int nz) {
 template <int TH, int R>
 static void launch_rhs_t(const Geometry& geo, const KParams& kp, const float* phi_s, const float* W, const float* g,
                          const float* D, float* out, int nz, DevScal* sc, hipStream_t st) {
-    k_rhs<TH, R><<<tile_grid(geo.M, geo.N, TH, nz), dim3(kTileThreads), sizeof(float) * RhsTile<TH, R>::lds_floats,
-                   st>>>(kp, geo.M, geo.N, phi_s, W, g, D, out, sc);
+    launch_iter(k_rhs<TH, R>, tile_grid(geo.M, geo.N, TH, nz), dim3(kTileThreads),
+                sizeof(float) * RhsTile<TH, R>::lds_floats, st, kp, geo.M, geo.N, phi_s, W, g, D, out, sc);
 }
 template <int TH, int R>
 static void launch_wstep_t(const Geometry& geo, const KParams& kp, const float* phin, float* P0, const float* Wold,
                            const float* Bold, const float* g, float* Wnew, float* Bnew, float* D, double* part,
                            double* rhist, int nz, DevScal* sc, hipStream_t st) {
-    k_wstep<TH, R><<<tile_grid(geo.M, geo.N, TH, nz), dim3(kTileThreads), sizeof(float) * WTile<TH, R>::lds_floats,
-                     st>>>(kp, geo.M, geo.N, phin, P0, Wold, Bold, g, Wnew, Bnew, D, part, rhist, sc);
+    launch_iter(k_wstep<TH, R>, tile_grid(geo.M, geo.N, TH, nz), dim3(kTileThreads),
+                sizeof(float) * WTile<TH, R>::lds_floats, st, kp, geo.M, geo.N, phin, P0, Wold, Bold, g, Wnew, Bnew, D,
+                part, rhist, sc);
 }
 
 #define SR_R_DISPATCH(FN, TH, R, ...)                                                          \
@@ -1163,7 +1190,7 @@ void launch_rhs(const Geometry& geo, const KParams& kp, const float* phi_s, cons
 
 void launch_wstep(const Geometry& geo, const KParams& kp, const float* phin, float* P0, const float* Wold,
                   const float* Bold, const float* g, float* Wnew, float* Bnew, float* D, double* part,
-                  double* rhist, int nz, DevScal* sc, hipStream_t st, bool finalize) {
+                  double* rhist, int nz, DevScal* sc, hipStream_t st) {
     const int TH = tile_height(geo, nz);
     if (TH == 32) {
         SR_R_DISPATCH(launch_wstep_t, 32, kp.R, geo, kp, phin, P0, Wold, Bold, g, Wnew, Bnew, D, part, rhist, nz, sc,
@@ -1175,7 +1202,6 @@ void launch_wstep(const Geometry& geo, const KParams& kp, const float* phin, flo
         SR_R_DISPATCH(launch_wstep_t, 8, kp.R, geo, kp, phin, P0, Wold, Bold, g, Wnew, Bnew, D, part, rhist, nz, sc,
                       st);
     }
-    if (!finalize) return;
     const int nb = ((geo.N + kTileW - 1) / kTileW) * ((geo.M + TH - 1) / TH);
     hipLaunchKernelGGL(k_fin_outer, dim3(nz), dim3(1024), 0, st, part, nb, rhist, sc);
 }

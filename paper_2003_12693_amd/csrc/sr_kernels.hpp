@@ -12,13 +12,23 @@ namespace sr {
 // length N and the column length M, and tau * mu of eq (32).
 struct Geometry {
     int M, N;
-    const float2* twM;
-    const float2* twN;
+    const float2* twM;      // W_M^n, n < M (FP64-computed, rounded)
+    const float2* twN;      // W_N^n, n < N
+    const float2* stM;      // stage twiddle table of the column transforms (length M)
+    const float2* stN;      // stage twiddle table of the row transforms (length N)
     float taumu;
     int tile_th = 0;   // stencil tile height (16 or 32); 0 = size heuristic
 };
 
 int tile_blocks(int M, int N);
+// Stage twiddle tables of the FFT passes: float2 entries, and the host-side
+// construction (col: the column pass's table for length L, else the row passes').
+int fft_stage_table_len(int L, bool col);
+// While set (non-null) on the calling host thread, the iteration kernels
+// (rhs, the three FFT passes, w step) are launched with these events, which
+// record the kernel's own start and end; set both to nullptr to stop.
+void set_launch_events(hipEvent_t start, hipEvent_t stop);
+void fft_stage_table(int L, bool col, float2* out);
 
 void launch_edge(const Geometry& geo, const float* f, float* tmp, float* fs, float* g, const float* taps, int r,
                  float rho, int s_exp, DevScal* sc, hipStream_t st, int nz = 1);
@@ -36,11 +46,9 @@ void launch_solve(const Geometry& geo, const float* rhs, const float* phi_in, fl
 // 1: column solve, 2: inverse rows), for per-kernel timing.
 void launch_solve_pass(int pass, const Geometry& geo, const float* rhs, const float* phi_in, float* phi_out,
                        float2* spec, float tol_inner, double* part, int nz, DevScal* sc, hipStream_t st);
-// finalize = false launches the w step alone (no outer-residual finalize):
-// used by the per-kernel timing.
 void launch_wstep(const Geometry& geo, const KParams& kp, const float* phin, float* P0, const float* Wold,
                   const float* Bold, const float* g, float* Wnew, float* Bnew, float* D, double* part,
-                  double* rhist, int nz, DevScal* sc, hipStream_t st, bool finalize = true);
+                  double* rhist, int nz, DevScal* sc, hipStream_t st);
 void launch_energy(const Geometry& geo, const KParams& kp, const float* phi, const float* g, double* part,
                    int nz, DevScal* sc, hipStream_t st);
 void launch_repulsion(const Geometry& geo, const KParams& kp, const float* phi, const float* W, float* V,

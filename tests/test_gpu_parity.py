@@ -311,25 +311,30 @@ def test_determinism_and_checkpoint(sr):
     assert np.array_equal(d.phi().cpu().numpy(), pa)
 
 
-def test_profile_kernels_then_restore(sr):
-    """Per-kernel timing overwrites the iterate; restoring the saved state
-    makes the continued run bit-identical to an untimed one."""
-    _note("profile kernels / restore")
+def test_profile_kernels_advance_like_step(sr):
+    """The per-kernel timing runs real outer iterations (without a graph):
+    3 steps + 4 timed iterations give bitwise the phi of 7 plain steps, the
+    iteration count advances, and every kind reports its launch count."""
+    _note("profile kernels")
     f, phi0 = synth.two_disks(seed=5)
-    a = sr.Solver(128, 128, gpu_params())
+    kw = gpu_params()
+    a = sr.Solver(128, 128, kw)
     a.set_image(_cuda(f), _cuda(phi0))
     a.step(7)
     pa = a.phi().cpu().numpy()
-    b = sr.Solver(128, 128, gpu_params())
+    b = sr.Solver(128, 128, kw)
     b.set_image(_cuda(f), _cuda(phi0))
     b.step(3)
-    snap = b.get_state()
     prof = sr.sr_profile_kernels(b.ctx, 4)
     assert set(prof) == set(sr.KERNEL_KINDS)
-    assert all(ms > 0.0 and n == 4 for ms, n in prof.values()), prof
-    b.set_state(*snap)
-    b.step(4)
+    S = kw.S
+    for k, (ms, n) in prof.items():
+        assert ms > 0.0 and n == (4 if k == "w_step" else 4 * S), (k, ms, n)
     assert np.array_equal(b.phi().cpu().numpy(), pa)
+    assert b.get_state()[3] == 7
+    with pytest.raises(sr.SRError) as e:
+        sr.sr_profile_kernels(b.ctx, 0)
+    assert e.value.code == sr.SR_EINVAL
 
 
 def test_nonfinite_input_rejected(sr):
