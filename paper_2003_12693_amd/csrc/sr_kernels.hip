@@ -389,10 +389,13 @@ __global__ __launch_bounds__(kTileThreads) void k_repulsion(KParams kp, int M, i
 // the column pass reads 128-byte runs (2 adjacent columns x 8 rows).
 constexpr int kSpecTile = 8;
 
-// RT tiles (8 RT rows, 4 RT complex transforms) per workgroup.
-template <int N>
+// RT tiles (8 RT rows, 4 RT complex transforms) per workgroup.  LR > 0 fixes
+// log2(rows per workgroup) at compile time (the common launch shapes, so the
+// index arithmetic folds); LR = 0 takes it from lrpw.
+template <int N, int LR>
 __global__ __launch_bounds__(1024) void k_row_fwd(const float* __restrict__ src, float2* __restrict__ spec,
-                                                  const float2* __restrict__ stN, int M, int lrpw, DevScal* sc) {
+                                                  const float2* __restrict__ stN, int M, int lrpw_rt, DevScal* sc) {
+    const int lrpw = LR ? LR : lrpw_rt;
     constexpr int NT = FftShape<N>::NT, E = FftShape<N>::E, H = N / 2;
     const int z = blockIdx.z;
     if (!sc[z].active || sc[z].inner_done) return;
@@ -412,7 +415,7 @@ __global__ __launch_bounds__(1024) void k_row_fwd(const float* __restrict__ src,
     fft_lds<N, RowE<N>::v, false>(x, stN, t);
     // Whole 8-row tiles are one contiguous run of 4N float2 each; with fewer
     // rows per workgroup it writes its rows of every 8-row run.
-    const int nthr = blockDim.x;
+    const int nthr = LR ? ((1 << LR) / 2) * NT : (int)blockDim.x;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int o = threadIdx.x + e * nthr;
@@ -447,11 +450,17 @@ __global__ __launch_bounds__(1024) void k_row_fwd(const float* __restrict__ src,
 // by M N (1 + tau mu (4 - 2cos(2 pi l1/M) - 2cos(2 pi l2/N))), inverse FFT.
 // Column 0 holds two real-signal spectra (l2 = 0 and l2 = N/2) packed as
 // a + i b; they are separated, scaled by their own symbols and re-packed.
-template <int M>
-__global__ __launch_bounds__(1024) void k_col_solve(float2* __restrict__ spec, const float2* __restrict__ twM,
+// GT > 0 fixes G at compile time (the common shape); GT = 0 takes G, lrun.
+template <int M, int GT>
+// At most 64 VGPRs (8 waves per SIMD): two 1024-thread workgroups of the
+// 4096-point pass share a CU (their LDS fits twice), which the pass needs.
+__global__ __launch_bounds__(1024, 8) void k_col_solve(float2* __restrict__ spec, const float2* __restrict__ twM,
                                                     const float2* __restrict__ twN, const float2* __restrict__ stM,
-                                                    int N, int G, int lrun, float taumu, float inv_mn,
+                                                    int N, int G_rt, int lrun_rt, float taumu, float inv_mn,
                                                     DevScal* sc) {
+    const int G = GT ? GT : G_rt;
+    const int lrun = GT ? Ilog2<kSpecTile * (GT ? GT : 1)>::v : lrun_rt;
+    const int nthr = GT ? FftShape<M, ColE<M>::v>::NT * GT : (int)blockDim.x;
     constexpr int NT = FftShape<M, ColE<M>::v>::NT, E = FftShape<M, ColE<M>::v>::E;
     constexpr int LD = LdsLen<M>::v;
     const int z = blockIdx.z;
@@ -467,12 +476,12 @@ __global__ __launch_bounds__(1024) void k_col_solve(float2* __restrict__ spec, c
         float2 ld[E];
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            const int idx = threadIdx.x + e * blockDim.x;
+            const int idx = threadIdx.x + e * nthr;
             ld[e] = base[(size_t)(idx >> lrun) * H * kSpecTile + (idx & (run - 1))];
         }
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            const int idx = threadIdx.x + e * blockDim.x;
+            const int idx = threadIdx.x + e * nthr;
             const int rem = idx & (run - 1);
             xs[(rem >> 3) * LD + sk((idx >> lrun) * kSpecTile + (rem & 7))] = ld[e];
         }
@@ -508,9 +517,14 @@ __global__ __launch_bounds__(1024) void k_col_solve(float2* __restrict__ spec, c
     if (t == 0) scale_pair(M / 2);
     fft_lds<M, ColE<M>::v, true>(x, stM, t);
     __syncthreads();
+    // An empty asm on the thread index keeps the compiler from computing the
+    // store addresses at the top and holding them (or spilling them) through
+    // both transforms.
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-        const int idx = threadIdx.x + e * blockDim.x;
+        const int idx = tid + e * nthr;
         const int q = idx >> lrun, rem = idx & (run - 1);
         base[(size_t)q * H * kSpecTile + rem] = xs[(rem >> 3) * LD + sk(q * kSpecTile + (rem & 7))];
     }
@@ -520,11 +534,12 @@ __global__ __launch_bounds__(1024) void k_col_solve(float2* __restrict__ spec, c
 // With tol_inner > 0, also the inner stop rule ||dphi|| / (||phi_s|| + 1e-6)
 // <= tol (grid-wide sum, last workgroup decides).  Once the rule has fired,
 // the remaining inner steps of the outer iteration copy phi_s through.
-template <int N>
+template <int N, int LR>
 __global__ __launch_bounds__(1024) void k_row_inv(const float2* __restrict__ spec, const float* __restrict__ phi_in,
                                                   float* __restrict__ phi_out, const float2* __restrict__ stN,
-                                                  int M, int lrpw, float tol_inner, double* __restrict__ part,
+                                                  int M, int lrpw_rt, float tol_inner, double* __restrict__ part,
                                                   DevScal* sc) {
+    const int lrpw = LR ? LR : lrpw_rt;
     constexpr int NT = FftShape<N>::NT, E = FftShape<N>::E, H = N / 2;
     const int z = blockIdx.z;
     DevScal& S = sc[z];
@@ -543,7 +558,7 @@ __global__ __launch_bounds__(1024) void k_row_inv(const float2* __restrict__ spe
     extern __shared__ float2 xs[];
     __shared__ double red[2 * 16];
     constexpr int LX = LdsLen<N>::v;
-    const int nthr = blockDim.x;
+    const int nthr = LR ? ((1 << LR) / 2) * NT : (int)blockDim.x;
     // stage the half spectra: row a of transform gg at x[k], row b at x[H + k]
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -1087,7 +1102,8 @@ static void launch_row_fwd_t(const float* src, float2* spec, const float2* stN, 
     const int NT = FftShape<N>::NT;
     const int lr = fft_row_split(M, N, nz, SR_ROW_FWD_MIN_WG);
     const size_t lds = sizeof(float2) * ((1 << lr) / 2) * LdsLen<N>::v;
-    launch_iter(k_row_fwd<N>, dim3(M >> lr, 1, nz), dim3(((1 << lr) / 2) * NT), lds, st, src, spec, stN, M, lr, sc);
+    auto k = lr == 3 ? k_row_fwd<N, 3> : lr == 2 ? k_row_fwd<N, 2> : k_row_fwd<N, 0>;
+    launch_iter(k, dim3(M >> lr, 1, nz), dim3(((1 << lr) / 2) * NT), lds, st, src, spec, stN, M, lr, sc);
 }
 template <int M>
 static void launch_col_t(float2* spec, const float2* twM, const float2* twN, const float2* stM, int N, float taumu,
@@ -1097,8 +1113,8 @@ static void launch_col_t(float2* spec, const float2* twM, const float2* twN, con
     const size_t lds = sizeof(float2) * G * LdsLen<M>::v;
     int lrun = 0;
     while ((1 << lrun) < kSpecTile * G) ++lrun;
-    launch_iter(k_col_solve<M>, dim3(N / 2 / G, 1, nz), dim3(NT * G), lds, st, spec, twM, twN, stM, N, G, lrun, taumu,
-                inv_mn, sc);
+    auto k = G == 2 ? k_col_solve<M, 2> : k_col_solve<M, 0>;
+    launch_iter(k, dim3(N / 2 / G, 1, nz), dim3(NT * G), lds, st, spec, twM, twN, stM, N, G, lrun, taumu, inv_mn, sc);
 }
 template <int N>
 static void launch_row_inv_t(const float2* spec, const float* phi_in, float* phi_out, const float2* stN, int M,
@@ -1107,17 +1123,19 @@ static void launch_row_inv_t(const float2* spec, const float* phi_in, float* phi
     const int lr = fft_row_split(M, N, nz, SR_ROW_INV_MIN_WG);
     const size_t lds = sizeof(float2) * ((1 << lr) / 2) * LdsLen<N>::v;
     const int nb = M >> lr;
-    launch_iter(k_row_inv<N>, dim3(nb, 1, nz), dim3(((1 << lr) / 2) * NT), lds, st, spec, phi_in, phi_out, stN, M, lr,
-                tol, part, sc);
+    auto k = lr == 3 ? k_row_inv<N, 3> : lr == 2 ? k_row_inv<N, 2> : k_row_inv<N, 0>;
+    launch_iter(k, dim3(nb, 1, nz), dim3(((1 << lr) / 2) * NT), lds, st, spec, phi_in, phi_out, stN, M, lr, tol, part,
+                sc);
     if (tol > 0.0f) hipLaunchKernelGGL(k_fin_inner, dim3(nz), dim3(1024), 0, st, part, nb, tol, sc);
 }
 
 template <int L>
 static void set_fft_attrs() {
     const int bytes = 160 * 1024 - 1024;
-    (void)hipFuncSetAttribute((const void*)k_row_fwd<L>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    (void)hipFuncSetAttribute((const void*)k_col_solve<L>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    (void)hipFuncSetAttribute((const void*)k_row_inv<L>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    const void* fns[] = {(const void*)k_row_fwd<L, 0>, (const void*)k_row_fwd<L, 2>, (const void*)k_row_fwd<L, 3>,
+                         (const void*)k_col_solve<L, 0>, (const void*)k_col_solve<L, 2>,
+                         (const void*)k_row_inv<L, 0>, (const void*)k_row_inv<L, 2>, (const void*)k_row_inv<L, 3>};
+    for (const void* f : fns) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
 void launch_solve_pass(int pass, const Geometry& geo, const float* rhs, const float* phi_in, float* phi_out,
