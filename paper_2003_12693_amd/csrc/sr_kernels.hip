@@ -389,6 +389,19 @@ __global__ __launch_bounds__(kTileThreads) void k_repulsion(KParams kp, int M, i
 // the column pass reads 128-byte runs (2 adjacent columns x 8 rows).
 constexpr int kSpecTile = 8;
 
+// First row of workgroup b's rows (2^lrpw of them; nb workgroups).  When a
+// workgroup holds fewer than the 8 rows of a spectrum tile, the pieces of one
+// tile go to workgroups b, b + 8, ... which the dispatcher sends to the same
+// XCD (it deals workgroups to the 8 XCDs in turn), so each tile's 64-byte
+// runs are completed (written, or re-read) in one L2.
+__device__ __forceinline__ int row_piece0(int b, int nb, int lrpw) {
+    if (lrpw >= 3) return b << lrpw;
+    const int P = 8 >> lrpw;                 // pieces per tile
+    if (nb % (8 * P)) return b << lrpw;      // small grids: linear order
+    const int x = b & 7, s = b >> 3;
+    return ((s / P) * 8 + x) * 8 + ((s % P) << lrpw);
+}
+
 // RT tiles (8 RT rows, 4 RT complex transforms) per workgroup.  LR > 0 fixes
 // log2(rows per workgroup) at compile time (the common launch shapes, so the
 // index arithmetic folds); LR = 0 takes it from lrpw.
@@ -403,7 +416,7 @@ __global__ __launch_bounds__(1024) void k_row_fwd(const float* __restrict__ src,
     spec += (size_t)z * M * H;
     extern __shared__ float2 xs[];
     const int g = threadIdx.x / NT, t = threadIdx.x - g * NT;
-    const int row0 = blockIdx.x << lrpw;            // 2^lrpw rows (2^(lrpw-1) transforms) per workgroup
+    const int row0 = row_piece0(blockIdx.x, gridDim.x, lrpw);   // 2^lrpw rows (2^(lrpw-1) transforms)
     const size_t ra = (size_t)(row0 + 2 * g) * N, rb = ra + N;
     constexpr int LX = LdsLen<N>::v;
     float2* x = xs + g * LX;
@@ -548,7 +561,7 @@ __global__ __launch_bounds__(1024) void k_row_inv(const float2* __restrict__ spe
     spec += (size_t)z * M * H;
     if (phi_in) phi_in += z * MN;
     phi_out += z * MN;
-    const int row0 = blockIdx.x << lrpw;
+    const int row0 = row_piece0(blockIdx.x, gridDim.x, lrpw);
     if (S.inner_done) {
         const size_t base = (size_t)row0 * N;
         for (int idx = threadIdx.x; idx < (N << lrpw); idx += blockDim.x)
@@ -577,8 +590,17 @@ __global__ __launch_bounds__(1024) void k_row_inv(const float2* __restrict__ spe
         }
         xs[(r >> 1) * LX + sk((r & 1) * H + kk)] = spec[si];
     }
-    __syncthreads();
     const int g = threadIdx.x / NT, t = threadIdx.x - g * NT;
+    // phi_s of this thread's outputs, loaded now so that the loads overlap the transform
+    const size_t ra = (size_t)(row0 + 2 * g) * N, rb = ra + N;
+    float pav[E], pbv[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int n = t + e * NT;
+        pav[e] = phi_in ? phi_in[ra + n] : 0.0f;
+        pbv[e] = phi_in ? phi_in[rb + n] : 0.0f;
+    }
+    __syncthreads();
     float2* x = xs + g * LX;
     float2 va[E / 2], vb[E / 2];
 #pragma unroll
@@ -601,14 +623,12 @@ __global__ __launch_bounds__(1024) void k_row_inv(const float2* __restrict__ spe
         }
     }
     fft_lds<N, RowE<N>::v, true>(x, stN, t);
-    const size_t ra = (size_t)(row0 + 2 * g) * N, rb = ra + N;
     double sd = 0.0, sp = 0.0;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int n = t + e * NT;
         const float2 Zv = x[sk(n)];
-        const float pa = phi_in ? phi_in[ra + n] : 0.0f;
-        const float pb = phi_in ? phi_in[rb + n] : 0.0f;
+        const float pa = pav[e], pb = pbv[e];
         phi_out[ra + n] = pa + Zv.x;
         phi_out[rb + n] = pb + Zv.y;
         sd += (double)Zv.x * Zv.x + (double)Zv.y * Zv.y;
@@ -998,21 +1018,23 @@ static int fft_nt_rt(int L, bool col) {
 }
 // log2 of the rows per workgroup of the row passes: whole 8-row tiles
 // (several for short rows, so a workgroup holds at least one wave), split
-// into 4- or 2-row pieces while the grid would have fewer than min_wg
-// workgroups and a piece still holds a full wave.  Measured at 1024^2: the
-// inverse pass gains from 256 workgroups (11.1 -> 9.8 us), the forward pass
-// does not (9.6 -> 10.5 us), so only the inverse pass splits.
+// into 4- or 2-row pieces (down to 2^min_lr rows) while the grid would have
+// fewer than min_wg workgroups and a piece still holds a full wave; the
+// pieces of a tile share an XCD (row_piece0).  Measured (per launch, 1024^2 /
+// 4096^2): forward pass 8 rows 6.5 / 43.5 us, split to 1024 workgroups
+// 6.2 / 39.5; inverse pass (phi_s prefetched) 4 rows 5.3 / 44.0 us, 2 rows
+// at 1024^2 5.8, 8 rows at 4096^2 52.1.
 #ifndef SR_ROW_FWD_MIN_WG
-#define SR_ROW_FWD_MIN_WG 0
+#define SR_ROW_FWD_MIN_WG 1024
 #endif
 #ifndef SR_ROW_INV_MIN_WG
-#define SR_ROW_INV_MIN_WG 256
+#define SR_ROW_INV_MIN_WG 1024
 #endif
-int fft_row_split(int M, int N, int nz, int min_wg) {
+int fft_row_split(int M, int N, int nz, int min_wg, int min_lr) {
     const int NT = fft_nt_rt(N, false);
     int lr = 3;
     while ((1 << lr) * 2 * NT < 64 * 4 && (2 << lr) <= M) ++lr;   // 4 * RT transforms of NT threads >= 64
-    while (lr > 1 && (M >> lr) * nz < min_wg && (1 << (lr - 2)) * NT >= 64) --lr;
+    while (lr > min_lr && lr > 1 && (M >> lr) * nz < min_wg && (1 << (lr - 2)) * NT >= 64) --lr;
     return lr;
 }
 // Columns per workgroup of the column pass: 2 (128-byte runs), more for short
@@ -1100,9 +1122,9 @@ template <int N>
 static void launch_row_fwd_t(const float* src, float2* spec, const float2* stN, int M, int nz, DevScal* sc,
                              hipStream_t st) {
     const int NT = FftShape<N>::NT;
-    const int lr = fft_row_split(M, N, nz, SR_ROW_FWD_MIN_WG);
+    const int lr = fft_row_split(M, N, nz, SR_ROW_FWD_MIN_WG, 1);
     const size_t lds = sizeof(float2) * ((1 << lr) / 2) * LdsLen<N>::v;
-    auto k = lr == 3 ? k_row_fwd<N, 3> : lr == 2 ? k_row_fwd<N, 2> : k_row_fwd<N, 0>;
+    auto k = lr == 3 ? k_row_fwd<N, 3> : lr == 2 ? k_row_fwd<N, 2> : lr == 1 ? k_row_fwd<N, 1> : k_row_fwd<N, 0>;
     launch_iter(k, dim3(M >> lr, 1, nz), dim3(((1 << lr) / 2) * NT), lds, st, src, spec, stN, M, lr, sc);
 }
 template <int M>
@@ -1120,7 +1142,7 @@ template <int N>
 static void launch_row_inv_t(const float2* spec, const float* phi_in, float* phi_out, const float2* stN, int M,
                              float tol, double* part, int nz, DevScal* sc, hipStream_t st) {
     const int NT = FftShape<N>::NT;
-    const int lr = fft_row_split(M, N, nz, SR_ROW_INV_MIN_WG);
+    const int lr = fft_row_split(M, N, nz, SR_ROW_INV_MIN_WG, 2);
     const size_t lds = sizeof(float2) * ((1 << lr) / 2) * LdsLen<N>::v;
     const int nb = M >> lr;
     auto k = lr == 3 ? k_row_inv<N, 3> : lr == 2 ? k_row_inv<N, 2> : k_row_inv<N, 0>;
@@ -1132,7 +1154,8 @@ static void launch_row_inv_t(const float2* spec, const float* phi_in, float* phi
 template <int L>
 static void set_fft_attrs() {
     const int bytes = 160 * 1024 - 1024;
-    const void* fns[] = {(const void*)k_row_fwd<L, 0>, (const void*)k_row_fwd<L, 2>, (const void*)k_row_fwd<L, 3>,
+    const void* fns[] = {(const void*)k_row_fwd<L, 0>, (const void*)k_row_fwd<L, 1>, (const void*)k_row_fwd<L, 2>,
+                         (const void*)k_row_fwd<L, 3>,
                          (const void*)k_col_solve<L, 0>, (const void*)k_col_solve<L, 2>,
                          (const void*)k_row_inv<L, 0>, (const void*)k_row_inv<L, 2>, (const void*)k_row_inv<L, 3>};
     for (const void* f : fns) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
