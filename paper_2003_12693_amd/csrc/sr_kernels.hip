@@ -386,7 +386,8 @@ __global__ __launch_bounds__(kTileThreads) void k_repulsion(KParams kp, int M, i
 // DC slot carrying (X[0], X[N/2]) as its real and imaginary parts) is stored
 // in 8-row tiles: element (row i, k) at ((i / 8) * (N/2) + k) * 8 + i % 8.
 // Row passes then write / read 64-byte runs (8 rows of one frequency) and
-// the column pass reads 128-byte runs (2 adjacent columns x 8 rows).
+// the column pass reads 64-byte runs (8 rows of one column; the two columns
+// of a 128-byte run are read by workgroups on one XCD).
 constexpr int kSpecTile = 8;
 
 // First row of workgroup b's rows (2^lrpw of them; nb workgroups).  When a
@@ -465,8 +466,9 @@ __global__ __launch_bounds__(1024) void k_row_fwd(const float* __restrict__ src,
 // a + i b; they are separated, scaled by their own symbols and re-packed.
 // GT > 0 fixes G at compile time (the common shape); GT = 0 takes G, lrun.
 template <int M, int GT>
-// At most 64 VGPRs (8 waves per SIMD): two 1024-thread workgroups of the
-// 4096-point pass share a CU (their LDS fits twice), which the pass needs.
+// At most 64 VGPRs (8 waves per SIMD): four 512-thread workgroups of the
+// 4096-point pass share a CU (their LDS fits four times), which the pass
+// needs to overlap loads with transforms.
 __global__ __launch_bounds__(1024, 8) void k_col_solve(float2* __restrict__ spec, const float2* __restrict__ twM,
                                                     const float2* __restrict__ twN, const float2* __restrict__ stM,
                                                     int N, int G_rt, int lrun_rt, float taumu, float inv_mn,
@@ -481,7 +483,14 @@ __global__ __launch_bounds__(1024, 8) void k_col_solve(float2* __restrict__ spec
     const int H = N / 2;
     spec += (size_t)z * M * H;
     extern __shared__ float2 xs[];
-    const int k0 = blockIdx.x * G;
+    // Single columns: columns 2c and 2c + 1 (one 128-byte run per 8-row tile)
+    // go to workgroups b and b + 8, which share an XCD, so the run is read
+    // from HBM once.
+    int k0 = blockIdx.x * G;
+    if (G == 1 && (gridDim.x & 15) == 0) {
+        const int b = blockIdx.x, s = b >> 3;
+        k0 = (((s >> 1) << 3) + (b & 7)) * 2 + (s & 1);
+    }
     const int run = kSpecTile * G;                 // contiguous float2 per row tile (2^lrun)
     float2* base = spec + (size_t)k0 * kSpecTile;
     // M * G elements over NT * G threads: exactly E per thread, all loads first
@@ -1037,18 +1046,18 @@ int fft_row_split(int M, int N, int nz, int min_wg, int min_lr) {
     while (lr > min_lr && lr > 1 && (M >> lr) * nz < min_wg && (1 << (lr - 2)) * NT >= 64) --lr;
     return lr;
 }
-// Columns per workgroup of the column pass: 2 (128-byte runs), more for short
-// columns so a workgroup holds at least one wave; 1 while the grid would have
-// fewer than SR_COL_MIN_WG workgroups.
-#ifndef SR_COL_MIN_WG
-#define SR_COL_MIN_WG 0
-#endif
+// Columns per workgroup of the column pass: one column when its transform
+// fills at least a wave (the two columns of a 128-byte run then go to
+// workgroups on one XCD), else as many as make a wave.  Measured per launch
+// (1024^2 / 4096^2): one column 7.6 / 46.4 us, two 8.0 / 50.5 us (more
+// workgroups per CU overlap one another's loads with their transforms).
 int fft_col_group(int M, int N, int nz) {
+    (void)nz;
     const int NT = fft_nt_rt(M, true);
+    if (NT >= 64) return 1;
     int G = 2;
     while (G * NT < 64 && G * 2 <= N / 2) G <<= 1;
     if (G > N / 2) G = N / 2;
-    if (G == 2 && NT >= 64 && (N / 2 / 2) * nz < SR_COL_MIN_WG) G = 1;
     return G;
 }
 
@@ -1135,7 +1144,7 @@ static void launch_col_t(float2* spec, const float2* twM, const float2* twN, con
     const size_t lds = sizeof(float2) * G * LdsLen<M>::v;
     int lrun = 0;
     while ((1 << lrun) < kSpecTile * G) ++lrun;
-    auto k = G == 2 ? k_col_solve<M, 2> : k_col_solve<M, 0>;
+    auto k = G == 2 ? k_col_solve<M, 2> : G == 1 ? k_col_solve<M, 1> : k_col_solve<M, 0>;
     launch_iter(k, dim3(N / 2 / G, 1, nz), dim3(NT * G), lds, st, spec, twM, twN, stM, N, G, lrun, taumu, inv_mn, sc);
 }
 template <int N>
@@ -1156,7 +1165,7 @@ static void set_fft_attrs() {
     const int bytes = 160 * 1024 - 1024;
     const void* fns[] = {(const void*)k_row_fwd<L, 0>, (const void*)k_row_fwd<L, 1>, (const void*)k_row_fwd<L, 2>,
                          (const void*)k_row_fwd<L, 3>,
-                         (const void*)k_col_solve<L, 0>, (const void*)k_col_solve<L, 2>,
+                         (const void*)k_col_solve<L, 0>, (const void*)k_col_solve<L, 1>, (const void*)k_col_solve<L, 2>,
                          (const void*)k_row_inv<L, 0>, (const void*)k_row_inv<L, 2>, (const void*)k_row_inv<L, 3>};
     for (const void* f : fns) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
