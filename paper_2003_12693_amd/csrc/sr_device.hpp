@@ -160,11 +160,17 @@ template <int L> struct RowE {
     static constexpr int v = L <= 1024 ? (SR_ROW_E < L ? SR_ROW_E : L)
                                        : (L == 2048 ? (SR_ROW_E > 8 ? SR_ROW_E : 8) : 16);
 };
-// The column pass runs two transforms per workgroup, so it can afford more
+// The column pass holds one transform per workgroup, so it can afford more
 // threads per transform (fewer registers per thread) at 4096 points.
+#ifndef SR_COL_E_LONG
+#define SR_COL_E_LONG 8
+#endif
 template <int L> struct ColE {
-    static constexpr int v = L <= 2048 ? (SR_COL_E < L ? SR_COL_E : L) : (SR_COL_E > 8 ? SR_COL_E : 8);
+    static constexpr int v = L <= 2048 ? (SR_COL_E < L ? SR_COL_E : L) : SR_COL_E_LONG;
 };
+// Waves per SIMD the column pass is compiled for (a VGPR cap): 8 (64 VGPRs)
+// unless 16-element transforms need more registers.
+template <int L> struct ColWaves { static constexpr int v = ColE<L>::v >= 16 ? 4 : 8; };
 template <int L, int EE = RowE<L>::v> struct FftShape {
     static constexpr int E = EE;
     static constexpr int NT = L / E;

@@ -466,10 +466,11 @@ __global__ __launch_bounds__(1024) void k_row_fwd(const float* __restrict__ src,
 // a + i b; they are separated, scaled by their own symbols and re-packed.
 // GT > 0 fixes G at compile time (the common shape); GT = 0 takes G, lrun.
 template <int M, int GT>
-// At most 64 VGPRs (8 waves per SIMD): four 512-thread workgroups of the
-// 4096-point pass share a CU (their LDS fits four times), which the pass
-// needs to overlap loads with transforms.
-__global__ __launch_bounds__(1024, 8) void k_col_solve(float2* __restrict__ spec, const float2* __restrict__ twM,
+// VGPR cap from ColWaves: at most 64 VGPRs (8 waves per SIMD) for 8-element
+// transforms, so four 512-thread workgroups of the 4096-point pass share a
+// CU (their LDS fits four times), which the pass needs to overlap loads with
+// transforms.
+__global__ __attribute__((amdgpu_flat_work_group_size(1, 1024), amdgpu_waves_per_eu(ColWaves<M>::v))) void k_col_solve(float2* __restrict__ spec, const float2* __restrict__ twM,
                                                     const float2* __restrict__ twN, const float2* __restrict__ stM,
                                                     int N, int G_rt, int lrun_rt, float taumu, float inv_mn,
                                                     DevScal* sc) {
