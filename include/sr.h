@@ -191,8 +191,10 @@ int sr_profile_kernels(sr_ctx* ctx, int32_t n_iter, double ms[SR_NUM_KERNEL_KIND
 
 /* ---- autotuner ----------------------------------------------------------
  * Chooses the row height of the stencil tiles (8, 16 or 32 rows of 64
- * columns) of the two window kernels (eq 37 right-hand side; eqs 40-42 w
- * step).  Each candidate is timed on the context's current state by
+ * columns) of the right-hand-side window kernel (eq 37), launched S times
+ * per outer iteration (the w step, eqs 40-42, always takes 16-row tiles,
+ * its fastest at every measured size).  Each candidate is timed on the
+ * context's current state by
  * launching the right-hand-side kernel, which reads the state and writes
  * only its own scratch plane, so the iterate is unchanged and so is every
  * later result (the per-pixel arithmetic does not depend on the tile

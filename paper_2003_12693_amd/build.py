@@ -25,6 +25,10 @@ SOURCES = ["sr_kernels.hip", "sr_api.hip", "cnn.hip"]
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # multiply-adds are fused only within one source expression, so a kernel's
+    # rounding does not depend on how a template instance happens to be
+    # unrolled (results stay bitwise independent of tile shapes)
+    "-ffp-contract=on",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
     "-I", os.path.join(ROOT, "include"),
 ]

@@ -18,7 +18,8 @@ constexpr int kMaxR = 8;        // largest repulsion window half-width
 constexpr int kMaxTaps = 2 * kMaxR + 1;
 constexpr int kMaxGaussR = 16;  // largest Gaussian radius ceil(3 sigma)
 constexpr int kTileW = 64;      // tile width of the stencil kernels (one wave per row)
-constexpr int kTileThreads = 256;
+constexpr int kTileThreads = 256;   // threads per stencil tile (w step, energy, repulsion)
+constexpr int kRhsThreads = 512;    // threads per tile of the right-hand-side kernel
 constexpr int kScalStride = 64; // int64 words of per-instance device scalars
 constexpr int kRHist = 1024;    // residual history ring (per instance)
 

@@ -182,7 +182,7 @@ __device__ __forceinline__ void xcd_tile(int& tx, int& ty) {
 
 template <int TH, int R>
 struct RhsTile {
-    static constexpr int TW = kTileW, T = kTileThreads;
+    static constexpr int TW = kTileW, T = kRhsThreads;
     static constexpr int EH = TH + 2 * R, EW = TW + 2 * R, NEXT = EH * EW;
     static constexpr int PH = TH + 2, PW = TW + 2;
     static constexpr int NE = (NEXT + T - 1) / T, NHZ = (EH * TW + T - 1) / T, NO = TH * TW / T;
@@ -190,7 +190,7 @@ struct RhsTile {
 };
 
 template <int TH, int R>
-__global__ __launch_bounds__(kTileThreads) void k_rhs(KParams kp, int M, int N,
+__global__ __launch_bounds__(kRhsThreads) void k_rhs(KParams kp, int M, int N,
                                                       const float* __restrict__ phi_s,
                                                       const float* __restrict__ W,
                                                       const float* __restrict__ g,
@@ -1190,8 +1190,8 @@ void launch_solve(const Geometry& geo, const float* rhs, const float* phi_in, fl
         launch_solve_pass(pass, geo, rhs, phi_in, phi_out, spec, tol_inner, part, nz, sc, st);
 }
 
-// Tile height: 32 rows unless that leaves fewer than ~4 workgroups per CU
-// (a context may fix it, e.g. from the autotuner).
+// Tile height of the right-hand-side kernel: the context's (from the
+// autotuner or SR_TILE_TH), else 16 rows.
 static int tile_height(const Geometry& geo, int nz) {
     if (geo.tile_th == 8 || geo.tile_th == 16 || geo.tile_th == 32) return geo.tile_th;
     (void)nz;
@@ -1201,7 +1201,7 @@ static int tile_height(const Geometry& geo, int nz) {
 template <int TH, int R>
 static void launch_rhs_t(const Geometry& geo, const KParams& kp, const float* phi_s, const float* W, const float* g,
                          const float* D, float* out, int nz, DevScal* sc, hipStream_t st) {
-    launch_iter(k_rhs<TH, R>, tile_grid(geo.M, geo.N, TH, nz), dim3(kTileThreads),
+    launch_iter(k_rhs<TH, R>, tile_grid(geo.M, geo.N, TH, nz), dim3(kRhsThreads),
                 sizeof(float) * RhsTile<TH, R>::lds_floats, st, kp, geo.M, geo.N, phi_s, W, g, D, out, sc);
 }
 template <int TH, int R>
@@ -1242,17 +1242,11 @@ void launch_rhs(const Geometry& geo, const KParams& kp, const float* phi_s, cons
 void launch_wstep(const Geometry& geo, const KParams& kp, const float* phin, float* P0, const float* Wold,
                   const float* Bold, const float* g, float* Wnew, float* Bnew, float* D, double* part,
                   double* rhist, int nz, DevScal* sc, hipStream_t st) {
-    const int TH = tile_height(geo, nz);
-    if (TH == 32) {
-        SR_R_DISPATCH(launch_wstep_t, 32, kp.R, geo, kp, phin, P0, Wold, Bold, g, Wnew, Bnew, D, part, rhist, nz, sc,
-                      st);
-    } else if (TH == 16) {
-        SR_R_DISPATCH(launch_wstep_t, 16, kp.R, geo, kp, phin, P0, Wold, Bold, g, Wnew, Bnew, D, part, rhist, nz, sc,
-                      st);
-    } else {
-        SR_R_DISPATCH(launch_wstep_t, 8, kp.R, geo, kp, phin, P0, Wold, Bold, g, Wnew, Bnew, D, part, rhist, nz, sc,
-                      st);
-    }
+    // 16-row tiles: the fastest for this kernel at 1024^2 and 4096^2 whatever
+    // height the autotuner picks for the right-hand side (measured 17.8 / 160 us
+    // against 18.8 / 180 for 8 rows and 19.5 / 194 for 32).
+    constexpr int TH = 16;
+    SR_R_DISPATCH(launch_wstep_t, 16, kp.R, geo, kp, phin, P0, Wold, Bold, g, Wnew, Bnew, D, part, rhist, nz, sc, st);
     const int nb = ((geo.N + kTileW - 1) / kTileW) * ((geo.M + TH - 1) / TH);
     hipLaunchKernelGGL(k_fin_outer, dim3(nz), dim3(1024), 0, st, part, nb, rhist, sc);
 }
