@@ -270,10 +270,14 @@ __device__ __forceinline__ void dft(float2 (&u)[R]) {
 // One radix-R Stockham stage: sub-transform size Ns -> R Ns.  Butterfly j
 // reads x[j + r L/R], twiddles by W_{R Ns}^{r k} (k = j mod Ns), applies the
 // R-point DFT and writes x[(j - k) R + k + r Ns].  tws: this stage's block of
-// the stage twiddle table.
-template <int L, int EE, int R, int Ns, bool INV>
-__device__ __forceinline__ void fft_stage(float2* x, const float2* __restrict__ tws, int t) {
+// the stage twiddle table.  FROM_REGS (first stage, Ns = 1): the inputs come
+// from io instead of LDS, io[e] holding element t + e NT; TO_REGS (last
+// stage, Ns = L/R): the outputs go to io in that same layout instead of LDS.
+template <int L, int EE, int R, int Ns, bool INV, bool FROM_REGS, bool TO_REGS>
+__device__ __forceinline__ void fft_stage(float2* x, const float2* __restrict__ tws, int t, float2 (&io)[EE]) {
     constexpr int E = EE, NT = L / E, NB = E / R, Q = L / R;
+    static_assert(!FROM_REGS || Ns == 1, "register input is the first stage");
+    static_assert(!TO_REGS || Ns * R == L, "register output is the last stage");
     float2 w[NB][R];
     if constexpr (Ns > 1) {   // issued first: their latency overlaps the LDS reads
 #pragma unroll
@@ -291,11 +295,14 @@ __device__ __forceinline__ void fft_stage(float2* x, const float2* __restrict__ 
     float2 v[E];
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-        const int j = t + b * NT;
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[b * R + r] = x[sk(j + r * Q)];
+        for (int r = 0; r < R; ++r) {
+            // element j + r Q = t + (b + r NB) NT
+            if constexpr (FROM_REGS) v[b * R + r] = io[b + r * NB];
+            else v[b * R + r] = x[sk(t + b * NT + r * Q)];
+        }
     }
-    __syncthreads();
+    if constexpr (!FROM_REGS && !TO_REGS) __syncthreads();
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         const int j = t + b * NT;
@@ -308,32 +315,45 @@ __device__ __forceinline__ void fft_stage(float2* x, const float2* __restrict__ 
             for (int r = 1; r < R; ++r) u[r] = INV ? cmulc(u[r], w[b][r]) : cmul(u[r], w[b][r]);
         }
         dft<R, INV>(u);
-        const int base = (j - k) * R + k;
+        if constexpr (TO_REGS) {
+            // last stage: k = j, so output r of butterfly b is element j + r L/R
 #pragma unroll
-        for (int r = 0; r < R; ++r) x[sk(base + r * Ns)] = u[r];
+            for (int r = 0; r < R; ++r) io[b + r * NB] = u[r];
+        } else {
+            const int base = (j - k) * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) x[sk(base + r * Ns)] = u[r];
+        }
     }
-    __syncthreads();
+    if constexpr (!TO_REGS) __syncthreads();
 }
 
 // OFF: offset of this stage's block in the stage twiddle table.
-template <int L, int EE, bool INV, int Ns, int OFF>
-__device__ __forceinline__ void fft_stages(float2* x, const float2* __restrict__ tab, int t) {
+template <int L, int EE, bool INV, bool IN, bool OUT, int Ns, int OFF>
+__device__ __forceinline__ void fft_stages(float2* x, const float2* __restrict__ tab, int t, float2 (&io)[EE]) {
     if constexpr (Ns < L) {
         constexpr int R = fft_radix(L, EE, Ns);
-        fft_stage<L, EE, R, Ns, INV>(x, tab + OFF, t);
-        fft_stages<L, EE, INV, Ns * R, OFF + (Ns > 1 ? Ns * R : 0)>(x, tab, t);
+        fft_stage<L, EE, R, Ns, INV, IN && Ns == 1, OUT && Ns * R == L>(x, tab + OFF, t, io);
+        fft_stages<L, EE, INV, IN, OUT, Ns * R, OFF + (Ns > 1 ? Ns * R : 0)>(x, tab, t, io);
     }
 }
 
 // In-place length-L complex FFT of x (in LDS, skewed by sk()) by the NT = L/EE
 // threads t = 0..NT-1 of one transform: mixed-radix Stockham stages of radix
-// min(EE, remaining length); tab: the stage twiddle table of (L, EE).  Every
-// thread of the workgroup must call it (it contains workgroup barriers).
-// INV: unnormalised inverse.
+// min(EE, remaining length); tab: the stage twiddle table of (L, EE).  IN: the
+// input is in io (io[e] = element t + e NT) rather than in x; OUT: the output
+// is left in io (same layout) rather than in x.  Every thread of the
+// workgroup must call it (it contains workgroup barriers); with IN, nothing
+// else may be reading x when it starts.  INV: unnormalised inverse.
+template <int L, int EE, bool INV, bool IN = false, bool OUT = false>
+__device__ __forceinline__ void fft_lds(float2* x, const float2* __restrict__ tab, int t, float2 (&io)[EE]) {
+    if constexpr (!IN) __syncthreads();
+    fft_stages<L, EE, INV, IN, OUT, 1, 0>(x, tab, t, io);
+}
 template <int L, int EE, bool INV>
 __device__ __forceinline__ void fft_lds(float2* x, const float2* __restrict__ tab, int t) {
-    __syncthreads();
-    fft_stages<L, EE, INV, 1, 0>(x, tab, t);
+    float2 unused[EE];
+    fft_lds<L, EE, INV, false, false>(x, tab, t, unused);
 }
 
 // ---------------------------------------------------------------------------

@@ -421,12 +421,13 @@ __global__ __launch_bounds__(1024) void k_row_fwd(const float* __restrict__ src,
     const size_t ra = (size_t)(row0 + 2 * g) * N, rb = ra + N;
     constexpr int LX = LdsLen<N>::v;
     float2* x = xs + g * LX;
+    float2 io[E];   // element t + e NT of the complex row: the first stage's inputs
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int n = t + e * NT;
-        x[sk(n)] = make_float2(src[ra + n], src[rb + n]);
+        io[e] = make_float2(src[ra + n], src[rb + n]);
     }
-    fft_lds<N, RowE<N>::v, false>(x, stN, t);
+    fft_lds<N, RowE<N>::v, false, true, false>(x, stN, t, io);
     // Whole 8-row tiles are one contiguous run of 4N float2 each; with fewer
     // rows per workgroup it writes its rows of every 8-row run.
     const int nthr = LR ? ((1 << LR) / 2) * NT : (int)blockDim.x;
@@ -494,25 +495,28 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, 1024), amdgpu_waves_per
     }
     const int run = kSpecTile * G;                 // contiguous float2 per row tile (2^lrun)
     float2* base = spec + (size_t)k0 * kSpecTile;
-    // M * G elements over NT * G threads: exactly E per thread, all loads first
-    {
-        float2 ld[E];
+    // M * G elements over NT * G threads: exactly E per thread, all loads first.
+    // With one column per workgroup, element idx of the column is thread
+    // idx % NT's input e = idx / NT of the first stage: no staging in LDS.
+    constexpr bool ONE = GT == 1;
+    float2 io[E];
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const int idx = threadIdx.x + e * nthr;
-            ld[e] = base[(size_t)(idx >> lrun) * H * kSpecTile + (idx & (run - 1))];
-        }
+    for (int e = 0; e < E; ++e) {
+        const int idx = threadIdx.x + e * nthr;
+        io[e] = base[(size_t)(idx >> lrun) * H * kSpecTile + (idx & (run - 1))];
+    }
+    if constexpr (!ONE) {
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int idx = threadIdx.x + e * nthr;
             const int rem = idx & (run - 1);
-            xs[(rem >> 3) * LD + sk((idx >> lrun) * kSpecTile + (rem & 7))] = ld[e];
+            xs[(rem >> 3) * LD + sk((idx >> lrun) * kSpecTile + (rem & 7))] = io[e];
         }
     }
     const int g = threadIdx.x / NT, t = threadIdx.x - g * NT;
     const int col = k0 + g;
     float2* x = xs + g * LD;
-    fft_lds<M, ColE<M>::v, false>(x, stM, t);
+    fft_lds<M, ColE<M>::v, false, ONE, false>(x, stM, t, io);
     // Divide by the symbol.  The symbol is even in l1, so each thread owns the
     // mirror pair (l, M - l): column 0's two packed real spectra mix Z[l]
     // with conj(Z[M - l]), every other column scales pointwise.
@@ -538,13 +542,25 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, 1024), amdgpu_waves_per
 #pragma unroll
     for (int e = 0; e < E / 2; ++e) scale_pair(t + e * NT);   // l in [0, M/2)
     if (t == 0) scale_pair(M / 2);
-    fft_lds<M, ColE<M>::v, true>(x, stM, t);
-    __syncthreads();
+    // A fresh copy of t (through an empty asm) keeps the compiler from holding
+    // the forward transform's LDS addresses live across the division.
+    int t_inv = t;
+    asm volatile("" : "+v"(t_inv));
+    fft_lds<M, ColE<M>::v, true, false, ONE>(x, stM, t_inv, io);
+    if constexpr (!ONE) __syncthreads();
     // An empty asm on the thread index keeps the compiler from computing the
     // store addresses at the top and holding them (or spilling them) through
     // both transforms.
     int tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
+    if constexpr (ONE) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int idx = tid + e * nthr;
+            base[(size_t)(idx >> lrun) * H * kSpecTile + (idx & (run - 1))] = io[e];
+        }
+        return;
+    }
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int idx = tid + e * nthr;
@@ -632,12 +648,13 @@ __global__ __launch_bounds__(1024) void k_row_inv(const float2* __restrict__ spe
             x[sk(N - k)] = make_float2(Xa.x + Xb.y, Xb.x - Xa.y);
         }
     }
-    fft_lds<N, RowE<N>::v, true>(x, stN, t);
+    float2 io[E];   // the last stage's outputs: element t + e NT
+    fft_lds<N, RowE<N>::v, true, false, true>(x, stN, t, io);
     double sd = 0.0, sp = 0.0;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int n = t + e * NT;
-        const float2 Zv = x[sk(n)];
+        const float2 Zv = io[e];
         const float pa = pav[e], pb = pbv[e];
         phi_out[ra + n] = pa + Zv.x;
         phi_out[rb + n] = pb + Zv.y;
