@@ -691,9 +691,9 @@ __global__ __launch_bounds__(1024) void k_fin_inner(const double* __restrict__ p
 // The tile computes w, b on one extra row above and column left so that the
 // backward divergence of its own pixels is local.
 // ---------------------------------------------------------------------------
-template <int TH, int R>
+template <int TH, int R, int TT>
 struct WTile {
-    static constexpr int TW = kTileW, T = kTileThreads;
+    static constexpr int TW = kTileW, T = TT;
     static constexpr int CH = TH + 1, CW = TW + 1;           // computed region (one extra row / column)
     static constexpr int EH = CH + 2 * R, EW = CW + 2 * R, NEXT = EH * EW;
     static constexpr int PH = TH + 2, PW = TW + 2;
@@ -703,8 +703,8 @@ struct WTile {
     static constexpr size_t lds_floats = su_floats + 2 * EH * CW + PH * PW;
 };
 
-template <int TH, int R>
-__global__ __launch_bounds__(kTileThreads) void k_wstep(KParams kp, int M, int N,
+template <int TH, int R, int TT>
+__global__ __launch_bounds__(TT) void k_wstep(KParams kp, int M, int N,
                                                         const float* __restrict__ phin,
                                                         float* __restrict__ P0,
                                                         const float* __restrict__ Wold,
@@ -713,7 +713,7 @@ __global__ __launch_bounds__(kTileThreads) void k_wstep(KParams kp, int M, int N
                                                         float* __restrict__ Wnew, float* __restrict__ Bnew,
                                                         float* __restrict__ D, double* __restrict__ part,
                                                         double* __restrict__ rhist, DevScal* sc) {
-    using C = WTile<TH, R>;
+    using C = WTile<TH, R, TT>;
     constexpr int TW = C::TW, T = C::T, CH = C::CH, CW = C::CW, EH = C::EH, EW = C::EW, NEXT = C::NEXT;
     constexpr int PH = C::PH, PW = C::PW;
     const int z = blockIdx.z;
@@ -1221,13 +1221,28 @@ static void launch_rhs_t(const Geometry& geo, const KParams& kp, const float* ph
     launch_iter(k_rhs<TH, R>, tile_grid(geo.M, geo.N, TH, nz), dim3(kRhsThreads),
                 sizeof(float) * RhsTile<TH, R>::lds_floats, st, kp, geo.M, geo.N, phi_s, W, g, D, out, sc);
 }
-template <int TH, int R>
+template <int TH, int R, int TT>
 static void launch_wstep_t(const Geometry& geo, const KParams& kp, const float* phin, float* P0, const float* Wold,
                            const float* Bold, const float* g, float* Wnew, float* Bnew, float* D, double* part,
                            double* rhist, int nz, DevScal* sc, hipStream_t st) {
-    launch_iter(k_wstep<TH, R>, tile_grid(geo.M, geo.N, TH, nz), dim3(kTileThreads),
-                sizeof(float) * WTile<TH, R>::lds_floats, st, kp, geo.M, geo.N, phin, P0, Wold, Bold, g, Wnew, Bnew, D,
-                part, rhist, sc);
+    launch_iter(k_wstep<TH, R, TT>, tile_grid(geo.M, geo.N, TH, nz), dim3(TT),
+                sizeof(float) * WTile<TH, R, TT>::lds_floats, st, kp, geo.M, geo.N, phin, P0, Wold, Bold, g, Wnew,
+                Bnew, D, part, rhist, sc);
+}
+// The two w-step tile shapes in use: 64 x 32 on 512 threads up to 4 Mpx per
+// launch, 64 x 16 on 256 threads above (measured 16.0 / 171 us against
+// 17.8 / 160 us at 1024^2 / 4096^2).
+template <int TH, int R>
+static void launch_wstep_small(const Geometry& geo, const KParams& kp, const float* phin, float* P0,
+                               const float* Wold, const float* Bold, const float* g, float* Wnew, float* Bnew,
+                               float* D, double* part, double* rhist, int nz, DevScal* sc, hipStream_t st) {
+    launch_wstep_t<TH, R, 512>(geo, kp, phin, P0, Wold, Bold, g, Wnew, Bnew, D, part, rhist, nz, sc, st);
+}
+template <int TH, int R>
+static void launch_wstep_large(const Geometry& geo, const KParams& kp, const float* phin, float* P0,
+                               const float* Wold, const float* Bold, const float* g, float* Wnew, float* Bnew,
+                               float* D, double* part, double* rhist, int nz, DevScal* sc, hipStream_t st) {
+    launch_wstep_t<TH, R, 256>(geo, kp, phin, P0, Wold, Bold, g, Wnew, Bnew, D, part, rhist, nz, sc, st);
 }
 
 #define SR_R_DISPATCH(FN, TH, R, ...)                                                          \
@@ -1259,11 +1274,17 @@ void launch_rhs(const Geometry& geo, const KParams& kp, const float* phi_s, cons
 void launch_wstep(const Geometry& geo, const KParams& kp, const float* phin, float* P0, const float* Wold,
                   const float* Bold, const float* g, float* Wnew, float* Bnew, float* D, double* part,
                   double* rhist, int nz, DevScal* sc, hipStream_t st) {
-    // 16-row tiles: the fastest for this kernel at 1024^2 and 4096^2 whatever
-    // height the autotuner picks for the right-hand side (measured 17.8 / 160 us
-    // against 18.8 / 180 for 8 rows and 19.5 / 194 for 32).
-    constexpr int TH = 16;
-    SR_R_DISPATCH(launch_wstep_t, 16, kp.R, geo, kp, phin, P0, Wold, Bold, g, Wnew, Bnew, D, part, rhist, nz, sc, st);
+    // Fixed shapes, whatever tile height the autotuner picks for the right-hand
+    // side (on 256 threads, 8 and 32 rows measured 18.8 / 180 and 19.5 / 194 us).
+    const bool small = (size_t)geo.M * geo.N * nz <= ((size_t)1 << 22);
+    const int TH = small ? 32 : 16;
+    if (small) {
+        SR_R_DISPATCH(launch_wstep_small, 32, kp.R, geo, kp, phin, P0, Wold, Bold, g, Wnew, Bnew, D, part, rhist, nz,
+                      sc, st);
+    } else {
+        SR_R_DISPATCH(launch_wstep_large, 16, kp.R, geo, kp, phin, P0, Wold, Bold, g, Wnew, Bnew, D, part, rhist, nz,
+                      sc, st);
+    }
     const int nb = ((geo.N + kTileW - 1) / kTileW) * ((geo.M + TH - 1) / TH);
     hipLaunchKernelGGL(k_fin_outer, dim3(nz), dim3(1024), 0, st, part, nb, rhist, sc);
 }
@@ -1272,7 +1293,10 @@ template <int TH, int R>
 static void set_tile_attrs_one() {
     const int bytes = 160 * 1024 - 1024;
     (void)hipFuncSetAttribute((const void*)k_rhs<TH, R>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    (void)hipFuncSetAttribute((const void*)k_wstep<TH, R>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if constexpr (TH == 32)
+        (void)hipFuncSetAttribute((const void*)k_wstep<32, R, 512>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if constexpr (TH == 16)
+        (void)hipFuncSetAttribute((const void*)k_wstep<16, R, 256>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 template <int TH>
 static void set_tile_attrs() {
