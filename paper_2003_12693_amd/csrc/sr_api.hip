@@ -155,6 +155,7 @@ struct sr_ctx {
     hipStream_t cap;           // capture stream (graphs are replayed on `stream`)
     hipGraphExec_t g1[2] = {nullptr, nullptr};   // one iteration from parity p
     hipGraphExec_t g2[2] = {nullptr, nullptr};   // two iterations from parity p
+    hipGraphExec_t g8[2] = {nullptr, nullptr};   // eight iterations from parity p
     bool use_graphs = true;
     int parity = 0;            // state in W[parity], B[parity]
     long long k = 0;
@@ -243,17 +244,25 @@ static hipError_t upload_tables(const Bufs& b, int M, int N, hipStream_t st) {
 // S x [rhs -> row FFT -> column solve -> inverse row FFT], then the w step.
 // before(kind) runs ahead of each iteration kernel's launch (kinds as in
 // sr_profile_kernels); the per-kernel timing uses it to arm events.
+// fold_in: the first rhs launch runs the previous iteration's finalize
+// (FinFold); fin_out = false: this iteration's w step leaves its finalize to
+// the next iteration's first rhs.  Both only inside captured graphs and only
+// with the inner stop rule off (can_fold).
 struct NoHook { void operator()(int) const {} };
+static bool can_fold(const sr_ctx* c) { return c->p.tol_inner <= 0.0; }
 template <typename Hook = NoHook>
-static void enqueue_iteration(sr_ctx* c, int p, hipStream_t st, Hook&& before = Hook{}) {
+static void enqueue_iteration(sr_ctx* c, int p, hipStream_t st, Hook&& before = Hook{}, bool fold_in = false,
+                              bool fin_out = true) {
     Bufs& b = c->b;
     const int S = c->p.S;
     const float* in = b.P0;
     float* outs[2] = {b.P1, b.P2};
+    const sr::FinFold fold{b.part, sr::wstep_blocks(c->geo, c->nz), b.rhist};
     for (int s = 0; s < S; ++s) {
         float* out = outs[s & 1];
         before(0);
-        sr::launch_rhs(c->geo, c->kp, in, b.W[p], b.g, b.D, b.Rb, c->nz, b.scal, st);
+        sr::launch_rhs(c->geo, c->kp, in, b.W[p], b.g, b.D, b.Rb, c->nz, b.scal, st,
+                       (fold_in && s == 0) ? &fold : nullptr);
         for (int pass = 0; pass < 3; ++pass) {
             before(1 + pass);
             sr::launch_solve_pass(pass, c->geo, b.Rb, in, out, b.spec, c->kp.tol_inner, b.part, c->nz, b.scal, st);
@@ -262,13 +271,21 @@ static void enqueue_iteration(sr_ctx* c, int p, hipStream_t st, Hook&& before = 
     }
     before(4);
     sr::launch_wstep(c->geo, c->kp, in, b.P0, b.W[p], b.B[p], b.g, b.W[1 - p], b.B[1 - p], b.D, b.part, b.rhist,
-                     c->nz, b.scal, st);
+                     c->nz, b.scal, st, fin_out);
+}
+
+// iters outer iterations from parity p; inside a graph the finalize of each
+// but the last is folded into the next iteration's first rhs.
+static void enqueue_chunk(sr_ctx* c, int p, int iters, hipStream_t st) {
+    const bool fold = can_fold(c);
+    for (int i = 0; i < iters; ++i)
+        enqueue_iteration(c, (p + i) & 1, st, NoHook{}, fold && i > 0, !fold || i == iters - 1);
 }
 
 static int capture(sr_ctx* c, int p, int iters, hipGraphExec_t* out) {
     hipGraph_t graph = nullptr;
     HIP_TRY(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
-    for (int i = 0; i < iters; ++i) enqueue_iteration(c, (p + i) & 1, c->cap);
+    enqueue_chunk(c, p, iters, c->cap);
     hipError_t e = hipStreamEndCapture(c->cap, &graph);
     if (e != hipSuccess) return fail(SR_EHIP, "graph capture: %s", hipGetErrorString(e));
     e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
@@ -319,7 +336,8 @@ static void drop_graphs(sr_ctx* c) {
     for (int p = 0; p < 2; ++p) {
         if (c->g1[p]) (void)hipGraphExecDestroy(c->g1[p]);
         if (c->g2[p]) (void)hipGraphExecDestroy(c->g2[p]);
-        c->g1[p] = c->g2[p] = nullptr;
+        if (c->g8[p]) (void)hipGraphExecDestroy(c->g8[p]);
+        c->g1[p] = c->g2[p] = c->g8[p] = nullptr;
     }
 }
 
@@ -335,7 +353,12 @@ static int enqueue_iters(sr_ctx* c, int n) {
             n -= 1;
             continue;
         }
-        if (n >= 2) {
+        if (n >= 8) {
+            if (!c->g8[p]) { int rc = capture(c, p, 8, &c->g8[p]); if (rc) return rc; }
+            HIP_TRY(hipGraphLaunch(c->g8[p], c->stream));
+            c->k += 8;
+            n -= 8;
+        } else if (n >= 2) {
             if (!c->g2[p]) { int rc = capture(c, p, 2, &c->g2[p]); if (rc) return rc; }
             HIP_TRY(hipGraphLaunch(c->g2[p], c->stream));
             c->k += 2;
@@ -461,6 +484,7 @@ void sr_destroy(sr_ctx* c) {
     for (int i = 0; i < 2; ++i) {
         if (c->g1[i]) (void)hipGraphExecDestroy(c->g1[i]);
         if (c->g2[i]) (void)hipGraphExecDestroy(c->g2[i]);
+        if (c->g8[i]) (void)hipGraphExecDestroy(c->g8[i]);
     }
     (void)hipStreamDestroy(c->cap);
     delete c;
@@ -865,7 +889,7 @@ int sr_solve_batch(sr_batch_item* items, int32_t n, void* workspace, size_t byte
         e = hipEventRecord(fork, cap);
         for (int i = 0; i < NB && e == hipSuccess; ++i) e = hipStreamWaitEvent(br[i], fork, 0);
         for (int gi = 0; gi < G && e == hipSuccess; ++gi)
-            for (int it = 0; it < chunk; ++it) enqueue_iteration(&ctx[gi], it & 1, br[gi % NB]);
+            enqueue_chunk(&ctx[gi], 0, chunk, br[gi % NB]);
         for (int i = 0; i < NB && e == hipSuccess; ++i) {
             e = hipEventRecord(evb[i], br[i]);
             if (e == hipSuccess) e = hipStreamWaitEvent(cap, evb[i], 0);

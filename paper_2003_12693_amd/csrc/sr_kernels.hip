@@ -180,6 +180,24 @@ __device__ __forceinline__ void xcd_tile(int& tx, int& ty) {
     tx = b - ty * gx;
 }
 
+// Outer-iteration finalize of instance z, by every thread of one workgroup.
+__device__ __forceinline__ void fin_outer_body(const double* __restrict__ part, int nb, double* __restrict__ rhist,
+                                               DevScal& S, int z, double* red) {
+    double v[2];
+    sum_partials<2>(part + (size_t)z * 2 * nb, nb, v, red);
+    if (threadIdx.x == 0) {
+        const double r = sqrt(v[0]) / (sqrt(v[1]) + 1e-6);
+        S.r_last = r;
+        rhist[(size_t)z * kRHist + (S.k % kRHist)] = r;
+        S.k += 1;
+        S.inner_done = 0;
+        // batched solves retire an instance on the device: cap, tolerance, NaN
+        if (!(r == r) || r > 1e30) { S.nonfinite = 1; S.active = 0; }
+        else if (S.tol_outer > 0.0 && S.k >= S.min_iter && r < S.tol_outer) { S.converged = 1; S.active = 0; }
+        else if (S.max_iter > 0 && S.k >= S.max_iter) S.active = 0;
+    }
+}
+
 template <int TH, int R>
 struct RhsTile {
     static constexpr int TW = kTileW, T = kRhsThreads;
@@ -195,11 +213,17 @@ __global__ __launch_bounds__(kRhsThreads) void k_rhs(KParams kp, int M, int N,
                                                       const float* __restrict__ W,
                                                       const float* __restrict__ g,
                                                       const float* __restrict__ D,
-                                                      float* __restrict__ out, DevScal* sc) {
+                                                      float* __restrict__ out,
+                                                      const double* __restrict__ fin_part, int fin_nb,
+                                                      double* __restrict__ fin_rhist, DevScal* sc) {
     using C = RhsTile<TH, R>;
     constexpr int TW = C::TW, T = C::T, EH = C::EH, EW = C::EW, NEXT = C::NEXT, PW = C::PW, PH = C::PH;
     const int z = blockIdx.z;
     if (!sc[z].active || sc[z].inner_done) return;
+    if (fin_part != nullptr && blockIdx.x == 0 && blockIdx.y == 0) {   // folded finalize (FinFold)
+        __shared__ double fred[2 * 16];
+        fin_outer_body(fin_part, fin_nb, fin_rhist, sc[z], z, fred);
+    }
     const size_t MN = (size_t)M * N;
     phi_s += z * MN; W += 2 * z * MN; g += z * MN; D += z * MN; out += z * MN;
 
@@ -921,19 +945,7 @@ __global__ __launch_bounds__(1024) void k_fin_outer(const double* __restrict__ p
     const int z = blockIdx.x;
     DevScal& S = sc[z];
     if (!S.active) return;
-    double v[2];
-    sum_partials<2>(part + (size_t)z * 2 * nb, nb, v, red);
-    if (threadIdx.x == 0) {
-        const double r = sqrt(v[0]) / (sqrt(v[1]) + 1e-6);
-        S.r_last = r;
-        rhist[(size_t)z * kRHist + (S.k % kRHist)] = r;
-        S.k += 1;
-        S.inner_done = 0;
-        // batched solves retire an instance on the device: cap, tolerance, NaN
-        if (!(r == r) || r > 1e30) { S.nonfinite = 1; S.active = 0; }
-        else if (S.tol_outer > 0.0 && S.k >= S.min_iter && r < S.tol_outer) { S.converged = 1; S.active = 0; }
-        else if (S.max_iter > 0 && S.k >= S.max_iter) S.active = 0;
-    }
+    fin_outer_body(part, nb, rhist, S, z, red);
 }
 
 // ---------------------------------------------------------------------------
@@ -1217,9 +1229,10 @@ static int tile_height(const Geometry& geo, int nz) {
 
 template <int TH, int R>
 static void launch_rhs_t(const Geometry& geo, const KParams& kp, const float* phi_s, const float* W, const float* g,
-                         const float* D, float* out, int nz, DevScal* sc, hipStream_t st) {
+                         const float* D, float* out, int nz, DevScal* sc, hipStream_t st, const FinFold* fold) {
     launch_iter(k_rhs<TH, R>, tile_grid(geo.M, geo.N, TH, nz), dim3(kRhsThreads),
-                sizeof(float) * RhsTile<TH, R>::lds_floats, st, kp, geo.M, geo.N, phi_s, W, g, D, out, sc);
+                sizeof(float) * RhsTile<TH, R>::lds_floats, st, kp, geo.M, geo.N, phi_s, W, g, D, out,
+                fold ? fold->part : nullptr, fold ? fold->nb : 0, fold ? fold->rhist : nullptr, sc);
 }
 template <int TH, int R, int TT>
 static void launch_wstep_t(const Geometry& geo, const KParams& kp, const float* phin, float* P0, const float* Wold,
@@ -1260,24 +1273,29 @@ static void launch_wstep_large(const Geometry& geo, const KParams& kp, const flo
     }
 
 void launch_rhs(const Geometry& geo, const KParams& kp, const float* phi_s, const float* W, const float* g,
-                const float* D, float* out, int nz, DevScal* sc, hipStream_t st) {
+                const float* D, float* out, int nz, DevScal* sc, hipStream_t st, const FinFold* fold) {
     const int TH = tile_height(geo, nz);
     if (TH == 32) {
-        SR_R_DISPATCH(launch_rhs_t, 32, kp.R, geo, kp, phi_s, W, g, D, out, nz, sc, st);
+        SR_R_DISPATCH(launch_rhs_t, 32, kp.R, geo, kp, phi_s, W, g, D, out, nz, sc, st, fold);
     } else if (TH == 16) {
-        SR_R_DISPATCH(launch_rhs_t, 16, kp.R, geo, kp, phi_s, W, g, D, out, nz, sc, st);
+        SR_R_DISPATCH(launch_rhs_t, 16, kp.R, geo, kp, phi_s, W, g, D, out, nz, sc, st, fold);
     } else {
-        SR_R_DISPATCH(launch_rhs_t, 8, kp.R, geo, kp, phi_s, W, g, D, out, nz, sc, st);
+        SR_R_DISPATCH(launch_rhs_t, 8, kp.R, geo, kp, phi_s, W, g, D, out, nz, sc, st, fold);
     }
+}
+
+static bool wstep_small(const Geometry& geo, int nz) { return (size_t)geo.M * geo.N * nz <= ((size_t)1 << 22); }
+int wstep_blocks(const Geometry& geo, int nz) {
+    const int TH = wstep_small(geo, nz) ? 32 : 16;
+    return ((geo.N + kTileW - 1) / kTileW) * ((geo.M + TH - 1) / TH);
 }
 
 void launch_wstep(const Geometry& geo, const KParams& kp, const float* phin, float* P0, const float* Wold,
                   const float* Bold, const float* g, float* Wnew, float* Bnew, float* D, double* part,
-                  double* rhist, int nz, DevScal* sc, hipStream_t st) {
+                  double* rhist, int nz, DevScal* sc, hipStream_t st, bool finalize) {
     // Fixed shapes, whatever tile height the autotuner picks for the right-hand
     // side (on 256 threads, 8 and 32 rows measured 18.8 / 180 and 19.5 / 194 us).
-    const bool small = (size_t)geo.M * geo.N * nz <= ((size_t)1 << 22);
-    const int TH = small ? 32 : 16;
+    const bool small = wstep_small(geo, nz);
     if (small) {
         SR_R_DISPATCH(launch_wstep_small, 32, kp.R, geo, kp, phin, P0, Wold, Bold, g, Wnew, Bnew, D, part, rhist, nz,
                       sc, st);
@@ -1285,8 +1303,8 @@ void launch_wstep(const Geometry& geo, const KParams& kp, const float* phin, flo
         SR_R_DISPATCH(launch_wstep_large, 16, kp.R, geo, kp, phin, P0, Wold, Bold, g, Wnew, Bnew, D, part, rhist, nz,
                       sc, st);
     }
-    const int nb = ((geo.N + kTileW - 1) / kTileW) * ((geo.M + TH - 1) / TH);
-    hipLaunchKernelGGL(k_fin_outer, dim3(nz), dim3(1024), 0, st, part, nb, rhist, sc);
+    if (!finalize) return;
+    hipLaunchKernelGGL(k_fin_outer, dim3(nz), dim3(1024), 0, st, part, wstep_blocks(geo, nz), rhist, sc);
 }
 
 template <int TH, int R>

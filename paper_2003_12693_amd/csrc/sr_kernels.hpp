@@ -38,17 +38,31 @@ void launch_set_D(const Geometry& geo, const float* W, const float* B, float* D,
 void launch_reset_scal(DevScal* sc, int n, int active, hipStream_t st);
 void launch_set_k(DevScal* sc, long long k, hipStream_t st);
 
+// The outer-iteration finalize (residual r_k, iteration count, retirement)
+// of the preceding w step, folded into a right-hand-side launch: its first
+// workgroup of each instance runs it before its own tile.  Only valid while
+// the inner stop rule is off (tol_inner = 0), since the other workgroups of
+// that launch may read the instance's flags before the finalize updates them.
+struct FinFold {
+    const double* part;   // the w step's residual partials
+    int nb;               // their count per instance (wstep_blocks)
+    double* rhist;
+};
 void launch_rhs(const Geometry& geo, const KParams& kp, const float* phi_s, const float* W, const float* g,
-                const float* D, float* out, int nz, DevScal* sc, hipStream_t st);
+                const float* D, float* out, int nz, DevScal* sc, hipStream_t st, const FinFold* fold = nullptr);
 void launch_solve(const Geometry& geo, const float* rhs, const float* phi_in, float* phi_out, float2* spec,
                   float tol_inner, double* part, int nz, DevScal* sc, hipStream_t st);
 // The three passes of launch_solve separately (pass 0: forward rows,
 // 1: column solve, 2: inverse rows), for per-kernel timing.
 void launch_solve_pass(int pass, const Geometry& geo, const float* rhs, const float* phi_in, float* phi_out,
                        float2* spec, float tol_inner, double* part, int nz, DevScal* sc, hipStream_t st);
+// finalize = false leaves the outer-iteration finalize to a FinFold in the
+// next right-hand-side launch.
 void launch_wstep(const Geometry& geo, const KParams& kp, const float* phin, float* P0, const float* Wold,
                   const float* Bold, const float* g, float* Wnew, float* Bnew, float* D, double* part,
-                  double* rhist, int nz, DevScal* sc, hipStream_t st);
+                  double* rhist, int nz, DevScal* sc, hipStream_t st, bool finalize = true);
+// Residual partials per instance written by launch_wstep.
+int wstep_blocks(const Geometry& geo, int nz);
 void launch_energy(const Geometry& geo, const KParams& kp, const float* phi, const float* g, double* part,
                    int nz, DevScal* sc, hipStream_t st);
 void launch_repulsion(const Geometry& geo, const KParams& kp, const float* phi, const float* W, float* V,

@@ -337,6 +337,31 @@ def test_profile_kernels_advance_like_step(sr):
     assert e.value.code == sr.SR_EINVAL
 
 
+def test_graph_replay_matches_direct_launches(sr):
+    """Graph replays (8-, 2- and 1-iteration graphs, the outer-iteration
+    finalize folded into the next iteration's first rhs launch) against
+    direct launches without graphs: bitwise the same phi, and the same k and
+    r_k, with and without the outer stop rule."""
+    _note("graph replay vs direct launches")
+    import os
+    f, phi0 = synth.two_disks(seed=3)
+    for kw in (dict(), dict(tol_outer=1e-3, check_every=3, min_iter=4)):
+        res = {}
+        for mode in ("direct", "graph"):
+            if mode == "direct":
+                os.environ["SR_NO_GRAPH"] = "1"
+            try:
+                s = sr.Solver(128, 128, gpu_params(**kw))
+            finally:
+                os.environ.pop("SR_NO_GRAPH", None)
+            s.set_image(_cuda(f), _cuda(phi0))
+            info = s.step(21)
+            res[mode] = (s.phi().cpu().numpy(), info["k"], info["r_last"], info["converged"])
+        a, b = res["direct"], res["graph"]
+        assert np.array_equal(a[0], b[0]), kw
+        assert a[1:] == b[1:], (kw, a[1:], b[1:])
+
+
 def test_nonfinite_input_rejected(sr):
     _note("nonfinite")
     s = sr.Solver(16, 16, gpu_params())
