@@ -190,7 +190,7 @@ __device__ __forceinline__ void fin_outer_body(const double* __restrict__ part, 
         S.r_last = r;
         rhist[(size_t)z * kRHist + (S.k % kRHist)] = r;
         S.k += 1;
-        S.inner_done = 0;
+        if (S.inner_done) S.inner_done = 0;   // (a folded finalize never finds it set)
         // batched solves retire an instance on the device: cap, tolerance, NaN
         if (!(r == r) || r > 1e30) { S.nonfinite = 1; S.active = 0; }
         else if (S.tol_outer > 0.0 && S.k >= S.min_iter && r < S.tol_outer) { S.converged = 1; S.active = 0; }
