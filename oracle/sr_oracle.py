@@ -17,6 +17,7 @@ It is a plain, slow, literal transcription of the method of Pan et al.,
   * repulsion window sum v (square window, Gaussian taps)  Sec. 4, after eq (37)
   * semi-implicit FFT solve of the phi sub-problem ....... eqs (30)-(33), (37)
   * generalised soft thresholding of w ................... eqs (41), (42)
+  * the alternative fixed-point iteration for w .......... eqs (38), (39)
   * projection onto |w| = 1 .............................. eq (40)
   * Bregman update ....................................... eq (23)
   * outer/inner loop ..................................... Algorithm 1, Sec. 4
@@ -64,6 +65,12 @@ class Params:
                          eq (42) (reading: the paper's 0 (0/|0|) = 0 applied to
                          B at rounding level, whose direction is noise); 0 is
                          the literal rule
+    w_solver           : 0: w by soft thresholding (eqs 41, 42) then eq (40);
+                         1: by the fixed-point iteration of eqs (38), (39) with
+                         the projection of eq (40) after every sweep
+    w_sweeps           : sweeps of that iteration, i.e. the paper's r = 0..R
+                         with R = w_sweeps - 1 (one sweep: the paper's
+                         "a single iteration is often enough")
     """
 
     gamma: float = 1.0
@@ -81,6 +88,8 @@ class Params:
     S: int = 3
     tol_inner: float = 0.0
     zero_tol: float = 1e-3
+    w_solver: int = 0
+    w_sweeps: int = 1
 
 
 # --------------------------------------------------------------------------
@@ -295,6 +304,29 @@ def w_subproblem(phi_new, w1, w2, b1, b2, g, P: Params):
     return project(s1, s2)
 
 
+def w_fixed_point(phi_new, w1, w2, b1, b2, g, P: Params):
+    """w^{k+1} by the fixed-point iteration of eqs (38)-(40): w^{k+1,0} = w^k;
+    sweep r builds v^{k+1,r} (eq 38) from w^{k+1,r} and h(phi^{k+1}), then
+      w~ = (mu grad phi^{k+1} + mu b^k + 2 beta h(phi^{k+1}) v^{k+1,r})
+           / (gamma g delta(phi^{k+1}) + mu)                       (eq 39)
+    and w^{k+1,r+1} = w~ / |w~| (eq 40); P.w_sweeps sweeps.  Zero rule
+    (the reading taken for eq 42, applied to the same vector): where the
+    numerator over mu -- B of eq (41) built from w^{k+1,r} -- has
+    |B| <= zero_tol, w^{k+1,r+1} is the zero vector."""
+    G1, G2 = grad_fwd(phi_new)
+    h = band(phi_new, P.eps, P.band_l)
+    den = P.gamma * g * dirac(phi_new, P.eps) + P.mu
+    wr1, wr2 = w1, w2
+    for _ in range(P.w_sweeps):
+        v1, v2 = repulsion_field(wr1, wr2, phi_new, P.eps, P.band_l, P.d, P.R)
+        n1 = P.mu * G1 + P.mu * b1 + 2.0 * P.beta * h * v1
+        n2 = P.mu * G2 + P.mu * b2 + 2.0 * P.beta * h * v2
+        t1, t2 = project(n1 / den, n2 / den)
+        live = np.sqrt(n1 * n1 + n2 * n2) / P.mu > P.zero_tol
+        wr1, wr2 = np.where(live, t1, 0.0), np.where(live, t2, 0.0)
+    return wr1, wr2
+
+
 def bregman(b1, b2, phi_new, w1_new, w2_new):
     """b^{k+1} = b^k + grad phi^{k+1} - w^{k+1}, eq (23)."""
     G1, G2 = grad_fwd(phi_new)
@@ -325,9 +357,11 @@ def initial_state(phi0):
 
 def sb_iteration(st: State, g, P: Params):
     """One outer iteration k of Algorithm 1: inner phi loop (eq 37),
-    w by eq (42) then eq (40), b by eq (23).  Returns (new state, info)."""
+    w by eq (42) then eq (40) (or by eqs 38-40 when P.w_solver = 1), b by
+    eq (23).  Returns (new state, info)."""
     phi_new, steps = phi_subproblem(st.phi, st.w1, st.w2, st.b1, st.b2, g, P)
-    w1n, w2n = w_subproblem(phi_new, st.w1, st.w2, st.b1, st.b2, g, P)
+    w_update = w_fixed_point if P.w_solver == 1 else w_subproblem
+    w1n, w2n = w_update(phi_new, st.w1, st.w2, st.b1, st.b2, g, P)
     b1n, b2n = bregman(st.b1, st.b2, phi_new, w1n, w2n)
     r = np.linalg.norm(phi_new - st.phi) / (np.linalg.norm(st.phi) + 1e-6)
     return State(phi_new, w1n, w2n, b1n, b2n, st.k + 1), {"r": r, "inner_steps": steps}

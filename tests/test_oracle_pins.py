@@ -414,3 +414,101 @@ def test_shrink_zero_tolerance_reading():
     np.testing.assert_array_equal(s[0], [0.0, 0.6])
     np.testing.assert_array_equal(s[1], [0.0, 0.8])
     assert O.Params().zero_tol == 1e-3
+
+
+# --------------------------------------------------------------------------
+# fixed-point iteration for w, eqs (38)-(40)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("sweeps", [1, 2, 3, 5])
+def test_w_fixed_point_uniform_field_recurrence(sweeps):
+    """On uniform fields (phi = c inside the band, so grad phi = 0, h and
+    delta constant; b = b0, w^k = a unit vector at angle th0) every sweep is
+    the planar map w <- (mu b0 + kappa w) / |mu b0 + kappa w| with
+    kappa = 2 beta h(c)^2 (sum_p a_p)^2: eq (38) gives v = h(c) (sum a)^2 w
+    for the full window.  The recurrence is iterated here with angles and
+    compared with the oracle."""
+    P = O.Params(R=3, d=3.0, beta=0.3, mu=0.5, gamma=1.0, eps=1.5, band_l=1.0, w_solver=1, w_sweeps=sweeps)
+    M = N = 16
+    c = 0.4
+    h0 = float(O.band(np.array(c), P.eps, P.band_l))
+    s_a = sum(math.exp(-(p * p) / (P.d * P.d)) for p in range(-P.R, P.R + 1))
+    kappa = 2.0 * P.beta * h0 * h0 * s_a * s_a
+    b0 = (0.3, -0.7)
+    th = 2.1
+    phi = np.full((M, N), c)
+    g = np.full((M, N), 0.8)
+    w1, w2 = np.full((M, N), math.cos(th)), np.full((M, N), math.sin(th))
+    b1, b2 = np.full((M, N), b0[0]), np.full((M, N), b0[1])
+    got1, got2 = O.w_fixed_point(phi, w1, w2, b1, b2, g, P)
+    x, y = math.cos(th), math.sin(th)
+    for _ in range(sweeps):
+        nx, ny = P.mu * b0[0] + kappa * x, P.mu * b0[1] + kappa * y
+        r = math.hypot(nx, ny)
+        x, y = nx / r, ny / r
+    np.testing.assert_allclose(got1, x, atol=1e-12)
+    np.testing.assert_allclose(got2, y, atol=1e-12)
+
+
+def test_w_fixed_point_one_sweep_is_open_gate_shrink():
+    """One sweep divides B of eq (41) (times mu) by a positive factor and
+    projects: where the soft-thresholding gate of eq (42) is open (|B| > t)
+    it gives the same unit vector as eqs (41)-(42)-(40); where the gate is
+    closed it still gives B/|B|, not 0."""
+    M, N = 24, 20
+    rng = np.random.default_rng(7)
+    phi = rng.uniform(-3, 3, (M, N))
+    w1, w2 = O.project(rng.normal(size=(M, N)), rng.normal(size=(M, N)))
+    b1, b2 = rng.normal(0, 0.5, (M, N)), rng.normal(0, 0.5, (M, N))
+    g = rng.uniform(0.1, 1.0, (M, N))
+    P = O.Params(R=2, d=2.0, w_solver=1, w_sweeps=1, zero_tol=1e-9)
+    f1, f2 = O.w_fixed_point(phi, w1, w2, b1, b2, g, P)
+    s1, s2 = O.w_subproblem(phi, w1, w2, b1, b2, g, P)
+    B1, B2, t = O.shrink_input(phi, w1, w2, b1, b2, g, P)
+    nb = np.hypot(B1, B2)
+    open_ = nb > t + 1e-9
+    closed = (nb < t - 1e-9) & (nb > 1e-6)
+    assert open_.sum() > 50 and closed.sum() > 5
+    np.testing.assert_allclose(f1[open_], s1[open_], atol=1e-12)
+    np.testing.assert_allclose(f2[open_], s2[open_], atol=1e-12)
+    np.testing.assert_allclose(f1[closed], (B1 / nb)[closed], atol=1e-12)
+    np.testing.assert_allclose(f2[closed], (B2 / nb)[closed], atol=1e-12)
+    assert np.all(s1[closed] == 0.0) and np.all(s2[closed] == 0.0)
+
+
+def test_w_fixed_point_converges_to_a_fixed_point():
+    """With a weak repulsion the sweeps contract: after many of them w solves
+    its own fixed-point equation, w = project(numerator of eq 39 built from
+    w), to rounding, and the result does not depend on the starting w."""
+    M, N = 20, 18
+    rng = np.random.default_rng(3)
+    phi = rng.uniform(-2, 2, (M, N))
+    g = rng.uniform(0.2, 1.0, (M, N))
+    b1, b2 = rng.normal(0, 1.0, (M, N)) + 1.5, rng.normal(0, 1.0, (M, N))
+    P = O.Params(R=2, d=2.0, beta=0.002, mu=1.0, w_solver=1, w_sweeps=60, zero_tol=0.0)
+    wa = O.w_fixed_point(phi, *O.project(rng.normal(size=(M, N)), rng.normal(size=(M, N))), b1, b2, g, P)
+    wb = O.w_fixed_point(phi, *O.project(rng.normal(size=(M, N)), rng.normal(size=(M, N))), b1, b2, g, P)
+    np.testing.assert_allclose(wa[0], wb[0], atol=1e-10)
+    np.testing.assert_allclose(wa[1], wb[1], atol=1e-10)
+    G1, G2 = O.grad_fwd(phi)
+    v1, v2 = O.repulsion_field(wa[0], wa[1], phi, P.eps, P.band_l, P.d, P.R)
+    h = O.band(phi, P.eps, P.band_l)
+    n1 = P.mu * (G1 + b1) + 2 * P.beta * h * v1
+    n2 = P.mu * (G2 + b2) + 2 * P.beta * h * v2
+    r1, r2 = O.project(n1, n2)
+    np.testing.assert_allclose(wa[0], r1, atol=1e-10)
+    np.testing.assert_allclose(wa[1], r2, atol=1e-10)
+
+
+def test_w_fixed_point_iteration_translation_equivariant():
+    """A whole outer iteration with the fixed-point w solver commutes with
+    periodic shifts of its inputs."""
+    M, N = 32, 24
+    rng = np.random.default_rng(11)
+    f = rng.uniform(0, 1, (M, N))
+    phi0 = np.add.outer(np.arange(M) - 15.5, np.zeros(N)) ** 2 / 20.0 - 4.0 + rng.normal(0, 0.1, (M, N))
+    P = O.Params(R=3, d=3.0, w_solver=1, w_sweeps=3)
+    a, ga, _ = O.solve(f, phi0, P, 2)
+    sh = (5, -7)
+    b, gb, _ = O.solve(np.roll(f, sh, (0, 1)), np.roll(phi0, sh, (0, 1)), P, 2)
+    np.testing.assert_allclose(b.phi, np.roll(a.phi, sh, (0, 1)), atol=1e-10)
+    np.testing.assert_allclose(b.w1, np.roll(a.w1, sh, (0, 1)), atol=1e-10)
