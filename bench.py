@@ -34,6 +34,8 @@ HBM_PEAK_GBS = 8000.0
 #   row inv: read spectrum 4 and phi_s 4, write phi 4
 #   w step: read phi^{k+1}, phi^k, w(2), b(2), g = 28, write phi, w(2), b(2), D = 24
 BYTES_PER_PX = {"rhs_repulsion": 24, "row_fft_fwd": 8, "col_fft_solve": 8, "row_fft_inv": 12, "w_step": 52}
+# a fixed-point w sweep before the last one: reads phi (4), w (8), b (8), g (4), writes w (8)
+BYTES_PER_PX_W_SWEEP = 32
 
 # The paper's two-circles weights (alpha = gamma = 4, beta = 0.2, mu = 8,
 # tau = 0.1, l = 1, d = 5, S = 3) with each workload's eps / R.
@@ -50,9 +52,12 @@ KERNEL_SRC = os.path.join(ROOT, "paper_2003_12693_amd", "csrc", "sr_kernels.hip"
 
 
 def params_kw(wl):
-    return dict(gamma=4.0, alpha=4.0, beta=0.2, mu=8.0, tau=0.1, eps=wl["eps"], band_l=1.0,
-                d=wl["d"], R=wl["R"], sigma=1.5, rho=1000.0, s_exp=2, S=wl["S"],
-                tol_inner=0.0, zero_tol=1e-3)
+    kw = dict(gamma=4.0, alpha=4.0, beta=0.2, mu=8.0, tau=0.1, eps=wl["eps"], band_l=1.0,
+              d=wl["d"], R=wl["R"], sigma=1.5, rho=1000.0, s_exp=2, S=wl["S"],
+              tol_inner=0.0, zero_tol=1e-3)
+    if wl.get("w_sweeps"):   # the fixed-point w solver of eqs 38-40
+        kw.update(w_solver=1, w_sweeps=wl["w_sweeps"])
+    return kw
 
 
 def make_input(name):
@@ -284,6 +289,8 @@ def main():
                     help="stencil tile height (default: chosen by the autotuner)")
     ap.add_argument("--cpu-iters", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--w-sweeps", type=int, default=0, metavar="R",
+                    help="use the fixed-point w solver (eqs 38-40) with R sweeps instead of soft thresholding")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB")
     ap.add_argument("--batch", type=int, default=0, metavar="COUNT",
                     help="time-to-converge of COUNT uneven instances, batched vs plain")
@@ -316,7 +323,10 @@ def main():
     import torch
     from paper_2003_12693_amd import sr
 
-    wl = WORKLOADS[args.workload]
+    wl = dict(WORKLOADS[args.workload])
+    if args.w_sweeps:
+        wl["w_sweeps"] = args.w_sweeps
+        wl["text"] += f"; fixed-point w solver, {args.w_sweeps} sweeps" 
     steps = args.steps if args.steps is not None else wl["default_steps"]
     M, N = wl["M"], wl["N"]
     f, phi0 = make_input(args.workload)
@@ -351,7 +361,10 @@ def main():
     per_iter_ms = {k: prof[k][0] * per_iter[k] for k in prof}
     dom = max(per_iter_ms, key=per_iter_ms.get)
     dom_ms = prof[dom][0]
-    alg_bytes = BYTES_PER_PX[dom] * M * N
+    bytes_px = dict(BYTES_PER_PX)
+    if args.w_sweeps > 1:   # w_step launches average the sweeps and the full step
+        bytes_px["w_step"] = (BYTES_PER_PX["w_step"] + BYTES_PER_PX_W_SWEEP * (args.w_sweeps - 1)) / args.w_sweeps
+    alg_bytes = bytes_px[dom] * M * N
     achieved = alg_bytes / (dom_ms * 1e-3) / 1e9
 
     out = {
@@ -368,10 +381,12 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": wl["text"], "M": M, "N": N, "R": wl["R"], "S": wl["S"], "tile_rows": tile_th,
-                   "bytes_per_px_iter": sum(BYTES_PER_PX[k] * per_iter[k] for k in prof)},
+                   "bytes_per_px_iter": sum(bytes_px[k] * per_iter[k] for k in prof),
+                   "w_solver": "fixed-point" if args.w_sweeps else "shrink", "w_sweeps": args.w_sweeps or None},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(args.workload, dom), "alg_bytes_per_launch": alg_bytes},
+                     "traffic": None if args.w_sweeps else measured_traffic(args.workload, dom),
+                     "alg_bytes_per_launch": alg_bytes},
         "kernels_ms": {k: round(v[0], 5) for k, v in prof.items()},
         "iteration_ms_sum_of_kernels": round(sum(per_iter_ms.values()), 5),
         "energy_after": E,

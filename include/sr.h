@@ -85,6 +85,11 @@ typedef struct sr_params {
     int32_t w0_mode;       /* 0: w^0 = grad phi^0 (Algorithm 1), 1: w^0 = 0 (eq 23's text) */
     double zero_tol;       /* |B| <= zero_tol is the zero vector of eq (42) (its
                               0 (0/|0|) = 0 rule at rounding level); 0 = literal */
+    int32_t w_solver;      /* 0: w by soft thresholding, eqs (41)-(42), then eq (40);
+                              1: by the fixed-point iteration of eqs (38)-(39), each
+                              sweep projected by eq (40) (same zero rule)        */
+    int32_t w_sweeps;      /* sweeps of that iteration, 1..16 (the paper's r = 0..R,
+                              R = w_sweeps - 1); ignored when w_solver = 0       */
 } sr_params;
 
 /* Per-call report of sr_step. */
@@ -183,7 +188,9 @@ int sr_implicit_solve(sr_ctx* ctx, const float* rhs, float* u_out, uint32_t flag
  *   ms[2] column FFT solve (eqs 31-33)     ms[3] inverse row FFT + update
  *   ms[4] w / b step (eqs 40-42, 23)
  * count[i] receives the number of launches timed (n_iter S for the first
- * four kinds, n_iter for the w step).  Synchronises; ignores tol_outer.
+ * four kinds, n_iter for the w step, n_iter w_sweeps with the fixed-point
+ * w solver, whose intermediate sweeps count as w-step launches).
+ * Synchronises; ignores tol_outer.
  * Returns SR_EINVAL for n_iter < 1, SR_ESTATE before sr_set_image. */
 #define SR_NUM_KERNEL_KINDS 5
 int sr_profile_kernels(sr_ctx* ctx, int32_t n_iter, double ms[SR_NUM_KERNEL_KINDS],

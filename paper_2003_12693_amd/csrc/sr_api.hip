@@ -92,6 +92,8 @@ static int validate(int32_t M, int32_t N, const sr_params* p) {
     if (p->min_iter < 0) return fail(SR_EINVAL, "min_iter must be >= 0");
     if (p->w0_mode != 0 && p->w0_mode != 1) return fail(SR_EINVAL, "w0_mode must be 0 or 1");
     if (p->zero_tol < 0) return fail(SR_EINVAL, "zero_tol must be >= 0");
+    if (p->w_solver != 0 && p->w_solver != 1) return fail(SR_EINVAL, "w_solver must be 0 or 1");
+    if (p->w_sweeps < 1 || p->w_sweeps > 16) return fail(SR_EINVAL, "w_sweeps must be in [1, 16]");
     return SR_OK;
 }
 
@@ -99,13 +101,18 @@ static int validate(int32_t M, int32_t N, const sr_params* p) {
 // workspace layout
 // ---------------------------------------------------------------------------
 struct Layout {
-    size_t twM, twN, stM, stN, g, P0, P1, P2, W0, W1, B0, B1, D, Rb, spec, part, scal, rhist, total;
+    size_t twM, twN, stM, stN, g, P0, P1, P2, W0, W1, B0, B1, D, Rb, spec, part, scal, rhist, X0, X1, total;
 };
 
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// w buffers of the intermediate sweeps of the fixed-point w solver.
+static int sweep_buffers(const sr_params& p) {
+    return p.w_solver == 1 ? std::min(2, p.w_sweeps - 1) : 0;
+}
+
 // nz instances of one size class laid out plane-by-plane ([nz][M][N] each).
-static Layout make_layout(int M, int N, int nz) {
+static Layout make_layout(int M, int N, int nz, int xbufs = 0) {
     Layout L{};
     const size_t MN = (size_t)M * N, pl = MN * 4 * nz, vec = 2 * pl;
     size_t o = 0;
@@ -129,6 +136,8 @@ static Layout make_layout(int M, int N, int nz) {
     L.part = take(sizeof(double) * 3 * (size_t)nb * nz);
     L.scal = take(sizeof(DevScal) * nz);
     L.rhist = take(sizeof(double) * sr::kRHist * nz);
+    L.X0 = xbufs > 0 ? take(vec) : 0;
+    L.X1 = xbufs > 1 ? take(vec) : 0;
     L.total = o;
     return L;
 }
@@ -143,6 +152,7 @@ struct Bufs {
     double* part;
     DevScal* scal;
     double* rhist;
+    float* X[2];   // intermediate w of the fixed-point sweeps (when allocated)
 };
 
 struct sr_ctx {
@@ -183,6 +193,8 @@ static void carve(Bufs& b, char* base, const Layout& L) {
     b.part = (double*)(base + L.part);
     b.scal = (DevScal*)(base + L.scal);
     b.rhist = (double*)(base + L.rhist);
+    b.X[0] = L.X0 ? (float*)(base + L.X0) : nullptr;
+    b.X[1] = L.X1 ? (float*)(base + L.X1) : nullptr;
 }
 
 static void make_kparams(const sr_params& p, KParams& kp) {
@@ -196,7 +208,10 @@ static void make_kparams(const sr_params& p, KParams& kp) {
     kp.inv_eps = (float)(1.0 / p.eps);
     kp.band_l = (float)p.band_l;
     kp.c_rep = (float)(2.0 * p.beta / p.mu);
-    kp.c_thr = (float)(p.gamma / p.mu);
+    // the fixed-point w solver (eqs 38-39) has no soft-thresholding gate:
+    // after the projection its sweep is B / |B| (the positive denominator of
+    // eq 39 cancels), i.e. the eq (42) gate with a zero threshold
+    kp.c_thr = p.w_solver == 1 ? 0.0f : (float)(p.gamma / p.mu);
     kp.tol_inner = (float)p.tol_inner;
     kp.zero_tol = (float)p.zero_tol;
     kp.R = p.R;
@@ -269,8 +284,19 @@ static void enqueue_iteration(sr_ctx* c, int p, hipStream_t st, Hook&& before = 
         }
         in = out;
     }
+    // fixed-point w solver: w_sweeps - 1 sweeps that write only w (into the
+    // X buffers), then the full w step from the last of them
+    const float* w_in = b.W[p];
+    if (c->p.w_solver == 1)
+        for (int r = 0; r + 1 < c->p.w_sweeps; ++r) {
+            float* w_out = b.X[r & 1];
+            before(4);
+            sr::launch_wstep(c->geo, c->kp, in, b.P0, w_in, b.B[p], b.g, w_out, nullptr, nullptr, nullptr,
+                             nullptr, c->nz, b.scal, st, false, true);
+            w_in = w_out;
+        }
     before(4);
-    sr::launch_wstep(c->geo, c->kp, in, b.P0, b.W[p], b.B[p], b.g, b.W[1 - p], b.B[1 - p], b.D, b.part, b.rhist,
+    sr::launch_wstep(c->geo, c->kp, in, b.P0, w_in, b.B[p], b.g, b.W[1 - p], b.B[1 - p], b.D, b.part, b.rhist,
                      c->nz, b.scal, st, fin_out);
 }
 
@@ -421,6 +447,8 @@ int sr_params_default(sr_params* p) {
     p->check_every = 10;
     p->w0_mode = 0;
     p->zero_tol = 1e-3;
+    p->w_solver = 0;
+    p->w_sweeps = 1;
     return SR_OK;
 }
 
@@ -428,7 +456,7 @@ int sr_workspace_size(int32_t M, int32_t N, const sr_params* p, size_t* bytes) {
     if (!bytes) return fail(SR_EINVAL, "bytes is NULL");
     int rc = validate(M, N, p);
     if (rc) return rc;
-    *bytes = make_layout(M, N, 1).total;
+    *bytes = make_layout(M, N, 1, sweep_buffers(*p)).total;
     return SR_OK;
 }
 
@@ -440,7 +468,7 @@ int sr_create(sr_ctx** out, int32_t M, int32_t N, const sr_params* p, void* work
     if (rc) return rc;
     if (!workspace) return fail(SR_EINVAL, "workspace is NULL");
     if ((uintptr_t)workspace & 255) return fail(SR_EWORKSPACE, "workspace must be 256-byte aligned");
-    const Layout L = make_layout(M, N, 1);
+    const Layout L = make_layout(M, N, 1, sweep_buffers(*p));
     if (bytes < L.total) return fail(SR_EWORKSPACE, "workspace has %zu bytes, needs %zu", bytes, L.total);
 
     sr::configure_kernels();
@@ -696,7 +724,9 @@ int sr_profile_kernels(sr_ctx* c, int32_t n_iter, double ms[SR_NUM_KERNEL_KINDS]
     // n_iter outer iterations launched directly on the stream (no graph), the
     // same kernels in the same order as a graph replay, each iteration kernel
     // with its own start / stop events; synchronised after every iteration.
-    const int per = 4 * c->p.S + 1;
+    // iteration kernels per outer iteration: S x 4, then the w step (one
+    // launch per fixed-point sweep with that solver)
+    const int per = 4 * c->p.S + (c->p.w_solver == 1 ? c->p.w_sweeps : 1);
     std::vector<hipEvent_t> ev(2 * (size_t)per, nullptr);
     std::vector<int> kind(per, 0);
     hipError_t e = hipSuccess;
@@ -707,6 +737,10 @@ int sr_profile_kernels(sr_ctx* c, int32_t n_iter, double ms[SR_NUM_KERNEL_KINDS]
     for (int it = 0; it < n_iter && e == hipSuccess; ++it) {
         int slot = 0;
         enqueue_iteration(c, c->parity, c->stream, [&](int k) {
+            if (slot >= per) {   // cannot happen while per matches enqueue_iteration
+                sr::set_launch_events(nullptr, nullptr);
+                return;
+            }
             sr::set_launch_events(ev[2 * slot], ev[2 * slot + 1]);
             kind[slot++] = k;
         });
@@ -745,7 +779,8 @@ static bool same_class(const sr_batch_item& a, const sr_batch_item& b) {
     return a.M == b.M && a.N == b.N && x.gamma == y.gamma && x.alpha == y.alpha && x.beta == y.beta &&
            x.mu == y.mu && x.tau == y.tau && x.eps == y.eps && x.band_l == y.band_l && x.d == y.d && x.R == y.R &&
            x.sigma == y.sigma && x.rho == y.rho && x.s_exp == y.s_exp && x.S == y.S &&
-           x.tol_inner == y.tol_inner && x.w0_mode == y.w0_mode && x.zero_tol == y.zero_tol;
+           x.tol_inner == y.tol_inner && x.w0_mode == y.w0_mode && x.zero_tol == y.zero_tol &&
+           x.w_solver == y.w_solver && (x.w_solver == 0 || x.w_sweeps == y.w_sweeps);
 }
 
 struct BatchPlan {
@@ -769,7 +804,7 @@ static int plan_batch(const sr_batch_item* items, int32_t n, BatchPlan& plan) {
     size_t o = 0;
     for (auto& g : plan.groups) {
         plan.offset.push_back(o);
-        o += align256(make_layout(items[g[0]].M, items[g[0]].N, (int)g.size()).total);
+        o += align256(make_layout(items[g[0]].M, items[g[0]].N, (int)g.size(), sweep_buffers(items[g[0]].params)).total);
     }
     plan.total = o;
     return SR_OK;
@@ -810,7 +845,7 @@ int sr_solve_batch(sr_batch_item* items, int32_t n, void* workspace, size_t byte
         c.stream = st;
         make_kparams(c.p, c.kp);
         make_gauss(c.p.sigma, c.gauss, c.gauss_r);
-        carve(c.b, (char*)workspace + plan.offset[gi], make_layout(c.M, c.N, c.nz));
+        carve(c.b, (char*)workspace + plan.offset[gi], make_layout(c.M, c.N, c.nz, sweep_buffers(c.p)));
         c.geo.M = c.M; c.geo.N = c.N; c.geo.twM = c.b.twM; c.geo.twN = c.b.twN;
         c.geo.stM = c.b.stM; c.geo.stN = c.b.stN;
         c.geo.taumu = (float)(c.p.tau * c.p.mu);

@@ -736,7 +736,7 @@ __global__ __launch_bounds__(TT) void k_wstep(KParams kp, int M, int N,
                                                         const float* __restrict__ g,
                                                         float* __restrict__ Wnew, float* __restrict__ Bnew,
                                                         float* __restrict__ D, double* __restrict__ part,
-                                                        double* __restrict__ rhist, DevScal* sc) {
+                                                        double* __restrict__ rhist, int sweep, DevScal* sc) {
     using C = WTile<TH, R, TT>;
     constexpr int TW = C::TW, T = C::T, CH = C::CH, CW = C::CW, EH = C::EH, EW = C::EW, NEXT = C::NEXT;
     constexpr int PH = C::PH, PW = C::PW;
@@ -882,7 +882,7 @@ __global__ __launch_bounds__(TT) void k_wstep(KParams kp, int M, int N,
                 if (ci >= 1 && cj >= 1 && i0 - 1 + ci < M && j0 - 1 + cj < N) {
                     const size_t o = (size_t)(i0 - 1 + ci) * N + (j0 - 1 + cj);
                     Wnew[o] = w1; Wnew[MN + o] = w2;
-                    Bnew[o] = bn1; Bnew[MN + o] = bn2;
+                    if (!sweep) { Bnew[o] = bn1; Bnew[MN + o] = bn2; }
                 }
             }
         }
@@ -908,11 +908,12 @@ __global__ __launch_bounds__(TT) void k_wstep(KParams kp, int M, int N,
                 if (ci >= 1 && cj >= 1 && i0 - 1 + ci < M && j0 - 1 + cj < N) {
                     const size_t o = (size_t)(i0 - 1 + ci) * N + (j0 - 1 + cj);
                     Wnew[o] = w1; Wnew[MN + o] = w2;
-                    Bnew[o] = bn1; Bnew[MN + o] = bn2;
+                    if (!sweep) { Bnew[o] = bn1; Bnew[MN + o] = bn2; }
                 }
             }
         }
     }
+    if (sweep) return;   // a fixed-point sweep writes w only
     __syncthreads();
     double sdiff = 0.0, sold = 0.0;
 #pragma unroll
@@ -1237,10 +1238,10 @@ static void launch_rhs_t(const Geometry& geo, const KParams& kp, const float* ph
 template <int TH, int R, int TT>
 static void launch_wstep_t(const Geometry& geo, const KParams& kp, const float* phin, float* P0, const float* Wold,
                            const float* Bold, const float* g, float* Wnew, float* Bnew, float* D, double* part,
-                           double* rhist, int nz, DevScal* sc, hipStream_t st) {
+                           double* rhist, int sweep, int nz, DevScal* sc, hipStream_t st) {
     launch_iter(k_wstep<TH, R, TT>, tile_grid(geo.M, geo.N, TH, nz), dim3(TT),
                 sizeof(float) * WTile<TH, R, TT>::lds_floats, st, kp, geo.M, geo.N, phin, P0, Wold, Bold, g, Wnew,
-                Bnew, D, part, rhist, sc);
+                Bnew, D, part, rhist, sweep, sc);
 }
 // The two w-step tile shapes in use: 64 x 32 on 512 threads up to 4 Mpx per
 // launch, 64 x 16 on 256 threads above (measured 16.0 / 171 us against
@@ -1248,14 +1249,16 @@ static void launch_wstep_t(const Geometry& geo, const KParams& kp, const float* 
 template <int TH, int R>
 static void launch_wstep_small(const Geometry& geo, const KParams& kp, const float* phin, float* P0,
                                const float* Wold, const float* Bold, const float* g, float* Wnew, float* Bnew,
-                               float* D, double* part, double* rhist, int nz, DevScal* sc, hipStream_t st) {
-    launch_wstep_t<TH, R, 512>(geo, kp, phin, P0, Wold, Bold, g, Wnew, Bnew, D, part, rhist, nz, sc, st);
+                               float* D, double* part, double* rhist, int sweep, int nz, DevScal* sc,
+                               hipStream_t st) {
+    launch_wstep_t<TH, R, 512>(geo, kp, phin, P0, Wold, Bold, g, Wnew, Bnew, D, part, rhist, sweep, nz, sc, st);
 }
 template <int TH, int R>
 static void launch_wstep_large(const Geometry& geo, const KParams& kp, const float* phin, float* P0,
                                const float* Wold, const float* Bold, const float* g, float* Wnew, float* Bnew,
-                               float* D, double* part, double* rhist, int nz, DevScal* sc, hipStream_t st) {
-    launch_wstep_t<TH, R, 256>(geo, kp, phin, P0, Wold, Bold, g, Wnew, Bnew, D, part, rhist, nz, sc, st);
+                               float* D, double* part, double* rhist, int sweep, int nz, DevScal* sc,
+                               hipStream_t st) {
+    launch_wstep_t<TH, R, 256>(geo, kp, phin, P0, Wold, Bold, g, Wnew, Bnew, D, part, rhist, sweep, nz, sc, st);
 }
 
 #define SR_R_DISPATCH(FN, TH, R, ...)                                                          \
@@ -1292,18 +1295,18 @@ int wstep_blocks(const Geometry& geo, int nz) {
 
 void launch_wstep(const Geometry& geo, const KParams& kp, const float* phin, float* P0, const float* Wold,
                   const float* Bold, const float* g, float* Wnew, float* Bnew, float* D, double* part,
-                  double* rhist, int nz, DevScal* sc, hipStream_t st, bool finalize) {
+                  double* rhist, int nz, DevScal* sc, hipStream_t st, bool finalize, bool sweep) {
     // Fixed shapes, whatever tile height the autotuner picks for the right-hand
     // side (on 256 threads, 8 and 32 rows measured 18.8 / 180 and 19.5 / 194 us).
     const bool small = wstep_small(geo, nz);
     if (small) {
-        SR_R_DISPATCH(launch_wstep_small, 32, kp.R, geo, kp, phin, P0, Wold, Bold, g, Wnew, Bnew, D, part, rhist, nz,
-                      sc, st);
+        SR_R_DISPATCH(launch_wstep_small, 32, kp.R, geo, kp, phin, P0, Wold, Bold, g, Wnew, Bnew, D, part, rhist,
+                      (int)sweep, nz, sc, st);
     } else {
-        SR_R_DISPATCH(launch_wstep_large, 16, kp.R, geo, kp, phin, P0, Wold, Bold, g, Wnew, Bnew, D, part, rhist, nz,
-                      sc, st);
+        SR_R_DISPATCH(launch_wstep_large, 16, kp.R, geo, kp, phin, P0, Wold, Bold, g, Wnew, Bnew, D, part, rhist,
+                      (int)sweep, nz, sc, st);
     }
-    if (!finalize) return;
+    if (!finalize || sweep) return;
     hipLaunchKernelGGL(k_fin_outer, dim3(nz), dim3(1024), 0, st, part, wstep_blocks(geo, nz), rhist, sc);
 }
 

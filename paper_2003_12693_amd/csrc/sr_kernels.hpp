@@ -57,10 +57,12 @@ void launch_solve(const Geometry& geo, const float* rhs, const float* phi_in, fl
 void launch_solve_pass(int pass, const Geometry& geo, const float* rhs, const float* phi_in, float* phi_out,
                        float2* spec, float tol_inner, double* part, int nz, DevScal* sc, hipStream_t st);
 // finalize = false leaves the outer-iteration finalize to a FinFold in the
-// next right-hand-side launch.
+// next right-hand-side launch.  sweep = true: one sweep of the fixed-point w
+// solver only, w from Wold into Wnew (Bnew, D, part, rhist unused; P0 not
+// written; no finalize).
 void launch_wstep(const Geometry& geo, const KParams& kp, const float* phin, float* P0, const float* Wold,
                   const float* Bold, const float* g, float* Wnew, float* Bnew, float* D, double* part,
-                  double* rhist, int nz, DevScal* sc, hipStream_t st, bool finalize = true);
+                  double* rhist, int nz, DevScal* sc, hipStream_t st, bool finalize = true, bool sweep = false);
 // Residual partials per instance written by launch_wstep.
 int wstep_blocks(const Geometry& geo, int nz);
 void launch_energy(const Geometry& geo, const KParams& kp, const float* phi, const float* g, double* part,

@@ -43,21 +43,23 @@ def test_struct_layout_matches_c(sr, tmp_path):
     src = tmp_path / "layout.c"
     src.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "sr.h"\n'
-        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(sr_params), sizeof(sr_step_info),"
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(sr_params), sizeof(sr_step_info),"
         " sizeof(sr_batch_item), offsetof(sr_params, w0_mode), offsetof(sr_batch_item, params),"
-        " offsetof(sr_batch_item, energy), offsetof(sr_params, tol_outer)); return 0;}\n")
+        " offsetof(sr_batch_item, energy), offsetof(sr_params, tol_outer), offsetof(sr_params, w_sweeps));"
+        " return 0;}\n")
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     vals = list(map(int, subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()))
     assert vals == [C.sizeof(sr.sr_params), C.sizeof(sr.sr_step_info), C.sizeof(sr.sr_batch_item),
                     sr.sr_params.w0_mode.offset, sr.sr_batch_item.params.offset,
-                    sr.sr_batch_item.energy.offset, sr.sr_params.tol_outer.offset]
+                    sr.sr_batch_item.energy.offset, sr.sr_params.tol_outer.offset, sr.sr_params.w_sweeps.offset]
 
 
 def test_defaults_are_the_two_circles_set(sr):
     p = sr.sr_params_default()
     assert p.struct_size == C.sizeof(sr.sr_params)
     assert (p.alpha, p.gamma, p.beta, p.mu, p.tau, p.S, p.band_l, p.d) == (4.0, 4.0, 0.2, 8.0, 0.1, 3, 1.0, 5.0)
+    assert (p.w_solver, p.w_sweeps) == (0, 1)
 
 
 @pytest.mark.parametrize("M,N,kw,code", [
@@ -131,3 +133,19 @@ def test_batch_validation_before_hip(sr):
     assert lib.sr_batch_workspace_size(items, 2, C.byref(n)) == sr.SR_EINVAL
     items[1].max_iter = 10
     assert lib.sr_solve_batch(items, 2, None, 0, None) == sr.SR_EINVAL     # NULL buffers
+
+
+def test_fixed_point_w_solver_parameters(sr):
+    """w_solver / w_sweeps are validated before any HIP call, and the
+    workspace carries the intermediate w of the sweeps (one 2-plane buffer
+    for two sweeps, two from three on)."""
+    base = sr.sr_workspace_size(64, 64, sr.sr_params_default())
+    for bad in (dict(w_solver=2), dict(w_solver=1, w_sweeps=0), dict(w_solver=1, w_sweeps=17)):
+        with pytest.raises(sr.SRError) as e:
+            sr.sr_workspace_size(64, 64, sr.sr_params_default(**bad))
+        assert e.value.code == sr.SR_EINVAL, bad
+    vec = 2 * 64 * 64 * 4
+    assert sr.sr_workspace_size(64, 64, sr.sr_params_default(w_solver=1, w_sweeps=1)) == base
+    assert sr.sr_workspace_size(64, 64, sr.sr_params_default(w_solver=1, w_sweeps=2)) == base + vec
+    assert sr.sr_workspace_size(64, 64, sr.sr_params_default(w_solver=1, w_sweeps=5)) == base + 2 * vec
+    assert sr.sr_workspace_size(64, 64, sr.sr_params_default(w_solver=0, w_sweeps=5)) == base

@@ -155,3 +155,23 @@ def test_autotune_leaves_state_and_results_unchanged(sr):
         t.set_image(_cuda(f), _cuda(p))
         t.step(5)
         assert np.array_equal(t.phi().cpu().numpy(), want), forced
+
+
+def test_fixed_point_w_batch_matches_single(sr):
+    """17 instances of 512^2 with the fixed-point w solver (3 sweeps): the
+    batch (above 4 Mpx per launch: 64x16 w-step tiles on 256 threads) gives
+    bitwise the results of single solves (64x32 tiles on 512 threads), whose
+    sweeps the teacher-forced tests check against the oracle."""
+    _note("fixed-point w: batch vs single")
+    kw = gpu_params(w_solver=1, w_sweeps=3)
+    inst = [synth.ellipses(512, 512, seed=900 + i, n_shapes=3, axis_lo=15.0, axis_hi=60.0, inset=16)
+            for i in range(17)]
+    items = [dict(f=_cuda(f), phi0=_cuda(p), max_iter=3, params=kw) for (f, p) in inst]
+    rc, res = sr.solve_batch(items)
+    assert rc == 0
+    for (f, p), r in zip(inst[:4] + inst[-2:], res[:4] + res[-2:]):
+        assert r["iters"] == 3 and r["status"] == 0
+        s = sr.Solver(512, 512, kw)
+        s.set_image(_cuda(f), _cuda(p))
+        s.step(3)
+        assert np.array_equal(r["phi"].cpu().numpy(), s.phi().cpu().numpy())

@@ -169,6 +169,19 @@ def test_teacher_forced_variants(sr, kw):
     _check_w_b(ref, gw, gb)
 
 
+@pytest.mark.parametrize("sweeps", [1, 2, 3, 5])
+@pytest.mark.parametrize("k", [3, 20])
+def test_teacher_forced_fixed_point_w(sr, sweeps, k):
+    """The fixed-point w solver (eqs 38-40, w_sweeps sweeps, each with the
+    repulsion field rebuilt from the previous sweep's w) against the oracle."""
+    _note(f"teacher forced fixed-point w sweeps={sweeps} k={k}")
+    kw = dict(w_solver=1, w_sweeps=sweeps)
+    f, phi0, P, states = _c1_states([k], **kw)
+    ref, gphi, gw, gb, kk, res = _teacher_forced(sr, f, P, states[k], kw, 128, 128)
+    assert rel_l2(gphi, ref.phi) <= 1e-5
+    _check_w_b(ref, gw, gb)
+
+
 @pytest.mark.parametrize("shape", [(8, 8), (16, 128), (64, 32), (256, 512)])
 def test_teacher_forced_shapes(sr, shape):
     """Ragged / tiny grids: tiles larger than the image, wrap-around halos."""
@@ -335,6 +348,13 @@ def test_profile_kernels_advance_like_step(sr):
     with pytest.raises(sr.SRError) as e:
         sr.sr_profile_kernels(b.ctx, 0)
     assert e.value.code == sr.SR_EINVAL
+    # the fixed-point w solver: every sweep is a timed w-step launch
+    c = sr.Solver(128, 128, gpu_params(w_solver=1, w_sweeps=3))
+    c.set_image(_cuda(f), _cuda(phi0))
+    c.step(2)
+    prof = sr.sr_profile_kernels(c.ctx, 2)
+    assert prof["w_step"][1] == 6 and prof["rhs_repulsion"][1] == 2 * kw.S, prof
+    assert c.get_state()[3] == 4
 
 
 def test_graph_replay_matches_direct_launches(sr):
