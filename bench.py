@@ -75,15 +75,18 @@ def source_sha():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload, kernel):
+def measured_traffic(workload, kernel, tile_rows):
     """HBM bytes per launch from the committed rocprofv3 counter summary,
-    or None if it was taken on different kernel sources."""
+    or None if it was taken on different kernel sources.  The right-hand-side
+    kernel's traffic depends on its tile height (halo rows), so it is listed
+    per height ("rhs_repulsion@16")."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     sha = source_sha()
+    key = f"{kernel}@{tile_rows}" if kernel == "rhs_repulsion" else kernel
     for line in open(TRAFFIC_FILE):
         parts = line.split("#", 1)[0].split()
-        if len(parts) == 4 and parts[0] == workload and parts[1] == kernel and parts[3] == sha:
+        if len(parts) == 4 and parts[0] == workload and parts[1] == key and parts[3] == sha:
             return int(parts[2])
     return None
 
@@ -385,7 +388,7 @@ def main():
                    "w_solver": "fixed-point" if args.w_sweeps else "shrink", "w_sweeps": args.w_sweeps or None},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None if args.w_sweeps else measured_traffic(args.workload, dom),
+                     "traffic": None if args.w_sweeps else measured_traffic(args.workload, dom, tile_th),
                      "alg_bytes_per_launch": alg_bytes},
         "kernels_ms": {k: round(v[0], 5) for k, v in prof.items()},
         "iteration_ms_sum_of_kernels": round(sum(per_iter_ms.values()), 5),

@@ -205,7 +205,8 @@ int sr_profile_kernels(sr_ctx* ctx, int32_t n_iter, double ms[SR_NUM_KERNEL_KIND
  * launching the right-hand-side kernel, which reads the state and writes
  * only its own scratch plane, so the iterate is unchanged and so is every
  * later result (the per-pixel arithmetic does not depend on the tile
- * height).  The fastest is kept for the context and recorded process-wide
+ * height).  The fastest is kept (16 rows unless another is at least 3%
+ * faster, so that near ties give one choice) for the context and recorded process-wide
  * for its size class (M, N, R); sr_create and every size-class group of
  * sr_solve_batch take a recorded choice, and sr_solve_batch tunes classes
  * it has not seen.  reps >= 1 timed launches per candidate after one warm-
