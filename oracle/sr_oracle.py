@@ -16,6 +16,7 @@ It is a plain, slow, literal transcription of the method of Pan et al.,
     backward divergence (unit spacing) ................... eqs (35), (36)
   * repulsion window sum v (square window, Gaussian taps)  Sec. 4, after eq (37)
   * semi-implicit FFT solve of the phi sub-problem ....... eqs (30)-(33), (37)
+  * or its AOS solve with constant A_l (Thomas algorithm)  eqs (18), (20), end of Sec. 4
   * generalised soft thresholding of w ................... eqs (41), (42)
   * the alternative fixed-point iteration for w .......... eqs (38), (39)
   * projection onto |w| = 1 .............................. eq (40)
@@ -71,6 +72,12 @@ class Params:
     w_sweeps           : sweeps of that iteration, i.e. the paper's r = 0..R
                          with R = w_sweeps - 1 (one sweep: the paper's
                          "a single iteration is often enough")
+    phi_solver         : 0: the FFT solve of eqs (30)-(33); 1: the AOS scheme
+                         the paper names as the alternative (end of Sec. 4):
+                         phi = (v + w) / 2 with (1 - 2 tau A_l) v = F along
+                         columns and rows, A_l = mu x the periodic second
+                         difference (constant A_l), each solved by the
+                         Thomas algorithm
     """
 
     gamma: float = 1.0
@@ -90,6 +97,7 @@ class Params:
     zero_tol: float = 1e-3
     w_solver: int = 0
     w_sweeps: int = 1
+    phi_solver: int = 0
 
 
 # --------------------------------------------------------------------------
@@ -230,6 +238,59 @@ def implicit_solve(F, tau, mu):
     return np.real(np.fft.ifft2(np.fft.fft2(F) / symbol(M, N, tau, mu)))
 
 
+def thomas_cyclic(off, diag, F):
+    """Solve off x_{i-1} + diag x_i + off x_{i+1} = F_i, i = 0..n-1, with
+    periodic indices, for every column of F (axis 0 is i), by the Thomas
+    algorithm (LR decomposition, forward and backward substitution) on the
+    tridiagonal part and the Sherman-Morrison formula for the two corner
+    entries of the cyclic matrix."""
+    F = np.asarray(F, dtype=np.float64)
+    n = F.shape[0]
+    gam = -diag
+    # T = A - u v^T: corners removed, T[0,0] = diag - gam, T[n-1,n-1] = diag - off^2 / gam,
+    # with u = (gam, 0, ..., 0, off), v = (1, 0, ..., 0, off / gam)
+    d = np.full(n, diag, dtype=np.float64)
+    d[0] -= gam
+    d[-1] -= off * off / gam
+
+    def tri(rhs):
+        # LR decomposition of T (its sub- and super-diagonal are both `off`)
+        l = np.zeros(n)
+        r = np.zeros(n)
+        r[0] = d[0]
+        for i in range(1, n):
+            l[i] = off / r[i - 1]
+            r[i] = d[i] - l[i] * off
+        y = np.array(rhs, dtype=np.float64, copy=True)
+        for i in range(1, n):                    # forward substitution (L y = rhs)
+            y[i] = y[i] - l[i] * y[i - 1]
+        x = np.empty_like(y)
+        x[n - 1] = y[n - 1] / r[n - 1]
+        for i in range(n - 2, -1, -1):           # backward substitution (R x = y)
+            x[i] = (y[i] - off * x[i + 1]) / r[i]
+        return x
+
+    u = np.zeros(n)
+    u[0], u[-1] = gam, off
+    y = tri(F)
+    z = tri(u if F.ndim == 1 else u[:, None] * np.ones((1,) + F.shape[1:]))
+    vy = y[0] + (off / gam) * y[-1]
+    vz = z[0] + (off / gam) * z[-1]
+    return y - (vy / (1.0 + vz)) * z
+
+
+def aos_solve(F, tau, mu):
+    """AOS solve of the phi sub-problem with constant A_l (the paper's
+    alternative to the FFT, end of Sec. 4, in the form of eqs 18 and 20):
+    (1 - 2 tau mu D_l) v_l = F for the periodic second difference D_l along
+    columns (l = 1, index i) and rows (l = 2, index j); phi = (v_1 + v_2) / 2."""
+    off = -2.0 * tau * mu
+    diag = 1.0 + 4.0 * tau * mu
+    v1 = thomas_cyclic(off, diag, F)
+    v2 = thomas_cyclic(off, diag, F.T).T
+    return 0.5 * (v1 + v2)
+
+
 def phi_rhs(phi_s, w1, w2, b1, b2, g, P: Params):
     """F^{k,s} of eq (37), evaluated at phi^{k+1,s} (reading: the inner iterate),
     with w^k, b^k fixed over the inner loop:
@@ -253,7 +314,7 @@ def phi_subproblem(phi_k, w1, w2, b1, b2, g, P: Params):
     steps = 0
     for _ in range(P.S):
         F = phi_rhs(phi_s, w1, w2, b1, b2, g, P)
-        phi_new = implicit_solve(F, P.tau, P.mu)
+        phi_new = aos_solve(F, P.tau, P.mu) if P.phi_solver == 1 else implicit_solve(F, P.tau, P.mu)
         steps += 1
         rel = np.linalg.norm(phi_new - phi_s) / (np.linalg.norm(phi_s) + 1e-6)
         phi_s = phi_new

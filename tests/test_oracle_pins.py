@@ -512,3 +512,62 @@ def test_w_fixed_point_iteration_translation_equivariant():
     b, gb, _ = O.solve(np.roll(f, sh, (0, 1)), np.roll(phi0, sh, (0, 1)), P, 2)
     np.testing.assert_allclose(b.phi, np.roll(a.phi, sh, (0, 1)), atol=1e-10)
     np.testing.assert_allclose(b.w1, np.roll(a.w1, sh, (0, 1)), atol=1e-10)
+
+
+# --------------------------------------------------------------------------
+# AOS solve of the phi sub-problem with constant A_l (end of Sec. 4)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [3, 4, 7, 16, 33])
+def test_thomas_cyclic_against_dense_solve(n):
+    """The cyclic Thomas solve against a dense solve of the full periodic
+    tridiagonal matrix, built here entry by entry."""
+    rng = np.random.default_rng(n)
+    off, diag = -0.37, 1.0 + 4 * 0.37 + 0.05
+    A = np.zeros((n, n))
+    for i in range(n):
+        A[i, i] += diag
+        A[i, (i - 1) % n] += off
+        A[i, (i + 1) % n] += off
+    F = rng.normal(size=(n, 5))
+    np.testing.assert_allclose(O.thomas_cyclic(off, diag, F), np.linalg.solve(A, F), atol=1e-12)
+
+
+@pytest.mark.parametrize("tau,mu,a,b", [(0.1, 8.0, 3, 5), (0.4, 0.1, 1, 0), (0.1, 8.0, 0, 7)])
+def test_aos_solve_separable_mode(tau, mu, a, b):
+    """A separable Fourier mode is an eigenvector of both 1-D operators:
+    v_l = F / (1 + 2 tau mu (2 - 2 cos(2 pi k_l / n_l))), phi = (v_1 + v_2) / 2."""
+    M, N = 24, 16
+    i = np.arange(M)[:, None]
+    j = np.arange(N)[None, :]
+    F = np.cos(2 * np.pi * a * i / M + 0.3) * np.cos(2 * np.pi * b * j / N - 0.7)
+    s1 = 1 + 2 * tau * mu * (2 - 2 * math.cos(2 * math.pi * a / M))
+    s2 = 1 + 2 * tau * mu * (2 - 2 * math.cos(2 * math.pi * b / N))
+    np.testing.assert_allclose(O.aos_solve(F, tau, mu), 0.5 * (F / s1 + F / s2), atol=1e-12)
+
+
+def test_aos_solve_keeps_constants_and_is_first_order_close_to_fft():
+    """Constants pass unchanged (each 1-D operator has unit row sums); on a
+    smooth field the AOS solve differs from the exact FFT solve of
+    (1 - tau mu Delta) by O((tau mu)^2) times the mixed fourth differences."""
+    M, N = 32, 32
+    np.testing.assert_allclose(O.aos_solve(np.full((M, N), 3.25), 0.1, 8.0), 3.25, atol=1e-13)
+    i = np.arange(M)[:, None]
+    j = np.arange(N)[None, :]
+    F = np.sin(2 * np.pi * i / M) + np.cos(2 * np.pi * 2 * j / N) + 0.5 * np.sin(2 * np.pi * (i + j) / M)
+    for tm, bound in ((0.001, 1e-5), (0.01, 1e-3)):
+        d = np.abs(O.aos_solve(F, tm, 1.0) - O.implicit_solve(F, tm, 1.0)).max()
+        assert d < bound, (tm, d)
+
+
+def test_aos_iteration_translation_equivariant():
+    """A whole outer iteration with the AOS phi solver commutes with periodic
+    shifts of its inputs."""
+    M, N = 32, 24
+    rng = np.random.default_rng(21)
+    f = rng.uniform(0, 1, (M, N))
+    phi0 = np.add.outer(np.arange(M) - 15.5, np.zeros(N)) ** 2 / 20.0 - 4.0 + rng.normal(0, 0.1, (M, N))
+    P = O.Params(R=3, d=3.0, phi_solver=1)
+    a, _, _ = O.solve(f, phi0, P, 2)
+    sh = (-9, 4)
+    b, _, _ = O.solve(np.roll(f, sh, (0, 1)), np.roll(phi0, sh, (0, 1)), P, 2)
+    np.testing.assert_allclose(b.phi, np.roll(a.phi, sh, (0, 1)), atol=1e-10)
