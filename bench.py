@@ -36,6 +36,8 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_PX = {"rhs_repulsion": 24, "row_fft_fwd": 8, "col_fft_solve": 8, "row_fft_inv": 12, "w_step": 52}
 # a fixed-point w sweep before the last one: reads phi (4), w (8), b (8), g (4), writes w (8)
 BYTES_PER_PX_W_SWEEP = 32
+# the AOS phi solve (one launch in place of the three FFT passes): reads r and phi_s, writes phi
+BYTES_PER_PX_AOS = 12
 
 # The paper's two-circles weights (alpha = gamma = 4, beta = 0.2, mu = 8,
 # tau = 0.1, l = 1, d = 5, S = 3) with each workload's eps / R.
@@ -57,6 +59,12 @@ def params_kw(wl):
               tol_inner=0.0, zero_tol=1e-3)
     if wl.get("w_sweeps"):   # the fixed-point w solver of eqs 38-40
         kw.update(w_solver=1, w_sweeps=wl["w_sweeps"])
+    if wl.get("phi_solver") == "aos":   # AOS with constant A_l (end of Sec. 4)
+        # at tau mu = 0.8 the AOS average under-damps modes that oscillate along
+        # one axis (steady-state response up to 1 + 8 tau mu times the exact
+        # one) and the Bregman update amplifies that: the iteration diverges;
+        # tau = 0.04 (tau mu = 0.32) keeps it stable
+        kw.update(phi_solver=1, tau=0.04)
     return kw
 
 
@@ -294,6 +302,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--w-sweeps", type=int, default=0, metavar="R",
                     help="use the fixed-point w solver (eqs 38-40) with R sweeps instead of soft thresholding")
+    ap.add_argument("--phi-solver", default="fft", choices=["fft", "aos"],
+                    help="phi sub-problem solver: the FFT solve (eq 37) or AOS with constant A_l")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB")
     ap.add_argument("--batch", type=int, default=0, metavar="COUNT",
                     help="time-to-converge of COUNT uneven instances, batched vs plain")
@@ -329,7 +339,10 @@ def main():
     wl = dict(WORKLOADS[args.workload])
     if args.w_sweeps:
         wl["w_sweeps"] = args.w_sweeps
-        wl["text"] += f"; fixed-point w solver, {args.w_sweeps} sweeps" 
+        wl["text"] += f"; fixed-point w solver, {args.w_sweeps} sweeps"
+    if args.phi_solver == "aos":
+        wl["phi_solver"] = "aos"
+        wl["text"] += "; AOS phi solver, tau=0.04"
     steps = args.steps if args.steps is not None else wl["default_steps"]
     M, N = wl["M"], wl["N"]
     f, phi0 = make_input(args.workload)
@@ -360,11 +373,14 @@ def main():
     # launched without a graph, every iteration kernel with its own HIP events
     # (recorded at the kernel's start and end, on the solver's stream)
     prof = sr.sr_profile_kernels(s.ctx, args.profile_iters)
+    if args.phi_solver == "aos":   # the phi solve is timed in the column-solve slot
+        prof = {("aos_solve" if k == "col_fft_solve" else k): v for k, v in prof.items()
+                if k not in ("row_fft_fwd", "row_fft_inv")}
     per_iter = {k: prof[k][1] / args.profile_iters for k in prof}      # launches per outer iteration
     per_iter_ms = {k: prof[k][0] * per_iter[k] for k in prof}
     dom = max(per_iter_ms, key=per_iter_ms.get)
     dom_ms = prof[dom][0]
-    bytes_px = dict(BYTES_PER_PX)
+    bytes_px = dict(BYTES_PER_PX, aos_solve=BYTES_PER_PX_AOS)
     if args.w_sweeps > 1:   # w_step launches average the sweeps and the full step
         bytes_px["w_step"] = (BYTES_PER_PX["w_step"] + BYTES_PER_PX_W_SWEEP * (args.w_sweeps - 1)) / args.w_sweeps
     alg_bytes = bytes_px[dom] * M * N
@@ -385,10 +401,12 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl["text"], "M": M, "N": N, "R": wl["R"], "S": wl["S"], "tile_rows": tile_th,
                    "bytes_per_px_iter": sum(bytes_px[k] * per_iter[k] for k in prof),
-                   "w_solver": "fixed-point" if args.w_sweeps else "shrink", "w_sweeps": args.w_sweeps or None},
+                   "w_solver": "fixed-point" if args.w_sweeps else "shrink", "w_sweeps": args.w_sweeps or None,
+                   "phi_solver": args.phi_solver},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None if args.w_sweeps else measured_traffic(args.workload, dom, tile_th),
+                     "traffic": (None if args.w_sweeps or args.phi_solver != "fft"
+                                 else measured_traffic(args.workload, dom, tile_th)),
                      "alg_bytes_per_launch": alg_bytes},
         "kernels_ms": {k: round(v[0], 5) for k, v in prof.items()},
         "iteration_ms_sum_of_kernels": round(sum(per_iter_ms.values()), 5),

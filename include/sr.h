@@ -90,6 +90,12 @@ typedef struct sr_params {
                               sweep projected by eq (40) (same zero rule)        */
     int32_t w_sweeps;      /* sweeps of that iteration, 1..16 (the paper's r = 0..R,
                               R = w_sweeps - 1); ignored when w_solver = 0       */
+    int32_t phi_solver;    /* 0: FFT solve of the phi sub-problem (eqs 30-33);
+                              1: AOS with constant A_l (end of Sec. 4; eqs 18, 20):
+                              phi = (v_1 + v_2) / 2, (1 - 2 tau mu D_l) v_l = F per
+                              direction.  AOS needs tol_inner = 0, and M, N large
+                              enough for the inverse's entries to fall below 1e-9
+                              of the centre within +-64 (SR_EUNSUPPORTED otherwise) */
 } sr_params;
 
 /* Per-call report of sr_step. */
@@ -189,7 +195,9 @@ int sr_implicit_solve(sr_ctx* ctx, const float* rhs, float* u_out, uint32_t flag
  *   ms[4] w / b step (eqs 40-42, 23)
  * count[i] receives the number of launches timed (n_iter S for the first
  * four kinds, n_iter for the w step, n_iter w_sweeps with the fixed-point
- * w solver, whose intermediate sweeps count as w-step launches).
+ * w solver, whose intermediate sweeps count as w-step launches).  With the
+ * AOS phi solver its one launch per inner step is timed as ms[2] and the
+ * FFT kinds 1 and 3 are not launched (count 0).
  * Synchronises; ignores tol_outer.
  * Returns SR_EINVAL for n_iter < 1, SR_ESTATE before sr_set_image. */
 #define SR_NUM_KERNEL_KINDS 5

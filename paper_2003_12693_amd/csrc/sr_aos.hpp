@@ -1,0 +1,27 @@
+// AOS solve of the phi sub-problem (constant A_l), see sr_aos.hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+
+#include "sr_device.hpp"
+
+namespace sr {
+
+constexpr int kAosMaxK = 64;   // largest truncation radius of the inverse circulants
+
+// FP64 entries c_0..c_K of the inverse of the periodic (1 - 2 tau mu D) on
+// n points, truncated where they fall below 1e-9 c_0, into taps (kAosMaxK+1
+// floats).  Returns K, or -1 when the cut needs K > kAosMaxK or more offsets
+// than the n points hold.
+int aos_taps(int n, double tau, double mu, float* taps);
+size_t aos_lds_bytes(int Kx, int Ky);
+void configure_aos();
+// phi_out = AOS solve of the right-hand side r = rhs (tau (N + D + mu Lap phi_in))
+// around phi_in; ev0 / ev1 (nullable): events recorded at the kernel's start and end.
+void launch_aos(int M, int N, const float* rhs, const float* phi_in, float* phi_out, const float* cx, int Kx,
+                const float* cy, int Ky, float taumu, int nz, DevScal* sc, hipStream_t st, hipEvent_t ev0 = nullptr,
+                hipEvent_t ev1 = nullptr);
+
+}  // namespace sr

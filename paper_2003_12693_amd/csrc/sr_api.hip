@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "../../include/sr.h"
+#include "sr_aos.hpp"
 #include "sr_device.hpp"
 #include "sr_kernels.hpp"
 
@@ -94,6 +95,14 @@ static int validate(int32_t M, int32_t N, const sr_params* p) {
     if (p->zero_tol < 0) return fail(SR_EINVAL, "zero_tol must be >= 0");
     if (p->w_solver != 0 && p->w_solver != 1) return fail(SR_EINVAL, "w_solver must be 0 or 1");
     if (p->w_sweeps < 1 || p->w_sweeps > 16) return fail(SR_EINVAL, "w_sweeps must be in [1, 16]");
+    if (p->phi_solver != 0 && p->phi_solver != 1) return fail(SR_EINVAL, "phi_solver must be 0 or 1");
+    if (p->phi_solver == 1) {
+        if (p->tol_inner > 0) return fail(SR_EUNSUPPORTED, "the AOS phi solver runs a fixed S (tol_inner = 0)");
+        float taps[sr::kAosMaxK + 1];
+        if (sr::aos_taps(M, p->tau, p->mu, taps) < 0 || sr::aos_taps(N, p->tau, p->mu, taps) < 0)
+            return fail(SR_EUNSUPPORTED, "AOS: the inverse of (1 - 2 tau mu D) on %d or %d points does not decay "
+                        "below 1e-9 within +-%d", M, N, sr::kAosMaxK);
+    }
     return SR_OK;
 }
 
@@ -101,7 +110,7 @@ static int validate(int32_t M, int32_t N, const sr_params* p) {
 // workspace layout
 // ---------------------------------------------------------------------------
 struct Layout {
-    size_t twM, twN, stM, stN, g, P0, P1, P2, W0, W1, B0, B1, D, Rb, spec, part, scal, rhist, X0, X1, total;
+    size_t twM, twN, stM, stN, aos, g, P0, P1, P2, W0, W1, B0, B1, D, Rb, spec, part, scal, rhist, X0, X1, total;
 };
 
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -121,6 +130,7 @@ static Layout make_layout(int M, int N, int nz, int xbufs = 0) {
     L.twN = take(sizeof(float2) * N);
     L.stM = take(sizeof(float2) * sr::fft_stage_table_len(M, true));
     L.stN = take(sizeof(float2) * sr::fft_stage_table_len(N, false));
+    L.aos = take(sizeof(float) * 2 * (sr::kAosMaxK + 1));
     L.g = take(pl);
     L.P0 = take(pl);
     L.P1 = take(pl);
@@ -147,6 +157,7 @@ static Layout make_layout(int M, int N, int nz, int xbufs = 0) {
 // ---------------------------------------------------------------------------
 struct Bufs {
     float2 *twM, *twN, *stM, *stN;
+    float* aos;    // AOS inverse taps: rows direction at [0], columns at [kAosMaxK + 1]
     float *g, *P0, *P1, *P2, *W[2], *B[2], *D, *Rb;
     float2* spec;
     double* part;
@@ -170,6 +181,7 @@ struct sr_ctx {
     int parity = 0;            // state in W[parity], B[parity]
     long long k = 0;
     bool image_set = false;
+    int aosKx = 0, aosKy = 0;  // AOS truncation radii (phi_solver = 1)
     std::vector<float> gauss;  // Gaussian taps
     int gauss_r = 0;
 };
@@ -179,6 +191,7 @@ static void carve(Bufs& b, char* base, const Layout& L) {
     b.twN = (float2*)(base + L.twN);
     b.stM = (float2*)(base + L.stM);
     b.stN = (float2*)(base + L.stN);
+    b.aos = (float*)(base + L.aos);
     b.g = (float*)(base + L.g);
     b.P0 = (float*)(base + L.P0);
     b.P1 = (float*)(base + L.P1);
@@ -255,6 +268,21 @@ static hipError_t upload_tables(const Bufs& b, int M, int N, hipStream_t st) {
     return e;
 }
 
+// AOS inverse taps of a context (phi_solver = 1), after validate() has
+// checked that both directions truncate.
+static hipError_t upload_aos(sr_ctx* c, hipStream_t st) {
+    if (c->p.phi_solver != 1) return hipSuccess;
+    std::vector<float> t(2 * (sr::kAosMaxK + 1), 0.0f);
+    c->aosKx = sr::aos_taps(c->M, c->p.tau, c->p.mu, t.data());
+    c->aosKy = sr::aos_taps(c->N, c->p.tau, c->p.mu, t.data() + sr::kAosMaxK + 1);
+    hipError_t e = hipMemcpyAsync(c->b.aos, t.data(), sizeof(float) * t.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    return e;
+}
+
+// Events of the AOS launch while sr_profile_kernels times a launch.
+static thread_local hipEvent_t t_aos_ev[2] = {nullptr, nullptr};
+
 // The launch sequence of one outer iteration from parity p (Algorithm 1):
 // S x [rhs -> row FFT -> column solve -> inverse row FFT], then the w step.
 // before(kind) runs ahead of each iteration kernel's launch (kinds as in
@@ -278,9 +306,16 @@ static void enqueue_iteration(sr_ctx* c, int p, hipStream_t st, Hook&& before = 
         before(0);
         sr::launch_rhs(c->geo, c->kp, in, b.W[p], b.g, b.D, b.Rb, c->nz, b.scal, st,
                        (fold_in && s == 0) ? &fold : nullptr);
-        for (int pass = 0; pass < 3; ++pass) {
-            before(1 + pass);
-            sr::launch_solve_pass(pass, c->geo, b.Rb, in, out, b.spec, c->kp.tol_inner, b.part, c->nz, b.scal, st);
+        if (c->p.phi_solver == 1) {   // AOS: one launch, timed as the solve kind (2)
+            before(2);
+            sr::launch_aos(c->M, c->N, b.Rb, in, out, b.aos, c->aosKx, b.aos + sr::kAosMaxK + 1, c->aosKy,
+                           c->geo.taumu, c->nz, b.scal, st, t_aos_ev[0], t_aos_ev[1]);
+        } else {
+            for (int pass = 0; pass < 3; ++pass) {
+                before(1 + pass);
+                sr::launch_solve_pass(pass, c->geo, b.Rb, in, out, b.spec, c->kp.tol_inner, b.part, c->nz, b.scal,
+                                      st);
+            }
         }
         in = out;
     }
@@ -453,6 +488,7 @@ int sr_params_default(sr_params* p) {
     p->zero_tol = 1e-3;
     p->w_solver = 0;
     p->w_sweeps = 1;
+    p->phi_solver = 0;
     return SR_OK;
 }
 
@@ -476,6 +512,7 @@ int sr_create(sr_ctx** out, int32_t M, int32_t N, const sr_params* p, void* work
     if (bytes < L.total) return fail(SR_EWORKSPACE, "workspace has %zu bytes, needs %zu", bytes, L.total);
 
     sr::configure_kernels();
+    sr::configure_aos();
     sr_ctx* c = new sr_ctx();
     c->M = M;
     c->N = N;
@@ -500,6 +537,7 @@ int sr_create(sr_ctx** out, int32_t M, int32_t N, const sr_params* p, void* work
     hipError_t e = hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking);
     if (e != hipSuccess) { delete c; return fail(SR_EHIP, "hipStreamCreate: %s", hipGetErrorString(e)); }
     e = upload_tables(c->b, M, N, c->stream);
+    if (e == hipSuccess) e = upload_aos(c, c->stream);
     if (e == hipSuccess) { sr::launch_reset_scal(c->b.scal, 1, 1, c->stream); e = hipGetLastError(); }
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {
@@ -730,7 +768,7 @@ int sr_profile_kernels(sr_ctx* c, int32_t n_iter, double ms[SR_NUM_KERNEL_KINDS]
     // with its own start / stop events; synchronised after every iteration.
     // iteration kernels per outer iteration: S x 4, then the w step (one
     // launch per fixed-point sweep with that solver)
-    const int per = 4 * c->p.S + (c->p.w_solver == 1 ? c->p.w_sweeps : 1);
+    const int per = (c->p.phi_solver == 1 ? 2 : 4) * c->p.S + (c->p.w_solver == 1 ? c->p.w_sweeps : 1);
     std::vector<hipEvent_t> ev(2 * (size_t)per, nullptr);
     std::vector<int> kind(per, 0);
     hipError_t e = hipSuccess;
@@ -743,12 +781,16 @@ int sr_profile_kernels(sr_ctx* c, int32_t n_iter, double ms[SR_NUM_KERNEL_KINDS]
         enqueue_iteration(c, c->parity, c->stream, [&](int k) {
             if (slot >= per) {   // cannot happen while per matches enqueue_iteration
                 sr::set_launch_events(nullptr, nullptr);
+                t_aos_ev[0] = t_aos_ev[1] = nullptr;
                 return;
             }
             sr::set_launch_events(ev[2 * slot], ev[2 * slot + 1]);
+            t_aos_ev[0] = ev[2 * slot];
+            t_aos_ev[1] = ev[2 * slot + 1];
             kind[slot++] = k;
         });
         sr::set_launch_events(nullptr, nullptr);
+        t_aos_ev[0] = t_aos_ev[1] = nullptr;
         e = hipGetLastError();
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
         for (int s = 0; s < slot && e == hipSuccess; ++s) {
@@ -784,7 +826,8 @@ static bool same_class(const sr_batch_item& a, const sr_batch_item& b) {
            x.mu == y.mu && x.tau == y.tau && x.eps == y.eps && x.band_l == y.band_l && x.d == y.d && x.R == y.R &&
            x.sigma == y.sigma && x.rho == y.rho && x.s_exp == y.s_exp && x.S == y.S &&
            x.tol_inner == y.tol_inner && x.w0_mode == y.w0_mode && x.zero_tol == y.zero_tol &&
-           x.w_solver == y.w_solver && (x.w_solver == 0 || x.w_sweeps == y.w_sweeps);
+           x.w_solver == y.w_solver && (x.w_solver == 0 || x.w_sweeps == y.w_sweeps) &&
+           x.phi_solver == y.phi_solver;
 }
 
 struct BatchPlan {
@@ -835,6 +878,7 @@ int sr_solve_batch(sr_batch_item* items, int32_t n, void* workspace, size_t byte
     if ((uintptr_t)workspace & 255) return fail(SR_EWORKSPACE, "workspace must be 256-byte aligned");
     if (bytes < plan.total) return fail(SR_EWORKSPACE, "workspace has %zu bytes, needs %zu", bytes, plan.total);
     sr::configure_kernels();
+    sr::configure_aos();
     hipStream_t st = (hipStream_t)hip_stream;
     const int G = (int)plan.groups.size();
     std::vector<sr_ctx> ctx(G);
@@ -854,6 +898,7 @@ int sr_solve_batch(sr_batch_item* items, int32_t n, void* workspace, size_t byte
         c.geo.stM = c.b.stM; c.geo.stN = c.b.stN;
         c.geo.taumu = (float)(c.p.tau * c.p.mu);
         HIP_TRY(upload_tables(c.b, c.M, c.N, st));
+        HIP_TRY(upload_aos(&c, st));
         HIP_TRY(hipStreamSynchronize(st));
         hs[gi].assign(c.nz, DevScal{});
         for (int z = 0; z < c.nz; ++z) {

@@ -149,3 +149,21 @@ def test_fixed_point_w_solver_parameters(sr):
     assert sr.sr_workspace_size(64, 64, sr.sr_params_default(w_solver=1, w_sweeps=2)) == base + vec
     assert sr.sr_workspace_size(64, 64, sr.sr_params_default(w_solver=1, w_sweeps=5)) == base + 2 * vec
     assert sr.sr_workspace_size(64, 64, sr.sr_params_default(w_solver=0, w_sweeps=5)) == base
+
+
+def test_aos_phi_solver_parameters(sr):
+    """phi_solver is validated before any HIP call: 0 / 1 only, a fixed S
+    (tol_inner = 0), and sizes on which the inverse of (1 - 2 tau mu D)
+    truncates within +-64 points (not 8 points at tau mu = 0.8)."""
+    with pytest.raises(sr.SRError) as e:
+        sr.sr_workspace_size(64, 64, sr.sr_params_default(phi_solver=2))
+    assert e.value.code == sr.SR_EINVAL
+    with pytest.raises(sr.SRError) as e:
+        sr.sr_workspace_size(64, 64, sr.sr_params_default(phi_solver=1, tol_inner=1e-3))
+    assert e.value.code == sr.SR_EUNSUPPORTED
+    with pytest.raises(sr.SRError) as e:
+        sr.sr_workspace_size(8, 64, sr.sr_params_default(phi_solver=1))
+    assert e.value.code == sr.SR_EUNSUPPORTED
+    assert sr.sr_workspace_size(64, 64, sr.sr_params_default(phi_solver=1)) == \
+        sr.sr_workspace_size(64, 64, sr.sr_params_default())
+    assert sr.sr_params_default().phi_solver == 0

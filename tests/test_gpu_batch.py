@@ -175,3 +175,20 @@ def test_fixed_point_w_batch_matches_single(sr):
         s.set_image(_cuda(f), _cuda(p))
         s.step(3)
         assert np.array_equal(r["phi"].cpu().numpy(), s.phi().cpu().numpy())
+
+
+def test_aos_batch_matches_single(sr):
+    """Uneven instances with the AOS phi solver: the batched solve gives
+    bitwise the single solves' results."""
+    _note("AOS: batch vs single")
+    kw = gpu_params(phi_solver=1)
+    inst = _instances()[:5]
+    items = [dict(f=_cuda(f), phi0=_cuda(p), max_iter=4, params=gpu_params(phi_solver=1, R=R, d=float(R)))
+             for (M, N, R, f, p) in inst]
+    rc, res = sr.solve_batch(items)
+    assert rc == 0
+    for (M, N, R, f, p), r in zip(inst, res):
+        s = sr.Solver(M, N, gpu_params(phi_solver=1, R=R, d=float(R)))
+        s.set_image(_cuda(f), _cuda(p))
+        s.step(4)
+        assert np.array_equal(r["phi"].cpu().numpy(), s.phi().cpu().numpy())

@@ -182,6 +182,42 @@ def test_teacher_forced_fixed_point_w(sr, sweeps, k):
     _check_w_b(ref, gw, gb)
 
 
+@pytest.mark.parametrize("kw", [dict(), dict(gamma=1.0, alpha=1.0, beta=0.05, mu=0.1, tau=0.4),
+                                dict(R=5, d=5.0, eps=2.0), dict(w_solver=1, w_sweeps=2)])
+@pytest.mark.parametrize("k", [3, 20])
+def test_teacher_forced_aos(sr, kw, k):
+    """The AOS phi solver (constant A_l, Thomas algorithm in the oracle, the
+    inverse circulants as truncated convolutions on the GPU) against the
+    oracle, one outer iteration from identical states."""
+    _note(f"teacher forced AOS {kw} k={k}")
+    kw = dict(kw, phi_solver=1)
+    f, phi0, P, states = _c1_states([k], **kw)
+    ref, gphi, gw, gb, kk, res = _teacher_forced(sr, f, P, states[k], kw, 128, 128)
+    assert rel_l2(gphi, ref.phi) <= 1e-5
+    _check_w_b(ref, gw, gb)
+
+
+@pytest.mark.parametrize("shape", [(64, 64), (256, 128), (64, 512)])
+def test_teacher_forced_aos_shapes(sr, shape):
+    """Non-square grids (different truncation per direction, tiles wider than
+    the halo) with the AOS phi solver."""
+    _note(f"teacher forced AOS shape {shape}")
+    M, N = shape
+    rng = np.random.default_rng(M * 3 + N)
+    i = np.arange(M)[:, None]
+    j = np.arange(N)[None, :]
+    phi = np.sqrt((i - M / 2 + 0.3) ** 2 + (j - N / 2 + 0.2) ** 2) - min(M, N) / 4
+    f = (phi < -1).astype(float) + 0.1 * rng.normal(size=shape)
+    kw = dict(phi_solver=1)
+    P = oracle_params(**kw)
+    st = O.initial_state(as64(phi))
+    st.b1 = 0.2 * rng.normal(size=shape)
+    st.b2 = 0.2 * rng.normal(size=shape)
+    ref, gphi, gw, gb, kk, res = _teacher_forced(sr, f, P, st, kw, M, N)
+    assert rel_l2(gphi, ref.phi) <= 1e-5
+    _check_w_b(ref, gw, gb, frac=2e-3)
+
+
 @pytest.mark.parametrize("shape", [(8, 8), (16, 128), (64, 32), (256, 512)])
 def test_teacher_forced_shapes(sr, shape):
     """Ragged / tiny grids: tiles larger than the image, wrap-around halos."""
@@ -355,6 +391,12 @@ def test_profile_kernels_advance_like_step(sr):
     prof = sr.sr_profile_kernels(c.ctx, 2)
     assert prof["w_step"][1] == 6 and prof["rhs_repulsion"][1] == 2 * kw.S, prof
     assert c.get_state()[3] == 4
+    # the AOS phi solver: one solve launch per inner step, timed as kind 2
+    a2 = sr.Solver(128, 128, gpu_params(phi_solver=1))
+    a2.set_image(_cuda(f), _cuda(phi0))
+    prof = sr.sr_profile_kernels(a2.ctx, 2)
+    assert prof["col_fft_solve"][1] == 2 * kw.S and prof["row_fft_fwd"][1] == 0 and prof["row_fft_inv"][1] == 0
+    assert prof["col_fft_solve"][0] > 0.0
 
 
 def test_graph_replay_matches_direct_launches(sr):
