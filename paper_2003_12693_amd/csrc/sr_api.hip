@@ -130,7 +130,7 @@ static Layout make_layout(int M, int N, int nz, int xbufs = 0) {
     L.twN = take(sizeof(float2) * N);
     L.stM = take(sizeof(float2) * sr::fft_stage_table_len(M, true));
     L.stN = take(sizeof(float2) * sr::fft_stage_table_len(N, false));
-    L.aos = take(sizeof(float) * 2 * (sr::kAosMaxK + 1));
+    L.aos = take(sizeof(float) * sr::kAosTapFloats);
     L.g = take(pl);
     L.P0 = take(pl);
     L.P1 = take(pl);
@@ -157,7 +157,7 @@ static Layout make_layout(int M, int N, int nz, int xbufs = 0) {
 // ---------------------------------------------------------------------------
 struct Bufs {
     float2 *twM, *twN, *stM, *stN;
-    float* aos;    // AOS inverse taps: rows direction at [0], columns at [kAosMaxK + 1]
+    float* aos;    // AOS tap buffer (sr::aos_tap_buffer layout)
     float *g, *P0, *P1, *P2, *W[2], *B[2], *D, *Rb;
     float2* spec;
     double* part;
@@ -272,9 +272,8 @@ static hipError_t upload_tables(const Bufs& b, int M, int N, hipStream_t st) {
 // checked that both directions truncate.
 static hipError_t upload_aos(sr_ctx* c, hipStream_t st) {
     if (c->p.phi_solver != 1) return hipSuccess;
-    std::vector<float> t(2 * (sr::kAosMaxK + 1), 0.0f);
-    c->aosKx = sr::aos_taps(c->M, c->p.tau, c->p.mu, t.data());
-    c->aosKy = sr::aos_taps(c->N, c->p.tau, c->p.mu, t.data() + sr::kAosMaxK + 1);
+    std::vector<float> t(sr::kAosTapFloats);
+    (void)sr::aos_tap_buffer(c->M, c->N, c->p.tau, c->p.mu, t.data(), &c->aosKx, &c->aosKy);
     hipError_t e = hipMemcpyAsync(c->b.aos, t.data(), sizeof(float) * t.size(), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     return e;
@@ -308,7 +307,7 @@ static void enqueue_iteration(sr_ctx* c, int p, hipStream_t st, Hook&& before = 
                        (fold_in && s == 0) ? &fold : nullptr);
         if (c->p.phi_solver == 1) {   // AOS: one launch, timed as the solve kind (2)
             before(2);
-            sr::launch_aos(c->M, c->N, b.Rb, in, out, b.aos, c->aosKx, b.aos + sr::kAosMaxK + 1, c->aosKy,
+            sr::launch_aos(c->M, c->N, b.Rb, in, out, b.aos, c->aosKx, c->aosKy,
                            c->geo.taumu, c->nz, b.scal, st, t_aos_ev[0], t_aos_ev[1]);
         } else {
             for (int pass = 0; pass < 3; ++pass) {

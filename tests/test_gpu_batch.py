@@ -177,10 +177,12 @@ def test_fixed_point_w_batch_matches_single(sr):
         assert np.array_equal(r["phi"].cpu().numpy(), s.phi().cpu().numpy())
 
 
-def test_aos_batch_matches_single(sr):
+@pytest.mark.parametrize("kernel", ["gather", "slide"])
+def test_aos_batch_matches_single(sr, kernel, monkeypatch):
     """Uneven instances with the AOS phi solver: the batched solve gives
     bitwise the single solves' results."""
-    _note("AOS: batch vs single")
+    monkeypatch.setenv("SR_AOS_KERNEL", kernel)
+    _note(f"AOS: batch vs single ({kernel})")
     kw = gpu_params(phi_solver=1)
     inst = _instances()[:5]
     items = [dict(f=_cuda(f), phi0=_cuda(p), max_iter=4, params=gpu_params(phi_solver=1, R=R, d=float(R)))

@@ -182,14 +182,16 @@ def test_teacher_forced_fixed_point_w(sr, sweeps, k):
     _check_w_b(ref, gw, gb)
 
 
+@pytest.mark.parametrize("kernel", ["gather", "slide"])
 @pytest.mark.parametrize("kw", [dict(), dict(gamma=1.0, alpha=1.0, beta=0.05, mu=0.1, tau=0.4),
                                 dict(R=5, d=5.0, eps=2.0), dict(w_solver=1, w_sweeps=2)])
 @pytest.mark.parametrize("k", [3, 20])
-def test_teacher_forced_aos(sr, kw, k):
+def test_teacher_forced_aos(sr, kw, k, kernel, monkeypatch):
     """The AOS phi solver (constant A_l, Thomas algorithm in the oracle, the
-    inverse circulants as truncated convolutions on the GPU) against the
-    oracle, one outer iteration from identical states."""
-    _note(f"teacher forced AOS {kw} k={k}")
+    inverse circulants as truncated convolutions on the GPU, by either
+    kernel) against the oracle, one outer iteration from identical states."""
+    monkeypatch.setenv("SR_AOS_KERNEL", kernel)
+    _note(f"teacher forced AOS {kw} k={k} {kernel}")
     kw = dict(kw, phi_solver=1)
     f, phi0, P, states = _c1_states([k], **kw)
     ref, gphi, gw, gb, kk, res = _teacher_forced(sr, f, P, states[k], kw, 128, 128)
@@ -197,11 +199,14 @@ def test_teacher_forced_aos(sr, kw, k):
     _check_w_b(ref, gw, gb)
 
 
-@pytest.mark.parametrize("shape", [(64, 64), (256, 128), (64, 512)])
-def test_teacher_forced_aos_shapes(sr, shape):
-    """Non-square grids (different truncation per direction, tiles wider than
-    the halo) with the AOS phi solver."""
-    _note(f"teacher forced AOS shape {shape}")
+@pytest.mark.parametrize("kernel", ["gather", "slide"])
+@pytest.mark.parametrize("shape", [(64, 64), (256, 128), (64, 512), (64, 1024)])
+def test_teacher_forced_aos_shapes(sr, shape, kernel, monkeypatch):
+    """Non-square grids (different truncation per direction, tiles wider or
+    taller than the grid, several tiles per direction) with the AOS phi
+    solver, by either kernel."""
+    monkeypatch.setenv("SR_AOS_KERNEL", kernel)
+    _note(f"teacher forced AOS shape {shape} {kernel}")
     M, N = shape
     rng = np.random.default_rng(M * 3 + N)
     i = np.arange(M)[:, None]
