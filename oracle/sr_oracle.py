@@ -16,6 +16,8 @@ It is a plain, slow, literal transcription of the method of Pan et al.,
     backward divergence (unit spacing) ................... eqs (35), (36)
   * repulsion window sum v (square window, Gaussian taps)  Sec. 4, after eq (37)
   * semi-implicit FFT solve of the phi sub-problem ....... eqs (30)-(33), (37)
+  * or, with Neumann boundaries (eq 17's boundary condition,
+    eq 27's), its DCT-II solve .......................... eqs (17), (27), (32)
   * or its AOS solve with constant A_l (Thomas algorithm)  eqs (18), (20), end of Sec. 4
   * generalised soft thresholding of w ................... eqs (41), (42)
   * the alternative fixed-point iteration for w .......... eqs (38), (39)
@@ -23,7 +25,8 @@ It is a plain, slow, literal transcription of the method of Pan et al.,
   * Bregman update ....................................... eq (23)
   * outer/inner loop ..................................... Algorithm 1, Sec. 4
 
-Readings of passages the paper leaves open (all periodic boundaries, the
+Readings of passages the paper leaves open (periodic boundaries by default,
+Neumann ones as the alternative with mirror stencils and window, the
 Frobenius norm in the stop rule, phi^{k+1,s} inside F^{k,s}, the window
 bounds, w^0 = grad phi^0, shrink -> project -> Bregman order, the discrete
 energy) are listed in the design notes of the repository; each function
@@ -78,6 +81,13 @@ class Params:
                          columns and rows, A_l = mu x the periodic second
                          difference (constant A_l), each solved by the
                          Thomas algorithm
+    bc                 : boundaries. 0: periodic (every operator wraps, the
+                         FFT symbol of eq 32); 1: Neumann (eq 17's and eq
+                         27's zero normal derivative): half-sample mirror
+                         ghost values for every stencil, the Gaussian and the
+                         repulsion window, the forward difference zero on
+                         the last row / column, the divergence its negative
+                         adjoint, and the DCT-II in place of the FFT
     """
 
     gamma: float = 1.0
@@ -98,6 +108,7 @@ class Params:
     w_solver: int = 0
     w_sweeps: int = 1
     phi_solver: int = 0
+    bc: int = 0
 
 
 # --------------------------------------------------------------------------
@@ -139,25 +150,56 @@ def band_prime(phi, eps, l):
 
 
 # --------------------------------------------------------------------------
-# discrete operators, unit spacing, periodic boundaries  (eqs 35, 36)
+# discrete operators, unit spacing  (eqs 35, 36)
 # --------------------------------------------------------------------------
 # Array axis 0 is the row index i (first gradient component), axis 1 is the
-# column index j (second component).  u[(i+1) % M, j] is np.roll(u, -1, 0).
+# column index j (second component).  at(u, k, axis, bc) is u at index i + k
+# along `axis`: periodic (bc = 0), or mirrored about the half-sample points
+# -1/2 and n - 1/2 (bc = 1: the ghost value beyond an edge repeats the edge,
+# ... u1 u0 | u0 u1 ... u_{n-1} | u_{n-1} u_{n-2} ...), which is the zero
+# normal derivative of the Neumann condition.
 
-def grad_fwd(u):
-    """Forward-difference gradient of eq (35): (u[i+1,j]-u[i,j], u[i,j+1]-u[i,j])."""
-    return (np.roll(u, -1, axis=0) - u, np.roll(u, -1, axis=1) - u)
+def at(u, k, axis, bc=0):
+    """u[i + k] along `axis` (|k| <= n), periodic or half-sample mirrored."""
+    n = u.shape[axis]
+    idx = np.arange(n) + k
+    if bc == 0:
+        idx = idx % n
+    else:
+        idx = np.where(idx < 0, -1 - idx, idx)
+        idx = np.where(idx >= n, 2 * n - 1 - idx, idx)
+    return np.take(u, idx, axis=axis)
 
 
-def div_bwd(p, q):
-    """Backward-difference divergence of eq (36): (p[i,j]-p[i-1,j]) + (q[i,j]-q[i,j-1])."""
-    return (p - np.roll(p, 1, axis=0)) + (q - np.roll(q, 1, axis=1))
+def grad_fwd(u, bc=0):
+    """Forward-difference gradient of eq (35): (u[i+1,j]-u[i,j], u[i,j+1]-u[i,j]);
+    with Neumann boundaries the mirror ghost makes it zero on the last row
+    (first component) and the last column (second component)."""
+    return (at(u, 1, 0, bc) - u, at(u, 1, 1, bc) - u)
 
 
-def laplacian(u):
-    """Five-point Laplacian of eq (35)."""
-    return (np.roll(u, 1, axis=0) + np.roll(u, -1, axis=0)
-            + np.roll(u, 1, axis=1) + np.roll(u, -1, axis=1) - 4.0 * u)
+def _div1(p, axis, bc):
+    if bc == 0:
+        return p - at(p, -1, axis, 0)
+    # negative adjoint of the Neumann forward difference along `axis`:
+    # p[i] [i < n-1] - p[i-1] [i > 0]
+    n = p.shape[axis]
+    i = np.arange(n).reshape([-1 if a == axis else 1 for a in range(p.ndim)])
+    return np.where(i < n - 1, p, 0.0) - np.where(i > 0, at(p, -1, axis, 1), 0.0)
+
+
+def div_bwd(p, q, bc=0):
+    """Backward-difference divergence of eq (36): (p[i,j]-p[i-1,j]) + (q[i,j]-q[i,j-1]),
+    periodic; with Neumann boundaries the negative adjoint of grad_fwd (p
+    taken as zero at index -1 and at the last index), so that
+    div(grad u) is the mirrored Laplacian."""
+    return _div1(p, 0, bc) + _div1(q, 1, bc)
+
+
+def laplacian(u, bc=0):
+    """Five-point Laplacian of eq (35) (mirror ghosts for Neumann boundaries)."""
+    return (at(u, -1, 0, bc) + at(u, 1, 0, bc)
+            + at(u, -1, 1, bc) + at(u, 1, 1, bc) - 4.0 * u)
 
 
 # --------------------------------------------------------------------------
@@ -172,25 +214,25 @@ def gaussian_taps(sigma):
     return t.astype(int), k / k.sum()
 
 
-def gaussian_smooth(f, sigma):
-    """G_sigma * f with periodic wrap: a row pass then a column pass."""
+def gaussian_smooth(f, sigma, bc=0):
+    """G_sigma * f with periodic wrap (or mirror): a row pass then a column pass."""
     offs, k = gaussian_taps(sigma)
     f = np.asarray(f, dtype=np.float64)
     rows = np.zeros_like(f)
     for t, kt in zip(offs, k):          # along axis 1 (within each row)
-        rows += kt * np.roll(f, -t, axis=1)
+        rows += kt * at(f, t, 1, bc)
     out = np.zeros_like(f)
     for t, kt in zip(offs, k):          # along axis 0 (within each column)
-        out += kt * np.roll(rows, -t, axis=0)
+        out += kt * at(rows, t, 0, bc)
     return out
 
 
-def edge_map(f, sigma, rho, s_exp):
+def edge_map(f, sigma, rho, s_exp, bc=0):
     """g = 1 / (1 + rho |grad(G_sigma * f)|^s), eq (1), with central
     differences for the gradient of the smoothed image."""
-    fs = gaussian_smooth(f, sigma)
-    gx = 0.5 * (np.roll(fs, -1, axis=0) - np.roll(fs, 1, axis=0))
-    gy = 0.5 * (np.roll(fs, -1, axis=1) - np.roll(fs, 1, axis=1))
+    fs = gaussian_smooth(f, sigma, bc)
+    gx = 0.5 * (at(fs, 1, 0, bc) - at(fs, -1, 0, bc))
+    gy = 0.5 * (at(fs, 1, 1, bc) - at(fs, -1, 1, bc))
     mag = np.sqrt(gx * gx + gy * gy)
     return 1.0 / (1.0 + rho * mag ** s_exp)
 
@@ -204,9 +246,9 @@ def repulsion_weights(R, d):
     return np.exp(-(p[:, None] ** 2 + p[None, :] ** 2) / (d * d))
 
 
-def repulsion_field(w1, w2, phi, eps, l, d, R):
+def repulsion_field(w1, w2, phi, eps, l, d, R, bc=0):
     """v[i,j] = sum_{p,q=-R..R} exp(-(p^2+q^2)/d^2) w[i+p,j+q] h_eps(phi[i+p,j+q]),
-    periodic indices, centre tap included.  Direct (2R+1)^2-term sum."""
+    periodic (or mirrored) indices, centre tap included.  Direct (2R+1)^2-term sum."""
     h = band(phi, eps, l)
     u1, u2 = w1 * h, w2 * h
     K = repulsion_weights(R, d)
@@ -215,8 +257,8 @@ def repulsion_field(w1, w2, phi, eps, l, d, R):
     for p in range(-R, R + 1):
         for q in range(-R, R + 1):
             kpq = K[p + R, q + R]
-            v1 += kpq * np.roll(u1, (-p, -q), axis=(0, 1))
-            v2 += kpq * np.roll(u2, (-p, -q), axis=(0, 1))
+            v1 += kpq * at(at(u1, p, 0, bc), q, 1, bc)
+            v2 += kpq * at(at(u2, p, 0, bc), q, 1, bc)
     return v1, v2
 
 
@@ -231,11 +273,54 @@ def symbol(M, N, tau, mu):
     return 1.0 - tau * mu * (2.0 * np.cos(z1)[:, None] + 2.0 * np.cos(z2)[None, :] - 4.0)
 
 
-def implicit_solve(F, tau, mu):
+def implicit_solve(F, tau, mu, bc=0):
     """phi = Re( IFFT( FFT(F) / symbol ) ), eq (33): the solution of
-    (1 - tau mu Delta) phi = F on the periodic grid."""
+    (1 - tau mu Delta) phi = F on the periodic grid; with Neumann
+    boundaries the same solve in the DCT-II basis (the eigenvectors of the
+    mirrored Laplacian)."""
     M, N = F.shape
+    if bc == 1:
+        return dct_solve(F, tau, mu)
     return np.real(np.fft.ifft2(np.fft.fft2(F) / symbol(M, N, tau, mu)))
+
+
+def symbol_neumann(M, N, tau, mu):
+    """Eigenvalues of (1 - tau mu Delta) for the mirrored Laplacian on the
+    DCT-II modes cos(pi l (i + 1/2) / M) cos(pi m (j + 1/2) / N):
+    1 + tau mu (4 - 2 cos(pi l / M) - 2 cos(pi m / N))."""
+    z1 = np.pi * np.arange(M, dtype=np.float64) / M
+    z2 = np.pi * np.arange(N, dtype=np.float64) / N
+    return 1.0 + tau * mu * (4.0 - 2.0 * np.cos(z1)[:, None] - 2.0 * np.cos(z2)[None, :])
+
+
+def dct_solve(F, tau, mu):
+    """(1 - tau mu Delta) phi = F with Neumann boundaries: orthonormal
+    DCT-II in both directions, division by the symbol, inverse transform."""
+    from scipy import fft as sfft
+    M, N = F.shape
+    spec = sfft.dctn(np.asarray(F, dtype=np.float64), type=2, norm="ortho")
+    return sfft.idctn(spec / symbol_neumann(M, N, tau, mu), type=2, norm="ortho")
+
+
+def thomas(off, d, F):
+    """Solve off x_{i-1} + d_i x_i + off x_{i+1} = F_i, i = 0..n-1 (no
+    wrap-around), for every column of F (axis 0 is i): LR decomposition,
+    forward substitution, backward substitution."""
+    n = len(d)
+    l = np.zeros(n)
+    r = np.zeros(n)
+    r[0] = d[0]
+    for i in range(1, n):
+        l[i] = off / r[i - 1]
+        r[i] = d[i] - l[i] * off
+    y = np.array(F, dtype=np.float64, copy=True)
+    for i in range(1, n):                    # forward substitution (L y = F)
+        y[i] = y[i] - l[i] * y[i - 1]
+    x = np.empty_like(y)
+    x[n - 1] = y[n - 1] / r[n - 1]
+    for i in range(n - 2, -1, -1):           # backward substitution (R x = y)
+        x[i] = (y[i] - off * x[i + 1]) / r[i]
+    return x
 
 
 def thomas_cyclic(off, diag, F):
@@ -253,39 +338,31 @@ def thomas_cyclic(off, diag, F):
     d[0] -= gam
     d[-1] -= off * off / gam
 
-    def tri(rhs):
-        # LR decomposition of T (its sub- and super-diagonal are both `off`)
-        l = np.zeros(n)
-        r = np.zeros(n)
-        r[0] = d[0]
-        for i in range(1, n):
-            l[i] = off / r[i - 1]
-            r[i] = d[i] - l[i] * off
-        y = np.array(rhs, dtype=np.float64, copy=True)
-        for i in range(1, n):                    # forward substitution (L y = rhs)
-            y[i] = y[i] - l[i] * y[i - 1]
-        x = np.empty_like(y)
-        x[n - 1] = y[n - 1] / r[n - 1]
-        for i in range(n - 2, -1, -1):           # backward substitution (R x = y)
-            x[i] = (y[i] - off * x[i + 1]) / r[i]
-        return x
-
     u = np.zeros(n)
     u[0], u[-1] = gam, off
-    y = tri(F)
-    z = tri(u if F.ndim == 1 else u[:, None] * np.ones((1,) + F.shape[1:]))
+    y = thomas(off, d, F)
+    z = thomas(off, d, u if F.ndim == 1 else u[:, None] * np.ones((1,) + F.shape[1:]))
     vy = y[0] + (off / gam) * y[-1]
     vz = z[0] + (off / gam) * z[-1]
     return y - (vy / (1.0 + vz)) * z
 
 
-def aos_solve(F, tau, mu):
+def aos_solve(F, tau, mu, bc=0):
     """AOS solve of the phi sub-problem with constant A_l (the paper's
     alternative to the FFT, end of Sec. 4, in the form of eqs 18 and 20):
     (1 - 2 tau mu D_l) v_l = F for the periodic second difference D_l along
-    columns (l = 1, index i) and rows (l = 2, index j); phi = (v_1 + v_2) / 2."""
+    columns (l = 1, index i) and rows (l = 2, index j); phi = (v_1 + v_2) / 2.
+    With Neumann boundaries D_l is the mirrored second difference (end rows
+    u_1 - u_0 and u_{n-2} - u_{n-1}): a plain tridiagonal system whose end
+    diagonal entries are 1 + 2 tau mu."""
     off = -2.0 * tau * mu
     diag = 1.0 + 4.0 * tau * mu
+    if bc == 1:
+        def solve1(G):
+            d = np.full(G.shape[0], diag)
+            d[0] = d[-1] = 1.0 + 2.0 * tau * mu
+            return thomas(off, d, G)
+        return 0.5 * (solve1(F) + solve1(F.T).T)
     v1 = thomas_cyclic(off, diag, F)
     v2 = thomas_cyclic(off, diag, F.T).T
     return 0.5 * (v1 + v2)
@@ -296,12 +373,12 @@ def phi_rhs(phi_s, w1, w2, b1, b2, g, P: Params):
     with w^k, b^k fixed over the inner loop:
       F = phi_s + tau ( -gamma g |w| delta'(phi_s) + alpha g delta(phi_s)
                         + 2 beta h'(phi_s) w . v + mu div(b - w) )."""
-    v1, v2 = repulsion_field(w1, w2, phi_s, P.eps, P.band_l, P.d, P.R)
+    v1, v2 = repulsion_field(w1, w2, phi_s, P.eps, P.band_l, P.d, P.R, P.bc)
     wnorm = np.sqrt(w1 * w1 + w2 * w2)
     force = (-P.gamma * g * wnorm * dirac_prime(phi_s, P.eps)
              + P.alpha * g * dirac(phi_s, P.eps)
              + 2.0 * P.beta * band_prime(phi_s, P.eps, P.band_l) * (w1 * v1 + w2 * v2)
-             + P.mu * div_bwd(b1 - w1, b2 - w2))
+             + P.mu * div_bwd(b1 - w1, b2 - w2, P.bc))
     return phi_s + P.tau * force
 
 
@@ -314,7 +391,10 @@ def phi_subproblem(phi_k, w1, w2, b1, b2, g, P: Params):
     steps = 0
     for _ in range(P.S):
         F = phi_rhs(phi_s, w1, w2, b1, b2, g, P)
-        phi_new = aos_solve(F, P.tau, P.mu) if P.phi_solver == 1 else implicit_solve(F, P.tau, P.mu)
+        if P.phi_solver == 1:
+            phi_new = aos_solve(F, P.tau, P.mu, P.bc)
+        else:
+            phi_new = implicit_solve(F, P.tau, P.mu, P.bc)
         steps += 1
         rel = np.linalg.norm(phi_new - phi_s) / (np.linalg.norm(phi_s) + 1e-6)
         phi_s = phi_new
@@ -347,8 +427,8 @@ def shrink_input(phi_new, w1, w2, b1, b2, g, P: Params):
     """B^{k+1} of eq (41) and the threshold of eq (42):
     B = grad phi^{k+1} + b^k + (2 beta / mu) h(phi^{k+1}) v, with v built from
     w^k and h(phi^{k+1}); t = (gamma / mu) g delta(phi^{k+1})."""
-    G1, G2 = grad_fwd(phi_new)
-    v1, v2 = repulsion_field(w1, w2, phi_new, P.eps, P.band_l, P.d, P.R)
+    G1, G2 = grad_fwd(phi_new, P.bc)
+    v1, v2 = repulsion_field(w1, w2, phi_new, P.eps, P.band_l, P.d, P.R, P.bc)
     h = band(phi_new, P.eps, P.band_l)
     c = 2.0 * P.beta / P.mu
     B1 = G1 + b1 + c * h * v1
@@ -374,12 +454,12 @@ def w_fixed_point(phi_new, w1, w2, b1, b2, g, P: Params):
     (the reading taken for eq 42, applied to the same vector): where the
     numerator over mu -- B of eq (41) built from w^{k+1,r} -- has
     |B| <= zero_tol, w^{k+1,r+1} is the zero vector."""
-    G1, G2 = grad_fwd(phi_new)
+    G1, G2 = grad_fwd(phi_new, P.bc)
     h = band(phi_new, P.eps, P.band_l)
     den = P.gamma * g * dirac(phi_new, P.eps) + P.mu
     wr1, wr2 = w1, w2
     for _ in range(P.w_sweeps):
-        v1, v2 = repulsion_field(wr1, wr2, phi_new, P.eps, P.band_l, P.d, P.R)
+        v1, v2 = repulsion_field(wr1, wr2, phi_new, P.eps, P.band_l, P.d, P.R, P.bc)
         n1 = P.mu * G1 + P.mu * b1 + 2.0 * P.beta * h * v1
         n2 = P.mu * G2 + P.mu * b2 + 2.0 * P.beta * h * v2
         t1, t2 = project(n1 / den, n2 / den)
@@ -388,9 +468,9 @@ def w_fixed_point(phi_new, w1, w2, b1, b2, g, P: Params):
     return wr1, wr2
 
 
-def bregman(b1, b2, phi_new, w1_new, w2_new):
+def bregman(b1, b2, phi_new, w1_new, w2_new, bc=0):
     """b^{k+1} = b^k + grad phi^{k+1} - w^{k+1}, eq (23)."""
-    G1, G2 = grad_fwd(phi_new)
+    G1, G2 = grad_fwd(phi_new, bc)
     return b1 + G1 - w1_new, b2 + G2 - w2_new
 
 
@@ -407,11 +487,11 @@ class State:
     k: int = 0
 
 
-def initial_state(phi0):
+def initial_state(phi0, bc=0):
     """Initialisation of Algorithm 1: phi^0 given (a signed distance function),
     w^0 = grad phi^0, b^0 = 0."""
     phi0 = np.asarray(phi0, dtype=np.float64)
-    w1, w2 = grad_fwd(phi0)
+    w1, w2 = grad_fwd(phi0, bc)
     z = np.zeros_like(phi0)
     return State(phi0.copy(), w1, w2, z.copy(), z.copy(), 0)
 
@@ -423,7 +503,7 @@ def sb_iteration(st: State, g, P: Params):
     phi_new, steps = phi_subproblem(st.phi, st.w1, st.w2, st.b1, st.b2, g, P)
     w_update = w_fixed_point if P.w_solver == 1 else w_subproblem
     w1n, w2n = w_update(phi_new, st.w1, st.w2, st.b1, st.b2, g, P)
-    b1n, b2n = bregman(st.b1, st.b2, phi_new, w1n, w2n)
+    b1n, b2n = bregman(st.b1, st.b2, phi_new, w1n, w2n, P.bc)
     r = np.linalg.norm(phi_new - st.phi) / (np.linalg.norm(st.phi) + 1e-6)
     return State(phi_new, w1n, w2n, b1n, b2n, st.k + 1), {"r": r, "inner_steps": steps}
 
@@ -432,8 +512,8 @@ def solve(f, phi0, P: Params, iters, tol_outer=0.0, min_iters=0, callback=None):
     """Algorithm 1 from the image f and phi^0 for at most `iters` outer
     iterations; stops early when the relative phi change r_k < tol_outer
     (after min_iters).  Returns (final state, g, list of r_k)."""
-    g = edge_map(f, P.sigma, P.rho, P.s_exp)
-    st = initial_state(phi0)
+    g = edge_map(f, P.sigma, P.rho, P.s_exp, P.bc)
+    st = initial_state(phi0, P.bc)
     hist = []
     for _ in range(iters):
         st, info = sb_iteration(st, g, P)
@@ -455,11 +535,11 @@ def energy_terms(phi, g, P: Params):
       E_g = sum g |grad phi| delta(phi)
       E_a = sum g (1 - H(phi))
       E_r = - sum_x (grad phi h)(x) . sum_y K(x-y) (grad phi h)(y)."""
-    G1, G2 = grad_fwd(phi)
+    G1, G2 = grad_fwd(phi, P.bc)
     Eg = np.sum(g * np.sqrt(G1 * G1 + G2 * G2) * dirac(phi, P.eps))
     Ea = np.sum(g * (1.0 - heaviside(phi, P.eps)))
     h = band(phi, P.eps, P.band_l)
-    v1, v2 = repulsion_field(G1, G2, phi, P.eps, P.band_l, P.d, P.R)
+    v1, v2 = repulsion_field(G1, G2, phi, P.eps, P.band_l, P.d, P.R, P.bc)
     Er = -np.sum(G1 * h * v1 + G2 * h * v2)
     return P.gamma * Eg, P.alpha * Ea, P.beta * Er
 

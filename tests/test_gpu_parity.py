@@ -223,6 +223,21 @@ def test_teacher_forced_aos_shapes(sr, shape, kernel, monkeypatch):
     _check_w_b(ref, gw, gb, frac=2e-3)
 
 
+def test_teacher_forced_aos_2048(sr):
+    """2048 x 2048 with the AOS phi solver at tau = 0.04, in the launch
+    configuration the AOS benchmark times at 4096^2 (the sliding kernel, its
+    default from 2048^2 on, same tile, same truncation radius)."""
+    _note("teacher forced AOS 2048^2")
+    f, phi0 = synth.ellipses(2048, 2048, seed=7)
+    kw = dict(phi_solver=1, tau=0.04)
+    P = oracle_params(**kw)
+    g = O.edge_map(as64(f), P.sigma, P.rho, P.s_exp)
+    st, _ = O.sb_iteration(O.initial_state(as64(phi0)), g, P)
+    ref, gphi, gw, gb, kk, res = _teacher_forced(sr, f, P, st, kw, 2048, 2048)
+    assert rel_l2(gphi, ref.phi) <= 1e-5
+    _check_w_b(ref, gw, gb)
+
+
 @pytest.mark.parametrize("shape", [(8, 8), (16, 128), (64, 32), (256, 512)])
 def test_teacher_forced_shapes(sr, shape):
     """Ragged / tiny grids: tiles larger than the image, wrap-around halos."""

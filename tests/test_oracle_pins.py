@@ -571,3 +571,207 @@ def test_aos_iteration_translation_equivariant():
     sh = (-9, 4)
     b, _, _ = O.solve(np.roll(f, sh, (0, 1)), np.roll(phi0, sh, (0, 1)), P, 2)
     np.testing.assert_allclose(b.phi, np.roll(a.phi, sh, (0, 1)), atol=1e-10)
+
+
+# --------------------------------------------------------------------------
+# Neumann boundaries (eq 17's and eq 27's zero normal derivative; bc = 1):
+# mirror ghosts, the adjoint divergence, the DCT-II solve, the plain
+# tridiagonal AOS solve
+# --------------------------------------------------------------------------
+def _mirror(i, n):
+    """Half-sample mirror of an index, written out case by case."""
+    if i < 0:
+        return -1 - i
+    if i >= n:
+        return 2 * n - 1 - i
+    return i
+
+
+def _neumann_second_difference(n):
+    """Dense 1-D second difference with the Neumann end rows (u_1 - u_0 and
+    u_{n-2} - u_{n-1}), entry by entry."""
+    D = np.zeros((n, n))
+    for i in range(n):
+        for k in (i - 1, i + 1):
+            D[i, _mirror(k, n)] += 1.0
+        D[i, i] -= 2.0
+    return D
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 8])
+def test_mirror_index_matches_numpy_symmetric_pad(n):
+    """at(.., bc=1) is NumPy's 'symmetric' padding (the edge sample repeated)."""
+    u = RNG.normal(size=(n, 3))
+    pad = np.pad(u, ((n, n), (0, 0)), mode="symmetric")
+    for k in range(-n, n + 1):
+        np.testing.assert_array_equal(O.at(u, k, 0, 1), pad[n + k:n + k + n])
+
+
+def test_neumann_gradient_divergence_laplacian():
+    """Forward differences vanish on the last row / column; the divergence is
+    the negative adjoint of the gradient; div grad is the Laplacian, equal to
+    the Kronecker sum of dense Neumann second differences; its sum vanishes."""
+    M, N = 7, 10
+    u = RNG.normal(size=(M, N))
+    g1, g2 = O.grad_fwd(u, 1)
+    assert np.all(g1[-1] == 0.0) and np.all(g2[:, -1] == 0.0)
+    np.testing.assert_array_equal(g1[:-1], u[1:] - u[:-1])
+    np.testing.assert_array_equal(g2[:, :-1], u[:, 1:] - u[:, :-1])
+    p, q = RNG.normal(size=(M, N)), RNG.normal(size=(M, N))
+    assert np.sum(g1 * p + g2 * q) == pytest.approx(-np.sum(u * O.div_bwd(p, q, 1)), rel=1e-13)
+    lap = O.laplacian(u, 1)
+    np.testing.assert_allclose(lap, O.div_bwd(*O.grad_fwd(u, 1), 1), atol=1e-13)
+    L = np.kron(_neumann_second_difference(M), np.eye(N)) + np.kron(np.eye(M), _neumann_second_difference(N))
+    np.testing.assert_allclose(lap.ravel(), L @ u.ravel(), atol=1e-13)
+    assert abs(lap.sum()) < 1e-12
+
+
+@pytest.mark.parametrize("sigma", [0.5, 1.5, 2.0])
+def test_neumann_gaussian_and_edge_map_match_scipy_reflect(sigma):
+    """SciPy's 'reflect' mode is the half-sample mirror."""
+    f = RNG.uniform(size=(20, 33))
+    ref = ndimage.gaussian_filter1d(f, sigma, axis=1, mode="reflect", truncate=3.0)
+    ref = ndimage.gaussian_filter1d(ref, sigma, axis=0, mode="reflect", truncate=3.0)
+    np.testing.assert_allclose(O.gaussian_smooth(f, sigma, 1), ref, atol=1e-13)
+    fs = ndimage.gaussian_filter(f, 1.5, mode="reflect", truncate=3.0)
+    gx = ndimage.correlate1d(fs, [-0.5, 0.0, 0.5], axis=0, mode="reflect")
+    gy = ndimage.correlate1d(fs, [-0.5, 0.0, 0.5], axis=1, mode="reflect")
+    np.testing.assert_allclose(O.edge_map(f, 1.5, 1000.0, 2, 1), 1.0 / (1.0 + 1000.0 * np.hypot(gx, gy) ** 2),
+                               rtol=1e-12)
+
+
+@pytest.mark.parametrize("shape,R,d", [((7, 9), 2, 2.0), ((12, 11), 5, 5.0), ((6, 6), 5, 3.0)])
+def test_neumann_repulsion_brute_force(shape, R, d):
+    M, N = shape
+    phi = RNG.uniform(-4, 4, size=shape)
+    w1, w2 = RNG.normal(size=shape), RNG.normal(size=shape)
+    hh = O.band(phi, 1.5, 1.0)
+    v1 = np.zeros(shape)
+    v2 = np.zeros(shape)
+    for i in range(M):
+        for j in range(N):
+            for p in range(-R, R + 1):
+                for q in range(-R, R + 1):
+                    k = math.exp(-(p * p + q * q) / (d * d))
+                    ii, jj = _mirror(i + p, M), _mirror(j + q, N)
+                    v1[i, j] += k * w1[ii, jj] * hh[ii, jj]
+                    v2[i, j] += k * w2[ii, jj] * hh[ii, jj]
+    got = O.repulsion_field(w1, w2, phi, 1.5, 1.0, d, R, 1)
+    np.testing.assert_allclose(got[0], v1, atol=1e-12)
+    np.testing.assert_allclose(got[1], v2, atol=1e-12)
+
+
+@pytest.mark.parametrize("shape,tau,mu", [((16, 16), 0.1, 8.0), ((8, 32), 0.4, 0.1), ((9, 14), 1.0, 3.0)])
+def test_dct_solve_residual_and_mirror_extension(shape, tau, mu):
+    """The DCT solve satisfies (1 - tau mu Lap_N) phi = F, and equals the
+    periodic FFT solve on the 2M x 2N mirror extension of F, restricted."""
+    M, N = shape
+    F = RNG.normal(size=shape) * 20.0
+    phi = O.implicit_solve(F, tau, mu, 1)
+    np.testing.assert_allclose(phi - tau * mu * O.laplacian(phi, 1), F, atol=1e-11)
+    ext = np.concatenate([F, F[::-1]], axis=0)
+    ext = np.concatenate([ext, ext[:, ::-1]], axis=1)
+    sym = 1.0 - tau * mu * (2 * np.cos(2 * np.pi * np.arange(2 * M) / (2 * M))[:, None]
+                            + 2 * np.cos(2 * np.pi * np.arange(2 * N) / (2 * N))[None, :] - 4)
+    per = np.real(np.fft.ifft2(np.fft.fft2(ext) / sym))[:M, :N]
+    np.testing.assert_allclose(phi, per, atol=1e-11)
+
+
+def test_dct_solve_cosine_mode():
+    M, N, a, b, tau, mu = 12, 20, 3, 7, 0.1, 8.0
+    i = np.arange(M)[:, None]
+    j = np.arange(N)[None, :]
+    F = np.cos(np.pi * a * (i + 0.5) / M) * np.cos(np.pi * b * (j + 0.5) / N)
+    s = 1 + tau * mu * (4 - 2 * math.cos(math.pi * a / M) - 2 * math.cos(math.pi * b / N))
+    np.testing.assert_allclose(O.implicit_solve(F, tau, mu, 1), F / s, atol=1e-13)
+
+
+@pytest.mark.parametrize("shape", [(5, 8), (16, 9)])
+def test_aos_neumann_against_dense_solves(shape):
+    """(1 - 2 tau mu D_l) v_l = F with the dense Neumann D_l in each
+    direction, phi = (v_1 + v_2) / 2; constants pass unchanged."""
+    M, N = shape
+    tau, mu = 0.1, 8.0
+    F = RNG.normal(size=shape)
+    v1 = np.linalg.solve(np.eye(M) - 2 * tau * mu * _neumann_second_difference(M), F)
+    v2 = np.linalg.solve(np.eye(N) - 2 * tau * mu * _neumann_second_difference(N), F.T).T
+    np.testing.assert_allclose(O.aos_solve(F, tau, mu, 1), 0.5 * (v1 + v2), atol=1e-12)
+    np.testing.assert_allclose(O.aos_solve(np.full(shape, -1.75), tau, mu, 1), -1.75, atol=1e-13)
+
+
+def _kernel_matrix_neumann(M, N, R, d):
+    """Dense window operator with mirrored indices (symmetric: a mirrored
+    pair of points sees each other with the same total weight)."""
+    K = np.zeros((M * N, M * N))
+    for i in range(M):
+        for j in range(N):
+            for p in range(-R, R + 1):
+                for q in range(-R, R + 1):
+                    K[i * N + j, _mirror(i + p, M) * N + _mirror(j + q, N)] += math.exp(-(p * p + q * q) / (d * d))
+    return K
+
+
+def _split_energy_neumann(phi, w1, w2, b1, b2, g, P, K):
+    """E(phi, w) of eq (22) with Neumann forward differences (zero on the
+    last row / column), written directly."""
+    wn = np.sqrt(w1 ** 2 + w2 ** 2)
+    Eg = np.sum(g * wn * O.dirac(phi, P.eps))
+    Ea = np.sum(g * (1 - O.heaviside(phi, P.eps)))
+    hv = O.band(phi, P.eps, P.band_l).ravel()
+    W1, W2 = w1.ravel(), w2.ravel()
+    Er = -(np.einsum("x,y,xy->", W1 * hv, W1 * hv, K) + np.einsum("x,y,xy->", W2 * hv, W2 * hv, K))
+    d1 = np.zeros_like(phi)
+    d2 = np.zeros_like(phi)
+    d1[:-1] = phi[1:] - phi[:-1]
+    d2[:, :-1] = phi[:, 1:] - phi[:, :-1]
+    Es = 0.5 * P.mu * np.sum((w1 - d1 - b1) ** 2 + (w2 - d2 - b2) ** 2)
+    return P.gamma * Eg + P.alpha * Ea + P.beta * Er + Es
+
+
+def test_neumann_rhs_is_negative_gradient_of_split_energy():
+    """With Neumann boundaries (F - phi)/tau + mu Lap_N(phi) is -dE/dphi of
+    eq (22): pins the mirrored window, the adjoint divergence and the
+    boundary rows of the gradient."""
+    M, N = 7, 8
+    P = O.Params(gamma=1.3, alpha=0.7, beta=0.45, mu=2.0, tau=0.3, eps=1.5, band_l=1.0, d=3.0, R=3, bc=1)
+    phi = RNG.uniform(-2.8, 2.8, size=(M, N))
+    w1, w2 = RNG.normal(size=(M, N)), RNG.normal(size=(M, N))
+    b1, b2 = 0.3 * RNG.normal(size=(M, N)), 0.3 * RNG.normal(size=(M, N))
+    g = RNG.uniform(0.05, 1.0, size=(M, N))
+    K = _kernel_matrix_neumann(M, N, P.R, P.d)
+    assert np.allclose(K, K.T)
+    F = O.phi_rhs(phi, w1, w2, b1, b2, g, P)
+    flow = (F - phi) / P.tau + P.mu * O.laplacian(phi, 1)
+    h = 1e-6
+    grad = np.zeros((M, N))
+    for i in range(M):
+        for j in range(N):
+            pp = phi.copy(); pp[i, j] += h
+            pm = phi.copy(); pm[i, j] -= h
+            grad[i, j] = (_split_energy_neumann(pp, w1, w2, b1, b2, g, P, K)
+                          - _split_energy_neumann(pm, w1, w2, b1, b2, g, P, K)) / (2 * h)
+    np.testing.assert_allclose(flow, -grad, atol=2e-6 * np.abs(grad).max())
+
+
+def test_neumann_energy_equals_split_energy_at_consistent_w():
+    M, N = 8, 7
+    P = O.Params(gamma=1.1, alpha=0.9, beta=0.7, mu=3.0, eps=1.5, band_l=1.0, d=3.0, R=3, bc=1)
+    phi = RNG.uniform(-3, 3, size=(M, N))
+    g = RNG.uniform(0.1, 1, size=(M, N))
+    w1, w2 = O.grad_fwd(phi, 1)
+    z = np.zeros((M, N))
+    K = _kernel_matrix_neumann(M, N, P.R, P.d)
+    assert O.energy(phi, g, P) == pytest.approx(_split_energy_neumann(phi, w1, w2, z, z, g, P, K), rel=1e-12)
+
+
+@pytest.mark.parametrize("phi_solver", [0, 1])
+def test_neumann_transpose_symmetry(phi_solver):
+    f, phi0 = _small_problem(M=32, N=32)
+    P = O.Params(**{**PSMALL.__dict__, "bc": 1, "phi_solver": phi_solver,
+                    "tau": 0.04 if phi_solver else PSMALL.tau})
+    st, _, _ = O.solve(f, phi0, P, 4)
+    st2, _, _ = O.solve(f.T.copy(), phi0.T.copy(), P, 4)
+    np.testing.assert_allclose(st.phi.T, st2.phi, atol=1e-10)
+    np.testing.assert_allclose(st.w1.T, st2.w2, atol=1e-10)
+    np.testing.assert_allclose(st.b2.T, st2.b1, atol=1e-10)
+
