@@ -96,6 +96,20 @@ typedef struct sr_params {
                               direction.  AOS needs tol_inner = 0, and M, N large
                               enough for the inverse's entries to fall below 1e-9
                               of the centre within +-64 (SR_EUNSUPPORTED otherwise) */
+    int32_t bc;            /* boundaries.  0: periodic (every stencil, the Gaussian
+                              and the window wrap; the FFT symbol of eq 32).
+                              1: Neumann, the zero normal derivative of eqs (17)
+                              and (27): mirror ghost values (the edge sample
+                              repeated) for every stencil, the Gaussian and the
+                              repulsion window, the forward difference zero on
+                              the last row / column, the divergence its negative
+                              adjoint.  The phi solve is then the DCT-II one
+                              (phi_solver = 0; run as the periodic FFT solve of
+                              the 2M x 2N mirror extension, restricted: needs
+                              M, N <= 2048 and tol_inner = 0, SR_EUNSUPPORTED
+                              otherwise; sr_implicit_solve follows it) or AOS
+                              with the Neumann tridiagonal systems
+                              (phi_solver = 1)                                  */
 } sr_params;
 
 /* Per-call report of sr_step. */

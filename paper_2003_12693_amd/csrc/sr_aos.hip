@@ -10,7 +10,10 @@
 // direction l, exact to that truncation (far below FP32 rounding).  The
 // right-hand-side kernel delivers r = tau (N + D + mu Lap phi_s); this kernel
 // forms F = phi_s + r - tau mu Lap phi_s on a tile and its halo in LDS and
-// applies both convolutions.  Two kernels: a gather kernel (one thread per
+// applies both convolutions.  With Neumann boundaries (mirror ghosts) the
+// 1-D operator's inverse is the restriction of the 2n-periodic circulant's
+// inverse to the mirror extension of F, so the same convolution with the
+// taps of period 2n, read through mirrored indices, is the exact solve.  Two kernels: a gather kernel (one thread per
 // output, taps read per output from LDS) for grids below 2048^2, where it
 // keeps enough waves in flight, and a sliding (scatter) kernel for larger
 // grids, which reads each source once per line.
@@ -42,6 +45,7 @@ constexpr int kGW = 64, kGH = 16, kGThreads = 256;
 // F = phi + r - tau mu Lap phi on the cross-shaped extended tile (rows
 // i0-Kx .. i0+TH+Kx, columns j0-Ky .. j0+64+Ky, periodic), then
 // out = (sum_k cx[|k|] F(i+k, j) + sum_k cy[|k|] F(i, j+k)) / 2.
+template <int BC>
 __global__ __launch_bounds__(kGThreads) void k_aos_gather(const float* __restrict__ rhs,
                                                            const float* __restrict__ phi, float* __restrict__ out,
                                                            const float* __restrict__ taps, int Kx, int Ky,
@@ -62,11 +66,11 @@ __global__ __launch_bounds__(kGThreads) void k_aos_gather(const float* __restric
         const int ei_ = ei - Kx, ej_ = ej - Ky;
         // only the cross-shaped part is read by the convolutions
         if ((ei_ < 0 || ei_ >= kGH) && (ej_ < 0 || ej_ >= kGW)) continue;
-        const int gi = (i0 + ei_) & (M - 1), gj = (j0 + ej_) & (N - 1);
+        const int gi = bidx<BC>(i0 + ei_, M), gj = bidx<BC>(j0 + ej_, N);
         const size_t o = (size_t)gi * N + gj;
         const float p = phi[o];
-        const float lap = (phi[(size_t)((gi - 1) & (M - 1)) * N + gj] + phi[(size_t)((gi + 1) & (M - 1)) * N + gj]) +
-                          (phi[(size_t)gi * N + ((gj - 1) & (N - 1))] + phi[(size_t)gi * N + ((gj + 1) & (N - 1))]) -
+        const float lap = (phi[(size_t)bidx<BC>(gi - 1, M) * N + gj] + phi[(size_t)bidx<BC>(gi + 1, M) * N + gj]) +
+                          (phi[(size_t)gi * N + bidx<BC>(gj - 1, N)] + phi[(size_t)gi * N + bidx<BC>(gj + 1, N)]) -
                           4.0f * p;
         sF[e] = p + (rhs[o] - taumu * lap);
     }
@@ -123,7 +127,7 @@ __device__ __forceinline__ void slide4(float (&acc)[TH], const float* __restrict
     }
 }
 
-template <int TH, int TW>
+template <int TH, int TW, int BC>
 __global__ __launch_bounds__(TW) void k_aos_slide(const float* __restrict__ rhs, const float* __restrict__ phi,
                                                   float* __restrict__ out, const float* __restrict__ taps, int Kx,
                                                   int Ky, float taumu, int M, int N, DevScal* sc) {
@@ -142,18 +146,18 @@ __global__ __launch_bounds__(TW) void k_aos_slide(const float* __restrict__ rhs,
     float* sH = reinterpret_cast<float*>(lds4);           // F on rows 0..TH-1, columns -K4y .. TW+K4y-1
     const int tid = threadIdx.x;
     const int i0 = blockIdx.y * TH, j0 = blockIdx.x * TW;
-    const uint32_t Mm = M - 1, Nm = N - 1;
 
     // horizontal halo of F: rows 0..TH-1, columns -K4y..-1 and TW..TW+K4y-1
 #pragma unroll 2
     for (int e = tid; e < 2 * K4y * TH; e += TW) {
         const int i = e / (2 * K4y), c0 = e - i * 2 * K4y;
         const int c = c0 < K4y ? c0 - K4y : TW + (c0 - K4y);
-        const uint32_t gi = (i0 + i) & Mm, gj = (j0 + c) & Nm;
-        const uint32_t o = gi * N + gj;
+        const int gi = bidx<BC>(i0 + i, M), gj = bidx<BC>(j0 + c, N);
+        const uint32_t o = (uint32_t)gi * N + gj;
         const float p = phi[o];
-        const float lap = (phi[((gi - 1) & Mm) * N + gj] + phi[((gi + 1) & Mm) * N + gj]) +
-                          (phi[gi * N + ((gj - 1) & Nm)] + phi[gi * N + ((gj + 1) & Nm)]) - 4.0f * p;
+        const float lap = (phi[(uint32_t)bidx<BC>(gi - 1, M) * N + gj] + phi[(uint32_t)bidx<BC>(gi + 1, M) * N + gj]) +
+                          (phi[(uint32_t)gi * N + bidx<BC>(gj - 1, N)] + phi[(uint32_t)gi * N + bidx<BC>(gj + 1, N)]) -
+                          4.0f * p;
         sH[i * pitch + K4y + c] = p + (rhs[o] - taumu * lap);
     }
 
@@ -164,15 +168,16 @@ __global__ __launch_bounds__(TW) void k_aos_slide(const float* __restrict__ rhs,
     {
         // the loads of the next block of 4 rows are issued before the
         // arithmetic of the current one
-        const uint32_t gj = (j0 + tid) & Nm, gl = (gj - 1) & Nm, gr = (gj + 1) & Nm;
-        float pu = phi[((i0 - K4x - 1) & Mm) * N + gj];
-        float pc = phi[((i0 - K4x) & Mm) * N + gj];
+        const int gjs = bidx<BC>(j0 + tid, N);
+        const uint32_t gj = gjs, gl = bidx<BC>(gjs - 1, N), gr = bidx<BC>(gjs + 1, N);
+        float pu = phi[(uint32_t)bidx<BC>(i0 - K4x - 1, M) * N + gj];
+        float pc = phi[(uint32_t)bidx<BC>(i0 - K4x, M) * N + gj];
         float nd[4], nl[4], nr[4], nh[4];
         auto load_block = [&](int r) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const uint32_t row = ((i0 + r + q) & Mm) * N;
-                nd[q] = phi[((i0 + r + q + 1) & Mm) * N + gj];
+                const uint32_t row = (uint32_t)bidx<BC>(i0 + r + q, M) * N;
+                nd[q] = phi[(uint32_t)bidx<BC>(i0 + r + q + 1, M) * N + gj];
                 nl[q] = phi[row + gl];
                 nr[q] = phi[row + gr];
                 nh[q] = rhs[row + gj];
@@ -268,10 +273,11 @@ int aos_taps(int n, double tau, double mu, float* taps) {
     return K;
 }
 
-int aos_tap_buffer(int M, int N, double tau, double mu, float* buf, int* Kx, int* Ky) {
+int aos_tap_buffer(int M, int N, double tau, double mu, int bc, float* buf, int* Kx, int* Ky) {
     for (int i = 0; i < kAosTapFloats; ++i) buf[i] = 0.0f;
-    *Kx = aos_taps(M, tau, mu, buf);
-    *Ky = aos_taps(N, tau, mu, buf + kAosMaxK + 1);
+    const int per = bc == 1 ? 2 : 1;   // Neumann: the circulant of the 2n-point mirror extension
+    *Kx = aos_taps(per * M, tau, mu, buf);
+    *Ky = aos_taps(per * N, tau, mu, buf + kAosMaxK + 1);
     if (*Kx < 0 || *Ky < 0) return -1;
     for (int m = -kTapOff; m < kTapOff; ++m) {
         const int am = m < 0 ? -m : m;
@@ -290,16 +296,17 @@ void configure_aos() {
     static bool done = false;
     if (done) return;
     done = true;
-    (void)hipFuncSetAttribute((const void*)k_aos_gather, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              160 * 1024 - 1024);
-    (void)hipFuncSetAttribute((const void*)k_aos_slide<kSH, kSW>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              64 * 1024);
+    for (const void* f : {(const void*)k_aos_gather<0>, (const void*)k_aos_gather<1>})
+        (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 1024);
+    for (const void* f : {(const void*)k_aos_slide<kSH, kSW, 0>, (const void*)k_aos_slide<kSH, kSW, 1>})
+        (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024);
 }
 
-void launch_aos(int M, int N, const float* rhs, const float* phi_in, float* phi_out, const float* taps, int Kx,
-                int Ky, float taumu, int nz, DevScal* sc, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+void launch_aos(int M, int N, int bc, const float* rhs, const float* phi_in, float* phi_out, const float* taps,
+                int Kx, int Ky, float taumu, int nz, DevScal* sc, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
     const bool slide = use_slide(M, N);
-    auto kern = slide ? k_aos_slide<kSH, kSW> : k_aos_gather;
+    auto kern = slide ? (bc ? k_aos_slide<kSH, kSW, 1> : k_aos_slide<kSH, kSW, 0>)
+                      : (bc ? k_aos_gather<1> : k_aos_gather<0>);
     const int TH = slide ? kSH : kGH, TW = slide ? kSW : kGW, threads = slide ? kSW : kGThreads;
     const dim3 grid((N + TW - 1) / TW, (M + TH - 1) / TH, nz);
     const uint32_t lds = (uint32_t)(slide ? slide_lds_bytes(Ky) : gather_lds_bytes(Kx, Ky));

@@ -19,16 +19,18 @@ constexpr int kAosTapFloats = ((2 * (kAosMaxK + 1) + 3) & ~3) + 2 * 208;
 // offsets than the n points hold.
 int aos_taps(int n, double tau, double mu, float* taps);
 // The device tap buffer of an M x N grid (host memory, kAosTapFloats):
-// both directions' taps and their mirrored tables T[m] = c_|m|.  Returns -1
-// (and *Kx or *Ky < 0) when a direction does not truncate.
-int aos_tap_buffer(int M, int N, double tau, double mu, float* buf, int* Kx, int* Ky);
+// both directions' taps and their mirrored tables T[m] = c_|m|; with
+// Neumann boundaries (bc = 1) the taps of the 2M- and 2N-point circulants.
+// Returns -1 (and *Kx or *Ky < 0) when a direction does not truncate.
+int aos_tap_buffer(int M, int N, double tau, double mu, int bc, float* buf, int* Kx, int* Ky);
 size_t aos_lds_bytes(int Kx, int Ky);
 void configure_aos();
 // phi_out = AOS solve of the right-hand side r = rhs (tau (N + D + mu Lap phi_in))
 // around phi_in, with the taps of aos_tap_buffer (device copy); ev0 / ev1
 // (nullable): events recorded at the kernel's start and end.
-void launch_aos(int M, int N, const float* rhs, const float* phi_in, float* phi_out, const float* taps, int Kx,
-                int Ky, float taumu, int nz, DevScal* sc, hipStream_t st, hipEvent_t ev0 = nullptr,
+// bc: 0 periodic, 1 Neumann (mirrored reads).
+void launch_aos(int M, int N, int bc, const float* rhs, const float* phi_in, float* phi_out, const float* taps,
+                int Kx, int Ky, float taumu, int nz, DevScal* sc, hipStream_t st, hipEvent_t ev0 = nullptr,
                 hipEvent_t ev1 = nullptr);
 
 }  // namespace sr

@@ -96,10 +96,19 @@ static int validate(int32_t M, int32_t N, const sr_params* p) {
     if (p->w_solver != 0 && p->w_solver != 1) return fail(SR_EINVAL, "w_solver must be 0 or 1");
     if (p->w_sweeps < 1 || p->w_sweeps > 16) return fail(SR_EINVAL, "w_sweeps must be in [1, 16]");
     if (p->phi_solver != 0 && p->phi_solver != 1) return fail(SR_EINVAL, "phi_solver must be 0 or 1");
+    if (p->bc != 0 && p->bc != 1) return fail(SR_EINVAL, "bc must be 0 (periodic) or 1 (Neumann)");
+    if (p->bc == 1 && p->phi_solver == 0) {
+        if (2 * M > 4096 || 2 * N > 4096)
+            return fail(SR_EUNSUPPORTED, "Neumann boundaries with the FFT solve need M, N <= 2048 (the solve runs on "
+                        "the 2M x 2N mirror extension)");
+        if (p->tol_inner > 0)
+            return fail(SR_EUNSUPPORTED, "Neumann boundaries with the FFT solve run a fixed S (tol_inner = 0)");
+    }
     if (p->phi_solver == 1) {
         if (p->tol_inner > 0) return fail(SR_EUNSUPPORTED, "the AOS phi solver runs a fixed S (tol_inner = 0)");
-        float taps[sr::kAosMaxK + 1];
-        if (sr::aos_taps(M, p->tau, p->mu, taps) < 0 || sr::aos_taps(N, p->tau, p->mu, taps) < 0)
+        std::vector<float> taps(sr::kAosTapFloats);
+        int kx, ky;
+        if (sr::aos_tap_buffer(M, N, p->tau, p->mu, p->bc, taps.data(), &kx, &ky) < 0)
             return fail(SR_EUNSUPPORTED, "AOS: the inverse of (1 - 2 tau mu D) on %d or %d points does not decay "
                         "below 1e-9 within +-%d", M, N, sr::kAosMaxK);
     }
@@ -110,7 +119,9 @@ static int validate(int32_t M, int32_t N, const sr_params* p) {
 // workspace layout
 // ---------------------------------------------------------------------------
 struct Layout {
-    size_t twM, twN, stM, stN, aos, g, P0, P1, P2, W0, W1, B0, B1, D, Rb, spec, part, scal, rhist, X0, X1, total;
+    size_t twM, twN, stM, stN, aos, g, P0, P1, P2, W0, W1, B0, B1, D, Rb, spec, part, scal, rhist, X0, X1;
+    size_t xtwM, xtwN, xstM, xstN, xr, xd, xspec;   // Neumann FFT solve on the 2M x 2N mirror extension
+    size_t total;
 };
 
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -120,8 +131,11 @@ static int sweep_buffers(const sr_params& p) {
     return p.w_solver == 1 ? std::min(2, p.w_sweeps - 1) : 0;
 }
 
+// Neumann boundaries with the FFT solve: work on the 2M x 2N mirror extension.
+static bool neumann_fft(const sr_params& p) { return p.bc == 1 && p.phi_solver == 0; }
+
 // nz instances of one size class laid out plane-by-plane ([nz][M][N] each).
-static Layout make_layout(int M, int N, int nz, int xbufs = 0) {
+static Layout make_layout(int M, int N, int nz, int xbufs = 0, bool ext = false) {
     Layout L{};
     const size_t MN = (size_t)M * N, pl = MN * 4 * nz, vec = 2 * pl;
     size_t o = 0;
@@ -148,6 +162,15 @@ static Layout make_layout(int M, int N, int nz, int xbufs = 0) {
     L.rhist = take(sizeof(double) * sr::kRHist * nz);
     L.X0 = xbufs > 0 ? take(vec) : 0;
     L.X1 = xbufs > 1 ? take(vec) : 0;
+    if (ext) {
+        L.xtwM = take(sizeof(float2) * 2 * M);
+        L.xtwN = take(sizeof(float2) * 2 * N);
+        L.xstM = take(sizeof(float2) * sr::fft_stage_table_len(2 * M, true));
+        L.xstN = take(sizeof(float2) * sr::fft_stage_table_len(2 * N, false));
+        L.xr = take(4 * pl);
+        L.xd = take(4 * pl);
+        L.xspec = take(4 * pl);
+    }
     L.total = o;
     return L;
 }
@@ -164,6 +187,9 @@ struct Bufs {
     DevScal* scal;
     double* rhist;
     float* X[2];   // intermediate w of the fixed-point sweeps (when allocated)
+    float2 *xtwM, *xtwN, *xstM, *xstN;   // Neumann FFT solve (when allocated)
+    float *xr, *xd;
+    float2* xspec;
 };
 
 struct sr_ctx {
@@ -171,6 +197,7 @@ struct sr_ctx {
     sr_params p;
     KParams kp;
     Geometry geo;
+    Geometry xgeo;             // 2M x 2N periodic geometry of the Neumann FFT solve
     Bufs b;
     hipStream_t stream;
     hipStream_t cap;           // capture stream (graphs are replayed on `stream`)
@@ -208,6 +235,26 @@ static void carve(Bufs& b, char* base, const Layout& L) {
     b.rhist = (double*)(base + L.rhist);
     b.X[0] = L.X0 ? (float*)(base + L.X0) : nullptr;
     b.X[1] = L.X1 ? (float*)(base + L.X1) : nullptr;
+    b.xtwM = L.xr ? (float2*)(base + L.xtwM) : nullptr;
+    b.xtwN = L.xr ? (float2*)(base + L.xtwN) : nullptr;
+    b.xstM = L.xr ? (float2*)(base + L.xstM) : nullptr;
+    b.xstN = L.xr ? (float2*)(base + L.xstN) : nullptr;
+    b.xr = L.xr ? (float*)(base + L.xr) : nullptr;
+    b.xd = L.xr ? (float*)(base + L.xd) : nullptr;
+    b.xspec = L.xr ? (float2*)(base + L.xspec) : nullptr;
+}
+
+// The 2M x 2N geometry of the Neumann FFT solve (periodic on the extension).
+static void make_xgeo(const Bufs& b, int M, int N, float taumu, Geometry& x) {
+    x = Geometry{};
+    x.M = 2 * M;
+    x.N = 2 * N;
+    x.twM = b.xtwM;
+    x.twN = b.xtwN;
+    x.stM = b.xstM;
+    x.stN = b.xstN;
+    x.taumu = taumu;
+    x.bc = 0;
 }
 
 static void make_kparams(const sr_params& p, KParams& kp) {
@@ -253,18 +300,25 @@ static std::vector<float2> twiddles(int L) {
 
 // Twiddle tables of a context (full tables for lengths M and N, stage tables
 // of the column and row transforms), copied from pageable host memory.
-static hipError_t upload_tables(const Bufs& b, int M, int N, hipStream_t st) {
+static hipError_t upload_tables_to(float2* twM, float2* twN, float2* stM, float2* stN, int M, int N,
+                                   hipStream_t st) {
     const std::vector<float2> tm = twiddles(M), tn = twiddles(N);
     std::vector<float2> sm(sr::fft_stage_table_len(M, true)), sn(sr::fft_stage_table_len(N, false));
     sr::fft_stage_table(M, true, sm.data());
     sr::fft_stage_table(N, false, sn.data());
-    hipError_t e = hipMemcpyAsync(b.twM, tm.data(), sizeof(float2) * M, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(b.twN, tn.data(), sizeof(float2) * N, hipMemcpyHostToDevice, st);
+    hipError_t e = hipMemcpyAsync(twM, tm.data(), sizeof(float2) * M, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(twN, tn.data(), sizeof(float2) * N, hipMemcpyHostToDevice, st);
     if (e == hipSuccess && !sm.empty())
-        e = hipMemcpyAsync(b.stM, sm.data(), sizeof(float2) * sm.size(), hipMemcpyHostToDevice, st);
+        e = hipMemcpyAsync(stM, sm.data(), sizeof(float2) * sm.size(), hipMemcpyHostToDevice, st);
     if (e == hipSuccess && !sn.empty())
-        e = hipMemcpyAsync(b.stN, sn.data(), sizeof(float2) * sn.size(), hipMemcpyHostToDevice, st);
+        e = hipMemcpyAsync(stN, sn.data(), sizeof(float2) * sn.size(), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);   // the host vectors are released on return
+    return e;
+}
+
+static hipError_t upload_tables(const Bufs& b, int M, int N, hipStream_t st) {
+    hipError_t e = upload_tables_to(b.twM, b.twN, b.stM, b.stN, M, N, st);
+    if (e == hipSuccess && b.xr) e = upload_tables_to(b.xtwM, b.xtwN, b.xstM, b.xstN, 2 * M, 2 * N, st);
     return e;
 }
 
@@ -273,7 +327,7 @@ static hipError_t upload_tables(const Bufs& b, int M, int N, hipStream_t st) {
 static hipError_t upload_aos(sr_ctx* c, hipStream_t st) {
     if (c->p.phi_solver != 1) return hipSuccess;
     std::vector<float> t(sr::kAosTapFloats);
-    (void)sr::aos_tap_buffer(c->M, c->N, c->p.tau, c->p.mu, t.data(), &c->aosKx, &c->aosKy);
+    (void)sr::aos_tap_buffer(c->M, c->N, c->p.tau, c->p.mu, c->p.bc, t.data(), &c->aosKx, &c->aosKy);
     hipError_t e = hipMemcpyAsync(c->b.aos, t.data(), sizeof(float) * t.size(), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     return e;
@@ -307,8 +361,13 @@ static void enqueue_iteration(sr_ctx* c, int p, hipStream_t st, Hook&& before = 
                        (fold_in && s == 0) ? &fold : nullptr);
         if (c->p.phi_solver == 1) {   // AOS: one launch, timed as the solve kind (2)
             before(2);
-            sr::launch_aos(c->M, c->N, b.Rb, in, out, b.aos, c->aosKx, c->aosKy,
+            sr::launch_aos(c->M, c->N, c->p.bc, b.Rb, in, out, b.aos, c->aosKx, c->aosKy,
                            c->geo.taumu, c->nz, b.scal, st, t_aos_ev[0], t_aos_ev[1]);
+        } else if (c->p.bc == 1) {   // DCT solve as the periodic solve of the mirror extension
+            for (int pass = 0; pass < 3; ++pass) {
+                before(1 + pass);
+                sr::launch_solve_neumann_pass(pass, c->xgeo, b.Rb, in, out, b.xr, b.xd, b.xspec, c->nz, b.scal, st);
+            }
         } else {
             for (int pass = 0; pass < 3; ++pass) {
                 before(1 + pass);
@@ -488,6 +547,7 @@ int sr_params_default(sr_params* p) {
     p->w_solver = 0;
     p->w_sweeps = 1;
     p->phi_solver = 0;
+    p->bc = 0;
     return SR_OK;
 }
 
@@ -495,7 +555,7 @@ int sr_workspace_size(int32_t M, int32_t N, const sr_params* p, size_t* bytes) {
     if (!bytes) return fail(SR_EINVAL, "bytes is NULL");
     int rc = validate(M, N, p);
     if (rc) return rc;
-    *bytes = make_layout(M, N, 1, sweep_buffers(*p)).total;
+    *bytes = make_layout(M, N, 1, sweep_buffers(*p), neumann_fft(*p)).total;
     return SR_OK;
 }
 
@@ -507,7 +567,7 @@ int sr_create(sr_ctx** out, int32_t M, int32_t N, const sr_params* p, void* work
     if (rc) return rc;
     if (!workspace) return fail(SR_EINVAL, "workspace is NULL");
     if ((uintptr_t)workspace & 255) return fail(SR_EWORKSPACE, "workspace must be 256-byte aligned");
-    const Layout L = make_layout(M, N, 1, sweep_buffers(*p));
+    const Layout L = make_layout(M, N, 1, sweep_buffers(*p), neumann_fft(*p));
     if (bytes < L.total) return fail(SR_EWORKSPACE, "workspace has %zu bytes, needs %zu", bytes, L.total);
 
     sr::configure_kernels();
@@ -528,6 +588,8 @@ int sr_create(sr_ctx** out, int32_t M, int32_t N, const sr_params* p, void* work
     c->geo.stM = c->b.stM;
     c->geo.stN = c->b.stN;
     c->geo.taumu = (float)(c->p.tau * c->p.mu);
+    c->geo.bc = c->p.bc;
+    make_xgeo(c->b, M, N, c->geo.taumu, c->xgeo);
     const char* ng = std::getenv("SR_NO_GRAPH");
     c->use_graphs = !(ng && ng[0] == '1');
     const char* th = std::getenv("SR_TILE_TH");
@@ -739,7 +801,15 @@ int sr_implicit_solve(sr_ctx* c, const float* rhs, float* u_out, uint32_t flags)
         rd = c->b.P1;
         ud = c->b.P2;
     }
-    sr::launch_solve(c->geo, rd, nullptr, ud, c->b.spec, 0.0f, c->b.part, 1, c->b.scal, c->stream);
+    if (c->p.bc == 1 && c->b.xr) {
+        for (int pass = 0; pass < 3; ++pass)
+            sr::launch_solve_neumann_pass(pass, c->xgeo, rd, nullptr, ud, c->b.xr, c->b.xd, c->b.xspec, 1, c->b.scal,
+                                          c->stream);
+    } else if (c->p.bc == 1) {
+        return fail(SR_EUNSUPPORTED, "the Neumann FFT solve is set up only with phi_solver = 0");
+    } else {
+        sr::launch_solve(c->geo, rd, nullptr, ud, c->b.spec, 0.0f, c->b.part, 1, c->b.scal, c->stream);
+    }
     HIP_TRY(hipGetLastError());
     if (flags & SR_HOST) return copy_out(c, u_out, ud, bytes, flags);
     return SR_OK;
@@ -826,7 +896,7 @@ static bool same_class(const sr_batch_item& a, const sr_batch_item& b) {
            x.sigma == y.sigma && x.rho == y.rho && x.s_exp == y.s_exp && x.S == y.S &&
            x.tol_inner == y.tol_inner && x.w0_mode == y.w0_mode && x.zero_tol == y.zero_tol &&
            x.w_solver == y.w_solver && (x.w_solver == 0 || x.w_sweeps == y.w_sweeps) &&
-           x.phi_solver == y.phi_solver;
+           x.phi_solver == y.phi_solver && x.bc == y.bc;
 }
 
 struct BatchPlan {
@@ -850,7 +920,9 @@ static int plan_batch(const sr_batch_item* items, int32_t n, BatchPlan& plan) {
     size_t o = 0;
     for (auto& g : plan.groups) {
         plan.offset.push_back(o);
-        o += align256(make_layout(items[g[0]].M, items[g[0]].N, (int)g.size(), sweep_buffers(items[g[0]].params)).total);
+        o += align256(make_layout(items[g[0]].M, items[g[0]].N, (int)g.size(), sweep_buffers(items[g[0]].params),
+                                  neumann_fft(items[g[0]].params))
+                          .total);
     }
     plan.total = o;
     return SR_OK;
@@ -892,10 +964,13 @@ int sr_solve_batch(sr_batch_item* items, int32_t n, void* workspace, size_t byte
         c.stream = st;
         make_kparams(c.p, c.kp);
         make_gauss(c.p.sigma, c.gauss, c.gauss_r);
-        carve(c.b, (char*)workspace + plan.offset[gi], make_layout(c.M, c.N, c.nz, sweep_buffers(c.p)));
+        carve(c.b, (char*)workspace + plan.offset[gi],
+              make_layout(c.M, c.N, c.nz, sweep_buffers(c.p), neumann_fft(c.p)));
         c.geo.M = c.M; c.geo.N = c.N; c.geo.twM = c.b.twM; c.geo.twN = c.b.twN;
         c.geo.stM = c.b.stM; c.geo.stN = c.b.stN;
         c.geo.taumu = (float)(c.p.tau * c.p.mu);
+        c.geo.bc = c.p.bc;
+        make_xgeo(c.b, c.M, c.N, c.geo.taumu, c.xgeo);
         HIP_TRY(upload_tables(c.b, c.M, c.N, st));
         HIP_TRY(upload_aos(&c, st));
         HIP_TRY(hipStreamSynchronize(st));

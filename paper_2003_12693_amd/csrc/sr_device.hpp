@@ -422,4 +422,18 @@ __device__ __forceinline__ void sum_partials(const double* part, int nblocks, do
     block_sum<NV>(v, red);
 }
 
+// Row / column index i (any integer, e.g. a halo position) on an n-point
+// axis, n a power of two: periodic (BC = 0), or mirrored about the half-
+// sample points -1/2 and n - 1/2 (BC = 1, the Neumann ghost values; the
+// mirror extension has period 2n).
+template <int BC>
+__device__ __forceinline__ int bidx(int i, int n) {
+    if constexpr (BC == 0) {
+        return i & (n - 1);
+    } else {
+        const int m = i & (2 * n - 1);
+        return m < n ? m : 2 * n - 1 - m;
+    }
+}
+
 }  // namespace sr

@@ -29,6 +29,7 @@ namespace sr {
 // ---------------------------------------------------------------------------
 struct GaussTaps { float k[2 * kMaxGaussR + 1]; int r; };
 
+template <int BC>
 __global__ __launch_bounds__(256) void k_blur_rows(const float* __restrict__ src, float* __restrict__ dst,
                                                    int M, int N, GaussTaps gt, DevScal* sc) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -37,12 +38,13 @@ __global__ __launch_bounds__(256) void k_blur_rows(const float* __restrict__ src
     const size_t zo = (size_t)blockIdx.z * M * N;
     const float* row = src + zo + (size_t)i * N;
     float acc = 0.0f;
-    for (int t = -gt.r; t <= gt.r; ++t) acc += gt.k[t + gt.r] * row[(j + t) & (N - 1)];
+    for (int t = -gt.r; t <= gt.r; ++t) acc += gt.k[t + gt.r] * row[bidx<BC>(j + t, N)];
     const float c = row[j];
     if (!isfinite(c)) sc[blockIdx.z].nonfinite = 1;
     dst[zo + (size_t)i * N + j] = acc;
 }
 
+template <int BC>
 __global__ __launch_bounds__(256) void k_blur_cols(const float* __restrict__ src, float* __restrict__ dst,
                                                    int M, int N, GaussTaps gt) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -51,11 +53,12 @@ __global__ __launch_bounds__(256) void k_blur_cols(const float* __restrict__ src
     const size_t zo = (size_t)blockIdx.z * M * N;
     src += zo;
     float acc = 0.0f;
-    for (int t = -gt.r; t <= gt.r; ++t) acc += gt.k[t + gt.r] * src[(size_t)((i + t) & (M - 1)) * N + j];
+    for (int t = -gt.r; t <= gt.r; ++t) acc += gt.k[t + gt.r] * src[(size_t)bidx<BC>(i + t, M) * N + j];
     dst[zo + (size_t)i * N + j] = acc;
 }
 
 // g = 1 / (1 + rho |grad fs|^s), central differences.
+template <int BC>
 __global__ __launch_bounds__(256) void k_edge(const float* __restrict__ fs, float* __restrict__ g,
                                               int M, int N, float rho, int s_exp) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -64,8 +67,8 @@ __global__ __launch_bounds__(256) void k_edge(const float* __restrict__ fs, floa
     const size_t zo = (size_t)blockIdx.z * M * N;
     fs += zo;
     g += zo;
-    const float gx = 0.5f * (fs[(size_t)((i + 1) & (M - 1)) * N + j] - fs[(size_t)((i - 1) & (M - 1)) * N + j]);
-    const float gy = 0.5f * (fs[(size_t)i * N + ((j + 1) & (N - 1))] - fs[(size_t)i * N + ((j - 1) & (N - 1))]);
+    const float gx = 0.5f * (fs[(size_t)bidx<BC>(i + 1, M) * N + j] - fs[(size_t)bidx<BC>(i - 1, M) * N + j]);
+    const float gy = 0.5f * (fs[(size_t)i * N + bidx<BC>(j + 1, N)] - fs[(size_t)i * N + bidx<BC>(j - 1, N)]);
     const float m2 = gx * gx + gy * gy;
     const float m = (s_exp == 2) ? m2 : sqrtf(m2);
     g[(size_t)i * N + j] = 1.0f / (1.0f + rho * m);
@@ -73,6 +76,7 @@ __global__ __launch_bounds__(256) void k_edge(const float* __restrict__ fs, floa
 
 // State initialisation of Algorithm 1: phi = phi0, w = grad+ phi0 (or 0),
 // b = 0, D = mu div-(b - w) = -mu Lap phi0 (or 0).
+template <int BC>
 __global__ __launch_bounds__(256) void k_init(const float* __restrict__ phi0, float* __restrict__ P0,
                                               float* __restrict__ W, float* __restrict__ B,
                                               float* __restrict__ D, int M, int N, float mu, int w0_mode,
@@ -85,10 +89,10 @@ __global__ __launch_bounds__(256) void k_init(const float* __restrict__ phi0, fl
     phi0 += z * MN; P0 += z * MN; W += 2 * z * MN; B += 2 * z * MN; D += z * MN;
     const float p = phi0[o];
     if (!isfinite(p)) sc[z].nonfinite = 1;
-    const float pd = phi0[(size_t)((i + 1) & (M - 1)) * N + j];
-    const float pr = phi0[(size_t)i * N + ((j + 1) & (N - 1))];
-    const float pu = phi0[(size_t)((i - 1) & (M - 1)) * N + j];
-    const float pl = phi0[(size_t)i * N + ((j - 1) & (N - 1))];
+    const float pd = phi0[(size_t)bidx<BC>(i + 1, M) * N + j];
+    const float pr = phi0[(size_t)i * N + bidx<BC>(j + 1, N)];
+    const float pu = phi0[(size_t)bidx<BC>(i - 1, M) * N + j];
+    const float pl = phi0[(size_t)i * N + bidx<BC>(j - 1, N)];
     P0[o] = p;
     B[o] = 0.0f;
     B[MN + o] = 0.0f;
@@ -103,18 +107,52 @@ __global__ __launch_bounds__(256) void k_init(const float* __restrict__ phi0, fl
     }
 }
 
-// D = mu div-(b - w) (eq 36) from a given state (checkpoint restore).
+// D = mu div-(b - w) (eq 36) from a given state (checkpoint restore); with
+// Neumann boundaries the divergence is the negative adjoint of the forward
+// difference (terms at index -1 and at the last index dropped).
+template <int BC>
 __global__ __launch_bounds__(256) void k_set_D(const float* __restrict__ W, const float* __restrict__ B,
                                                float* __restrict__ D, int M, int N, float mu) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     const int i = blockIdx.y;
     if (j >= N) return;
     const size_t MN = (size_t)M * N, o = (size_t)i * N + j;
-    const size_t ou = (size_t)((i - 1) & (M - 1)) * N + j;
-    const size_t ol = (size_t)i * N + ((j - 1) & (N - 1));
-    const float e1 = B[o] - W[o], e1u = B[ou] - W[ou];
-    const float e2 = B[MN + o] - W[MN + o], e2l = B[MN + ol] - W[MN + ol];
+    const size_t ou = (size_t)bidx<BC>(i - 1, M) * N + j;
+    const size_t ol = (size_t)i * N + bidx<BC>(j - 1, N);
+    float e1 = B[o] - W[o], e1u = B[ou] - W[ou];
+    float e2 = B[MN + o] - W[MN + o], e2l = B[MN + ol] - W[MN + ol];
+    if constexpr (BC == 1) {
+        if (i == M - 1) e1 = 0.0f;
+        if (i == 0) e1u = 0.0f;
+        if (j == N - 1) e2 = 0.0f;
+        if (j == 0) e2l = 0.0f;
+    }
     D[o] = mu * ((e1 - e1u) + (e2 - e2l));
+}
+
+// Neumann solve through the periodic one: the half-sample mirror extension
+// of an M x N plane to 2M x 2N (its periodic FFT solve, restricted to the
+// first M x N block, is the DCT-II solve of the mirrored Laplacian).
+__global__ __launch_bounds__(256) void k_mirror_ext(const float* __restrict__ src, float* __restrict__ dst, int M,
+                                                    int N, DevScal* sc) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.y;
+    const int z = blockIdx.z;
+    if (j >= 2 * N || !sc[z].active || sc[z].inner_done) return;
+    const size_t MN = (size_t)M * N;
+    dst[4 * MN * z + (size_t)i * 2 * N + j] = src[MN * z + (size_t)bidx<1>(i, M) * N + bidx<1>(j, N)];
+}
+
+// out = base + ext restricted to the first M x N block (base nullable: copy).
+__global__ __launch_bounds__(256) void k_restrict_add(const float* __restrict__ ext, const float* __restrict__ base,
+                                                      float* __restrict__ out, int M, int N, DevScal* sc) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.y;
+    const int z = blockIdx.z;
+    if (j >= N || !sc[z].active || sc[z].inner_done) return;
+    const size_t MN = (size_t)M * N, o = MN * z + (size_t)i * N + j;
+    const float v = ext[4 * MN * z + (size_t)i * 2 * N + j];
+    out[o] = base ? base[o] + v : v;
 }
 
 __global__ void k_reset_scal(DevScal* sc, int n, int active) {
@@ -207,7 +245,7 @@ struct RhsTile {
     static constexpr size_t lds_floats = 2 * NEXT + 2 * EH * TW + PH * PW;
 };
 
-template <int TH, int R>
+template <int TH, int R, int BC>
 __global__ __launch_bounds__(kRhsThreads) void k_rhs(KParams kp, int M, int N,
                                                       const float* __restrict__ phi_s,
                                                       const float* __restrict__ W,
@@ -247,14 +285,14 @@ __global__ __launch_bounds__(kRhsThreads) void k_rhs(KParams kp, int M, int N,
         const int e = tid + u * T;
         if (e < NEXT) {
             const int ei = e / EW, ej = e - ei * EW;
-            lp[u] = phi_s[(size_t)((i0 - R + ei) & (M - 1)) * N + ((j0 - R + ej) & (N - 1))];
+            lp[u] = phi_s[(size_t)bidx<BC>(i0 - R + ei, M) * N + bidx<BC>(j0 - R + ej, N)];
         }
     }
     float dv[C::NO];
 #pragma unroll
     for (int u = 0; u < C::NO; ++u) {
         const int e = tid + u * T;
-        dv[u] = D[(size_t)((i0 + e / TW) & (M - 1)) * N + ((j0 + (e % TW)) & (N - 1))];
+        dv[u] = D[(size_t)bidx<BC>(i0 + e / TW, M) * N + bidx<BC>(j0 + (e % TW), N)];
     }
     int inband = 0;
 #pragma unroll
@@ -270,7 +308,7 @@ __global__ __launch_bounds__(kRhsThreads) void k_rhs(KParams kp, int M, int N,
     if constexpr (R == 0) {
         for (int e = tid; e < PH * PW; e += T) {
             const int si = e / PW, sj = e - si * PW;
-            sphi[e] = phi_s[(size_t)((i0 - 1 + si) & (M - 1)) * N + ((j0 - 1 + sj) & (N - 1))];
+            sphi[e] = phi_s[(size_t)bidx<BC>(i0 - 1 + si, M) * N + bidx<BC>(j0 - 1 + sj, N)];
         }
     }
     const bool band = __syncthreads_or(inband) != 0;
@@ -297,7 +335,7 @@ __global__ __launch_bounds__(kRhsThreads) void k_rhs(KParams kp, int M, int N,
         const int e = tid + u * T;
         if (e < NEXT) {
             const int ei = e / EW, ej = e - ei * EW;
-            const size_t o = (size_t)((i0 - R + ei) & (M - 1)) * N + ((j0 - R + ej) & (N - 1));
+            const size_t o = (size_t)bidx<BC>(i0 - R + ei, M) * N + bidx<BC>(j0 - R + ej, N);
             l1[u] = W[o];
             l2[u] = W[MN + o];
         }
@@ -306,7 +344,7 @@ __global__ __launch_bounds__(kRhsThreads) void k_rhs(KParams kp, int M, int N,
 #pragma unroll
     for (int u = 0; u < C::NO; ++u) {
         const int e = tid + u * T;
-        const size_t o = (size_t)((i0 + e / TW) & (M - 1)) * N + ((j0 + (e % TW)) & (N - 1));
+        const size_t o = (size_t)bidx<BC>(i0 + e / TW, M) * N + bidx<BC>(j0 + (e % TW), N);
         w1v[u] = W[o]; w2v[u] = W[MN + o]; gv[u] = g[o];
     }
 #pragma unroll
@@ -364,7 +402,7 @@ __global__ __launch_bounds__(kRhsThreads) void k_rhs(KParams kp, int M, int N,
 // ---------------------------------------------------------------------------
 // repulsion field alone (component operator): v = K (*) (w h(phi))
 // ---------------------------------------------------------------------------
-template <int TH>
+template <int TH, int BC>
 __global__ __launch_bounds__(kTileThreads) void k_repulsion(KParams kp, int M, int N,
                                                             const float* __restrict__ phi,
                                                             const float* __restrict__ W,
@@ -381,7 +419,7 @@ __global__ __launch_bounds__(kTileThreads) void k_repulsion(KParams kp, int M, i
     const int i0 = blockIdx.y * TH, j0 = blockIdx.x * TW;
     for (int e = threadIdx.x; e < eh * ew; e += blockDim.x) {
         const int ei = e / ew, ej = e - ei * ew;
-        const int gi = (i0 - R + ei) & (M - 1), gj = (j0 - R + ej) & (N - 1);
+        const int gi = bidx<BC>(i0 - R + ei, M), gj = bidx<BC>(j0 - R + ej, N);
         const size_t o = (size_t)gi * N + gj;
         const float h = band_h(phi[o], kp);
         su1[e] = W[o] * h;
@@ -727,7 +765,7 @@ struct WTile {
     static constexpr size_t lds_floats = su_floats + 2 * EH * CW + PH * PW;
 };
 
-template <int TH, int R, int TT>
+template <int TH, int R, int TT, int BC>
 __global__ __launch_bounds__(TT) void k_wstep(KParams kp, int M, int N,
                                                         const float* __restrict__ phin,
                                                         float* __restrict__ P0,
@@ -768,7 +806,7 @@ __global__ __launch_bounds__(TT) void k_wstep(KParams kp, int M, int N,
         const int e = tid + u * T;
         if (e < NEXT) {
             const int ei = e / EW, ej = e - ei * EW;
-            lp[u] = phin[(size_t)((i0 - 1 - R + ei) & (M - 1)) * N + ((j0 - 1 - R + ej) & (N - 1))];
+            lp[u] = phin[(size_t)bidx<BC>(i0 - 1 - R + ei, M) * N + bidx<BC>(j0 - 1 - R + ej, N)];
         }
     }
     // b on the computed region and phi^k on the tile (both paths need them)
@@ -778,7 +816,7 @@ __global__ __launch_bounds__(TT) void k_wstep(KParams kp, int M, int N,
         const int e = tid + u * T;
         if (e < CH * CW) {
             const int ci = e / CW, cj = e - ci * CW;
-            const size_t o = (size_t)((i0 - 1 + ci) & (M - 1)) * N + ((j0 - 1 + cj) & (N - 1));
+            const size_t o = (size_t)bidx<BC>(i0 - 1 + ci, M) * N + bidx<BC>(j0 - 1 + cj, N);
             b1v[u] = Bold[o]; b2v[u] = Bold[MN + o];
         }
     }
@@ -786,7 +824,7 @@ __global__ __launch_bounds__(TT) void k_wstep(KParams kp, int M, int N,
 #pragma unroll
     for (int u = 0; u < C::NO; ++u) {
         const int e = tid + u * T;
-        pold[u] = P0[(size_t)((i0 + e / TW) & (M - 1)) * N + ((j0 + (e % TW)) & (N - 1))];
+        pold[u] = P0[(size_t)bidx<BC>(i0 + e / TW, M) * N + bidx<BC>(j0 + (e % TW), N)];
     }
     int inband = 0;
 #pragma unroll
@@ -802,7 +840,7 @@ __global__ __launch_bounds__(TT) void k_wstep(KParams kp, int M, int N,
     if constexpr (R == 0) {
         for (int e = tid; e < PH * PW; e += T) {
             const int si = e / PW, sj = e - si * PW;
-            sphi[e] = phin[(size_t)((i0 - 1 + si) & (M - 1)) * N + ((j0 - 1 + sj) & (N - 1))];
+            sphi[e] = phin[(size_t)bidx<BC>(i0 - 1 + si, M) * N + bidx<BC>(j0 - 1 + sj, N)];
         }
     }
     const bool band = __syncthreads_or(inband) != 0;
@@ -813,7 +851,7 @@ __global__ __launch_bounds__(TT) void k_wstep(KParams kp, int M, int N,
             const int e = tid + u * T;
             if (e < NEXT) {
                 const int ei = e / EW, ej = e - ei * EW;
-                const size_t o = (size_t)((i0 - 1 - R + ei) & (M - 1)) * N + ((j0 - 1 - R + ej) & (N - 1));
+                const size_t o = (size_t)bidx<BC>(i0 - 1 - R + ei, M) * N + bidx<BC>(j0 - 1 - R + ej, N);
                 l1[u] = Wold[o];
                 l2[u] = Wold[MN + o];
             }
@@ -824,7 +862,7 @@ __global__ __launch_bounds__(TT) void k_wstep(KParams kp, int M, int N,
             const int e = tid + u * T;
             if (e < CH * CW) {
                 const int ci = e / CW, cj = e - ci * CW;
-                gv[u] = g[(size_t)((i0 - 1 + ci) & (M - 1)) * N + ((j0 - 1 + cj) & (N - 1))];
+                gv[u] = g[(size_t)bidx<BC>(i0 - 1 + ci, M) * N + bidx<BC>(j0 - 1 + cj, N)];
             }
         }
 #pragma unroll
@@ -923,7 +961,14 @@ __global__ __launch_bounds__(TT) void k_wstep(KParams kp, int M, int N,
         const int gi = i0 + i, gj = j0 + j;
         if (gi < M && gj < N) {
             const int c = (i + 1) * CW + (j + 1);
-            const float dvv = (sd1[c] - sd1[c - CW]) + (sd2[c] - sd2[c - 1]);
+            float dvv;
+            if constexpr (BC == 0) {
+                dvv = (sd1[c] - sd1[c - CW]) + (sd2[c] - sd2[c - 1]);
+            } else {   // negative adjoint of the Neumann forward difference
+                const float e1 = gi < M - 1 ? sd1[c] : 0.0f, e1u = gi > 0 ? sd1[c - CW] : 0.0f;
+                const float e2 = gj < N - 1 ? sd2[c] : 0.0f, e2l = gj > 0 ? sd2[c - 1] : 0.0f;
+                dvv = (e1 - e1u) + (e2 - e2l);
+            }
             const size_t o = (size_t)gi * N + gj;
             D[o] = kp.mu * dvv;
             const float pn = sphi[(i + 1) * PW + (j + 1)];
@@ -952,7 +997,7 @@ __global__ __launch_bounds__(1024) void k_fin_outer(const double* __restrict__ p
 // ---------------------------------------------------------------------------
 // SR energy (eqs 7-10) of phi, partial sums in double, last workgroup totals.
 // ---------------------------------------------------------------------------
-template <int TH>
+template <int TH, int BC>
 __global__ __launch_bounds__(kTileThreads) void k_energy(KParams kp, int M, int N,
                                                          const float* __restrict__ phi,
                                                          const float* __restrict__ g,
@@ -973,10 +1018,10 @@ __global__ __launch_bounds__(kTileThreads) void k_energy(KParams kp, int M, int 
     const int i0 = blockIdx.y * TH, j0 = blockIdx.x * TW;
     for (int e = threadIdx.x; e < eh * ew; e += blockDim.x) {
         const int ei = e / ew, ej = e - ei * ew;
-        const int gi = (i0 - R + ei) & (M - 1), gj = (j0 - R + ej) & (N - 1);
+        const int gi = bidx<BC>(i0 - R + ei, M), gj = bidx<BC>(j0 - R + ej, N);
         const float p = phi[(size_t)gi * N + gj];
-        const float G1 = phi[(size_t)((gi + 1) & (M - 1)) * N + gj] - p;
-        const float G2 = phi[(size_t)gi * N + ((gj + 1) & (N - 1))] - p;
+        const float G1 = phi[(size_t)bidx<BC>(gi + 1, M) * N + gj] - p;
+        const float G2 = phi[(size_t)gi * N + bidx<BC>(gj + 1, N)] - p;
         const float h = band_h(p, kp);
         su1[e] = G1 * h;
         su2[e] = G2 * h;
@@ -995,8 +1040,8 @@ __global__ __launch_bounds__(kTileThreads) void k_energy(KParams kp, int M, int 
         const float u1 = su1[c], u2 = su2[c];
         const size_t o = (size_t)gi * N + gj;
         const float p = phi[o];
-        const float G1 = phi[(size_t)((gi + 1) & (M - 1)) * N + gj] - p;
-        const float G2 = phi[(size_t)gi * N + ((gj + 1) & (N - 1))] - p;
+        const float G1 = phi[(size_t)bidx<BC>(gi + 1, M) * N + gj] - p;
+        const float G2 = phi[(size_t)gi * N + bidx<BC>(gj + 1, N)] - p;
         float H_, dl;
         heav_dirac(p, kp.eps, kp.inv_eps, H_, dl);
         const float gg = g[o];
@@ -1231,7 +1276,7 @@ static int tile_height(const Geometry& geo, int nz) {
 template <int TH, int R>
 static void launch_rhs_t(const Geometry& geo, const KParams& kp, const float* phi_s, const float* W, const float* g,
                          const float* D, float* out, int nz, DevScal* sc, hipStream_t st, const FinFold* fold) {
-    launch_iter(k_rhs<TH, R>, tile_grid(geo.M, geo.N, TH, nz), dim3(kRhsThreads),
+    launch_iter(geo.bc ? k_rhs<TH, R, 1> : k_rhs<TH, R, 0>, tile_grid(geo.M, geo.N, TH, nz), dim3(kRhsThreads),
                 sizeof(float) * RhsTile<TH, R>::lds_floats, st, kp, geo.M, geo.N, phi_s, W, g, D, out,
                 fold ? fold->part : nullptr, fold ? fold->nb : 0, fold ? fold->rhist : nullptr, sc);
 }
@@ -1239,7 +1284,7 @@ template <int TH, int R, int TT>
 static void launch_wstep_t(const Geometry& geo, const KParams& kp, const float* phin, float* P0, const float* Wold,
                            const float* Bold, const float* g, float* Wnew, float* Bnew, float* D, double* part,
                            double* rhist, int sweep, int nz, DevScal* sc, hipStream_t st) {
-    launch_iter(k_wstep<TH, R, TT>, tile_grid(geo.M, geo.N, TH, nz), dim3(TT),
+    launch_iter(geo.bc ? k_wstep<TH, R, TT, 1> : k_wstep<TH, R, TT, 0>, tile_grid(geo.M, geo.N, TH, nz), dim3(TT),
                 sizeof(float) * WTile<TH, R, TT>::lds_floats, st, kp, geo.M, geo.N, phin, P0, Wold, Bold, g, Wnew,
                 Bnew, D, part, rhist, sweep, sc);
 }
@@ -1313,11 +1358,20 @@ void launch_wstep(const Geometry& geo, const KParams& kp, const float* phin, flo
 template <int TH, int R>
 static void set_tile_attrs_one() {
     const int bytes = 160 * 1024 - 1024;
-    (void)hipFuncSetAttribute((const void*)k_rhs<TH, R>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    if constexpr (TH == 32)
-        (void)hipFuncSetAttribute((const void*)k_wstep<32, R, 512>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    if constexpr (TH == 16)
-        (void)hipFuncSetAttribute((const void*)k_wstep<16, R, 256>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    (void)hipFuncSetAttribute((const void*)k_rhs<TH, R, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    (void)hipFuncSetAttribute((const void*)k_rhs<TH, R, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if constexpr (TH == 32) {
+        (void)hipFuncSetAttribute((const void*)k_wstep<32, R, 512, 0>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  bytes);
+        (void)hipFuncSetAttribute((const void*)k_wstep<32, R, 512, 1>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  bytes);
+    }
+    if constexpr (TH == 16) {
+        (void)hipFuncSetAttribute((const void*)k_wstep<16, R, 256, 0>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  bytes);
+        (void)hipFuncSetAttribute((const void*)k_wstep<16, R, 256, 1>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  bytes);
+    }
 }
 template <int TH>
 static void set_tile_attrs() {
@@ -1328,16 +1382,18 @@ static void set_tile_attrs() {
 
 void launch_energy(const Geometry& geo, const KParams& kp, const float* phi, const float* g, double* part,
                    int nz, DevScal* sc, hipStream_t st) {
-    hipLaunchKernelGGL(k_energy<kTH>, tile_grid(geo.M, geo.N, kTH, nz), dim3(kTileThreads), lds_energy(kTH, kp.R),
-                       st, kp, geo.M, geo.N, phi, g, part, sc);
+    auto kern = geo.bc ? k_energy<kTH, 1> : k_energy<kTH, 0>;
+    hipLaunchKernelGGL(kern, tile_grid(geo.M, geo.N, kTH, nz), dim3(kTileThreads), lds_energy(kTH, kp.R), st, kp,
+                       geo.M, geo.N, phi, g, part, sc);
     const int nb = ((geo.N + kTileW - 1) / kTileW) * ((geo.M + kTH - 1) / kTH);
     hipLaunchKernelGGL(k_fin_energy, dim3(nz), dim3(1024), 0, st, part, nb, kp, sc);
 }
 
 void launch_repulsion(const Geometry& geo, const KParams& kp, const float* phi, const float* W, float* V,
                       hipStream_t st) {
-    hipLaunchKernelGGL(k_repulsion<kTH>, tile_grid(geo.M, geo.N, kTH, 1), dim3(kTileThreads),
-                       lds_energy(kTH, kp.R), st, kp, geo.M, geo.N, phi, W, V);
+    auto kern = geo.bc ? k_repulsion<kTH, 1> : k_repulsion<kTH, 0>;
+    hipLaunchKernelGGL(kern, tile_grid(geo.M, geo.N, kTH, 1), dim3(kTileThreads), lds_energy(kTH, kp.R), st, kp,
+                       geo.M, geo.N, phi, W, V);
 }
 
 void launch_edge(const Geometry& geo, const float* f, float* tmp, float* fs, float* g, const float* taps, int r,
@@ -1346,20 +1402,37 @@ void launch_edge(const Geometry& geo, const float* f, float* tmp, float* fs, flo
     gt.r = r;
     for (int t = 0; t <= 2 * r; ++t) gt.k[t] = taps[t];
     const dim3 blk(256), grd((geo.N + 255) / 256, geo.M, nz);
-    hipLaunchKernelGGL(k_blur_rows, grd, blk, 0, st, f, tmp, geo.M, geo.N, gt, sc);
-    hipLaunchKernelGGL(k_blur_cols, grd, blk, 0, st, tmp, fs, geo.M, geo.N, gt);
-    hipLaunchKernelGGL(k_edge, grd, blk, 0, st, fs, g, geo.M, geo.N, rho, s_exp);
+    auto rows = geo.bc ? k_blur_rows<1> : k_blur_rows<0>;
+    auto cols = geo.bc ? k_blur_cols<1> : k_blur_cols<0>;
+    auto edge = geo.bc ? k_edge<1> : k_edge<0>;
+    hipLaunchKernelGGL(rows, grd, blk, 0, st, f, tmp, geo.M, geo.N, gt, sc);
+    hipLaunchKernelGGL(cols, grd, blk, 0, st, tmp, fs, geo.M, geo.N, gt);
+    hipLaunchKernelGGL(edge, grd, blk, 0, st, fs, g, geo.M, geo.N, rho, s_exp);
 }
 
 void launch_init(const Geometry& geo, const float* phi0, float* P0, float* W, float* B, float* D, float mu,
                  int w0_mode, DevScal* sc, hipStream_t st, int nz) {
     const dim3 blk(256), grd((geo.N + 255) / 256, geo.M, nz);
-    hipLaunchKernelGGL(k_init, grd, blk, 0, st, phi0, P0, W, B, D, geo.M, geo.N, mu, w0_mode, sc);
+    auto kern = geo.bc ? k_init<1> : k_init<0>;
+    hipLaunchKernelGGL(kern, grd, blk, 0, st, phi0, P0, W, B, D, geo.M, geo.N, mu, w0_mode, sc);
 }
 
 void launch_set_D(const Geometry& geo, const float* W, const float* B, float* D, float mu, hipStream_t st) {
     const dim3 blk(256), grd((geo.N + 255) / 256, geo.M);
-    hipLaunchKernelGGL(k_set_D, grd, blk, 0, st, W, B, D, geo.M, geo.N, mu);
+    auto kern = geo.bc ? k_set_D<1> : k_set_D<0>;
+    hipLaunchKernelGGL(kern, grd, blk, 0, st, W, B, D, geo.M, geo.N, mu);
+}
+
+void launch_solve_neumann_pass(int pass, const Geometry& xgeo, const float* rhs, const float* phi_in,
+                               float* phi_out, float* xr, float* xd, float2* xspec, int nz, DevScal* sc,
+                               hipStream_t st) {
+    const int M = xgeo.M / 2, N = xgeo.N / 2;
+    if (pass == 0)
+        hipLaunchKernelGGL(k_mirror_ext, dim3((2 * N + 255) / 256, 2 * M, nz), dim3(256), 0, st, rhs, xr, M, N, sc);
+    launch_solve_pass(pass, xgeo, xr, nullptr, xd, xspec, 0.0f, nullptr, nz, sc, st);
+    if (pass == 2)
+        hipLaunchKernelGGL(k_restrict_add, dim3((N + 255) / 256, M, nz), dim3(256), 0, st, xd, phi_in, phi_out, M, N,
+                           sc);
 }
 
 void launch_reset_scal(DevScal* sc, int n, int active, hipStream_t st) {
@@ -1383,8 +1456,10 @@ void configure_kernels() {
     set_tile_attrs<8>();
     set_tile_attrs<16>();
     set_tile_attrs<32>();
-    (void)hipFuncSetAttribute((const void*)k_energy<kTH>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    (void)hipFuncSetAttribute((const void*)k_repulsion<kTH>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    (void)hipFuncSetAttribute((const void*)k_energy<kTH, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    (void)hipFuncSetAttribute((const void*)k_energy<kTH, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    (void)hipFuncSetAttribute((const void*)k_repulsion<kTH, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    (void)hipFuncSetAttribute((const void*)k_repulsion<kTH, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     set_fft_attrs<8>(); set_fft_attrs<16>(); set_fft_attrs<32>(); set_fft_attrs<64>(); set_fft_attrs<128>();
     set_fft_attrs<256>(); set_fft_attrs<512>(); set_fft_attrs<1024>(); set_fft_attrs<2048>(); set_fft_attrs<4096>();
     done = true;

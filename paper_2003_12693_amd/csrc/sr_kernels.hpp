@@ -18,6 +18,7 @@ struct Geometry {
     const float2* stN;      // stage twiddle table of the row transforms (length N)
     float taumu;
     int tile_th = 0;   // stencil tile height (16 or 32); 0 = size heuristic
+    int bc = 0;        // boundaries: 0 periodic, 1 Neumann (mirror ghosts)
 };
 
 int tile_blocks(int M, int N);
@@ -50,6 +51,14 @@ struct FinFold {
 };
 void launch_rhs(const Geometry& geo, const KParams& kp, const float* phi_s, const float* W, const float* g,
                 const float* D, float* out, int nz, DevScal* sc, hipStream_t st, const FinFold* fold = nullptr);
+// Pass `pass` (0..2) of the Neumann solve (phi_out = phi_in + u, phi_in
+// nullable, with (1 - tau mu Lap) u = rhs for the mirrored Laplacian) as the
+// periodic solve on the 2M x 2N mirror extension: xgeo is the 2M x 2N
+// geometry, xr / xd two 4MN-float planes per instance, xspec its spectrum;
+// pass 0 also writes the extension, pass 2 also the restriction.
+void launch_solve_neumann_pass(int pass, const Geometry& xgeo, const float* rhs, const float* phi_in,
+                               float* phi_out, float* xr, float* xd, float2* xspec, int nz, DevScal* sc,
+                               hipStream_t st);
 void launch_solve(const Geometry& geo, const float* rhs, const float* phi_in, float* phi_out, float2* spec,
                   float tol_inner, double* part, int nz, DevScal* sc, hipStream_t st);
 // The three passes of launch_solve separately (pass 0: forward rows,

@@ -49,6 +49,7 @@ class sr_params(C.Structure):
         ("min_iter", C.c_int32), ("check_every", C.c_int32), ("w0_mode", C.c_int32),
         ("zero_tol", C.c_double),
         ("w_solver", C.c_int32), ("w_sweeps", C.c_int32), ("phi_solver", C.c_int32),
+        ("bc", C.c_int32),
     ]
 
     def as_dict(self):

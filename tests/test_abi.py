@@ -43,16 +43,18 @@ def test_struct_layout_matches_c(sr, tmp_path):
     src = tmp_path / "layout.c"
     src.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "sr.h"\n'
-        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(sr_params), sizeof(sr_step_info),"
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(sr_params), sizeof(sr_step_info),"
         " sizeof(sr_batch_item), offsetof(sr_params, w0_mode), offsetof(sr_batch_item, params),"
-        " offsetof(sr_batch_item, energy), offsetof(sr_params, tol_outer), offsetof(sr_params, w_sweeps));"
+        " offsetof(sr_batch_item, energy), offsetof(sr_params, tol_outer), offsetof(sr_params, w_sweeps),"
+        " offsetof(sr_params, bc));"
         " return 0;}\n")
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     vals = list(map(int, subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()))
     assert vals == [C.sizeof(sr.sr_params), C.sizeof(sr.sr_step_info), C.sizeof(sr.sr_batch_item),
                     sr.sr_params.w0_mode.offset, sr.sr_batch_item.params.offset,
-                    sr.sr_batch_item.energy.offset, sr.sr_params.tol_outer.offset, sr.sr_params.w_sweeps.offset]
+                    sr.sr_batch_item.energy.offset, sr.sr_params.tol_outer.offset, sr.sr_params.w_sweeps.offset,
+                    sr.sr_params.bc.offset]
 
 
 def test_defaults_are_the_two_circles_set(sr):
@@ -167,3 +169,21 @@ def test_aos_phi_solver_parameters(sr):
     assert sr.sr_workspace_size(64, 64, sr.sr_params_default(phi_solver=1)) == \
         sr.sr_workspace_size(64, 64, sr.sr_params_default())
     assert sr.sr_params_default().phi_solver == 0
+
+
+def test_boundary_parameter(sr):
+    """bc is validated before any HIP call: 0 (periodic) / 1 (Neumann) only;
+    the Neumann FFT solve runs on the 2M x 2N mirror extension (M, N <= 2048,
+    fixed S, workspace for the extension), the Neumann AOS solve needs none."""
+    assert sr.sr_params_default().bc == 0
+    with pytest.raises(sr.SRError) as e:
+        sr.sr_workspace_size(64, 64, sr.sr_params_default(bc=2))
+    assert e.value.code == sr.SR_EINVAL
+    for M, N, kw in ((4096, 64, {}), (64, 4096, {}), (64, 64, dict(tol_inner=1e-3))):
+        with pytest.raises(sr.SRError) as e:
+            sr.sr_workspace_size(M, N, sr.sr_params_default(bc=1, **kw))
+        assert e.value.code == sr.SR_EUNSUPPORTED
+    base = sr.sr_workspace_size(64, 64, sr.sr_params_default())
+    assert sr.sr_workspace_size(64, 64, sr.sr_params_default(bc=1, phi_solver=1)) == base
+    assert sr.sr_workspace_size(64, 64, sr.sr_params_default(bc=1)) >= base + 3 * 4 * 64 * 64 * 4
+    assert sr.sr_workspace_size(2048, 2048, sr.sr_params_default(bc=1)) > 0

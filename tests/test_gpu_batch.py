@@ -194,3 +194,21 @@ def test_aos_batch_matches_single(sr, kernel, monkeypatch):
         s.set_image(_cuda(f), _cuda(p))
         s.step(4)
         assert np.array_equal(r["phi"].cpu().numpy(), s.phi().cpu().numpy())
+
+
+@pytest.mark.parametrize("phi_solver", [0, 1])
+def test_neumann_batch_matches_single(sr, phi_solver):
+    """Neumann boundaries: the batched solve gives bitwise the single solves'
+    results."""
+    _note(f"Neumann: batch vs single (phi_solver={phi_solver})")
+    inst = _instances()[:5]
+    items = [dict(f=_cuda(f), phi0=_cuda(p), max_iter=4,
+                  params=gpu_params(bc=1, phi_solver=phi_solver, R=R, d=float(R)))
+             for (M, N, R, f, p) in inst]
+    rc, res = sr.solve_batch(items)
+    assert rc == 0
+    for (M, N, R, f, p), r in zip(inst, res):
+        s = sr.Solver(M, N, gpu_params(bc=1, phi_solver=phi_solver, R=R, d=float(R)))
+        s.set_image(_cuda(f), _cuda(p))
+        s.step(4)
+        assert np.array_equal(r["phi"].cpu().numpy(), s.phi().cpu().numpy())
