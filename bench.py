@@ -65,6 +65,8 @@ def params_kw(wl):
         # one) and the Bregman update amplifies that: the iteration diverges;
         # tau = 0.04 (tau mu = 0.32) keeps it stable
         kw.update(phi_solver=1, tau=0.04)
+    if wl.get("bc") == "neumann":   # zero normal derivative (eqs 17, 27)
+        kw.update(bc=1)
     return kw
 
 
@@ -304,6 +306,9 @@ def main():
                     help="use the fixed-point w solver (eqs 38-40) with R sweeps instead of soft thresholding")
     ap.add_argument("--phi-solver", default="fft", choices=["fft", "aos"],
                     help="phi sub-problem solver: the FFT solve (eq 37) or AOS with constant A_l")
+    ap.add_argument("--bc", default="periodic", choices=["periodic", "neumann"],
+                    help="boundaries: periodic, or Neumann (mirror ghosts; the FFT solve then runs on the "
+                         "2M x 2N mirror extension)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB")
     ap.add_argument("--batch", type=int, default=0, metavar="COUNT",
                     help="time-to-converge of COUNT uneven instances, batched vs plain")
@@ -343,6 +348,9 @@ def main():
     if args.phi_solver == "aos":
         wl["phi_solver"] = "aos"
         wl["text"] += "; AOS phi solver, tau=0.04"
+    if args.bc == "neumann":
+        wl["bc"] = "neumann"
+        wl["text"] += "; Neumann boundaries" + ("" if args.phi_solver == "aos" else " (DCT solve via the mirror extension)")
     steps = args.steps if args.steps is not None else wl["default_steps"]
     M, N = wl["M"], wl["N"]
     f, phi0 = make_input(args.workload)
@@ -381,6 +389,10 @@ def main():
     dom = max(per_iter_ms, key=per_iter_ms.get)
     dom_ms = prof[dom][0]
     bytes_px = dict(BYTES_PER_PX, aos_solve=BYTES_PER_PX_AOS)
+    if args.bc == "neumann" and args.phi_solver == "fft":
+        # the three passes run on the 2M x 2N extension: 8 B per extended
+        # pixel each (the inverse pass writes the increment only)
+        bytes_px.update(row_fft_fwd=32, col_fft_solve=32, row_fft_inv=32)
     if args.w_sweeps > 1:   # w_step launches average the sweeps and the full step
         bytes_px["w_step"] = (BYTES_PER_PX["w_step"] + BYTES_PER_PX_W_SWEEP * (args.w_sweeps - 1)) / args.w_sweeps
     alg_bytes = bytes_px[dom] * M * N
@@ -402,10 +414,10 @@ def main():
         "config": {"workload": wl["text"], "M": M, "N": N, "R": wl["R"], "S": wl["S"], "tile_rows": tile_th,
                    "bytes_per_px_iter": sum(bytes_px[k] * per_iter[k] for k in prof),
                    "w_solver": "fixed-point" if args.w_sweeps else "shrink", "w_sweeps": args.w_sweeps or None,
-                   "phi_solver": args.phi_solver},
+                   "phi_solver": args.phi_solver, "bc": args.bc},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": (None if args.w_sweeps or args.phi_solver != "fft"
+                     "traffic": (None if args.w_sweeps or args.phi_solver != "fft" or args.bc != "periodic"
                                  else measured_traffic(args.workload, dom, tile_th)),
                      "alg_bytes_per_launch": alg_bytes},
         "kernels_ms": {k: round(v[0], 5) for k, v in prof.items()},
