@@ -117,6 +117,65 @@ def cpu_baseline(f, phi0, wl, iters):
                       f"({t2 - t1:.1f} s; edge map and initialisation excluded)"}
 
 
+# The paper's 3-D (mandible) weights with a 5 x 5 x 5 window.
+PARAMS_3D = dict(gamma=5.0, alpha=4.0, beta=0.2, mu=3.0, tau=0.05, eps=1.0, band_l=1.0, d=4.0, R=2, S=5,
+                 sigma=1.5, rho=1000.0, s_exp=2, tol_inner=0.0, zero_tol=1e-3)
+# algorithmic bytes per voxel per launch of each 3-D kernel kind (FP32):
+#   window: u = w h(phi) reads w (12) and phi (4), writes u (12); each of the
+#           three axis passes reads and writes 3 components (24): mean of 4
+#   rhs: reads phi, w, b, g, v (4 + 12 + 12 + 4 + 12), writes r (4)
+#   fft: first pass reads r (4), writes complex (8); three complex passes
+#        read and write 8 each; the last reads 8 + phi_s 4, writes 4: mean of 5
+#   w step: reads phi, b, g, v (4 + 12 + 4 + 12), writes w and b (24)
+BYTES_PER_VOX_3D = {"window": (28 + 3 * 24) / 4, "rhs": 48, "fft": (12 + 3 * 16 + 16) / 5, "w_step": 56}
+
+
+def volume_bench(S, steps, warmup, cpu):
+    """3-D solver on an S^3 volume of touching balls: throughput in
+    megavoxel-iterations per second, per-kernel-kind timing, roofline."""
+    import torch
+    from paper_2003_12693_amd import sr, synth
+    f, phi0 = synth.balls3d(S, S, S)
+    s = sr.Solver3D(S, S, S, sr.sr_params_default(**PARAMS_3D))
+    s.set_image(torch.from_numpy(f).cuda(), torch.from_numpy(phi0).cuda())
+    s.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(steps)
+    t1 = time.perf_counter()
+    value = S ** 3 * steps / 1e6 / (t1 - t0)
+    prof = sr.sr3_profile(s.ctx, 3)
+    per_iter_ms = {k: v[0] * v[1] / 3 for k, v in prof.items()}
+    dom = max(per_iter_ms, key=per_iter_ms.get)
+    achieved = BYTES_PER_VOX_3D[dom] * S ** 3 / (prof[dom][0] * 1e-3) / 1e9
+    out = {"metric": f"3-D SB megavoxel-iters/s at {S}^3", "value": round(value, 2), "unit": "MVox-it/s",
+           "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": round((t1 - t0) * 1e3 / steps, 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"balls3d-{S}: touching balls, bias 0.2, noise 0.15, box phi0; the paper's 3-D "
+                                  "weights (gamma 5, alpha 4, beta 0.2, mu 3, tau 0.05, eps 1, l 1, d 4, 5^3 window, "
+                                  "S 5)"},
+           "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                        "alg_bytes_per_launch": BYTES_PER_VOX_3D[dom] * S ** 3},
+           "kernels_ms": {k: round(v[0], 5) for k, v in prof.items()},
+           "iteration_ms_sum_of_kernels": round(sum(per_iter_ms.values()), 4)}
+    if cpu:
+        from oracle import sr_oracle as O
+        from oracle import sr_oracle3d as O3
+        n = 96
+        fc, pc = synth.balls3d(n, n, n)
+        P = O.Params(**{k: v for k, v in PARAMS_3D.items() if k in O.Params.__dataclass_fields__})
+        g = O3.edge_map(fc.astype(np.float64), P.sigma, P.rho, P.s_exp)
+        st = O3.initial_state(pc.astype(np.float64))
+        c0 = time.perf_counter()
+        O3.sb_iteration(st, g, P)
+        c1 = time.perf_counter()
+        out["cpu_baseline"] = {"value": round(n ** 3 / 1e6 / (c1 - c0), 4), "unit": "MVox-it/s", "cores": 1,
+                               "kind": "oracle", "sample": f"1 outer iteration of the FP64 NumPy 3-D oracle on a "
+                                                           f"{n}^3 volume of the same kind ({c1 - c0:.1f} s)"}
+    return out
+
+
 def batch_bench(count, cap, tol):
     """Time-to-converge of `count` uneven instances: one sr_solve_batch call
     against sequential plain solves (sr_step with the same stop rule)."""
@@ -318,6 +377,8 @@ def main():
     ap.add_argument("--warmstart", type=int, default=0, metavar="N",
                     help="time-to-solve of N held-out instances, plain vs CNN warm start")
     ap.add_argument("--cnn-size", type=int, default=512)
+    ap.add_argument("--volume", type=int, default=0, metavar="S",
+                    help="3-D solver throughput on an S^3 volume (S a power of two, 8..256)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the solver runs on a single "
@@ -328,6 +389,11 @@ def main():
         return
     if args.batch:
         print(json.dumps(batch_bench(args.batch, 500, 1e-4)), flush=True)
+        return
+    if args.volume:
+        steps = args.steps if args.steps is not None else 20
+        print(json.dumps(volume_bench(args.volume, steps, min(args.warmup, 3), not args.no_cpu_baseline)),
+              flush=True)
         return
     if args.warmstart:
         print(json.dumps(warmstart_bench(args.warmstart)), flush=True)

@@ -1,0 +1,605 @@
+// 3-D Split Bregman solver of the Self-repelling Snake model: the 2-D method
+// with a third axis (the paper's volume application, Sec. 5, Fig. 6).  One
+// outer iteration (Algorithm 1) on an M x N x P volume, periodic:
+//   S x [ u = w h(phi_s) (3 components), the cube window as three separable
+//         passes (k, j, i), r = tau (N(phi_s) + mu div(b - w) + mu Lap phi_s)
+//         (eq 37 in increment form), the 3-D FFT solve (eqs 30-33):
+//         forward along k (real input), along j, along i with the division by
+//         the symbol and the inverse along i, inverse along j, inverse along
+//         k with phi_{s+1} = phi_s + Re / (M N P) ]
+//   then u = w^k h(phi^{k+1}) and the window again, and the w step: B of
+//   eq (41), the eq (42) gate and the projection of eq (40) (B / |B|), b of
+//   eq (23), per voxel.
+// Every kernel is a plain per-voxel or per-line kernel: this path is the
+// functional 3-D row; the 2-D kernels carry the tiling work.
+#include <hip/hip_ext.h>
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "sr3d.h"
+#include "sr_device.hpp"
+
+namespace sr {
+int api_fail(int code, const char* msg);
+}
+
+using sr::KParams;
+
+namespace {
+
+constexpr int kT = 256;   // threads of the per-voxel kernels
+constexpr int kLines = 8; // lines per workgroup of the FFT kernels
+
+struct Gauss3 {
+    float k[2 * sr::kMaxGaussR + 1];
+    int r;
+};
+
+__device__ __forceinline__ int wrp(int i, int n) { return i & (n - 1); }
+
+__device__ __forceinline__ size_t vox(int i, int j, int k, int N, int P) { return ((size_t)i * N + j) * P + k; }
+
+// One axis of the cube Gaussian (eq 1), periodic.
+__global__ __launch_bounds__(kT) void k3_gauss(const float* __restrict__ src, float* __restrict__ dst, int M, int N,
+                                               int P, int axis, Gauss3 t) {
+    const size_t v = (size_t)blockIdx.x * kT + threadIdx.x;
+    if (v >= (size_t)M * N * P) return;
+    const int k = (int)(v % P), j = (int)((v / P) % N), i = (int)(v / ((size_t)N * P));
+    float acc = 0.0f;
+    for (int q = -t.r; q <= t.r; ++q) {
+        const size_t o = axis == 0 ? vox(wrp(i + q, M), j, k, N, P)
+                                   : axis == 1 ? vox(i, wrp(j + q, N), k, N, P) : vox(i, j, wrp(k + q, P), N, P);
+        acc += t.k[q + t.r] * src[o];
+    }
+    dst[v] = acc;
+}
+
+// g = 1 / (1 + rho |grad fs|^s), central differences.
+__global__ __launch_bounds__(kT) void k3_edge(const float* __restrict__ fs, float* __restrict__ g, int M, int N, int P,
+                                              float rho, int s_exp) {
+    const size_t v = (size_t)blockIdx.x * kT + threadIdx.x;
+    if (v >= (size_t)M * N * P) return;
+    const int k = (int)(v % P), j = (int)((v / P) % N), i = (int)(v / ((size_t)N * P));
+    const float gx = 0.5f * (fs[vox(wrp(i + 1, M), j, k, N, P)] - fs[vox(wrp(i - 1, M), j, k, N, P)]);
+    const float gy = 0.5f * (fs[vox(i, wrp(j + 1, N), k, N, P)] - fs[vox(i, wrp(j - 1, N), k, N, P)]);
+    const float gz = 0.5f * (fs[vox(i, j, wrp(k + 1, P), N, P)] - fs[vox(i, j, wrp(k - 1, P), N, P)]);
+    const float m2 = gx * gx + gy * gy + gz * gz;
+    g[v] = 1.0f / (1.0f + rho * (s_exp == 2 ? m2 : sqrtf(m2)));
+}
+
+// phi^0, w^0 = grad phi^0 (forward differences), b^0 = 0.
+__global__ __launch_bounds__(kT) void k3_init(const float* __restrict__ phi0, float* __restrict__ phi,
+                                              float* __restrict__ W, float* __restrict__ B, int M, int N, int P) {
+    const size_t n = (size_t)M * N * P, v = (size_t)blockIdx.x * kT + threadIdx.x;
+    if (v >= n) return;
+    const int k = (int)(v % P), j = (int)((v / P) % N), i = (int)(v / ((size_t)N * P));
+    const float p = phi0[v];
+    phi[v] = p;
+    W[v] = phi0[vox(wrp(i + 1, M), j, k, N, P)] - p;
+    W[n + v] = phi0[vox(i, wrp(j + 1, N), k, N, P)] - p;
+    W[2 * n + v] = phi0[vox(i, j, wrp(k + 1, P), N, P)] - p;
+    B[v] = 0.0f;
+    B[n + v] = 0.0f;
+    B[2 * n + v] = 0.0f;
+}
+
+// u = w h(phi), three components.
+__global__ __launch_bounds__(kT) void k3_u(const float* __restrict__ W, const float* __restrict__ phi,
+                                           float* __restrict__ U, size_t n, KParams kp) {
+    const size_t v = (size_t)blockIdx.x * kT + threadIdx.x;
+    if (v >= n) return;
+    const float h = sr::band_h(phi[v], kp);
+    U[v] = W[v] * h;
+    U[n + v] = W[n + v] * h;
+    U[2 * n + v] = W[2 * n + v] * h;
+}
+
+// One axis of the cube window, three components: dst = sum_q a_q src(x + q e_axis).
+__global__ __launch_bounds__(kT) void k3_win(const float* __restrict__ src, float* __restrict__ dst, int M, int N,
+                                             int P, int axis, KParams kp) {
+    const size_t n = (size_t)M * N * P, v = (size_t)blockIdx.x * kT + threadIdx.x;
+    if (v >= n) return;
+    const int k = (int)(v % P), j = (int)((v / P) % N), i = (int)(v / ((size_t)N * P));
+    float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f;
+    for (int q = -kp.R; q <= kp.R; ++q) {
+        const size_t o = axis == 0 ? vox(wrp(i + q, M), j, k, N, P)
+                                   : axis == 1 ? vox(i, wrp(j + q, N), k, N, P) : vox(i, j, wrp(k + q, P), N, P);
+        const float a = kp.taps[q + kp.R];
+        a0 += a * src[o];
+        a1 += a * src[n + o];
+        a2 += a * src[2 * n + o];
+    }
+    dst[v] = a0;
+    dst[n + v] = a1;
+    dst[2 * n + v] = a2;
+}
+
+// r = tau (-gamma g |w| delta' + alpha g delta + 2 beta h' w.v + mu div(b - w) + mu Lap phi).
+__global__ __launch_bounds__(kT) void k3_rhs(const float* __restrict__ phi, const float* __restrict__ W,
+                                             const float* __restrict__ B, const float* __restrict__ g,
+                                             const float* __restrict__ V, float* __restrict__ r, int M, int N,
+                                             int P, KParams kp) {
+    const size_t n = (size_t)M * N * P, v = (size_t)blockIdx.x * kT + threadIdx.x;
+    if (v >= n) return;
+    const int k = (int)(v % P), j = (int)((v / P) % N), i = (int)(v / ((size_t)N * P));
+    const size_t oi = vox(wrp(i - 1, M), j, k, N, P), oj = vox(i, wrp(j - 1, N), k, N, P),
+                 ok = vox(i, j, wrp(k - 1, P), N, P);
+    const float p = phi[v];
+    const float lap = (phi[vox(wrp(i + 1, M), j, k, N, P)] + phi[oi]) + (phi[vox(i, wrp(j + 1, N), k, N, P)] + phi[oj]) +
+                      (phi[vox(i, j, wrp(k + 1, P), N, P)] + phi[ok]) - 6.0f * p;
+    const float w0 = W[v], w1 = W[n + v], w2 = W[2 * n + v];
+    const float dv = ((B[v] - w0) - (B[oi] - W[oi])) + ((B[n + v] - w1) - (B[n + oj] - W[n + oj])) +
+                     ((B[2 * n + v] - w2) - (B[2 * n + ok] - W[2 * n + ok]));
+    float dl, ddl, h, dh;
+    sr::dirac_d(p, kp, dl, ddl);
+    sr::band_h_dh(p, kp, h, dh);
+    const float gv = g[v];
+    const float wn = sqrtf(w0 * w0 + w1 * w1 + w2 * w2);
+    const float wv = w0 * V[v] + w1 * V[n + v] + w2 * V[2 * n + v];
+    const float force = -kp.gamma * gv * wn * ddl + kp.alpha * gv * dl + 2.0f * kp.beta * dh * wv;
+    r[v] = kp.tau * (force + kp.mu * dv + kp.mu * lap);
+}
+
+// w step: B = grad phi + b + (2 beta / mu) h v, gate (eq 42) and projection
+// (eq 40) as B / |B|, b += grad phi - w; in place.
+__global__ __launch_bounds__(kT) void k3_wstep(const float* __restrict__ phi, float* __restrict__ W,
+                                               float* __restrict__ B, const float* __restrict__ g,
+                                               const float* __restrict__ V, int M, int N, int P, KParams kp) {
+    const size_t n = (size_t)M * N * P, v = (size_t)blockIdx.x * kT + threadIdx.x;
+    if (v >= n) return;
+    const int k = (int)(v % P), j = (int)((v / P) % N), i = (int)(v / ((size_t)N * P));
+    const float p = phi[v];
+    const float G0 = phi[vox(wrp(i + 1, M), j, k, N, P)] - p;
+    const float G1 = phi[vox(i, wrp(j + 1, N), k, N, P)] - p;
+    const float G2 = phi[vox(i, j, wrp(k + 1, P), N, P)] - p;
+    const float h = sr::band_h(p, kp);
+    float H_, dl;
+    sr::heav_dirac(p, kp.eps, kp.inv_eps, H_, dl);
+    const float b0 = B[v], b1 = B[n + v], b2 = B[2 * n + v];
+    const float B0 = G0 + b0 + kp.c_rep * h * V[v];
+    const float B1 = G1 + b1 + kp.c_rep * h * V[n + v];
+    const float B2 = G2 + b2 + kp.c_rep * h * V[2 * n + v];
+    const float thr = kp.c_thr * g[v] * dl;
+    const float nb = sqrtf(B0 * B0 + B1 * B1 + B2 * B2);
+    float w0 = 0.0f, w1 = 0.0f, w2 = 0.0f;
+    if (nb > thr && nb > kp.zero_tol) { w0 = B0 / nb; w1 = B1 / nb; w2 = B2 / nb; }
+    W[v] = w0;
+    W[n + v] = w1;
+    W[2 * n + v] = w2;
+    B[v] = b0 + G0 - w0;
+    B[n + v] = b1 + G1 - w1;
+    B[2 * n + v] = b2 + G2 - w2;
+}
+
+// ---- FFT along one axis: kLines lines of length L per workgroup ----------
+// Radix-2 Stockham (self-sorting): stage Ns = 1, 2, ..., L/2; butterfly b
+// takes x[b] and x[b + L/2], twiddle W_L^{(b mod Ns) L / (2 Ns)} on the
+// second, writes y[(b div Ns) 2 Ns + b mod Ns] and that + Ns.
+// mode 0: forward, real input; 1: forward; 2: forward, divide by the
+// symbol of (1 - tau mu Lap), inverse; 3: inverse; 4: inverse, real output
+// out = add + scale Re.  Lines of axis 2 are contiguous; lines of axes 0
+// and 1 are strided, kLines neighbours along k share a workgroup.
+template <int L>
+__device__ float2* stockham(float2* a, float2* b, const float2* __restrict__ tw, bool inv, int g, int bt) {
+    float2* x = a;
+    float2* y = b;
+    for (int Ns = 1; Ns < L; Ns <<= 1) {
+        const float2 v0 = x[g * L + bt];
+        float2 v1 = x[g * L + bt + L / 2];
+        const int kk = bt & (Ns - 1);
+        float2 w = tw[kk * (L / (2 * Ns))];
+        if (inv) w.y = -w.y;
+        v1 = sr::cmul(v1, w);
+        const int d = ((bt - kk) << 1) + kk;
+        y[g * L + d] = sr::cadd(v0, v1);
+        y[g * L + d + Ns] = sr::csub(v0, v1);
+        __syncthreads();
+        float2* t = x;
+        x = y;
+        y = t;
+    }
+    return x;
+}
+
+template <int L>
+__global__ __launch_bounds__(1024) void k3_fft(const float* __restrict__ rin, float2* __restrict__ C,
+                                               float* __restrict__ rout, const float* __restrict__ radd,
+                                               const float2* __restrict__ twM, const float2* __restrict__ twN,
+                                               const float2* __restrict__ twP, int M, int N, int P, int axis,
+                                               int mode, float taumu, float scale) {
+    __shared__ float2 s0[kLines * L], s1[kLines * L];
+    const int tid = threadIdx.x;
+    const int line0 = blockIdx.x * kLines;
+    const float2* tw = axis == 0 ? twM : axis == 1 ? twN : twP;
+    // element e of the block -> (line g, position n) and its address
+    auto addr = [&](int e, int& g, int& pos) -> size_t {
+        if (axis == 2) {
+            g = e / L;
+            pos = e - g * L;
+            return (size_t)(line0 + g) * P + pos;
+        }
+        pos = e / kLines;
+        g = e - pos * kLines;
+        const int l = line0 + g;
+        if (axis == 1) return (size_t)(l / P) * N * P + (size_t)pos * P + (l % P);
+        return (size_t)pos * N * P + l;
+    };
+    constexpr int T = kLines * L / 2;
+    for (int m = 0; m < 2; ++m) {
+        const int e = tid + m * T;
+        int g, pos;
+        const size_t o = addr(e, g, pos);
+        s0[g * L + pos] = mode == 0 ? make_float2(rin[o], 0.0f) : C[o];
+    }
+    __syncthreads();
+    const int g = tid / (L / 2), bt = tid - g * (L / 2);
+    float2* res = stockham<L>(s0, s1, tw, mode >= 3, g, bt);
+    if (mode == 2) {
+        // line l = j P + k holds frequencies (n, j, k): symbol
+        // 1 + tau mu (6 - 2 cos(2 pi n / M) - 2 cos(2 pi j / N) - 2 cos(2 pi k / P))
+        float2* other = res == s0 ? s1 : s0;
+        for (int m = 0; m < 2; ++m) {
+            const int e = tid + m * T;
+            const int pos = e / kLines, gg = e - pos * kLines;
+            const int l = line0 + gg;
+            const float cs = twM[pos].x + twN[l / P].x + twP[l % P].x;
+            const float sym = 1.0f + taumu * (6.0f - 2.0f * cs);
+            const float2 z = res[gg * L + pos];
+            res[gg * L + pos] = make_float2(z.x / sym, z.y / sym);
+        }
+        __syncthreads();
+        res = stockham<L>(res, other, tw, true, g, bt);
+    }
+    for (int m = 0; m < 2; ++m) {
+        const int e = tid + m * T;
+        int gg, pos;
+        const size_t o = addr(e, gg, pos);
+        const float2 z = res[gg * L + pos];
+        if (mode == 4)
+            rout[o] = radd[o] + scale * z.x;
+        else
+            C[o] = z;
+    }
+}
+
+std::vector<float2> host_twiddles(int L) {
+    std::vector<float2> t(L);
+    const double two_pi = 6.283185307179586476925286766559;
+    for (int n = 0; n < L; ++n) {
+        const double a = two_pi * (double)n / (double)L;
+        t[n] = make_float2((float)std::cos(a), (float)-std::sin(a));
+    }
+    return t;
+}
+
+bool pow2_in(int x) { return x >= 8 && x <= 256 && (x & (x - 1)) == 0; }
+
+struct Layout3 {
+    size_t g, pa, pb, W, B, U, T, R, C, twM, twN, twP, total;
+};
+
+Layout3 layout3(int M, int N, int P) {
+    Layout3 L{};
+    const size_t n = (size_t)M * N * P, pl = sizeof(float) * n;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o = (o + bytes + 255) & ~size_t(255); return at; };
+    L.g = take(pl);
+    L.pa = take(pl);
+    L.pb = take(pl);
+    L.W = take(3 * pl);
+    L.B = take(3 * pl);
+    L.U = take(3 * pl);
+    L.T = take(3 * pl);
+    L.R = take(pl);
+    L.C = take(2 * pl);
+    L.twM = take(sizeof(float2) * M);
+    L.twN = take(sizeof(float2) * N);
+    L.twP = take(sizeof(float2) * P);
+    L.total = o;
+    return L;
+}
+
+// Events of the launch being timed by sr3_profile (null: plain launch).
+thread_local hipEvent_t t_ev[2] = {nullptr, nullptr};
+
+template <typename... KArgs, typename... Args>
+void launch(void (*kernel)(KArgs...), dim3 grid, dim3 block, hipStream_t st, Args... args) {
+    if (t_ev[0])
+        hipExtLaunchKernelGGL(kernel, grid, block, 0, st, t_ev[0], t_ev[1], 0u, static_cast<KArgs>(args)...);
+    else
+        hipLaunchKernelGGL(kernel, grid, block, 0, st, static_cast<KArgs>(args)...);
+}
+
+}  // namespace
+
+struct sr3_ctx {
+    int M, N, P;
+    size_t n;
+    sr_params p;
+    KParams kp;
+    Gauss3 gauss;
+    hipStream_t st;
+    float *g, *phi, *alt, *W, *B, *U, *T, *R;
+    float2 *C, *twM, *twN, *twP;
+    float taumu;
+    long long k = 0;
+    bool image = false;
+    // sr3_profile: per-kind hooks (kind -> events armed before the launch)
+    std::vector<hipEvent_t>* prof_ev = nullptr;
+    std::vector<int>* prof_kind = nullptr;
+};
+
+namespace {
+
+void arm(sr3_ctx* c, int kind) {
+    if (!c->prof_ev) return;
+    hipEvent_t a, b;
+    (void)hipEventCreate(&a);
+    (void)hipEventCreate(&b);
+    c->prof_ev->push_back(a);
+    c->prof_ev->push_back(b);
+    c->prof_kind->push_back(kind);
+    t_ev[0] = a;
+    t_ev[1] = b;
+}
+
+void disarm() { t_ev[0] = t_ev[1] = nullptr; }
+
+unsigned vblocks(size_t n) { return (unsigned)((n + kT - 1) / kT); }
+
+template <int L>
+void fft_pass_t(sr3_ctx* c, int axis, int mode, const float* rin, float* rout, const float* radd) {
+    const int lines = (int)(c->n / L);
+    const float scale = 1.0f / (float)c->n;
+    launch(k3_fft<L>, dim3(lines / kLines), dim3(kLines * L / 2), c->st, rin, c->C, rout, radd, c->twM, c->twN,
+           c->twP, c->M, c->N, c->P, axis, mode, c->taumu, scale);
+}
+
+}  // namespace
+
+namespace {
+
+void fft_pass(sr3_ctx* c, int axis, int mode, const float* rin, float* rout, const float* radd) {
+    arm(c, 2);
+    const int L = axis == 0 ? c->M : axis == 1 ? c->N : c->P;
+    switch (L) {
+        case 8: fft_pass_t<8>(c, axis, mode, rin, rout, radd); break;
+        case 16: fft_pass_t<16>(c, axis, mode, rin, rout, radd); break;
+        case 32: fft_pass_t<32>(c, axis, mode, rin, rout, radd); break;
+        case 64: fft_pass_t<64>(c, axis, mode, rin, rout, radd); break;
+        case 128: fft_pass_t<128>(c, axis, mode, rin, rout, radd); break;
+        default: fft_pass_t<256>(c, axis, mode, rin, rout, radd); break;
+    }
+    disarm();
+}
+
+// phi_out = phi_in + u with (1 - tau mu Lap) u = r.
+void solve(sr3_ctx* c, const float* r, const float* phi_in, float* phi_out) {
+    fft_pass(c, 2, 0, r, nullptr, nullptr);
+    fft_pass(c, 1, 1, nullptr, nullptr, nullptr);
+    fft_pass(c, 0, 2, nullptr, nullptr, nullptr);
+    fft_pass(c, 1, 3, nullptr, nullptr, nullptr);
+    fft_pass(c, 2, 4, nullptr, phi_out, phi_in);
+}
+
+// V (in T) = cube window of u = W h(phi).
+void window(sr3_ctx* c, const float* phi) {
+    const unsigned nb = vblocks(c->n);
+    arm(c, 0);
+    launch(k3_u, dim3(nb), dim3(kT), c->st, c->W, phi, c->U, c->n, c->kp);
+    disarm();
+    arm(c, 0);
+    launch(k3_win, dim3(nb), dim3(kT), c->st, c->U, c->T, c->M, c->N, c->P, 2, c->kp);
+    disarm();
+    arm(c, 0);
+    launch(k3_win, dim3(nb), dim3(kT), c->st, c->T, c->U, c->M, c->N, c->P, 1, c->kp);
+    disarm();
+    arm(c, 0);
+    launch(k3_win, dim3(nb), dim3(kT), c->st, c->U, c->T, c->M, c->N, c->P, 0, c->kp);
+    disarm();
+}
+
+void iteration(sr3_ctx* c) {
+    const unsigned nb = vblocks(c->n);
+    for (int s = 0; s < c->p.S; ++s) {
+        window(c, c->phi);
+        arm(c, 1);
+        launch(k3_rhs, dim3(nb), dim3(kT), c->st, c->phi, c->W, c->B, c->g, c->T, c->R, c->M, c->N, c->P, c->kp);
+        disarm();
+        solve(c, c->R, c->phi, c->alt);
+        float* t = c->phi;
+        c->phi = c->alt;
+        c->alt = t;
+    }
+    window(c, c->phi);
+    arm(c, 3);
+    launch(k3_wstep, dim3(nb), dim3(kT), c->st, c->phi, c->W, c->B, c->g, c->T, c->M, c->N, c->P, c->kp);
+    disarm();
+    ++c->k;
+}
+
+int check_params(int M, int N, int P, const sr_params* p) {
+    if (!p) return sr::api_fail(SR_EINVAL, "NULL params");
+    if (!pow2_in(M) || !pow2_in(N) || !pow2_in(P))
+        return sr::api_fail(SR_EUNSUPPORTED, "3-D volumes need M, N, P powers of two in [8, 256]");
+    if (p->R < 0 || p->R > sr::kMaxR) return sr::api_fail(SR_EUNSUPPORTED, "R must be in [0, 8]");
+    if ((int)std::ceil(3.0 * p->sigma) > sr::kMaxGaussR || p->sigma < 0)
+        return sr::api_fail(SR_EUNSUPPORTED, "sigma must be in [0, 16/3]");
+    if (p->tau <= 0 || p->mu <= 0 || p->eps <= 0 || p->d <= 0 || p->S < 1)
+        return sr::api_fail(SR_EINVAL, "tau, mu, eps, d must be > 0 and S >= 1");
+    if (p->s_exp != 1 && p->s_exp != 2) return sr::api_fail(SR_EINVAL, "s_exp must be 1 or 2");
+    if (p->tol_inner > 0 || p->w_solver != 0 || p->phi_solver != 0 || p->bc != 0 || p->w0_mode != 0)
+        return sr::api_fail(SR_EUNSUPPORTED, "the 3-D solver runs a fixed S with the shrink w solver, the FFT "
+                                             "solve, periodic boundaries and w^0 = grad phi^0");
+    return SR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sr3_workspace_size(int32_t M, int32_t N, int32_t P, const sr_params* p, size_t* bytes) {
+    if (!bytes) return sr::api_fail(SR_EINVAL, "NULL bytes");
+    const int rc = check_params(M, N, P, p);
+    if (rc) return rc;
+    *bytes = layout3(M, N, P).total;
+    return SR_OK;
+}
+
+int sr3_create(sr3_ctx** out, int32_t M, int32_t N, int32_t P, const sr_params* p, void* workspace, size_t bytes,
+               void* hip_stream) {
+    if (!out || !workspace) return sr::api_fail(SR_EINVAL, "NULL argument");
+    const int rc = check_params(M, N, P, p);
+    if (rc) return rc;
+    const Layout3 L = layout3(M, N, P);
+    if (bytes < L.total) return sr::api_fail(SR_EINVAL, "workspace too small");
+    if ((uintptr_t)workspace & 255) return sr::api_fail(SR_EINVAL, "workspace must be 256-byte aligned");
+    sr3_ctx* c = new sr3_ctx();
+    c->M = M;
+    c->N = N;
+    c->P = P;
+    c->n = (size_t)M * N * P;
+    c->p = *p;
+    c->st = (hipStream_t)hip_stream;
+    KParams& kp = c->kp;
+    std::memset(&kp, 0, sizeof kp);
+    kp.gamma = (float)p->gamma;
+    kp.alpha = (float)p->alpha;
+    kp.beta = (float)p->beta;
+    kp.mu = (float)p->mu;
+    kp.tau = (float)p->tau;
+    kp.eps = (float)p->eps;
+    kp.inv_eps = (float)(1.0 / p->eps);
+    kp.band_l = (float)p->band_l;
+    kp.c_rep = (float)(2.0 * p->beta / p->mu);
+    kp.c_thr = (float)(p->gamma / p->mu);
+    kp.zero_tol = (float)p->zero_tol;
+    kp.R = p->R;
+    for (int q = -p->R; q <= p->R; ++q) kp.taps[q + p->R] = (float)std::exp(-(double)q * q / (p->d * p->d));
+    c->taumu = (float)(p->tau * p->mu);
+    // Gaussian taps of eq (1): sampled, truncated at ceil(3 sigma), unit sum
+    const int r = (int)std::ceil(3.0 * p->sigma);
+    c->gauss.r = r;
+    {
+        std::vector<double> kd(2 * r + 1);
+        double sum = 0.0;
+        for (int t = -r; t <= r; ++t) {
+            kd[t + r] = r == 0 ? 1.0 : std::exp(-(double)t * t / (2.0 * p->sigma * p->sigma));
+            sum += kd[t + r];
+        }
+        for (int t = 0; t <= 2 * r; ++t) c->gauss.k[t] = (float)(kd[t] / sum);
+    }
+    char* base = (char*)workspace;
+    c->g = (float*)(base + L.g);
+    c->phi = (float*)(base + L.pa);
+    c->alt = (float*)(base + L.pb);
+    c->W = (float*)(base + L.W);
+    c->B = (float*)(base + L.B);
+    c->U = (float*)(base + L.U);
+    c->T = (float*)(base + L.T);
+    c->R = (float*)(base + L.R);
+    c->C = (float2*)(base + L.C);
+    c->twM = (float2*)(base + L.twM);
+    c->twN = (float2*)(base + L.twN);
+    c->twP = (float2*)(base + L.twP);
+    const std::vector<float2> a = host_twiddles(M), b = host_twiddles(N), d = host_twiddles(P);
+    hipError_t e = hipMemcpyAsync(c->twM, a.data(), sizeof(float2) * M, hipMemcpyHostToDevice, c->st);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->twN, b.data(), sizeof(float2) * N, hipMemcpyHostToDevice, c->st);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->twP, d.data(), sizeof(float2) * P, hipMemcpyHostToDevice, c->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+    if (e != hipSuccess) {
+        delete c;
+        return sr::api_fail(SR_EHIP, hipGetErrorString(e));
+    }
+    *out = c;
+    return SR_OK;
+}
+
+int sr3_set_image(sr3_ctx* c, const float* f, const float* phi0) {
+    if (!c || !f || !phi0) return sr::api_fail(SR_EINVAL, "NULL argument");
+    const unsigned nb = vblocks(c->n);
+    // cube Gaussian: along k (f -> U), j (U -> T), i (T -> U), then g
+    hipLaunchKernelGGL(k3_gauss, dim3(nb), dim3(kT), 0, c->st, f, c->U, c->M, c->N, c->P, 2, c->gauss);
+    hipLaunchKernelGGL(k3_gauss, dim3(nb), dim3(kT), 0, c->st, c->U, c->T, c->M, c->N, c->P, 1, c->gauss);
+    hipLaunchKernelGGL(k3_gauss, dim3(nb), dim3(kT), 0, c->st, c->T, c->U, c->M, c->N, c->P, 0, c->gauss);
+    hipLaunchKernelGGL(k3_edge, dim3(nb), dim3(kT), 0, c->st, c->U, c->g, c->M, c->N, c->P, (float)c->p.rho,
+                       c->p.s_exp);
+    hipLaunchKernelGGL(k3_init, dim3(nb), dim3(kT), 0, c->st, phi0, c->phi, c->W, c->B, c->M, c->N, c->P);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return sr::api_fail(SR_EHIP, hipGetErrorString(e));
+    c->k = 0;
+    c->image = true;
+    return SR_OK;
+}
+
+int sr3_set_state(sr3_ctx* c, const float* phi, const float* w, const float* b, int64_t k) {
+    if (!c || !phi || !w || !b) return sr::api_fail(SR_EINVAL, "NULL argument");
+    if (!c->image) return sr::api_fail(SR_ESTATE, "sr3_set_image first (it computes g)");
+    const size_t pl = sizeof(float) * c->n;
+    hipError_t e = hipMemcpyAsync(c->phi, phi, pl, hipMemcpyDeviceToDevice, c->st);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->W, w, 3 * pl, hipMemcpyDeviceToDevice, c->st);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->B, b, 3 * pl, hipMemcpyDeviceToDevice, c->st);
+    if (e != hipSuccess) return sr::api_fail(SR_EHIP, hipGetErrorString(e));
+    c->k = k;
+    return SR_OK;
+}
+
+int sr3_step(sr3_ctx* c, int32_t n_iter, int64_t* k_out) {
+    if (!c) return sr::api_fail(SR_EINVAL, "NULL context");
+    if (n_iter < 1) return sr::api_fail(SR_EINVAL, "n_iter must be >= 1");
+    if (!c->image) return sr::api_fail(SR_ESTATE, "sr3_set_image first");
+    for (int it = 0; it < n_iter; ++it) iteration(c);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+    if (e != hipSuccess) return sr::api_fail(SR_EHIP, hipGetErrorString(e));
+    if (k_out) *k_out = c->k;
+    return SR_OK;
+}
+
+int sr3_get_state(sr3_ctx* c, float* phi, float* w, float* b, float* g) {
+    if (!c) return sr::api_fail(SR_EINVAL, "NULL context");
+    const size_t pl = sizeof(float) * c->n;
+    hipError_t e = hipSuccess;
+    if (phi) e = hipMemcpyAsync(phi, c->phi, pl, hipMemcpyDeviceToDevice, c->st);
+    if (e == hipSuccess && w) e = hipMemcpyAsync(w, c->W, 3 * pl, hipMemcpyDeviceToDevice, c->st);
+    if (e == hipSuccess && b) e = hipMemcpyAsync(b, c->B, 3 * pl, hipMemcpyDeviceToDevice, c->st);
+    if (e == hipSuccess && g) e = hipMemcpyAsync(g, c->g, pl, hipMemcpyDeviceToDevice, c->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+    if (e != hipSuccess) return sr::api_fail(SR_EHIP, hipGetErrorString(e));
+    return SR_OK;
+}
+
+int sr3_profile(sr3_ctx* c, int32_t n_iter, double ms[4], int64_t count[4]) {
+    if (!c || !ms || !count) return sr::api_fail(SR_EINVAL, "NULL argument");
+    if (n_iter < 1) return sr::api_fail(SR_EINVAL, "n_iter must be >= 1");
+    if (!c->image) return sr::api_fail(SR_ESTATE, "sr3_set_image first");
+    std::vector<hipEvent_t> ev;
+    std::vector<int> kind;
+    c->prof_ev = &ev;
+    c->prof_kind = &kind;
+    for (int it = 0; it < n_iter; ++it) iteration(c);
+    c->prof_ev = nullptr;
+    c->prof_kind = nullptr;
+    hipError_t e = hipStreamSynchronize(c->st);
+    for (int q = 0; q < 4; ++q) { ms[q] = 0.0; count[q] = 0; }
+    for (size_t q = 0; q < kind.size() && e == hipSuccess; ++q) {
+        float t = 0.0f;
+        e = hipEventElapsedTime(&t, ev[2 * q], ev[2 * q + 1]);
+        ms[kind[q]] += t;
+        count[kind[q]] += 1;
+    }
+    for (hipEvent_t h : ev) (void)hipEventDestroy(h);
+    if (e != hipSuccess) return sr::api_fail(SR_EHIP, hipGetErrorString(e));
+    for (int q = 0; q < 4; ++q)
+        if (count[q]) ms[q] /= (double)count[q];
+    return SR_OK;
+}
+
+void sr3_destroy(sr3_ctx* c) { delete c; }
+
+}  // extern "C"

@@ -44,6 +44,15 @@ static int fail(int code, const char* fmt, ...) {
     return code;
 }
 
+// The error text of the 3-D entry points (sr3d.hip) goes to the same
+// thread-local string that sr_last_error() returns.
+namespace sr {
+int api_fail(int code, const char* msg) {
+    g_err = msg;
+    return code;
+}
+}  // namespace sr
+
 #define HIP_TRY(expr)                                                                       \
     do {                                                                                    \
         hipError_t e_ = (expr);                                                             \

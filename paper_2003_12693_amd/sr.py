@@ -106,6 +106,14 @@ def load(path=LIB_PATH):
         "sr_autotune": (C.c_int, [P, I, C.POINTER(I), C.POINTER(D)]),
         "sr_destroy": (None, [P]),
         "sr_last_error": (C.c_char_p, []),
+        "sr3_workspace_size": (C.c_int, [I, I, I, C.POINTER(sr_params), C.POINTER(C.c_size_t)]),
+        "sr3_create": (C.c_int, [C.POINTER(P), I, I, I, C.POINTER(sr_params), P, C.c_size_t, P]),
+        "sr3_set_image": (C.c_int, [P, P, P]),
+        "sr3_set_state": (C.c_int, [P, P, P, P, C.c_int64]),
+        "sr3_step": (C.c_int, [P, I, C.POINTER(C.c_int64)]),
+        "sr3_get_state": (C.c_int, [P, P, P, P, P]),
+        "sr3_profile": (C.c_int, [P, I, C.POINTER(D), C.POINTER(C.c_int64)]),
+        "sr3_destroy": (None, [P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -381,3 +389,103 @@ def solve_batch(items, stream=None):
     res = [{"phi": outs[i], "iters": cs[i].iters, "status": cs[i].status, "r_last": cs[i].r_last,
             "energy": cs[i].energy} for i in range(len(cs))]
     return rc, res
+
+
+# ---------------------------------------------------------------------------
+# 3-D solver (include/sr3d.h); device tensors only
+# ---------------------------------------------------------------------------
+KERNEL_KINDS_3D = ("window", "rhs", "fft", "w_step")
+
+
+def _dev(x):
+    import torch
+    if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float32 and x.is_contiguous()):
+        raise ValueError("the 3-D entry points take contiguous float32 GPU tensors")
+    return x.data_ptr()
+
+
+def sr3_workspace_size(M, N, P, params):
+    n = C.c_size_t()
+    _check(load().sr3_workspace_size(M, N, P, C.byref(params), C.byref(n)))
+    return n.value
+
+
+def sr3_create(M, N, P, params, workspace, stream=None):
+    ctx = C.c_void_p()
+    st = stream.cuda_stream if stream is not None else None
+    _check(load().sr3_create(C.byref(ctx), M, N, P, C.byref(params), workspace.data_ptr(), workspace.numel(), st))
+    return ctx
+
+
+def sr3_set_image(ctx, f, phi0):
+    _check(load().sr3_set_image(ctx, _dev(f), _dev(phi0)))
+
+
+def sr3_set_state(ctx, phi, w, b, k):
+    _check(load().sr3_set_state(ctx, _dev(phi), _dev(w), _dev(b), int(k)))
+
+
+def sr3_step(ctx, n_iter):
+    k = C.c_int64()
+    _check(load().sr3_step(ctx, n_iter, C.byref(k)))
+    return k.value
+
+
+def sr3_get_state(ctx, phi=None, w=None, b=None, g=None):
+    ptr = lambda x: _dev(x) if x is not None else None
+    _check(load().sr3_get_state(ctx, ptr(phi), ptr(w), ptr(b), ptr(g)))
+
+
+def sr3_profile(ctx, n_iter):
+    ms = (C.c_double * 4)()
+    cnt = (C.c_int64 * 4)()
+    _check(load().sr3_profile(ctx, n_iter, ms, cnt))
+    return {k: (ms[i], cnt[i]) for i, k in enumerate(KERNEL_KINDS_3D)}
+
+
+def sr3_destroy(ctx):
+    if ctx:
+        load().sr3_destroy(ctx)
+
+
+class Solver3D:
+    """One M x N x P volume: owns the workspace tensor and the context."""
+
+    def __init__(self, M, N, P, params=None, device="cuda", stream=None, **overrides):
+        import torch
+        self.shape = (M, N, P)
+        self.params = params if params is not None else sr_params_default(**overrides)
+        nbytes = sr3_workspace_size(M, N, P, self.params)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        off = (-self.workspace.data_ptr()) % 256
+        self._ws = self.workspace[off:off + nbytes]
+        self.ctx = sr3_create(M, N, P, self.params, self._ws, stream)
+
+    def close(self):
+        if self.ctx:
+            sr3_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _empty(self, *lead):
+        import torch
+        return torch.empty(*lead, *self.shape, dtype=torch.float32, device=self.workspace.device)
+
+    def set_image(self, f, phi0):
+        sr3_set_image(self.ctx, f, phi0)
+
+    def set_state(self, phi, w, b, k):
+        sr3_set_state(self.ctx, phi, w, b, k)
+
+    def step(self, n):
+        return sr3_step(self.ctx, n)
+
+    def get_state(self):
+        phi, w, b, g = self._empty(), self._empty(3), self._empty(3), self._empty()
+        sr3_get_state(self.ctx, phi, w, b, g)
+        return phi, w, b, g

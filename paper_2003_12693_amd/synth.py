@@ -258,3 +258,47 @@ def batch_items(count=256, size_seed=4999, seed0=4000):
         f, phi0 = ellipses(M, N, seed=seed0 + k, n_shapes=n, axis_lo=lo, axis_hi=hi)
         items.append((M, N, R, f, phi0))
     return items
+
+
+# --------------------------------------------------------------------------
+# volumes for the 3-D solver: touching balls (a stand-in for the paper's CT
+# volume, which is not available)
+# --------------------------------------------------------------------------
+def balls3d(M=128, N=128, P=128, seed=6, n_balls=6, r_lo=0.08, r_hi=0.16, noise=0.15, bias=0.2, inset=0.08):
+    """f: n_balls balls of radius r_lo..r_hi (fractions of the smallest side),
+    centres drawn so that neighbours nearly touch (gaps of 1-4 voxels where
+    the draw allows), intensity 1 inside, `bias` background, Gaussian noise;
+    phi0: signed distance to the box inset by `inset` of each side (negative
+    inside), the initial contour enclosing every ball."""
+    rng = _rng(seed)
+    s = float(min(M, N, P))
+    i = np.arange(M, dtype=np.float64)[:, None, None]
+    j = np.arange(N, dtype=np.float64)[None, :, None]
+    k = np.arange(P, dtype=np.float64)[None, None, :]
+    lo = np.array([inset * M, inset * N, inset * P]) + r_hi * s + 2
+    hi = np.array([M, N, P]) - lo
+    balls = []
+    for _ in range(200):
+        if len(balls) == n_balls:
+            break
+        r = rng.uniform(r_lo, r_hi) * s
+        if balls and rng.uniform() < 0.7:       # next to an earlier ball, a small gap apart
+            c0, r0 = balls[rng.integers(len(balls))]
+            u = rng.normal(size=3)
+            u /= np.linalg.norm(u)
+            c = c0 + u * (r0 + r + rng.uniform(1.0, 4.0))
+        else:
+            c = rng.uniform(lo, hi)
+        if np.any(c < lo) or np.any(c > hi):
+            continue
+        if any(np.linalg.norm(c - c1) < r + r1 + 1.0 for c1, r1 in balls):
+            continue
+        balls.append((c, r))
+    f = np.full((M, N, P), bias)
+    for c, r in balls:
+        f[(i - c[0]) ** 2 + (j - c[1]) ** 2 + (k - c[2]) ** 2 <= r * r] = 1.0
+    f = f + noise * rng.normal(size=(M, N, P))
+    d = [np.maximum(inset * n - x, x - (n - 1 - inset * n)) for x, n in ((i, M), (j, N), (k, P))]
+    outside = np.sqrt(sum(np.maximum(a, 0.0) ** 2 for a in d))
+    inside = np.minimum(np.maximum(np.maximum(d[0], d[1]), d[2]), 0.0)
+    return f.astype(np.float32), (outside + inside).astype(np.float32)

@@ -187,3 +187,23 @@ def test_boundary_parameter(sr):
     assert sr.sr_workspace_size(64, 64, sr.sr_params_default(bc=1, phi_solver=1)) == base
     assert sr.sr_workspace_size(64, 64, sr.sr_params_default(bc=1)) >= base + 3 * 4 * 64 * 64 * 4
     assert sr.sr_workspace_size(2048, 2048, sr.sr_params_default(bc=1)) > 0
+
+
+def test_every_3d_symbol_is_exported_and_validated(sr):
+    """include/sr3d.h: every declared entry point is exported, and the size
+    and parameter checks run before any HIP call."""
+    text = open(os.path.join(ROOT, "include", "sr3d.h")).read()
+    names = sorted(set(re.findall(r"^(?:int|void)\s+(sr3_\w+)\s*\(", text, re.M)))
+    assert len(names) == 8
+    out = subprocess.run(["nm", "-D", "--defined-only", sr.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\sT\s(sr3_\w+)$", out, re.M))
+    assert not [n for n in names if n not in exported]
+    p = sr.sr_params_default()
+    n = sr.sr3_workspace_size(32, 16, 64, p)
+    assert n >= 4 * 32 * 16 * 64 * 18
+    for shape, kw in (((4, 16, 16), {}), ((16, 16, 512), {}), ((16, 24, 16), {}), ((16, 16, 16), dict(bc=1)),
+                      ((16, 16, 16), dict(phi_solver=1)), ((16, 16, 16), dict(tol_inner=1e-3)),
+                      ((16, 16, 16), dict(R=9))):
+        with pytest.raises(sr.SRError) as e:
+            sr.sr3_workspace_size(*shape, sr.sr_params_default(**kw))
+        assert e.value.code in (sr.SR_EUNSUPPORTED, sr.SR_EINVAL)
