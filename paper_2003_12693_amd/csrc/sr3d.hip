@@ -33,7 +33,8 @@ using sr::KParams;
 namespace {
 
 constexpr int kT = 256;   // threads of the per-voxel kernels
-constexpr int kLines = 8; // lines per workgroup of the FFT kernels
+constexpr int kLines = 8;          // lines per workgroup of the FFT along k (contiguous)
+constexpr int kStridedLines = 16;  // lines per workgroup of the FFTs along i and j (strided)
 
 struct Gauss3 {
     float k[2 * sr::kMaxGaussR + 1];
@@ -176,28 +177,46 @@ __global__ __launch_bounds__(kT) void k3_wstep(const float* __restrict__ phi, fl
     B[2 * n + v] = b2 + G2 - w2;
 }
 
-// ---- FFT along one axis: kLines lines of length L per workgroup ----------
+// ---- FFT along one axis: G lines of length L per workgroup ---------------
 // Radix-2 Stockham (self-sorting): stage Ns = 1, 2, ..., L/2; butterfly b
 // takes x[b] and x[b + L/2], twiddle W_L^{(b mod Ns) L / (2 Ns)} on the
-// second, writes y[(b div Ns) 2 Ns + b mod Ns] and that + Ns.
+// second, writes y[(b div Ns) 2 Ns + b mod Ns] and that + Ns.  A thread
+// runs NB butterflies of the block per stage.
 // mode 0: forward, real input; 1: forward; 2: forward, divide by the
 // symbol of (1 - tau mu Lap), inverse; 3: inverse; 4: inverse, real output
-// out = add + scale Re.  Lines of axis 2 are contiguous; lines of axes 0
-// and 1 are strided, kLines neighbours along k share a workgroup.
-template <int L>
-__device__ float2* stockham(float2* a, float2* b, const float2* __restrict__ tw, bool inv, int g, int bt) {
+// out = add + scale Re.  Lines of axis 2 are contiguous (G = 8 per
+// workgroup); lines of axes 0 and 1 are strided, and G = 32 neighbours
+// along k share a workgroup so that each load and store touches 256-byte
+// runs.
+constexpr int fft3_threads(int L, int G) { return G * L / 2 < 1024 ? G * L / 2 : 1024; }
+
+template <int L, int G>
+struct FftShape3 {
+    static constexpr int BF = G * L / 2;                    // butterflies per stage
+    static constexpr int T = BF < 1024 ? BF : 1024;          // threads
+    static constexpr int NB = BF / T;                        // butterflies per thread
+};
+
+template <int L, int G>
+__device__ float2* stockham(float2* a, float2* b, const float2* __restrict__ tw, bool inv) {
+    using S = FftShape3<L, G>;
     float2* x = a;
     float2* y = b;
     for (int Ns = 1; Ns < L; Ns <<= 1) {
-        const float2 v0 = x[g * L + bt];
-        float2 v1 = x[g * L + bt + L / 2];
-        const int kk = bt & (Ns - 1);
-        float2 w = tw[kk * (L / (2 * Ns))];
-        if (inv) w.y = -w.y;
-        v1 = sr::cmul(v1, w);
-        const int d = ((bt - kk) << 1) + kk;
-        y[g * L + d] = sr::cadd(v0, v1);
-        y[g * L + d + Ns] = sr::csub(v0, v1);
+#pragma unroll
+        for (int q = 0; q < S::NB; ++q) {
+            const int u = threadIdx.x + q * S::T;
+            const int g = u / (L / 2), bt = u - g * (L / 2);
+            const float2 v0 = x[g * L + bt];
+            float2 v1 = x[g * L + bt + L / 2];
+            const int kk = bt & (Ns - 1);
+            float2 w = tw[kk * (L / (2 * Ns))];
+            if (inv) w.y = -w.y;
+            v1 = sr::cmul(v1, w);
+            const int d = ((bt - kk) << 1) + kk;
+            y[g * L + d] = sr::cadd(v0, v1);
+            y[g * L + d + Ns] = sr::csub(v0, v1);
+        }
         __syncthreads();
         float2* t = x;
         x = y;
@@ -206,15 +225,19 @@ __device__ float2* stockham(float2* a, float2* b, const float2* __restrict__ tw,
     return x;
 }
 
-template <int L>
-__global__ __launch_bounds__(1024) void k3_fft(const float* __restrict__ rin, float2* __restrict__ C,
-                                               float* __restrict__ rout, const float* __restrict__ radd,
-                                               const float2* __restrict__ twM, const float2* __restrict__ twN,
-                                               const float2* __restrict__ twP, int M, int N, int P, int axis,
-                                               int mode, float taumu, float scale) {
-    __shared__ float2 s0[kLines * L], s1[kLines * L];
+template <int L, int G>
+__global__ __launch_bounds__(fft3_threads(L, G)) void k3_fft(const float* __restrict__ rin, float2* __restrict__ C,
+                                                             float* __restrict__ rout, const float* __restrict__ radd,
+                                                             const float2* __restrict__ twM,
+                                                             const float2* __restrict__ twN,
+                                                             const float2* __restrict__ twP, int M, int N, int P,
+                                                             int axis, int mode, float taumu, float scale) {
+    using S = FftShape3<L, G>;
+    extern __shared__ float2 lds3[];
+    float2* s0 = lds3;
+    float2* s1 = lds3 + G * L;
     const int tid = threadIdx.x;
-    const int line0 = blockIdx.x * kLines;
+    const int line0 = blockIdx.x * G;
     const float2* tw = axis == 0 ? twM : axis == 1 ? twN : twP;
     // element e of the block -> (line g, position n) and its address
     auto addr = [&](int e, int& g, int& pos) -> size_t {
@@ -223,29 +246,29 @@ __global__ __launch_bounds__(1024) void k3_fft(const float* __restrict__ rin, fl
             pos = e - g * L;
             return (size_t)(line0 + g) * P + pos;
         }
-        pos = e / kLines;
-        g = e - pos * kLines;
+        pos = e / G;
+        g = e - pos * G;
         const int l = line0 + g;
         if (axis == 1) return (size_t)(l / P) * N * P + (size_t)pos * P + (l % P);
         return (size_t)pos * N * P + l;
     };
-    constexpr int T = kLines * L / 2;
-    for (int m = 0; m < 2; ++m) {
-        const int e = tid + m * T;
+#pragma unroll
+    for (int m = 0; m < 2 * S::NB; ++m) {
+        const int e = tid + m * S::T;
         int g, pos;
         const size_t o = addr(e, g, pos);
         s0[g * L + pos] = mode == 0 ? make_float2(rin[o], 0.0f) : C[o];
     }
     __syncthreads();
-    const int g = tid / (L / 2), bt = tid - g * (L / 2);
-    float2* res = stockham<L>(s0, s1, tw, mode >= 3, g, bt);
+    float2* res = stockham<L, G>(s0, s1, tw, mode >= 3);
     if (mode == 2) {
         // line l = j P + k holds frequencies (n, j, k): symbol
         // 1 + tau mu (6 - 2 cos(2 pi n / M) - 2 cos(2 pi j / N) - 2 cos(2 pi k / P))
         float2* other = res == s0 ? s1 : s0;
-        for (int m = 0; m < 2; ++m) {
-            const int e = tid + m * T;
-            const int pos = e / kLines, gg = e - pos * kLines;
+#pragma unroll
+        for (int m = 0; m < 2 * S::NB; ++m) {
+            const int e = tid + m * S::T;
+            const int pos = e / G, gg = e - pos * G;
             const int l = line0 + gg;
             const float cs = twM[pos].x + twN[l / P].x + twP[l % P].x;
             const float sym = 1.0f + taumu * (6.0f - 2.0f * cs);
@@ -253,10 +276,11 @@ __global__ __launch_bounds__(1024) void k3_fft(const float* __restrict__ rin, fl
             res[gg * L + pos] = make_float2(z.x / sym, z.y / sym);
         }
         __syncthreads();
-        res = stockham<L>(res, other, tw, true, g, bt);
+        res = stockham<L, G>(res, other, tw, true);
     }
-    for (int m = 0; m < 2; ++m) {
-        const int e = tid + m * T;
+#pragma unroll
+    for (int m = 0; m < 2 * S::NB; ++m) {
+        const int e = tid + m * S::T;
         int gg, pos;
         const size_t o = addr(e, gg, pos);
         const float2 z = res[gg * L + pos];
@@ -308,11 +332,12 @@ Layout3 layout3(int M, int N, int P) {
 thread_local hipEvent_t t_ev[2] = {nullptr, nullptr};
 
 template <typename... KArgs, typename... Args>
-void launch(void (*kernel)(KArgs...), dim3 grid, dim3 block, hipStream_t st, Args... args) {
+void launch(void (*kernel)(KArgs...), dim3 grid, dim3 block, size_t lds, hipStream_t st, Args... args) {
     if (t_ev[0])
-        hipExtLaunchKernelGGL(kernel, grid, block, 0, st, t_ev[0], t_ev[1], 0u, static_cast<KArgs>(args)...);
+        hipExtLaunchKernelGGL(kernel, grid, block, (uint32_t)lds, st, t_ev[0], t_ev[1], 0u,
+                              static_cast<KArgs>(args)...);
     else
-        hipLaunchKernelGGL(kernel, grid, block, 0, st, static_cast<KArgs>(args)...);
+        hipLaunchKernelGGL(kernel, grid, block, lds, st, static_cast<KArgs>(args)...);
 }
 
 }  // namespace
@@ -352,12 +377,29 @@ void disarm() { t_ev[0] = t_ev[1] = nullptr; }
 
 unsigned vblocks(size_t n) { return (unsigned)((n + kT - 1) / kT); }
 
-template <int L>
-void fft_pass_t(sr3_ctx* c, int axis, int mode, const float* rin, float* rout, const float* radd) {
+template <int L, int G>
+void fft_pass_g(sr3_ctx* c, int axis, int mode, const float* rin, float* rout, const float* radd) {
     const int lines = (int)(c->n / L);
     const float scale = 1.0f / (float)c->n;
-    launch(k3_fft<L>, dim3(lines / kLines), dim3(kLines * L / 2), c->st, rin, c->C, rout, radd, c->twM, c->twN,
-           c->twP, c->M, c->N, c->P, axis, mode, c->taumu, scale);
+    const size_t lds = sizeof(float2) * 2 * G * L;
+    launch(k3_fft<L, G>, dim3(lines / G), dim3(FftShape3<L, G>::T), lds, c->st, rin, c->C, rout, radd, c->twM,
+           c->twN, c->twP, c->M, c->N, c->P, axis, mode, c->taumu, scale);
+}
+
+template <int L>
+void fft_pass_t(sr3_ctx* c, int axis, int mode, const float* rin, float* rout, const float* radd) {
+    if (axis == 2)
+        fft_pass_g<L, kLines>(c, axis, mode, rin, rout, radd);
+    else
+        fft_pass_g<L, kStridedLines>(c, axis, mode, rin, rout, radd);
+}
+
+template <int L>
+void fft_attrs() {
+    (void)hipFuncSetAttribute((const void*)k3_fft<L, kLines>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)(sizeof(float2) * 2 * kLines * L));
+    (void)hipFuncSetAttribute((const void*)k3_fft<L, kStridedLines>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)(sizeof(float2) * 2 * kStridedLines * L));
 }
 
 }  // namespace
@@ -391,16 +433,16 @@ void solve(sr3_ctx* c, const float* r, const float* phi_in, float* phi_out) {
 void window(sr3_ctx* c, const float* phi) {
     const unsigned nb = vblocks(c->n);
     arm(c, 0);
-    launch(k3_u, dim3(nb), dim3(kT), c->st, c->W, phi, c->U, c->n, c->kp);
+    launch(k3_u, dim3(nb), dim3(kT), 0, c->st, c->W, phi, c->U, c->n, c->kp);
     disarm();
     arm(c, 0);
-    launch(k3_win, dim3(nb), dim3(kT), c->st, c->U, c->T, c->M, c->N, c->P, 2, c->kp);
+    launch(k3_win, dim3(nb), dim3(kT), 0, c->st, c->U, c->T, c->M, c->N, c->P, 2, c->kp);
     disarm();
     arm(c, 0);
-    launch(k3_win, dim3(nb), dim3(kT), c->st, c->T, c->U, c->M, c->N, c->P, 1, c->kp);
+    launch(k3_win, dim3(nb), dim3(kT), 0, c->st, c->T, c->U, c->M, c->N, c->P, 1, c->kp);
     disarm();
     arm(c, 0);
-    launch(k3_win, dim3(nb), dim3(kT), c->st, c->U, c->T, c->M, c->N, c->P, 0, c->kp);
+    launch(k3_win, dim3(nb), dim3(kT), 0, c->st, c->U, c->T, c->M, c->N, c->P, 0, c->kp);
     disarm();
 }
 
@@ -409,7 +451,7 @@ void iteration(sr3_ctx* c) {
     for (int s = 0; s < c->p.S; ++s) {
         window(c, c->phi);
         arm(c, 1);
-        launch(k3_rhs, dim3(nb), dim3(kT), c->st, c->phi, c->W, c->B, c->g, c->T, c->R, c->M, c->N, c->P, c->kp);
+        launch(k3_rhs, dim3(nb), dim3(kT), 0, c->st, c->phi, c->W, c->B, c->g, c->T, c->R, c->M, c->N, c->P, c->kp);
         disarm();
         solve(c, c->R, c->phi, c->alt);
         float* t = c->phi;
@@ -418,7 +460,7 @@ void iteration(sr3_ctx* c) {
     }
     window(c, c->phi);
     arm(c, 3);
-    launch(k3_wstep, dim3(nb), dim3(kT), c->st, c->phi, c->W, c->B, c->g, c->T, c->M, c->N, c->P, c->kp);
+    launch(k3_wstep, dim3(nb), dim3(kT), 0, c->st, c->phi, c->W, c->B, c->g, c->T, c->M, c->N, c->P, c->kp);
     disarm();
     ++c->k;
 }
@@ -459,6 +501,11 @@ int sr3_create(sr3_ctx** out, int32_t M, int32_t N, int32_t P, const sr_params* 
     const Layout3 L = layout3(M, N, P);
     if (bytes < L.total) return sr::api_fail(SR_EINVAL, "workspace too small");
     if ((uintptr_t)workspace & 255) return sr::api_fail(SR_EINVAL, "workspace must be 256-byte aligned");
+    static bool attrs = false;
+    if (!attrs) {
+        fft_attrs<8>(); fft_attrs<16>(); fft_attrs<32>(); fft_attrs<64>(); fft_attrs<128>(); fft_attrs<256>();
+        attrs = true;
+    }
     sr3_ctx* c = new sr3_ctx();
     c->M = M;
     c->N = N;
