@@ -121,13 +121,13 @@ def cpu_baseline(f, phi0, wl, iters):
 PARAMS_3D = dict(gamma=5.0, alpha=4.0, beta=0.2, mu=3.0, tau=0.05, eps=1.0, band_l=1.0, d=4.0, R=2, S=5,
                  sigma=1.5, rho=1000.0, s_exp=2, tol_inner=0.0, zero_tol=1e-3)
 # algorithmic bytes per voxel per launch of each 3-D kernel kind (FP32):
-#   window: u = w h(phi) reads w (12) and phi (4), writes u (12); each of the
-#           three axis passes reads and writes 3 components (24): mean of 4
+#   window: the k pass reads w (12) and phi (4) and writes 3 components
+#           (12); the j and i passes read and write 3 components (24): mean of 3
 #   rhs: reads phi, w, b, g, v (4 + 12 + 12 + 4 + 12), writes r (4)
 #   fft: first pass reads r (4), writes complex (8); three complex passes
 #        read and write 8 each; the last reads 8 + phi_s 4, writes 4: mean of 5
 #   w step: reads phi, b, g, v (4 + 12 + 4 + 12), writes w and b (24)
-BYTES_PER_VOX_3D = {"window": (28 + 3 * 24) / 4, "rhs": 48, "fft": (12 + 3 * 16 + 16) / 5, "w_step": 56}
+BYTES_PER_VOX_3D = {"window": (28 + 2 * 24) / 3, "rhs": 48, "fft": (12 + 3 * 16 + 16) / 5, "w_step": 56}
 
 
 def volume_bench(S, steps, warmup, cpu):

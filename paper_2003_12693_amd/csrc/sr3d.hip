@@ -1,8 +1,8 @@
 // 3-D Split Bregman solver of the Self-repelling Snake model: the 2-D method
 // with a third axis (the paper's volume application, Sec. 5, Fig. 6).  One
 // outer iteration (Algorithm 1) on an M x N x P volume, periodic:
-//   S x [ u = w h(phi_s) (3 components), the cube window as three separable
-//         passes (k, j, i), r = tau (N(phi_s) + mu div(b - w) + mu Lap phi_s)
+//   S x [ the cube window of u = w h(phi_s) (3 components) as three
+//         separable passes (k with u formed on the fly, j, i), r = tau (N(phi_s) + mu div(b - w) + mu Lap phi_s)
 //         (eq 37 in increment form), the 3-D FFT solve (eqs 30-33):
 //         forward along k (real input), along j, along i with the division by
 //         the symbol and the inverse along i, inverse along j, inverse along
@@ -89,15 +89,26 @@ __global__ __launch_bounds__(kT) void k3_init(const float* __restrict__ phi0, fl
     B[2 * n + v] = 0.0f;
 }
 
-// u = w h(phi), three components.
-__global__ __launch_bounds__(kT) void k3_u(const float* __restrict__ W, const float* __restrict__ phi,
-                                           float* __restrict__ U, size_t n, KParams kp) {
-    const size_t v = (size_t)blockIdx.x * kT + threadIdx.x;
+// The first (k) axis of the cube window with u = w h(phi) formed on the fly:
+// dst = sum_q a_q w(x + q e_k) h(phi(x + q e_k)), three components.
+__global__ __launch_bounds__(kT) void k3_win_u(const float* __restrict__ W, const float* __restrict__ phi,
+                                               float* __restrict__ dst, int M, int N, int P, KParams kp) {
+    const size_t n = (size_t)M * N * P, v = (size_t)blockIdx.x * kT + threadIdx.x;
     if (v >= n) return;
-    const float h = sr::band_h(phi[v], kp);
-    U[v] = W[v] * h;
-    U[n + v] = W[n + v] * h;
-    U[2 * n + v] = W[2 * n + v] * h;
+    const int k = (int)(v % P);
+    const size_t row = v - k;
+    float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f;
+    for (int q = -kp.R; q <= kp.R; ++q) {
+        const size_t o = row + wrp(k + q, P);
+        const float h = sr::band_h(phi[o], kp);
+        const float a = kp.taps[q + kp.R];
+        a0 += a * (W[o] * h);
+        a1 += a * (W[n + o] * h);
+        a2 += a * (W[2 * n + o] * h);
+    }
+    dst[v] = a0;
+    dst[n + v] = a1;
+    dst[2 * n + v] = a2;
 }
 
 // One axis of the cube window, three components: dst = sum_q a_q src(x + q e_axis).
@@ -429,14 +440,11 @@ void solve(sr3_ctx* c, const float* r, const float* phi_in, float* phi_out) {
     fft_pass(c, 2, 4, nullptr, phi_out, phi_in);
 }
 
-// V (in T) = cube window of u = W h(phi).
+// V (in T) = cube window of u = W h(phi): the k pass forms u, then j, i.
 void window(sr3_ctx* c, const float* phi) {
     const unsigned nb = vblocks(c->n);
     arm(c, 0);
-    launch(k3_u, dim3(nb), dim3(kT), 0, c->st, c->W, phi, c->U, c->n, c->kp);
-    disarm();
-    arm(c, 0);
-    launch(k3_win, dim3(nb), dim3(kT), 0, c->st, c->U, c->T, c->M, c->N, c->P, 2, c->kp);
+    launch(k3_win_u, dim3(nb), dim3(kT), 0, c->st, c->W, phi, c->T, c->M, c->N, c->P, c->kp);
     disarm();
     arm(c, 0);
     launch(k3_win, dim3(nb), dim3(kT), 0, c->st, c->T, c->U, c->M, c->N, c->P, 1, c->kp);
