@@ -90,21 +90,29 @@ __global__ __launch_bounds__(kT) void k3_init(const float* __restrict__ phi0, fl
 }
 
 // The first (k) axis of the cube window with u = w h(phi) formed on the fly:
-// dst = sum_q a_q w(x + q e_k) h(phi(x + q e_k)), three components.
+// dst = sum_q a_q u(x + q e_k), three components.  A workgroup of kT
+// voxels holds whole k-lines (P <= kT, both powers of two), so u is formed
+// once per voxel in LDS and every tap, wrapped within its line, reads it
+// there.
 __global__ __launch_bounds__(kT) void k3_win_u(const float* __restrict__ W, const float* __restrict__ phi,
                                                float* __restrict__ dst, int M, int N, int P, KParams kp) {
-    const size_t n = (size_t)M * N * P, v = (size_t)blockIdx.x * kT + threadIdx.x;
-    if (v >= n) return;
+    __shared__ float su[3][kT];
+    const size_t n = (size_t)M * N * P, v = (size_t)blockIdx.x * kT + threadIdx.x;   // n is a multiple of kT
+    const int tid = threadIdx.x;
+    const float h = sr::band_h(phi[v], kp);
+    su[0][tid] = W[v] * h;
+    su[1][tid] = W[n + v] * h;
+    su[2][tid] = W[2 * n + v] * h;
+    __syncthreads();
     const int k = (int)(v % P);
-    const size_t row = v - k;
+    const int line = tid - k;
     float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f;
     for (int q = -kp.R; q <= kp.R; ++q) {
-        const size_t o = row + wrp(k + q, P);
-        const float h = sr::band_h(phi[o], kp);
+        const int o = line + wrp(k + q, P);
         const float a = kp.taps[q + kp.R];
-        a0 += a * (W[o] * h);
-        a1 += a * (W[n + o] * h);
-        a2 += a * (W[2 * n + o] * h);
+        a0 += a * su[0][o];
+        a1 += a * su[1][o];
+        a2 += a * su[2][o];
     }
     dst[v] = a0;
     dst[n + v] = a1;
@@ -189,23 +197,27 @@ __global__ __launch_bounds__(kT) void k3_wstep(const float* __restrict__ phi, fl
 }
 
 // ---- FFT along one axis: G lines of length L per workgroup ---------------
-// Radix-2 Stockham (self-sorting): stage Ns = 1, 2, ..., L/2; butterfly b
-// takes x[b] and x[b + L/2], twiddle W_L^{(b mod Ns) L / (2 Ns)} on the
-// second, writes y[(b div Ns) 2 Ns + b mod Ns] and that + Ns.  A thread
-// runs NB butterflies of the block per stage.
+// Stockham (self-sorting) with radix-4 stages, after one radix-2 stage when
+// log2 L is odd.  A radix-R stage at sub-transform length Ns takes, for
+// butterfly j < L/R, the inputs x[j + r L/R] (r < R), multiplies input r by
+// W_L^{r (j mod Ns) L / (R Ns)}, applies the R-point DFT and writes output r
+// to y[(j div Ns) R Ns + j mod Ns + r Ns].  A thread runs several
+// butterflies of the block per stage.
 // mode 0: forward, real input; 1: forward; 2: forward, divide by the
 // symbol of (1 - tau mu Lap), inverse; 3: inverse; 4: inverse, real output
-// out = add + scale Re.  Lines of axis 2 are contiguous (G = 8 per
-// workgroup); lines of axes 0 and 1 are strided, and G = 32 neighbours
-// along k share a workgroup so that each load and store touches 256-byte
-// runs.
-constexpr int fft3_threads(int L, int G) { return G * L / 2 < 1024 ? G * L / 2 : 1024; }
+// out = add + scale Re.  Lines of axis 2 are contiguous (kLines per
+// workgroup); lines of axes 0 and 1 are strided, and kStridedLines
+// neighbours along k share a workgroup so that each load and store touches
+// 128-byte runs.
+constexpr int fft3_threads(int L, int G) { return G * L / 4 < 1024 ? G * L / 4 : 1024; }
 
 template <int L, int G>
 struct FftShape3 {
-    static constexpr int BF = G * L / 2;                    // butterflies per stage
-    static constexpr int T = BF < 1024 ? BF : 1024;          // threads
-    static constexpr int NB = BF / T;                        // butterflies per thread
+    static constexpr int T = fft3_threads(L, G);   // threads
+    static constexpr int NB2 = G * L / 2 / T;      // radix-2 butterflies per thread
+    static constexpr int NB4 = G * L / 4 / T;      // radix-4 butterflies per thread
+    static constexpr int NE = G * L / T;           // elements loaded / stored per thread
+    static constexpr bool ODD = (__builtin_ctz(L) & 1) != 0;
 };
 
 template <int L, int G>
@@ -213,20 +225,46 @@ __device__ float2* stockham(float2* a, float2* b, const float2* __restrict__ tw,
     using S = FftShape3<L, G>;
     float2* x = a;
     float2* y = b;
-    for (int Ns = 1; Ns < L; Ns <<= 1) {
+    int Ns = 1;
+    if constexpr (S::ODD) {
 #pragma unroll
-        for (int q = 0; q < S::NB; ++q) {
+        for (int q = 0; q < S::NB2; ++q) {
             const int u = threadIdx.x + q * S::T;
             const int g = u / (L / 2), bt = u - g * (L / 2);
-            const float2 v0 = x[g * L + bt];
-            float2 v1 = x[g * L + bt + L / 2];
-            const int kk = bt & (Ns - 1);
-            float2 w = tw[kk * (L / (2 * Ns))];
-            if (inv) w.y = -w.y;
-            v1 = sr::cmul(v1, w);
-            const int d = ((bt - kk) << 1) + kk;
-            y[g * L + d] = sr::cadd(v0, v1);
-            y[g * L + d + Ns] = sr::csub(v0, v1);
+            const float2 v0 = x[g * L + bt], v1 = x[g * L + bt + L / 2];
+            y[g * L + 2 * bt] = sr::cadd(v0, v1);
+            y[g * L + 2 * bt + 1] = sr::csub(v0, v1);
+        }
+        __syncthreads();
+        float2* t = x;
+        x = y;
+        y = t;
+        Ns = 2;
+    }
+    for (; Ns < L; Ns <<= 2) {
+#pragma unroll
+        for (int q = 0; q < S::NB4; ++q) {
+            const int u = threadIdx.x + q * S::T;
+            const int g = u / (L / 4), j = u - g * (L / 4);
+            const int kk = j & (Ns - 1);
+            const int step = kk * (L / (4 * Ns));
+            float2 v0 = x[g * L + j], v1 = x[g * L + j + L / 4], v2 = x[g * L + j + L / 2],
+                   v3 = x[g * L + j + 3 * L / 4];
+            if (kk) {
+                float2 w1 = tw[step], w2 = tw[2 * step], w3 = tw[3 * step];
+                if (inv) { w1.y = -w1.y; w2.y = -w2.y; w3.y = -w3.y; }
+                v1 = sr::cmul(v1, w1);
+                v2 = sr::cmul(v2, w2);
+                v3 = sr::cmul(v3, w3);
+            }
+            const float2 a0 = sr::cadd(v0, v2), a1 = sr::csub(v0, v2), a2 = sr::cadd(v1, v3);
+            const float2 d = sr::csub(v1, v3);
+            const float2 a3 = inv ? make_float2(-d.y, d.x) : make_float2(d.y, -d.x);   // (+-i) d
+            const int o = g * L + ((j - kk) << 2) + kk;
+            y[o] = sr::cadd(a0, a2);
+            y[o + Ns] = sr::cadd(a1, a3);
+            y[o + 2 * Ns] = sr::csub(a0, a2);
+            y[o + 3 * Ns] = sr::csub(a1, a3);
         }
         __syncthreads();
         float2* t = x;
@@ -264,7 +302,7 @@ __global__ __launch_bounds__(fft3_threads(L, G)) void k3_fft(const float* __rest
         return (size_t)pos * N * P + l;
     };
 #pragma unroll
-    for (int m = 0; m < 2 * S::NB; ++m) {
+    for (int m = 0; m < S::NE; ++m) {
         const int e = tid + m * S::T;
         int g, pos;
         const size_t o = addr(e, g, pos);
@@ -277,7 +315,7 @@ __global__ __launch_bounds__(fft3_threads(L, G)) void k3_fft(const float* __rest
         // 1 + tau mu (6 - 2 cos(2 pi n / M) - 2 cos(2 pi j / N) - 2 cos(2 pi k / P))
         float2* other = res == s0 ? s1 : s0;
 #pragma unroll
-        for (int m = 0; m < 2 * S::NB; ++m) {
+        for (int m = 0; m < S::NE; ++m) {
             const int e = tid + m * S::T;
             const int pos = e / G, gg = e - pos * G;
             const int l = line0 + gg;
@@ -290,7 +328,7 @@ __global__ __launch_bounds__(fft3_threads(L, G)) void k3_fft(const float* __rest
         res = stockham<L, G>(res, other, tw, true);
     }
 #pragma unroll
-    for (int m = 0; m < 2 * S::NB; ++m) {
+    for (int m = 0; m < S::NE; ++m) {
         const int e = tid + m * S::T;
         int gg, pos;
         const size_t o = addr(e, gg, pos);
