@@ -2,16 +2,17 @@
 // with a third axis (the paper's volume application, Sec. 5, Fig. 6).  One
 // outer iteration (Algorithm 1) on an M x N x P volume, periodic:
 //   S x [ the cube window of u = w h(phi_s) (3 components) as three
-//         separable passes (k with u formed on the fly, j, i), r = tau (N(phi_s) + mu div(b - w) + mu Lap phi_s)
-//         (eq 37 in increment form), the 3-D FFT solve (eqs 30-33):
+//         separable passes (k, forming u in LDS; j; i),
+//         r = tau (N(phi_s) + mu div(b - w) + mu Lap phi_s) (eq 37 in
+//         increment form), the 3-D FFT solve (eqs 30-33):
 //         forward along k (real input), along j, along i with the division by
 //         the symbol and the inverse along i, inverse along j, inverse along
 //         k with phi_{s+1} = phi_s + Re / (M N P) ]
 //   then u = w^k h(phi^{k+1}) and the window again, and the w step: B of
 //   eq (41), the eq (42) gate and the projection of eq (40) (B / |B|), b of
 //   eq (23), per voxel.
-// Every kernel is a plain per-voxel or per-line kernel: this path is the
-// functional 3-D row; the 2-D kernels carry the tiling work.
+// The stencil kernels are per-voxel (the window's k pass shares u through
+// LDS); the FFT kernels transform groups of lines in LDS.
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
