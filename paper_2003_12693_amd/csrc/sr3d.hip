@@ -11,8 +11,8 @@
 //   then u = w^k h(phi^{k+1}) and the window again, and the w step: B of
 //   eq (41), the eq (42) gate and the projection of eq (40) (B / |B|), b of
 //   eq (23), per voxel.
-// The stencil kernels are per-voxel (the window's k pass shares u through
-// LDS); the FFT kernels transform groups of lines in LDS.
+// The Gaussian, edge, rhs and w-step kernels are per voxel; the window
+// passes and the FFTs stage lines or tiles in LDS.
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
@@ -120,24 +120,49 @@ __global__ __launch_bounds__(kT) void k3_win_u(const float* __restrict__ W, cons
     dst[2 * n + v] = a2;
 }
 
-// One axis of the cube window, three components: dst = sum_q a_q src(x + q e_axis).
-__global__ __launch_bounds__(kT) void k3_win(const float* __restrict__ src, float* __restrict__ dst, int M, int N,
-                                             int P, int axis, KParams kp) {
-    const size_t n = (size_t)M * N * P, v = (size_t)blockIdx.x * kT + threadIdx.x;
-    if (v >= n) return;
-    const int k = (int)(v % P), j = (int)((v / P) % N), i = (int)(v / ((size_t)N * P));
-    float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f;
-    for (int q = -kp.R; q <= kp.R; ++q) {
-        const size_t o = axis == 0 ? vox(wrp(i + q, M), j, k, N, P)
-                                   : axis == 1 ? vox(i, wrp(j + q, N), k, N, P) : vox(i, j, wrp(k + q, P), N, P);
-        const float a = kp.taps[q + kp.R];
-        a0 += a * src[o];
-        a1 += a * src[n + o];
-        a2 += a * src[2 * n + o];
+// The i or j axis of the cube window on a tile: TA positions along the axis
+// times KT consecutive k (KT = min(64, P)), staged with the R-halo along the
+// axis in LDS (loads run along k), three components: dst = sum_q a_q
+// src(x + q e_axis), q ascending.
+constexpr int kWinTA = 16;
+constexpr int kWinKT = 64;
+
+__global__ __launch_bounds__(kT) void k3_win_tile(const float* __restrict__ src, float* __restrict__ dst, int M,
+                                                  int N, int P, int axis, KParams kp) {
+    __shared__ float sv[3][(kWinTA + 2 * sr::kMaxR) * kWinKT];
+    const size_t n = (size_t)M * N * P;
+    const int KT = P < kWinKT ? P : kWinKT;
+    const int La = axis == 0 ? M : N;
+    const int TA = La < kWinTA ? La : kWinTA;
+    const int R = kp.R;
+    const int k0 = blockIdx.x * KT, a0 = blockIdx.y * TA, other = blockIdx.z;   // other: j (axis 0) or i (axis 1)
+    auto at = [&](int a, int k) -> size_t {   // a: index along the axis (wrapped), k: absolute
+        return axis == 0 ? vox(a, other, k, N, P) : vox(other, a, k, N, P);
+    };
+    const int EH = TA + 2 * R;
+    for (int e = threadIdx.x; e < EH * KT; e += kT) {
+        const int ea = e / KT, ek = e - ea * KT;
+        const size_t o = at(wrp(a0 - R + ea, La), k0 + ek);
+        sv[0][e] = src[o];
+        sv[1][e] = src[n + o];
+        sv[2][e] = src[2 * n + o];
     }
-    dst[v] = a0;
-    dst[n + v] = a1;
-    dst[2 * n + v] = a2;
+    __syncthreads();
+    for (int e = threadIdx.x; e < TA * KT; e += kT) {
+        const int ta = e / KT, tk = e - ta * KT;
+        float c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
+        for (int q = -R; q <= R; ++q) {
+            const int l = (ta + R + q) * KT + tk;
+            const float a = kp.taps[q + R];
+            c0 += a * sv[0][l];
+            c1 += a * sv[1][l];
+            c2 += a * sv[2][l];
+        }
+        const size_t o = at(a0 + ta, k0 + tk);
+        dst[o] = c0;
+        dst[n + o] = c1;
+        dst[2 * n + o] = c2;
+    }
 }
 
 // r = tau (-gamma g |w| delta' + alpha g delta + 2 beta h' w.v + mu div(b - w) + mu Lap phi).
@@ -482,14 +507,18 @@ void solve(sr3_ctx* c, const float* r, const float* phi_in, float* phi_out) {
 // V (in T) = cube window of u = W h(phi): the k pass forms u, then j, i.
 void window(sr3_ctx* c, const float* phi) {
     const unsigned nb = vblocks(c->n);
+    static_assert(kT == 256, "the k window pass holds whole k-lines of up to 256 voxels");
     arm(c, 0);
     launch(k3_win_u, dim3(nb), dim3(kT), 0, c->st, c->W, phi, c->T, c->M, c->N, c->P, c->kp);
     disarm();
+    const unsigned kb = (unsigned)(c->P < kWinKT ? 1 : c->P / kWinKT);
+    const unsigned jb = (unsigned)(c->N < kWinTA ? 1 : c->N / kWinTA);
+    const unsigned ib = (unsigned)(c->M < kWinTA ? 1 : c->M / kWinTA);
     arm(c, 0);
-    launch(k3_win, dim3(nb), dim3(kT), 0, c->st, c->T, c->U, c->M, c->N, c->P, 1, c->kp);
+    launch(k3_win_tile, dim3(kb, jb, c->M), dim3(kT), 0, c->st, c->T, c->U, c->M, c->N, c->P, 1, c->kp);
     disarm();
     arm(c, 0);
-    launch(k3_win, dim3(nb), dim3(kT), 0, c->st, c->U, c->T, c->M, c->N, c->P, 0, c->kp);
+    launch(k3_win_tile, dim3(kb, ib, c->N), dim3(kT), 0, c->st, c->U, c->T, c->M, c->N, c->P, 0, c->kp);
     disarm();
 }
 
