@@ -249,6 +249,7 @@ struct FftShape3 {
 template <int L, int G>
 __device__ float2* stockham(float2* a, float2* b, const float2* __restrict__ tw, bool inv) {
     using S = FftShape3<L, G>;
+    constexpr int LP = L + 1;
     float2* x = a;
     float2* y = b;
     int Ns = 1;
@@ -257,9 +258,9 @@ __device__ float2* stockham(float2* a, float2* b, const float2* __restrict__ tw,
         for (int q = 0; q < S::NB2; ++q) {
             const int u = threadIdx.x + q * S::T;
             const int g = u / (L / 2), bt = u - g * (L / 2);
-            const float2 v0 = x[g * L + bt], v1 = x[g * L + bt + L / 2];
-            y[g * L + 2 * bt] = sr::cadd(v0, v1);
-            y[g * L + 2 * bt + 1] = sr::csub(v0, v1);
+            const float2 v0 = x[g * LP + bt], v1 = x[g * LP + bt + L / 2];
+            y[g * LP + 2 * bt] = sr::cadd(v0, v1);
+            y[g * LP + 2 * bt + 1] = sr::csub(v0, v1);
         }
         __syncthreads();
         float2* t = x;
@@ -274,8 +275,8 @@ __device__ float2* stockham(float2* a, float2* b, const float2* __restrict__ tw,
             const int g = u / (L / 4), j = u - g * (L / 4);
             const int kk = j & (Ns - 1);
             const int step = kk * (L / (4 * Ns));
-            float2 v0 = x[g * L + j], v1 = x[g * L + j + L / 4], v2 = x[g * L + j + L / 2],
-                   v3 = x[g * L + j + 3 * L / 4];
+            float2 v0 = x[g * LP + j], v1 = x[g * LP + j + L / 4], v2 = x[g * LP + j + L / 2],
+                   v3 = x[g * LP + j + 3 * L / 4];
             if (kk) {
                 float2 w1 = tw[step], w2 = tw[2 * step], w3 = tw[3 * step];
                 if (inv) { w1.y = -w1.y; w2.y = -w2.y; w3.y = -w3.y; }
@@ -286,7 +287,7 @@ __device__ float2* stockham(float2* a, float2* b, const float2* __restrict__ tw,
             const float2 a0 = sr::cadd(v0, v2), a1 = sr::csub(v0, v2), a2 = sr::cadd(v1, v3);
             const float2 d = sr::csub(v1, v3);
             const float2 a3 = inv ? make_float2(-d.y, d.x) : make_float2(d.y, -d.x);   // (+-i) d
-            const int o = g * L + ((j - kk) << 2) + kk;
+            const int o = g * LP + ((j - kk) << 2) + kk;
             y[o] = sr::cadd(a0, a2);
             y[o + Ns] = sr::cadd(a1, a3);
             y[o + 2 * Ns] = sr::csub(a0, a2);
@@ -309,8 +310,9 @@ __global__ __launch_bounds__(fft3_threads(L, G)) void k3_fft(const float* __rest
                                                              int axis, int mode, float taumu, float scale) {
     using S = FftShape3<L, G>;
     extern __shared__ float2 lds3[];
+    constexpr int LP = L + 1;   // line pitch in LDS: strided loads of G lines hit distinct banks
     float2* s0 = lds3;
-    float2* s1 = lds3 + G * L;
+    float2* s1 = lds3 + G * LP;
     const int tid = threadIdx.x;
     const int line0 = blockIdx.x * G;
     const float2* tw = axis == 0 ? twM : axis == 1 ? twN : twP;
@@ -332,7 +334,7 @@ __global__ __launch_bounds__(fft3_threads(L, G)) void k3_fft(const float* __rest
         const int e = tid + m * S::T;
         int g, pos;
         const size_t o = addr(e, g, pos);
-        s0[g * L + pos] = mode == 0 ? make_float2(rin[o], 0.0f) : C[o];
+        s0[g * LP + pos] = mode == 0 ? make_float2(rin[o], 0.0f) : C[o];
     }
     __syncthreads();
     float2* res = stockham<L, G>(s0, s1, tw, mode >= 3);
@@ -347,8 +349,8 @@ __global__ __launch_bounds__(fft3_threads(L, G)) void k3_fft(const float* __rest
             const int l = line0 + gg;
             const float cs = twM[pos].x + twN[l / P].x + twP[l % P].x;
             const float sym = 1.0f + taumu * (6.0f - 2.0f * cs);
-            const float2 z = res[gg * L + pos];
-            res[gg * L + pos] = make_float2(z.x / sym, z.y / sym);
+            const float2 z = res[gg * LP + pos];
+            res[gg * LP + pos] = make_float2(z.x / sym, z.y / sym);
         }
         __syncthreads();
         res = stockham<L, G>(res, other, tw, true);
@@ -358,7 +360,7 @@ __global__ __launch_bounds__(fft3_threads(L, G)) void k3_fft(const float* __rest
         const int e = tid + m * S::T;
         int gg, pos;
         const size_t o = addr(e, gg, pos);
-        const float2 z = res[gg * L + pos];
+        const float2 z = res[gg * LP + pos];
         if (mode == 4)
             rout[o] = radd[o] + scale * z.x;
         else
@@ -456,7 +458,7 @@ template <int L, int G>
 void fft_pass_g(sr3_ctx* c, int axis, int mode, const float* rin, float* rout, const float* radd) {
     const int lines = (int)(c->n / L);
     const float scale = 1.0f / (float)c->n;
-    const size_t lds = sizeof(float2) * 2 * G * L;
+    const size_t lds = sizeof(float2) * 2 * G * (L + 1);
     launch(k3_fft<L, G>, dim3(lines / G), dim3(FftShape3<L, G>::T), lds, c->st, rin, c->C, rout, radd, c->twM,
            c->twN, c->twP, c->M, c->N, c->P, axis, mode, c->taumu, scale);
 }
@@ -472,9 +474,9 @@ void fft_pass_t(sr3_ctx* c, int axis, int mode, const float* rin, float* rout, c
 template <int L>
 void fft_attrs() {
     (void)hipFuncSetAttribute((const void*)k3_fft<L, kLines>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)(sizeof(float2) * 2 * kLines * L));
+                              (int)(sizeof(float2) * 2 * kLines * (L + 1)));
     (void)hipFuncSetAttribute((const void*)k3_fft<L, kStridedLines>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)(sizeof(float2) * 2 * kStridedLines * L));
+                              (int)(sizeof(float2) * 2 * kStridedLines * (L + 1)));
 }
 
 }  // namespace
