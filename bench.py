@@ -16,7 +16,6 @@ runs a plain 256 MiB device-to-device copy ten times and exits; profiled
 with rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE it calibrates those counters.
 """
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -28,12 +27,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# Algorithmic bytes per pixel per launch of each kernel kind (FP32 planes):
-#   rhs:   read phi_s, w(2), g, D = 20, write r = 4
-#   row fwd: read r 4, write half spectrum 4;  col solve: read 4, write 4
-#   row inv: read spectrum 4 and phi_s 4, write phi 4
-#   w step: read phi^{k+1}, phi^k, w(2), b(2), g = 28, write phi, w(2), b(2), D = 24
-BYTES_PER_PX = {"rhs_repulsion": 24, "row_fft_fwd": 8, "col_fft_solve": 8, "row_fft_inv": 12, "w_step": 52}
+# Algorithmic (compulsory) bytes per pixel per launch of each kernel kind, FP32
+# planes.  One inner step moves 40 B/px: read phi_s, w (2), g, D = 20 and
+# write the half spectrum 4 (the rhs fused into the forward row FFT), the
+# column solve reads and writes the spectrum (8), the inverse row FFT reads
+# it and writes phi (8); the w step reads phi, w (2), b (2), g = 24 and writes
+# w (2), b (2), D = 20.  Per outer iteration 40 S + 44 = 164 B/px at S = 3.
+# With the rhs and the forward row FFT as separate launches the rhs kind is
+# charged the reads (20) and the row FFT the spectrum write (4): the rhs
+# plane they pass between them is not compulsory traffic.
+BYTES_PER_PX = {"rhs_row_fft_fwd": 24, "rhs_repulsion": 20, "row_fft_fwd": 4, "col_fft_solve": 8,
+                "row_fft_inv": 8, "w_step": 44}
 # a fixed-point w sweep before the last one: reads phi (4), w (8), b (8), g (4), writes w (8)
 BYTES_PER_PX_W_SWEEP = 32
 # the AOS phi solve (one launch in place of the three FFT passes): reads r and phi_s, writes phi
@@ -50,7 +54,6 @@ WORKLOADS = {
                              "rectangle phi0; R=5, eps=2, d=5, S=3, paper two-circles weights"),
 }
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.txt")
-KERNEL_SRC = os.path.join(ROOT, "paper_2003_12693_amd", "csrc", "sr_kernels.hip")
 
 
 def params_kw(wl):
@@ -77,44 +80,82 @@ def make_input(name):
     return synth.annuli(4096, 4096, seed=3)
 
 
-def source_sha():
-    h = hashlib.sha256()
-    for fn in (KERNEL_SRC, os.path.join(ROOT, "paper_2003_12693_amd", "csrc", "sr_device.hpp")):
-        with open(fn, "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+def build_source_id():
+    """Digest of the sources in this tree, as the build script computes it
+    (compared with the loaded library's sr_build_id)."""
+    from paper_2003_12693_amd import build
+    return build.source_id()
 
 
-def measured_traffic(workload, kernel, tile_rows):
+def measured_traffic(workload, kernel, tile_rows, build_id):
     """HBM bytes per launch from the committed rocprofv3 counter summary,
-    or None if it was taken on different kernel sources.  The right-hand-side
-    kernel's traffic depends on its tile height (halo rows), so it is listed
-    per height ("rhs_repulsion@16")."""
+    or None if it was taken on a library built from other sources.  The
+    separate right-hand-side kernel's traffic depends on its tile height
+    (halo rows), so it is listed per height ("rhs_repulsion@16")."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
-    sha = source_sha()
     key = f"{kernel}@{tile_rows}" if kernel == "rhs_repulsion" else kernel
     for line in open(TRAFFIC_FILE):
         parts = line.split("#", 1)[0].split()
-        if len(parts) == 4 and parts[0] == workload and parts[1] == key and parts[3] == sha:
+        if len(parts) == 4 and parts[0] == workload and parts[1] == key and parts[3] == build_id:
             return int(parts[2])
     return None
 
 
-def cpu_baseline(f, phi0, wl, iters):
+def _oracle_run(f, phi0, kw, iters):
+    """Seconds for `iters` outer iterations of the FP64 oracle (edge map and
+    initialisation excluded); run in this process or in a worker."""
     from oracle import sr_oracle as O
-    P = O.Params(**params_kw(wl))
-    t0 = time.perf_counter()
+    P = O.Params(**kw)
     g = O.edge_map(f, P.sigma, P.rho, P.s_exp)
     st = O.initial_state(phi0)
     t1 = time.perf_counter()
     for _ in range(iters):
         st, _ = O.sb_iteration(st, g, P)
-    t2 = time.perf_counter()
+    return time.perf_counter() - t1
+
+
+def host_cpu():
+    """(usable cores, capped at 16 -- the host share of one GPU -- and the CPU model)."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return min(int(n or 1), 16), model
+
+
+def cpu_baseline(f, phi0, wl, iters, all_cores=True):
+    """The FP64 oracle as it stands (one NumPy process is single-threaded)
+    timed on the host: one process, and one process per usable core running
+    the same sample concurrently (the host's aggregate oracle throughput)."""
     M, N = f.shape
-    return {"value": M * N * iters / 1e6 / (t2 - t1), "unit": "MPix-it/s", "cores": 1, "kind": "oracle",
-            "sample": f"{iters} outer iterations of the FP64 NumPy oracle on the same {M}x{N} input "
-                      f"({t2 - t1:.1f} s; edge map and initialisation excluded)"}
+    kw = params_kw(wl)
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
+    t1 = _oracle_run(f, phi0, kw, iters)
+    one = M * N * iters / 1e6 / t1
+    cores, model = host_cpu()
+    out = {"value": one, "unit": "MPix-it/s", "cores": 1, "kind": "oracle",
+           "sample": f"{iters} outer iterations of the FP64 NumPy oracle on the same {M}x{N} input "
+                     f"({t1:.1f} s; edge map and initialisation excluded)",
+           "cpu": model, "nproc": cores}
+    if all_cores and cores > 1:
+        import multiprocessing as mp
+        ctx = mp.get_context("spawn")
+        t0 = time.perf_counter()
+        with ctx.Pool(cores) as pool:
+            secs = pool.starmap(_oracle_run, [(f, phi0, kw, iters)] * cores)
+        wall = time.perf_counter() - t0
+        slowest = max(secs)
+        out.update(value=cores * M * N * iters / 1e6 / slowest, cores=cores,
+                   sample=out["sample"] + f"; {cores} concurrent single-threaded oracle processes, aggregate over "
+                                          f"the slowest ({slowest:.1f} s; {wall:.1f} s with start-up)",
+                   single_core={"value": one, "cores": 1})
+    return out
 
 
 # The paper's 3-D (mandible) weights with a 5 x 5 x 5 window.
@@ -428,6 +469,7 @@ def main():
     s.set_image(ft, pt)
     tile_th = args.tile_rows or s.autotune(20)[0]
     s.step(args.warmup)
+    s.prepare()   # every graph sr_step replays is instantiated before the timed region
     torch.cuda.synchronize()
 
     stream = torch.cuda.current_stream()
@@ -450,6 +492,9 @@ def main():
     if args.phi_solver == "aos":   # the phi solve is timed in the column-solve slot
         prof = {("aos_solve" if k == "col_fft_solve" else k): v for k, v in prof.items()
                 if k not in ("row_fft_fwd", "row_fft_inv")}
+    elif prof["row_fft_fwd"][1] == 0:   # the rhs fused into the forward row FFT
+        prof = {("rhs_row_fft_fwd" if k == "rhs_repulsion" else k): v for k, v in prof.items()
+                if k != "row_fft_fwd"}
     per_iter = {k: prof[k][1] / args.profile_iters for k in prof}      # launches per outer iteration
     per_iter_ms = {k: prof[k][0] * per_iter[k] for k in prof}
     dom = max(per_iter_ms, key=per_iter_ms.get)
@@ -463,7 +508,16 @@ def main():
         bytes_px["w_step"] = (BYTES_PER_PX["w_step"] + BYTES_PER_PX_W_SWEEP * (args.w_sweeps - 1)) / args.w_sweeps
     alg_bytes = bytes_px[dom] * M * N
     achieved = alg_bytes / (dom_ms * 1e-3) / 1e9
+    build_id = sr.sr_build_id()
+    traffic = (None if args.w_sweeps or args.phi_solver != "fft" or args.bc != "periodic"
+               else measured_traffic(args.workload, dom, tile_th, build_id))
 
+    roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "alg_bytes_per_launch": alg_bytes}
+    if traffic is not None:   # bytes the counters saw move, over the same duration
+        roof["achieved_by_counters"] = round(traffic / (dom_ms * 1e-3) / 1e9, 1)
+        roof["frac_by_counters"] = round(roof["achieved_by_counters"] / HBM_PEAK_GBS, 4)
     out = {
         "metric": f"SB megapixel-iters/s at {M}^2" if M == N else f"SB megapixel-iters/s at {M}x{N}",
         "value": round(value, 2),
@@ -477,20 +531,19 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": wl["text"], "M": M, "N": N, "R": wl["R"], "S": wl["S"], "tile_rows": tile_th,
+        "config": {"workload": wl["text"], "M": M, "N": N, "R": wl["R"], "S": wl["S"],
+                   "tile_rows": None if "rhs_row_fft_fwd" in prof else tile_th,
                    "bytes_per_px_iter": sum(bytes_px[k] * per_iter[k] for k in prof),
+                   "launches_per_iter": sum(per_iter.values()),
                    "w_solver": "fixed-point" if args.w_sweeps else "shrink", "w_sweeps": args.w_sweeps or None,
                    "phi_solver": args.phi_solver, "bc": args.bc},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": (None if args.w_sweeps or args.phi_solver != "fft" or args.bc != "periodic"
-                                 else measured_traffic(args.workload, dom, tile_th)),
-                     "alg_bytes_per_launch": alg_bytes},
+        "roofline": roof,
         "kernels_ms": {k: round(v[0], 5) for k, v in prof.items()},
         "iteration_ms_sum_of_kernels": round(sum(per_iter_ms.values()), 5),
         "energy_after": E,
         "r_last": info.r_last,
-        "kernel_source_sha": source_sha(),
+        "build_id": build_id,
+        "build_matches_tree": build_id == build_source_id(),
     }
     if not args.no_cpu_baseline:
         iters = args.cpu_iters if args.cpu_iters is not None else (5 if M * N <= 1 << 20 else 1)

@@ -207,6 +207,9 @@ int sr_implicit_solve(sr_ctx* ctx, const float* rhs, float* u_out, uint32_t flag
  *   ms[0] rhs + repulsion window (eq 37)   ms[1] forward row FFT
  *   ms[2] column FFT solve (eqs 31-33)     ms[3] inverse row FFT + update
  *   ms[4] w / b step (eqs 40-42, 23)
+ * Where the right-hand side is fused with the forward row FFT (FFT phi
+ * solve, periodic boundaries, 64 <= N <= 1024) that one launch is timed as
+ * kind 0 and kind 1 reports count 0.
  * count[i] receives the number of launches timed (n_iter S for the first
  * four kinds, n_iter for the w step, n_iter w_sweeps with the fixed-point
  * w solver, whose intermediate sweeps count as w-step launches).  With the
@@ -236,6 +239,21 @@ int sr_profile_kernels(sr_ctx* ctx, int32_t n_iter, double ms[SR_NUM_KERNEL_KIND
  * in microseconds, *tile_th (nullable) the choice.  Requires sr_set_image;
  * synchronises; SR_EINVAL / SR_ESTATE / SR_EHIP on error. */
 int sr_autotune(sr_ctx* ctx, int32_t reps, int32_t* tile_th, double us_out[3]);
+
+/* ---- launch preparation -------------------------------------------------
+ * sr_step replays HIP graphs of one, two and eight outer iterations (one
+ * set per parity of the w / b ping-pong), capturing each the first time it
+ * is needed.  sr_prepare captures and instantiates all six now, without
+ * running any kernel or changing the state, so that a later sr_step spends
+ * no time on capture (e.g. before a timed region).  sr_autotune drops the
+ * graphs when it changes the tile height; call sr_prepare after it.
+ * SR_EINVAL on NULL, SR_EHIP if capture or instantiation fails. */
+int sr_prepare(sr_ctx* ctx);
+
+/* Identity of the compiled sources: a hex digest of the HIP sources and
+ * headers the library was built from (set by the build script), or
+ * "unknown".  The string is static; never NULL. */
+const char* sr_build_id(void);
 
 /* ---- batched solve (many independent images of uneven sizes) ----------
  * Each item is solved by Algorithm 1 from its own f and phi0, with its own

@@ -9,6 +9,8 @@ disabled for device code (-packed-fp32-ops) on purpose.
 from __future__ import annotations
 
 import concurrent.futures as cf
+import glob
+import hashlib
 import os
 import shutil
 import subprocess
@@ -34,6 +36,21 @@ FLAGS = [
 ]
 
 
+def source_id():
+    """Hex digest (16 digits) of every HIP source and header the library is
+    built from, the C headers and the compiler flags.  Compiled into the
+    library (sr_build_id), so a loaded libsr.so can be matched to a tree."""
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.hpp"))
+                   + glob.glob(os.path.join(ROOT, "include", "*.h")))
+    for fn in files:
+        h.update(os.path.basename(fn).encode())
+        with open(fn, "rb") as fh:
+            h.update(fh.read())
+    h.update(" ".join(FLAGS[:-2] + [ARCH]).encode())
+    return h.hexdigest()[:16]
+
+
 def _hipcc():
     for cand in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", shutil.which("hipcc")):
         if cand and os.path.exists(cand):
@@ -41,9 +58,9 @@ def _hipcc():
     raise RuntimeError("hipcc not found (ROCm required to build libsr.so)")
 
 
-def _compile(src, hipcc):
+def _compile(src, hipcc, sid):
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [hipcc, *FLAGS, f'-DSR_BUILD_ID="{sid}"', "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
@@ -55,8 +72,9 @@ def build(verbose=False):
     """Compile every HIP source for gfx950 and link libsr.so (always rebuilds)."""
     hipcc = _hipcc()
     os.makedirs(BUILD, exist_ok=True)
+    sid = source_id()
     with cf.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        results = list(ex.map(lambda s: _compile(s, hipcc), SOURCES))
+        results = list(ex.map(lambda s: _compile(s, hipcc, sid), SOURCES))
     objs = [o for o, _ in results]
     if verbose:
         for _, w in results:

@@ -214,6 +214,7 @@ struct sr_ctx {
     hipGraphExec_t g2[2] = {nullptr, nullptr};   // two iterations from parity p
     hipGraphExec_t g8[2] = {nullptr, nullptr};   // eight iterations from parity p
     bool use_graphs = true;
+    bool fused = false;        // rhs fused with the forward row FFT (sr::fused_rhs_supported)
     int parity = 0;            // state in W[parity], B[parity]
     long long k = 0;
     bool image_set = false;
@@ -264,6 +265,17 @@ static void make_xgeo(const Bufs& b, int M, int N, float taumu, Geometry& x) {
     x.stN = b.xstN;
     x.taumu = taumu;
     x.bc = 0;
+}
+
+// The fused right-hand-side + row FFT kernel replaces the rhs kernel and the
+// forward row pass where it exists (FFT phi solve, periodic, 64 <= N <= 1024);
+// SR_NO_FUSE=1 keeps the two separate launches (for A/B measurements).
+static bool use_fused(const sr_params& p, const Geometry& geo, const KParams& kp) {
+    static const bool off = [] {
+        const char* s = std::getenv("SR_NO_FUSE");
+        return s && s[0] == '1';
+    }();
+    return !off && p.phi_solver == 0 && p.bc == 0 && sr::fused_rhs_supported(geo, kp);
 }
 
 static void make_kparams(const sr_params& p, KParams& kp) {
@@ -366,8 +378,12 @@ static void enqueue_iteration(sr_ctx* c, int p, hipStream_t st, Hook&& before = 
     for (int s = 0; s < S; ++s) {
         float* out = outs[s & 1];
         before(0);
-        sr::launch_rhs(c->geo, c->kp, in, b.W[p], b.g, b.D, b.Rb, c->nz, b.scal, st,
-                       (fold_in && s == 0) ? &fold : nullptr);
+        if (c->fused)   // rhs fused with the forward row FFT: writes the spectrum
+            sr::launch_rhs_fwd(c->geo, c->kp, in, b.W[p], b.g, b.D, b.spec, c->nz, b.scal, st,
+                               (fold_in && s == 0) ? &fold : nullptr);
+        else
+            sr::launch_rhs(c->geo, c->kp, in, b.W[p], b.g, b.D, b.Rb, c->nz, b.scal, st,
+                           (fold_in && s == 0) ? &fold : nullptr);
         if (c->p.phi_solver == 1) {   // AOS: one launch, timed as the solve kind (2)
             before(2);
             sr::launch_aos(c->M, c->N, c->p.bc, b.Rb, in, out, b.aos, c->aosKx, c->aosKy,
@@ -378,7 +394,7 @@ static void enqueue_iteration(sr_ctx* c, int p, hipStream_t st, Hook&& before = 
                 sr::launch_solve_neumann_pass(pass, c->xgeo, b.Rb, in, out, b.xr, b.xd, b.xspec, c->nz, b.scal, st);
             }
         } else {
-            for (int pass = 0; pass < 3; ++pass) {
+            for (int pass = c->fused ? 1 : 0; pass < 3; ++pass) {
                 before(1 + pass);
                 sr::launch_solve_pass(pass, c->geo, b.Rb, in, out, b.spec, c->kp.tol_inner, b.part, c->nz, b.scal,
                                       st);
@@ -598,6 +614,7 @@ int sr_create(sr_ctx** out, int32_t M, int32_t N, const sr_params* p, void* work
     c->geo.stN = c->b.stN;
     c->geo.taumu = (float)(c->p.tau * c->p.mu);
     c->geo.bc = c->p.bc;
+    c->fused = use_fused(c->p, c->geo, c->kp);
     make_xgeo(c->b, M, N, c->geo.taumu, c->xgeo);
     const char* ng = std::getenv("SR_NO_GRAPH");
     c->use_graphs = !(ng && ng[0] == '1');
@@ -836,6 +853,24 @@ int sr_autotune(sr_ctx* c, int32_t reps, int32_t* tile_th, double us_out[3]) {
     return SR_OK;
 }
 
+int sr_prepare(sr_ctx* c) {
+    if (!c) return fail(SR_EINVAL, "NULL context");
+    if (!c->use_graphs) return SR_OK;
+    for (int p = 0; p < 2; ++p) {
+        int rc = SR_OK;
+        if (!c->g1[p]) rc = capture(c, p, 1, &c->g1[p]);
+        if (!rc && !c->g2[p]) rc = capture(c, p, 2, &c->g2[p]);
+        if (!rc && !c->g8[p]) rc = capture(c, p, 8, &c->g8[p]);
+        if (rc) return rc;
+    }
+    return SR_OK;
+}
+
+#ifndef SR_BUILD_ID
+#define SR_BUILD_ID "unknown"
+#endif
+const char* sr_build_id(void) { return SR_BUILD_ID; }
+
 int sr_profile_kernels(sr_ctx* c, int32_t n_iter, double ms[SR_NUM_KERNEL_KINDS],
                        int64_t count[SR_NUM_KERNEL_KINDS]) {
     if (!c || !ms || !count) return fail(SR_EINVAL, "NULL argument");
@@ -979,6 +1014,7 @@ int sr_solve_batch(sr_batch_item* items, int32_t n, void* workspace, size_t byte
         c.geo.stM = c.b.stM; c.geo.stN = c.b.stN;
         c.geo.taumu = (float)(c.p.tau * c.p.mu);
         c.geo.bc = c.p.bc;
+        c.fused = use_fused(c.p, c.geo, c.kp);
         make_xgeo(c.b, c.M, c.N, c.geo.taumu, c.xgeo);
         HIP_TRY(upload_tables(c.b, c.M, c.N, st));
         HIP_TRY(upload_aos(&c, st));

@@ -51,6 +51,13 @@ struct FinFold {
 };
 void launch_rhs(const Geometry& geo, const KParams& kp, const float* phi_s, const float* W, const float* g,
                 const float* D, float* out, int nz, DevScal* sc, hipStream_t st, const FinFold* fold = nullptr);
+// The right-hand side of eq (37) fused with the forward row FFT of its
+// solve: writes the half spectrum of the rhs into spec (as pass 0 of
+// launch_solve_pass would from the rhs plane).  Only where
+// fused_rhs_supported (periodic, 64 <= N <= 1024).
+bool fused_rhs_supported(const Geometry& geo, const KParams& kp);
+void launch_rhs_fwd(const Geometry& geo, const KParams& kp, const float* phi_s, const float* W, const float* g,
+                    const float* D, float2* spec, int nz, DevScal* sc, hipStream_t st, const FinFold* fold = nullptr);
 // Pass `pass` (0..2) of the Neumann solve (phi_out = phi_in + u, phi_in
 // nullable, with (1 - tau mu Lap) u = rhs for the mirrored Laplacian) as the
 // periodic solve on the 2M x 2N mirror extension: xgeo is the 2M x 2N

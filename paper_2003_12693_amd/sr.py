@@ -104,6 +104,8 @@ def load(path=LIB_PATH):
         "sr_solve_batch": (C.c_int, [C.POINTER(sr_batch_item), I, P, C.c_size_t, P]),
         "sr_profile_kernels": (C.c_int, [P, I, C.POINTER(D), C.POINTER(C.c_int64)]),
         "sr_autotune": (C.c_int, [P, I, C.POINTER(I), C.POINTER(D)]),
+        "sr_prepare": (C.c_int, [P]),
+        "sr_build_id": (C.c_char_p, []),
         "sr_destroy": (None, [P]),
         "sr_last_error": (C.c_char_p, []),
         "sr3_workspace_size": (C.c_int, [I, I, I, C.POINTER(sr_params), C.POINTER(C.c_size_t)]),
@@ -268,6 +270,14 @@ def sr_autotune(ctx, reps=5):
     return th.value, {8: us[0], 16: us[1], 32: us[2]}
 
 
+def sr_prepare(ctx):
+    _check(load().sr_prepare(ctx))
+
+
+def sr_build_id():
+    return load().sr_build_id().decode()
+
+
 def sr_destroy(ctx):
     if ctx:
         load().sr_destroy(ctx)
@@ -351,6 +361,9 @@ class Solver:
 
     def autotune(self, reps=5):
         return sr_autotune(self.ctx, reps)
+
+    def prepare(self):
+        sr_prepare(self.ctx)
 
     def edge_map(self, f):
         return sr_edge_map(self.ctx, f, self._empty(self.M, self.N))

@@ -404,7 +404,12 @@ def test_profile_kernels_advance_like_step(sr):
     prof = sr.sr_profile_kernels(b.ctx, 4)
     assert set(prof) == set(sr.KERNEL_KINDS)
     S = kw.S
+    # at 128^2 the right-hand side is fused with the forward row FFT: that
+    # launch is timed as the rhs kind and the row-forward kind stays empty
     for k, (ms, n) in prof.items():
+        if k == "row_fft_fwd":
+            assert ms == 0.0 and n == 0, (k, ms, n)
+            continue
         assert ms > 0.0 and n == (4 if k == "w_step" else 4 * S), (k, ms, n)
     assert np.array_equal(b.phi().cpu().numpy(), pa)
     assert b.get_state()[3] == 7
