@@ -171,7 +171,9 @@ template <int L> struct ColE {
 };
 // Waves per SIMD the column pass is compiled for (a VGPR cap): 8 (64 VGPRs)
 // unless 16-element transforms need more registers.
-template <int L> struct ColWaves { static constexpr int v = ColE<L>::v >= 16 ? 4 : 8; };
+// Four-element transforms (up to 2048 points) hold every stage twiddle in
+// registers (tw_preload), so they get the 128-VGPR budget too.
+template <int L> struct ColWaves { static constexpr int v = (ColE<L>::v >= 16 || ColE<L>::v <= 4) ? 4 : 8; };
 template <int L, int EE = RowE<L>::v> struct FftShape {
     static constexpr int E = EE;
     static constexpr int NT = L / E;
@@ -267,19 +269,67 @@ __device__ __forceinline__ void dft(float2 (&u)[R]) {
     }
 }
 
+// Stage twiddle factors one thread applies over a whole length-L transform:
+// R - 1 per butterfly of every stage with Ns > 1.  A kernel may load them all
+// into registers up front (tw_preload) so that no stage waits on a global
+// load; the column pass then uses one set for its forward and inverse
+// transforms (the inverse conjugates them).
+constexpr int tw_count(int L, int EE, int Ns = 1) {
+    return Ns >= L ? 0
+                   : (Ns > 1 ? (EE / fft_radix(L, EE, Ns)) * (fft_radix(L, EE, Ns) - 1) : 0) +
+                         tw_count(L, EE, Ns * fft_radix(L, EE, Ns));
+}
+template <int L, int EE> struct TwN { static constexpr int v = tw_count(L, EE) > 0 ? tw_count(L, EE) : 1; };
+
+template <int L, int EE, int Ns, int OFF, int IDX>
+__device__ __forceinline__ void tw_preload_stages(const float2* __restrict__ tab, int t,
+                                                  float2 (&twr)[TwN<L, EE>::v]) {
+    if constexpr (Ns < L) {
+        constexpr int R = fft_radix(L, EE, Ns), NB = EE / R, NT = L / EE;
+        if constexpr (Ns > 1) {
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const int k = (t + b * NT) & (Ns - 1);
+                const float4* p = reinterpret_cast<const float4*>(tab + OFF + (size_t)k * R);
+#pragma unroll
+                for (int h = 0; h < R / 2; ++h) {
+                    const float4 q = p[h];
+                    if (h > 0) twr[IDX + b * (R - 1) + 2 * h - 1] = make_float2(q.x, q.y);
+                    twr[IDX + b * (R - 1) + 2 * h] = make_float2(q.z, q.w);
+                }
+            }
+        }
+        tw_preload_stages<L, EE, Ns * R, OFF + (Ns > 1 ? Ns * R : 0), IDX + (Ns > 1 ? NB * (R - 1) : 0)>(tab, t,
+                                                                                                       twr);
+    }
+}
+// All stage twiddles of thread t of a length-L transform (EE elements per
+// thread) from the stage table of (L, EE).
+template <int L, int EE>
+__device__ __forceinline__ void tw_preload(const float2* __restrict__ tab, int t, float2 (&twr)[TwN<L, EE>::v]) {
+    tw_preload_stages<L, EE, 1, 0, 0>(tab, t, twr);
+}
+
 // One radix-R Stockham stage: sub-transform size Ns -> R Ns.  Butterfly j
 // reads x[j + r L/R], twiddles by W_{R Ns}^{r k} (k = j mod Ns), applies the
 // R-point DFT and writes x[(j - k) R + k + r Ns].  tws: this stage's block of
 // the stage twiddle table.  FROM_REGS (first stage, Ns = 1): the inputs come
 // from io instead of LDS, io[e] holding element t + e NT; TO_REGS (last
 // stage, Ns = L/R): the outputs go to io in that same layout instead of LDS.
-template <int L, int EE, int R, int Ns, bool INV, bool FROM_REGS, bool TO_REGS>
-__device__ __forceinline__ void fft_stage(float2* x, const float2* __restrict__ tws, int t, float2 (&io)[EE]) {
+// PIDX >= 0: the twiddles are twr[PIDX ...] (tw_preload) instead of tws.
+template <int L, int EE, int R, int Ns, bool INV, bool FROM_REGS, bool TO_REGS, int PIDX>
+__device__ __forceinline__ void fft_stage(float2* x, const float2* __restrict__ tws, int t, float2 (&io)[EE],
+                                          const float2 (&twr)[TwN<L, EE>::v]) {
     constexpr int E = EE, NT = L / E, NB = E / R, Q = L / R;
     static_assert(!FROM_REGS || Ns == 1, "register input is the first stage");
     static_assert(!TO_REGS || Ns * R == L, "register output is the last stage");
     float2 w[NB][R];
-    if constexpr (Ns > 1) {   // issued first: their latency overlaps the LDS reads
+    if constexpr (Ns > 1 && PIDX >= 0) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+            for (int r = 1; r < R; ++r) w[b][r] = twr[PIDX + b * (R - 1) + r - 1];
+    } else if constexpr (Ns > 1) {   // issued first: their latency overlaps the LDS reads
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
             const int k = (t + b * NT) & (Ns - 1);
@@ -328,13 +378,16 @@ __device__ __forceinline__ void fft_stage(float2* x, const float2* __restrict__ 
     if constexpr (!TO_REGS) __syncthreads();
 }
 
-// OFF: offset of this stage's block in the stage twiddle table.
-template <int L, int EE, bool INV, bool IN, bool OUT, int Ns, int OFF>
-__device__ __forceinline__ void fft_stages(float2* x, const float2* __restrict__ tab, int t, float2 (&io)[EE]) {
+// OFF: offset of this stage's block in the stage twiddle table; PIDX: index
+// of its factors in twr (-1: not preloaded).
+template <int L, int EE, bool INV, bool IN, bool OUT, int Ns, int OFF, int PIDX>
+__device__ __forceinline__ void fft_stages(float2* x, const float2* __restrict__ tab, int t, float2 (&io)[EE],
+                                           const float2 (&twr)[TwN<L, EE>::v]) {
     if constexpr (Ns < L) {
-        constexpr int R = fft_radix(L, EE, Ns);
-        fft_stage<L, EE, R, Ns, INV, IN && Ns == 1, OUT && Ns * R == L>(x, tab + OFF, t, io);
-        fft_stages<L, EE, INV, IN, OUT, Ns * R, OFF + (Ns > 1 ? Ns * R : 0)>(x, tab, t, io);
+        constexpr int R = fft_radix(L, EE, Ns), NB = EE / R;
+        fft_stage<L, EE, R, Ns, INV, IN && Ns == 1, OUT && Ns * R == L, PIDX>(x, tab + OFF, t, io, twr);
+        constexpr int NEXT = PIDX < 0 ? -1 : PIDX + (Ns > 1 ? NB * (R - 1) : 0);
+        fft_stages<L, EE, INV, IN, OUT, Ns * R, OFF + (Ns > 1 ? Ns * R : 0), NEXT>(x, tab, t, io, twr);
     }
 }
 
@@ -348,12 +401,21 @@ __device__ __forceinline__ void fft_stages(float2* x, const float2* __restrict__
 template <int L, int EE, bool INV, bool IN = false, bool OUT = false>
 __device__ __forceinline__ void fft_lds(float2* x, const float2* __restrict__ tab, int t, float2 (&io)[EE]) {
     if constexpr (!IN) __syncthreads();
-    fft_stages<L, EE, INV, IN, OUT, 1, 0>(x, tab, t, io);
+    float2 none[TwN<L, EE>::v];
+    fft_stages<L, EE, INV, IN, OUT, 1, 0, -1>(x, tab, t, io, none);
 }
 template <int L, int EE, bool INV>
 __device__ __forceinline__ void fft_lds(float2* x, const float2* __restrict__ tab, int t) {
     float2 unused[EE];
     fft_lds<L, EE, INV, false, false>(x, tab, t, unused);
+}
+// The same with every stage twiddle taken from twr (tw_preload of the same
+// (L, EE) table for this t).
+template <int L, int EE, bool INV, bool IN = false, bool OUT = false>
+__device__ __forceinline__ void fft_lds_pre(float2* x, const float2 (&twr)[TwN<L, EE>::v], int t,
+                                            float2 (&io)[EE]) {
+    if constexpr (!IN) __syncthreads();
+    fft_stages<L, EE, INV, IN, OUT, 1, 0, 0>(x, nullptr, t, io, twr);
 }
 
 // ---------------------------------------------------------------------------

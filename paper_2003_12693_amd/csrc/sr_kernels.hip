@@ -493,7 +493,14 @@ __global__ __launch_bounds__(1024) void k_row_fwd(const float* __restrict__ src,
         const int n = t + e * NT;
         io[e] = make_float2(src[ra + n], src[rb + n]);
     }
-    fft_lds<N, RowE<N>::v, false, true, false>(x, stN, t, io);
+    constexpr bool PRE = E <= 4;   // all stage twiddles in registers
+    float2 twr[TwN<N, E>::v];
+    if constexpr (PRE) {
+        tw_preload<N, E>(stN, t, twr);
+        fft_lds_pre<N, E, false, true, false>(x, twr, t, io);
+    } else {
+        fft_lds<N, E, false, true, false>(x, stN, t, io);
+    }
     // Whole 8-row tiles are one contiguous run of 4N float2 each; with fewer
     // rows per workgroup it writes its rows of every 8-row run.
     const int nthr = LR ? ((1 << LR) / 2) * NT : (int)blockDim.x;
@@ -557,6 +564,7 @@ struct RhsFwdShape {
     static constexpr size_t lds_fft = sizeof(float2) * NTR * LX;
     static constexpr size_t lds_bytes = lds_win > lds_fft ? lds_win : lds_fft;
     static_assert(CPT >= 1 && CPT * T == N, "a thread owns whole columns");
+    static_assert(E <= 4, "stage twiddles preloaded into registers");
 };
 
 // First row of workgroup b's strip of 2^lrpw rows.  Workgroups are dealt to
@@ -603,6 +611,10 @@ __global__ __launch_bounds__((RhsFwdShape<N, LR, R>::T)) void k_rhs_fwd(KParams 
     const int row0 = strip_row0(blockIdx.x, gridDim.x, LR);
     const int tid = threadIdx.x;
     const float lim = kp.band_l + kp.eps;
+    // the transform's stage twiddles, loaded now so that they arrive with phi
+    const int gq = tid / NT, t = tid - gq * NT;
+    float2 twr[TwN<N, E>::v];
+    tw_preload<N, E>(stN, t, twr);
 
     // phase 1 (per owned column): loads, u = w h(phi), vertical sums
     float ph[CPT][RW], lv[CPT][RW], dv[CPT][RW], w1o[CPT][RW], w2o[CPT][RW], go[CPT][RW];
@@ -689,14 +701,13 @@ __global__ __launch_bounds__((RhsFwdShape<N, LR, R>::T)) void k_rhs_fwd(KParams 
     __syncthreads();   // the FFT buffers alias the window buffers
     // phase 3: rows 2m, 2m + 1 as one complex row, forward FFT, R2C split, store
     extern __shared__ float2 xs[];
-    const int gq = tid / NT, t = tid - gq * NT;
     float2* x = xs + gq * LX;
+    float2 io[E];
     if constexpr (C::NTR == 1) {
         // one transform: thread t's columns t + q NT are its first-stage inputs
-        float2 io[E];
 #pragma unroll
         for (int q = 0; q < CPT; ++q) io[q] = make_float2(F[q][0], F[q][1]);
-        fft_lds<N, RowE<N>::v, false, true, false>(x, stN, t, io);
+        fft_lds_pre<N, E, false, true, false>(x, twr, t, io);
     } else {
 #pragma unroll
         for (int q = 0; q < CPT; ++q) {
@@ -704,7 +715,7 @@ __global__ __launch_bounds__((RhsFwdShape<N, LR, R>::T)) void k_rhs_fwd(KParams 
 #pragma unroll
             for (int r = 0; r < RW; r += 2) xs[(r >> 1) * LX + sk(c)] = make_float2(F[q][r], F[q][r + 1]);
         }
-        fft_lds<N, RowE<N>::v, false>(x, stN, t);
+        fft_lds_pre<N, E, false>(x, twr, t, io);
     }
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -791,7 +802,16 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, 1024), amdgpu_waves_per
     const int g = threadIdx.x / NT, t = threadIdx.x - g * NT;
     const int col = k0 + g;
     float2* x = xs + g * LD;
-    fft_lds<M, ColE<M>::v, false, ONE, false>(x, stM, t, io);
+    // up to 2048 points every stage twiddle is loaded once into registers
+    // and serves the forward and the inverse transform
+    constexpr bool PRE = E <= 4;
+    float2 twr[TwN<M, E>::v];
+    if constexpr (PRE) {
+        tw_preload<M, E>(stM, t, twr);
+        fft_lds_pre<M, E, false, ONE, false>(x, twr, t, io);
+    } else {
+        fft_lds<M, E, false, ONE, false>(x, stM, t, io);
+    }
     // Divide by the symbol.  The symbol is even in l1, so each thread owns the
     // mirror pair (l, M - l): column 0's two packed real spectra mix Z[l]
     // with conj(Z[M - l]), every other column scales pointwise.
@@ -821,7 +841,8 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, 1024), amdgpu_waves_per
     // the forward transform's LDS addresses live across the division.
     int t_inv = t;
     asm volatile("" : "+v"(t_inv));
-    fft_lds<M, ColE<M>::v, true, false, ONE>(x, stM, t_inv, io);
+    if constexpr (PRE) fft_lds_pre<M, E, true, false, ONE>(x, twr, t_inv, io);
+    else fft_lds<M, E, true, false, ONE>(x, stM, t_inv, io);
     if constexpr (!ONE) __syncthreads();
     // An empty asm on the thread index keeps the compiler from computing the
     // store addresses at the top and holding them (or spilling them) through
@@ -892,6 +913,10 @@ __global__ __launch_bounds__(1024) void k_row_inv(const float2* __restrict__ spe
         xs[(r >> 1) * LX + sk((r & 1) * H + kk)] = spec[si];
     }
     const int g = threadIdx.x / NT, t = threadIdx.x - g * NT;
+    // stage twiddles in registers (up to 1024 points), loaded with phi_s
+    constexpr bool PRE = E <= 4;
+    float2 twr[TwN<N, E>::v];
+    if constexpr (PRE) tw_preload<N, E>(stN, t, twr);
     // phi_s of this thread's outputs, loaded now so that the loads overlap the transform
     const size_t ra = (size_t)(row0 + 2 * g) * N, rb = ra + N;
     float pav[E], pbv[E];
@@ -924,7 +949,8 @@ __global__ __launch_bounds__(1024) void k_row_inv(const float2* __restrict__ spe
         }
     }
     float2 io[E];   // the last stage's outputs: element t + e NT
-    fft_lds<N, RowE<N>::v, true, false, true>(x, stN, t, io);
+    if constexpr (PRE) fft_lds_pre<N, E, true, false, true>(x, twr, t, io);
+    else fft_lds<N, E, true, false, true>(x, stN, t, io);
     double sd = 0.0, sp = 0.0;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
