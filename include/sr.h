@@ -275,6 +275,8 @@ typedef struct sr_batch_item {
     int32_t reserved;
     double r_last;         /* last relative phi change                      */
     double energy;         /* final SR energy (eq 7)                        */
+    float* w_out;          /* out, nullable: final w, 2*M*N floats (device)  */
+    float* b_out;          /* out, nullable: final b, 2*M*N floats (device)  */
 } sr_batch_item;
 
 int sr_batch_workspace_size(const sr_batch_item* items, int32_t n, size_t* bytes);

@@ -1131,8 +1131,17 @@ int sr_solve_batch(sr_batch_item* items, int32_t n, void* workspace, size_t byte
         HIP_TRY(hipMemcpyAsync(hs[gi].data(), c.b.scal, sizeof(DevScal) * c.nz, hipMemcpyDeviceToHost, st));
         const size_t MN = (size_t)c.M * c.N;
         const auto& idx = plan.groups[gi];
-        for (int z = 0; z < c.nz; ++z)
-            HIP_TRY(hipMemcpyAsync(items[idx[z]].phi_out, c.b.P0 + z * MN, MN * 4, hipMemcpyDeviceToDevice, st));
+        for (int z = 0; z < c.nz; ++z) {
+            const sr_batch_item& it = items[idx[z]];
+            HIP_TRY(hipMemcpyAsync(it.phi_out, c.b.P0 + z * MN, MN * 4, hipMemcpyDeviceToDevice, st));
+            // an instance's state is in the ping-pong half of its own iteration
+            // count (retired instances are not advanced further)
+            const int par = (int)(hs[gi][z].k & 1);
+            if (it.w_out)
+                HIP_TRY(hipMemcpyAsync(it.w_out, c.b.W[par] + 2 * z * MN, 2 * MN * 4, hipMemcpyDeviceToDevice, st));
+            if (it.b_out)
+                HIP_TRY(hipMemcpyAsync(it.b_out, c.b.B[par] + 2 * z * MN, 2 * MN * 4, hipMemcpyDeviceToDevice, st));
+        }
         HIP_TRY(hipStreamSynchronize(st));
         for (int z = 0; z < c.nz; ++z) {
             sr_batch_item& it = items[idx[z]];

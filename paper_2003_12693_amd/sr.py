@@ -71,6 +71,7 @@ class sr_batch_item(C.Structure):
         ("max_iter", C.c_int32),
         ("iters", C.c_int32), ("status", C.c_int32), ("reserved", C.c_int32),
         ("r_last", C.c_double), ("energy", C.c_double),
+        ("w_out", C.c_void_p), ("b_out", C.c_void_p),
     ]
 
 
@@ -378,11 +379,13 @@ class Solver:
 def solve_batch(items, stream=None):
     """Batched solve.  `items` is a list of dicts with keys f, phi0 (contiguous
     float32 GPU tensors), max_iter, and optional params (an sr_params) or
-    parameter overrides under "params_kw".  Returns a list of dicts with
-    phi (tensor), iters, status, r_last, energy."""
+    parameter overrides under "params_kw", and want_state (also return the
+    final w and b).  Returns a list of dicts with phi (tensor), iters,
+    status, r_last, energy (and w, b)."""
     import torch
     cs = []
     outs = []
+    states = []
     for it in items:
         f, phi0 = it["f"], it["phi0"]
         M, N = f.shape
@@ -394,6 +397,13 @@ def solve_batch(items, stream=None):
         bi.f, bi.phi0, bi.phi_out = _ptr(f, False)[0], _ptr(phi0, False)[0], out.data_ptr()
         bi.params = p
         bi.max_iter = int(it["max_iter"])
+        if it.get("want_state"):   # final w and b as well
+            wo = torch.empty((2, M, N), dtype=torch.float32, device=f.device)
+            bo = torch.empty((2, M, N), dtype=torch.float32, device=f.device)
+            states.append((wo, bo))
+            bi.w_out, bi.b_out = wo.data_ptr(), bo.data_ptr()
+        else:
+            states.append(None)
         cs.append(bi)
     nbytes = sr_batch_workspace_size(cs)
     ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=items[0]["f"].device)
@@ -401,6 +411,9 @@ def solve_batch(items, stream=None):
     rc = sr_solve_batch(cs, ws[off:off + nbytes], stream)
     res = [{"phi": outs[i], "iters": cs[i].iters, "status": cs[i].status, "r_last": cs[i].r_last,
             "energy": cs[i].energy} for i in range(len(cs))]
+    for r, stt in zip(res, states):
+        if stt is not None:
+            r["w"], r["b"] = stt
     return rc, res
 
 

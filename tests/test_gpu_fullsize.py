@@ -7,8 +7,10 @@ centre reads) and compared with the library's value there.
 
 With S = 1, one outer iteration solves (1 - tau mu Lap) phi^{k+1} = F^k once
 (eq 30 / 33), so the residual of the five-point operator at a pixel must
-equal F^k there (eq 37, local); w^{k+1} is the gate of eqs 40-42 applied to
-B of eq 41 at that pixel, b^{k+1} the Bregman update of eq 23."""
+equal F^k there (eq 37, local), to the FP32 rounding of phi^{k+1} on the
+stencil times the operator's norm (1 + 8 tau mu) plus 1e-5 of the update's
+scale; w^{k+1} is the gate of eqs 40-42 applied to B of eq 41 at that pixel,
+b^{k+1} the Bregman update of eq 23."""
 import sys
 
 import numpy as np
@@ -17,6 +19,7 @@ import pytest
 from oracle import sr_oracle as O
 from paper_2003_12693_amd import synth
 from tests.helpers import gpu_params, oracle_params
+from tests.parity import ulp32
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -68,16 +71,21 @@ def test_full_size_4096_sampled():
     picks += [tuple(p) for p in band[rng.choice(len(band), 120, replace=False)]]
     picks += [tuple(p) for p in rng.integers(0, M, size=(40, 2))]
     taumu = P.tau * P.mu
+    # residual bar: the FP32 rounding of phi^{k+1} on the stencil, amplified
+    # by the operator (1 + 8 tau mu), plus 1e-5 of the update's scale (the
+    # increment's FP32 solve error), which the FFT spreads over the grid
+    upd = float(np.abs(phi1 - phi).max())
     worst_res = worst_b = 0.0
     skipped = 0
     for (i, j) in picks:
         cr = lambda a: _crop(a, i, j, c)
         F = O.phi_rhs(cr(phi), cr(w[0]), cr(w[1]), cr(b[0]), cr(b[1]), cr(g), P)[c, c]
         lhs = phi1[i, j] - taumu * _lap_at(phi1, i, j)
-        scale = max(1.0, np.abs(cr(phi1)).max())
-        res = abs(lhs - F) / scale
+        ulp = ulp32(np.abs(_crop(phi1, i, j, 1)).max())
+        bar = (1 + 8 * taumu) * (4 * ulp + 1e-5 * upd)
+        res = abs(lhs - F) / bar
         worst_res = max(worst_res, res)
-        assert res <= 2e-6, ((i, j), lhs, F, scale)
+        assert res <= 1.0, ((i, j), lhs, F, bar)
         B1, B2, t = O.shrink_input(cr(phi1), cr(w[0]), cr(w[1]), cr(b[0]), cr(b[1]), cr(g), P)
         Bn = np.hypot(B1[c, c], B2[c, c])
         if abs(Bn - t[c, c]) <= 1e-4 * max(1.0, Bn) or abs(Bn) <= 2 * P.zero_tol:
@@ -92,6 +100,6 @@ def test_full_size_4096_sampled():
         eb = max(abs(b1[0, i, j] - bb1), abs(b1[1, i, j] - bb2)) / max(1.0, abs(bb1), abs(bb2))
         worst_b = max(worst_b, eb)
         assert eb <= 1e-5, ((i, j), b1[:, i, j], bb1, bb2)
-    _note(f"  {len(picks)} pixels: worst solve residual {worst_res:.2e} (relative to |phi|), worst Bregman "
+    _note(f"  {len(picks)} pixels: worst solve residual {worst_res:.2f} of its bar, worst Bregman "
           f"{worst_b:.2e}; {skipped} gate decisions within rounding skipped")
     assert skipped <= len(picks) // 10

@@ -2,12 +2,13 @@
 
 Every test feeds both sides the same seeded inputs (float32-rounded for the
 GPU, and the oracle recomputes from those same rounded values) and compares
-element by element.  Tolerances follow from FP32 arithmetic: relative L2
-error of phi after one teacher-forced outer iteration <= 1e-5; at the end of
-a run, relative energy difference <= 1e-4 and sign(phi) differing on
-<= 0.1 % of pixels.  w is the output of a discontinuous gate (|B| > t), so
-its comparison counts gate flips where |B| is within FP32 rounding of t and
-requires agreement elsewhere.
+element by element.  One teacher-forced outer iteration is held to the bars
+of tests/parity.py: |phi_gpu - phi_ora| <= 4 ulp32(phi) + 1e-5 max|update| at
+every pixel (4 ulp per inner step for the AOS solve), w and b gate-aware
+(a gate decision may differ only within the FP32 error of B of the
+threshold, agreement to error(B) / |B| elsewhere).  Short trajectories are
+compared as whole fields; the 200-iteration run is compared by sign(phi)
+and energy against the FP64 method's own sensitivity.
 """
 import math
 import sys
@@ -18,6 +19,7 @@ import pytest
 from oracle import sr_oracle as O
 from paper_2003_12693_amd import synth
 from tests.helpers import as64, f32, gpu_params, oracle_params, rel_l2
+from tests.parity import check_phi, check_w_b, phi_tol
 
 pytestmark = pytest.mark.gpu
 
@@ -130,40 +132,76 @@ def _teacher_forced(sr, f, P, st, gpu_kw, M, N):
     """One outer iteration on both sides from the float32-rounded state."""
     phi, w1, w2, b1, b2 = (as64(x) for x in (st.phi, st.w1, st.w2, st.b1, st.b2))
     g = O.edge_map(as64(f), P.sigma, P.rho, P.s_exp, P.bc)
-    ref, info = O.sb_iteration(O.State(phi, w1, w2, b1, b2, st.k), g, P)
+    start = O.State(phi, w1, w2, b1, b2, st.k)
+    ref, info = O.sb_iteration(start, g, P)
     s = sr.Solver(M, N, gpu_params(**gpu_kw))
     s.set_image(_cuda(f), _cuda(phi))
     s.set_state(_cuda(phi), _cuda(np.stack([w1, w2])), _cuda(np.stack([b1, b2])), st.k)
     res = s.step(1)
     gphi, gw, gb, k = s.get_state()
-    return ref, _np(gphi), _np(gw), _np(gb), k, res
+    return dict(ref=ref, start=start, g=g, gphi=_np(gphi), gw=_np(gw), gb=_np(gb), k=k, res=res)
 
 
-def _check_w_b(ref, gw, gb, frac=1e-3):
-    """w = B/|B| where the gate is open: its direction error is the FP32
-    error of B over |B|, so where |B| is near the gate (zero_tol = 1e-3) a
-    rounding-level difference in B moves w by up to ~1e-2.  All but a 1e-5
-    fraction (at least 2 pixels) of the agreeing pixels must match within
-    2e-3, every one within 2e-2."""
-    flips = (np.hypot(gw[0], gw[1]) > 0.5) != (np.hypot(ref.w1, ref.w2) > 0.5)
-    assert flips.mean() <= frac, flips.mean()
-    ok = ~flips
-    for a, b in ((gw[0][ok], ref.w1[ok]), (gw[1][ok], ref.w2[ok])):
-        d = np.abs(a - b)
-        assert np.count_nonzero(d > 2e-3) <= max(2, 1e-5 * d.size), (np.count_nonzero(d > 2e-3), d.max())
-        assert d.max() <= 2e-2, d.max()
-    np.testing.assert_allclose(gb[0][ok], ref.b1[ok], atol=2e-3 * (1 + np.abs(ref.b1[ok]).max()))
-    np.testing.assert_allclose(gb[1][ok], ref.b2[ok], atol=2e-3 * (1 + np.abs(ref.b2[ok]).max()))
+def _gate_inputs(ref, start, g, P):
+    """B of eq (41) (of the last sweep for the fixed-point solver, built from
+    the oracle's previous sweep) and the threshold of eq (42)."""
+    if P.w_solver == 1:
+        w1, w2 = start.w1, start.w2
+        if P.w_sweeps > 1:
+            Pp = O.Params(**dict(P.__dict__, w_sweeps=P.w_sweeps - 1))
+            w1, w2 = O.w_fixed_point(ref.phi, start.w1, start.w2, start.b1, start.b2, g, Pp)
+        B1, B2, _ = O.shrink_input(ref.phi, w1, w2, start.b1, start.b2, g, P)
+        return B1, B2, np.zeros_like(B1)
+    return O.shrink_input(ref.phi, start.w1, start.w2, start.b1, start.b2, g, P)
+
+
+def _verify(tf, P, frac=1e-3):
+    """Element-wise bars of tests/parity.py: phi, then w and b gate-aware.
+    Returns the gate flips."""
+    ref, start, g = tf["ref"], tf["start"], tf["g"]
+    ulps = 4.0 * P.S if P.phi_solver == 1 else 4.0   # the AOS solve rounds at the scale of phi
+    check_phi(tf["gphi"], ref.phi, start.phi, ulps=ulps)
+    B1, B2, t = _gate_inputs(ref, start, g, P)
+    return check_w_b(tf["gw"], tf["gb"], [ref.w1, ref.w2], [ref.b1, ref.b2], [start.b1, start.b2], [B1, B2], t,
+                     P.zero_tol, g, O.dirac(ref.phi, P.eps), math.pi / (2 * P.eps ** 2), P.gamma / P.mu,
+                     phi_tol(ref.phi, start.phi, ulps), max_flip_frac=frac)
 
 
 @pytest.mark.parametrize("k", [0, 1, 10, 50])
 def test_teacher_forced_iteration_c1(sr, k):
     _note(f"teacher forced c1 k={k}")
     f, phi0, P, states = _c1_states([k])
-    ref, gphi, gw, gb, kk, res = _teacher_forced(sr, f, P, states[k], {}, 128, 128)
-    assert kk == k + 1 and res["k"] == k + 1
-    assert rel_l2(gphi, ref.phi) <= 1e-5
-    _check_w_b(ref, gw, gb)
+    tf = _teacher_forced(sr, f, P, states[k], {}, 128, 128)
+    assert tf["k"] == k + 1 and tf["res"]["k"] == k + 1
+    _verify(tf, P)
+
+
+@pytest.mark.parametrize("k", [0, 5, 10])
+def test_teacher_forced_literal_zero_rule(sr, k):
+    """zero_tol = 0, the paper's literal 0 (0/|0|) = 0 (eq 42), on both sides.
+    The start is a circle centred on a pixel, so no forward difference of
+    phi^0 vanishes and |B| stays above 1e-2 at every pixel for these k (a
+    precondition checked here): the literal rule and the 1e-3 reading then
+    give the same w, and the library's literal mode is compared with it."""
+    _note(f"teacher forced zero_tol = 0, k={k}")
+    f, _ = synth.two_disks()
+    i, j = np.meshgrid(np.arange(128), np.arange(128), indexing="ij")
+    phi0 = np.sqrt((i - 64.0) ** 2 + (j - 64.0) ** 2) - 60.0
+    kw = dict(zero_tol=0.0)
+    P = oracle_params(**kw)
+    g = O.edge_map(as64(f), P.sigma, P.rho, P.s_exp)
+    st = O.initial_state(as64(phi0))
+    for _ in range(k):
+        st, _ = O.sb_iteration(st, g, P)
+        st = O.State(*(as64(x) for x in (st.phi, st.w1, st.w2, st.b1, st.b2)), st.k)
+    tf = _teacher_forced(sr, f, P, st, kw, 128, 128)
+    B1, B2, t = _gate_inputs(tf["ref"], tf["start"], tf["g"], P)
+    assert np.hypot(B1, B2).min() > 1e-2
+    flips = _verify(tf, P)
+    assert not flips.any()
+    # the 1e-3 reading changes nothing on this state
+    ref13, _ = O.sb_iteration(tf["start"], tf["g"], oracle_params(zero_tol=1e-3))
+    np.testing.assert_array_equal(ref13.w1, tf["ref"].w1)
 
 
 @pytest.mark.parametrize("kw", [dict(R=0), dict(R=8, d=3.0), dict(S=1), dict(S=5), dict(eps=2.0, R=5, d=5.0),
@@ -171,9 +209,8 @@ def test_teacher_forced_iteration_c1(sr, k):
 def test_teacher_forced_variants(sr, kw):
     _note(f"teacher forced variant {kw}")
     f, phi0, P, states = _c1_states([3], **kw)
-    ref, gphi, gw, gb, kk, res = _teacher_forced(sr, f, P, states[3], kw, 128, 128)
-    assert rel_l2(gphi, ref.phi) <= 1e-5
-    _check_w_b(ref, gw, gb)
+    tf = _teacher_forced(sr, f, P, states[3], kw, 128, 128)
+    _verify(tf, P)
 
 
 @pytest.mark.parametrize("sweeps", [1, 2, 3, 5])
@@ -184,9 +221,8 @@ def test_teacher_forced_fixed_point_w(sr, sweeps, k):
     _note(f"teacher forced fixed-point w sweeps={sweeps} k={k}")
     kw = dict(w_solver=1, w_sweeps=sweeps)
     f, phi0, P, states = _c1_states([k], **kw)
-    ref, gphi, gw, gb, kk, res = _teacher_forced(sr, f, P, states[k], kw, 128, 128)
-    assert rel_l2(gphi, ref.phi) <= 1e-5
-    _check_w_b(ref, gw, gb)
+    tf = _teacher_forced(sr, f, P, states[k], kw, 128, 128)
+    _verify(tf, P)
 
 
 @pytest.mark.parametrize("kernel", ["gather", "slide"])
@@ -201,9 +237,8 @@ def test_teacher_forced_aos(sr, kw, k, kernel, monkeypatch):
     _note(f"teacher forced AOS {kw} k={k} {kernel}")
     kw = dict(kw, phi_solver=1)
     f, phi0, P, states = _c1_states([k], **kw)
-    ref, gphi, gw, gb, kk, res = _teacher_forced(sr, f, P, states[k], kw, 128, 128)
-    assert rel_l2(gphi, ref.phi) <= 1e-5
-    _check_w_b(ref, gw, gb)
+    tf = _teacher_forced(sr, f, P, states[k], kw, 128, 128)
+    _verify(tf, P)
 
 
 @pytest.mark.parametrize("kernel", ["gather", "slide"])
@@ -225,9 +260,8 @@ def test_teacher_forced_aos_shapes(sr, shape, kernel, monkeypatch):
     st = O.initial_state(as64(phi))
     st.b1 = 0.2 * rng.normal(size=shape)
     st.b2 = 0.2 * rng.normal(size=shape)
-    ref, gphi, gw, gb, kk, res = _teacher_forced(sr, f, P, st, kw, M, N)
-    assert rel_l2(gphi, ref.phi) <= 1e-5
-    _check_w_b(ref, gw, gb, frac=2e-3)
+    tf = _teacher_forced(sr, f, P, st, kw, M, N)
+    _verify(tf, P, frac=2e-3)
 
 
 def test_teacher_forced_aos_2048(sr):
@@ -240,9 +274,8 @@ def test_teacher_forced_aos_2048(sr):
     P = oracle_params(**kw)
     g = O.edge_map(as64(f), P.sigma, P.rho, P.s_exp)
     st, _ = O.sb_iteration(O.initial_state(as64(phi0)), g, P)
-    ref, gphi, gw, gb, kk, res = _teacher_forced(sr, f, P, st, kw, 2048, 2048)
-    assert rel_l2(gphi, ref.phi) <= 1e-5
-    _check_w_b(ref, gw, gb)
+    tf = _teacher_forced(sr, f, P, st, kw, 2048, 2048)
+    _verify(tf, P)
 
 
 @pytest.mark.parametrize("shape", [(8, 8), (16, 128), (64, 32), (256, 512)])
@@ -259,9 +292,8 @@ def test_teacher_forced_shapes(sr, shape):
     st = O.initial_state(as64(phi))
     st.b1 = 0.2 * rng.normal(size=shape)
     st.b2 = 0.2 * rng.normal(size=shape)
-    ref, gphi, gw, gb, kk, res = _teacher_forced(sr, f, P, st, {}, M, N)
-    assert rel_l2(gphi, ref.phi) <= 1e-5
-    _check_w_b(ref, gw, gb, frac=2e-3)
+    tf = _teacher_forced(sr, f, P, st, {}, M, N)
+    _verify(tf, P, frac=2e-3)
 
 
 def test_teacher_forced_c2_full_size(sr):
@@ -273,9 +305,8 @@ def test_teacher_forced_c2_full_size(sr):
     st = O.initial_state(as64(phi0))
     for _ in range(2):
         st, _ = O.sb_iteration(st, g, P)
-    ref, gphi, gw, gb, kk, res = _teacher_forced(sr, f, P, st, {}, 1024, 1024)
-    assert rel_l2(gphi, ref.phi) <= 1e-5
-    _check_w_b(ref, gw, gb)
+    tf = _teacher_forced(sr, f, P, st, {}, 1024, 1024)
+    _verify(tf, P)
 
 
 # --------------------------------------------------------------------------
@@ -318,6 +349,37 @@ def test_c1_short_trajectory(sr):
     E, terms = s.energy()
     Eo = O.energy(st.phi, g, P)
     assert abs(E - Eo) / abs(Eo) <= 1e-4, (E, Eo)
+
+
+def test_c1_200_iterations_against_fp64_self_divergence(sr):
+    """The 128 x 128 two-disk workload run 200 iterations from set_image on
+    both sides (BASELINE's first configuration), compared at the end by
+    sign(phi) and energy.  The FP64 method itself does not meet the
+    at-convergence criterion here: the oracle against the oracle with f and
+    phi0 perturbed by 1e-7 (FP32-level) differs in sign on 0.42% of the
+    pixels and in energy by 3.4e-3 at k = 200 (a slow CPU test pins this).
+    The FP32 library is held to the same scale: at most 3x that
+    self-divergence (1.3% of the signs, 1e-2 of the energy), and inside the
+    reproducible horizon (k = 20) to the criterion itself."""
+    _note("c1 200 iterations")
+    f, phi0 = synth.two_disks()
+    P = oracle_params()
+    g = O.edge_map(as64(f), P.sigma, P.rho, P.s_exp)
+    st = O.initial_state(as64(phi0))
+    s = sr.Solver(128, 128, gpu_params())
+    s.set_image(_cuda(f), _cuda(phi0))
+    out = {}
+    for k in range(1, 201):
+        st, _ = O.sb_iteration(st, g, P)
+        if k in (20, 200):
+            s.step(k - s.step(0)["k"])
+            gphi = _np(s.phi())
+            E, _ = s.energy()
+            Eo = O.energy(st.phi, g, P)
+            out[k] = (float(np.mean(np.sign(gphi) != np.sign(st.phi))), abs(E - Eo) / abs(Eo))
+    _note(f"  sign fraction / energy difference: k=20 {out[20]}, k=200 {out[200]}")
+    assert out[20][0] <= 1e-3 and out[20][1] <= 1e-4, out
+    assert out[200][0] <= 3 * 4.2e-3 and out[200][1] <= 3 * 3.4e-3, out
 
 
 def test_energy_matches_oracle(sr):
@@ -549,9 +611,8 @@ def test_teacher_forced_neumann(sr, kw, k, solver, monkeypatch):
         monkeypatch.setenv("SR_AOS_KERNEL", solver)
     _note(f"teacher forced neumann {kw} k={k} {solver}")
     f, phi0, P, st = _neumann_state(k, **kw)
-    ref, gphi, gw, gb, kk, res = _teacher_forced(sr, f, P, st, dict(kw, bc=1), 128, 128)
-    assert rel_l2(gphi, ref.phi) <= 1e-5
-    _check_w_b(ref, gw, gb)
+    tf = _teacher_forced(sr, f, P, st, dict(kw, bc=1), 128, 128)
+    _verify(tf, P)
 
 
 @pytest.mark.parametrize("solver", ["fft", "gather", "slide"])
@@ -575,9 +636,8 @@ def test_teacher_forced_neumann_shapes(sr, shape, solver, monkeypatch):
     st = O.initial_state(as64(phi), 1)
     st.b1 = 0.2 * rng.normal(size=shape)
     st.b2 = 0.2 * rng.normal(size=shape)
-    ref, gphi, gw, gb, kk, res = _teacher_forced(sr, f, P, st, kw, M, N)
-    assert rel_l2(gphi, ref.phi) <= 1e-5
-    _check_w_b(ref, gw, gb, frac=2e-3)
+    tf = _teacher_forced(sr, f, P, st, kw, M, N)
+    _verify(tf, P, frac=2e-3)
 
 
 @pytest.mark.parametrize("phi_solver", [0, 1])
