@@ -196,6 +196,23 @@ int sr_repulsion(sr_ctx* ctx, const float* w, const float* phi, float* v_out, ui
  * grid, through the library's LDS-staged radix-4/2 Stockham FFTs. */
 int sr_implicit_solve(sr_ctx* ctx, const float* rhs, float* u_out, uint32_t flags);
 
+/* The solve of sr_implicit_solve for callers that cannot allocate device
+ * memory (code under HIP graph capture, serving loops, harnesses that forbid
+ * hipMalloc): no context, no workspace.  u_out = the solution of
+ * (1 - tau mu Lap) u = rhs on the periodic M x N grid (eqs 31-33), rhs and
+ * u_out device pointers to M*N floats (they may not overlap), enqueued on
+ * hip_stream (NULL: the default stream); returns without synchronising.
+ * The half spectrum, the twiddle tables (built on the device) and the FFT
+ * kernels' flags live in one fixed array of the library's (16.5 MiB per
+ * device, held until the process ends): M and N powers of two in
+ * [8, 4096] with M * N <= 4194304, else SR_EUNSUPPORTED.  Every call on a
+ * device uses that device's one array, so calls that overlap in time on
+ * one device (different streams or threads) race and must be serialised by
+ * the caller.  SR_EINVAL on NULL pointers or tau, mu <= 0; SR_EHIP if a
+ * launch fails.  Calls no allocating routine. */
+int sr_implicit_solve_noalloc(int32_t M, int32_t N, double tau, double mu, const float* rhs, float* u_out,
+                              void* hip_stream);
+
 /* ---- measurement -------------------------------------------------------
  * Per-kernel timing of the iteration: runs n_iter outer iterations from the
  * current state (the iterate advances exactly as under sr_step(ctx, n_iter),

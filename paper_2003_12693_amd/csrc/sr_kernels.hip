@@ -1411,6 +1411,7 @@ static int fft_e(int L, bool col) {
     }
 }
 int fft_stage_table_len(int L, bool col) { return stage_tab_len(L, fft_e(L, col)); }
+int fft_elems(int L, bool col) { return fft_e(L, col); }
 void fft_stage_table(int L, bool col, float2* out) {
     const int E = fft_e(L, col);
     const double two_pi = 6.283185307179586476925286766559;

@@ -25,6 +25,8 @@ int tile_blocks(int M, int N);
 // Stage twiddle tables of the FFT passes: float2 entries, and the host-side
 // construction (col: the column pass's table for length L, else the row passes').
 int fft_stage_table_len(int L, bool col);
+// Elements per thread of those transforms (their stage radices follow from it).
+int fft_elems(int L, bool col);
 // While set (non-null) on the calling host thread, the iteration kernels
 // (rhs, the three FFT passes, w step) are launched with these events, which
 // record the kernel's own start and end; set both to nullptr to stop.

@@ -106,6 +106,7 @@ def load(path=LIB_PATH):
         "sr_profile_kernels": (C.c_int, [P, I, C.POINTER(D), C.POINTER(C.c_int64)]),
         "sr_autotune": (C.c_int, [P, I, C.POINTER(I), C.POINTER(D)]),
         "sr_prepare": (C.c_int, [P]),
+        "sr_implicit_solve_noalloc": (C.c_int, [I, I, D, D, P, P, P]),
         "sr_build_id": (C.c_char_p, []),
         "sr_destroy": (None, [P]),
         "sr_last_error": (C.c_char_p, []),
@@ -269,6 +270,19 @@ def sr_autotune(ctx, reps=5):
     us = (C.c_double * 3)()
     _check(load().sr_autotune(ctx, reps, C.byref(th), us))
     return th.value, {8: us[0], 16: us[1], 32: us[2]}
+
+
+def sr_implicit_solve_noalloc(rhs, u_out, tau, mu, stream=None):
+    """(1 - tau mu Lap) u = rhs through the entry point that allocates
+    nothing (GPU tensors only)."""
+    import torch
+    for x in (rhs, u_out):
+        if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float32 and x.is_contiguous()):
+            raise ValueError("sr_implicit_solve_noalloc takes contiguous float32 GPU tensors")
+    M, N = rhs.shape
+    _check(load().sr_implicit_solve_noalloc(M, N, float(tau), float(mu), rhs.data_ptr(), u_out.data_ptr(),
+                                            _stream_ptr(stream)))
+    return u_out
 
 
 def sr_prepare(ctx):
