@@ -217,9 +217,15 @@ def volume_bench(S, steps, warmup, cpu):
     return out
 
 
-def batch_bench(count, cap, tol):
+def batch_bench(count, cap, tol, cpu):
     """Time-to-converge of `count` uneven instances: one sr_solve_batch call
-    against sequential plain solves (sr_step with the same stop rule)."""
+    against sequential plain solves (sr_step with the same stop rule).  With
+    the CPU leg, a size-stratified 32-instance subset is also run 5 and 6
+    iterations by the batch (final w, b returned) and the FP64 oracle times
+    one iteration from each instance's state after 5: its throughput is the
+    CPU baseline, and the batch's sixth iteration is compared with it per
+    pixel (|phi_gpu - phi_ora| against 4 ulp32 + 1e-5 of the update; w gate
+    decisions)."""
     import torch
     from paper_2003_12693_amd import sr, synth
     insts = synth.batch_items(count=count)
@@ -253,7 +259,7 @@ def batch_bench(count, cap, tol):
         agree.append((same_iters, rel))
         s.close()
     conv = sum(1 for r in res if r["status"] == 0)
-    return {
+    out = {
         "metric": f"time-to-converge, {count} uneven instances (sizes 128^2..512x1024, R 3-5, cap {cap}, r_k<{tol})",
         "value": round(t_batch, 4), "unit": "s", "higher_is_better": False,
         "plain_sequential_s": round(t_plain, 4), "speedup_vs_plain": round(t_plain / t_batch, 2),
@@ -263,6 +269,51 @@ def batch_bench(count, cap, tol):
         "max_rel_phi_diff_vs_plain_when_iters_equal": max([a[1] for a in agree if a[0]] or [0.0]),
         "n_gpus": 1, "dtype": "f32", "data": "synthetic",
     }
+    if cpu:
+        out["cpu_baseline"] = batch_oracle_leg(sr)
+    return out
+
+
+def batch_oracle_leg(sr, k=5, n=32):
+    """The oracle on the stratified subset: one iteration per instance from
+    the batch's state after k iterations, timed; agreement of the batch's
+    iteration k + 1 with it."""
+    import torch
+    from oracle import sr_oracle as O
+    from paper_2003_12693_amd import synth
+    sizes = synth.batch_sizes(256)
+    sub = synth.batch_subset(n)
+    inst = [sizes[i] + tuple(synth.batch_instance(i, sizes[i][0], sizes[i][1])) for i in sub]
+
+    def run(iters):
+        items = [dict(f=torch.from_numpy(f.astype(np.float32)).cuda(), phi0=torch.from_numpy(p.astype(np.float32)).cuda(),
+                      max_iter=iters, want_state=True,
+                      params=sr.sr_params_default(**params_kw(dict(eps=1.5, d=float(R), R=R, S=3))))
+                 for (M, N, R, f, p) in inst]
+        _, res = sr.solve_batch(items)
+        return [(r["phi"].cpu().numpy().astype(np.float64), r["w"].cpu().numpy().astype(np.float64),
+                 r["b"].cpu().numpy().astype(np.float64)) for r in res]
+
+    before, after = run(k), run(k + 1)
+    t_or, px, worst, gate_diff = 0.0, 0, 0.0, 0
+    for (M, N, R, f, p), (phi, w, b), (gphi, gw, gb) in zip(inst, before, after):
+        P = O.Params(**params_kw(dict(eps=1.5, d=float(R), R=R, S=3)))
+        g = O.edge_map(f.astype(np.float32).astype(np.float64), P.sigma, P.rho, P.s_exp)
+        st = O.State(phi, w[0], w[1], b[0], b[1], k)
+        c0 = time.perf_counter()
+        ref, _ = O.sb_iteration(st, g, P)
+        t_or += time.perf_counter() - c0
+        px += M * N
+        ulp = np.spacing(np.abs(ref.phi).astype(np.float32)).astype(np.float64)
+        bar = 4 * ulp + 1e-5 * np.abs(ref.phi - phi).max()
+        worst = max(worst, float((np.abs(gphi - ref.phi) / bar).max()))
+        gate_diff += int(np.count_nonzero((np.hypot(gw[0], gw[1]) > 0.5) != (np.hypot(ref.w1, ref.w2) > 0.5)))
+    return {"value": round(px / 1e6 / t_or, 4), "unit": "MPix-it/s", "cores": 1, "kind": "oracle",
+            "sample": f"one FP64 NumPy oracle iteration on each of a size-stratified {n}-instance subset "
+                      f"({t_or:.1f} s), from the batch's state after {k} iterations",
+            "agreement": {"instances": n, "teacher_forced_at_k": k,
+                          "worst_phi_error_over_bar": round(worst, 4), "w_gate_decisions_differing": gate_diff,
+                          "bar": "|phi_gpu - phi_oracle| <= 4 ulp32(phi) + 1e-5 max|update| per pixel"}}
 
 
 MFMA_BF16_PEAK_TFLOPS = 2500.0
@@ -429,7 +480,7 @@ def main():
         copy_probe(args.copy_probe)
         return
     if args.batch:
-        print(json.dumps(batch_bench(args.batch, 500, 1e-4)), flush=True)
+        print(json.dumps(batch_bench(args.batch, 500, 1e-4, not args.no_cpu_baseline)), flush=True)
         return
     if args.volume:
         steps = args.steps if args.steps is not None else 20

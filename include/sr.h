@@ -18,7 +18,8 @@
  *  - Vector fields (w, b, the repulsion field v) are two planes [2][M][N]
  *    (component 1 first), i.e. 2*M*N floats.
  *  - Boundaries are periodic for every operator (the symbol of eq 32 is the
- *    periodic five-point Laplacian's).
+ *    periodic five-point Laplacian's) unless sr_params.bc selects the
+ *    Neumann condition of eqs (17) and (27).
  *  - Pointers are device pointers unless the call takes `flags` and
  *    SR_HOST is set, in which case they are host pointers and the call
  *    stages through the workspace and synchronises the stream.
@@ -104,12 +105,11 @@ typedef struct sr_params {
                               repulsion window, the forward difference zero on
                               the last row / column, the divergence its negative
                               adjoint.  The phi solve is then the DCT-II one
-                              (phi_solver = 0; run as the periodic FFT solve of
-                              the 2M x 2N mirror extension, restricted: needs
-                              M, N <= 2048 and tol_inner = 0, SR_EUNSUPPORTED
-                              otherwise; sr_implicit_solve follows it) or AOS
-                              with the Neumann tridiagonal systems
-                              (phi_solver = 1)                                  */
+                              (phi_solver = 0: eigenvalues 1 + tau mu (4 -
+                              2 cos(pi l1/M) - 2 cos(pi l2/N)), every size, the
+                              inner stop rule allowed; sr_implicit_solve
+                              follows it) or AOS with the Neumann tridiagonal
+                              systems (phi_solver = 1)                          */
 } sr_params;
 
 /* Per-call report of sr_step. */
@@ -193,7 +193,9 @@ int sr_repulsion(sr_ctx* ctx, const float* w, const float* phi, float* v_out, ui
 
 /* Semi-implicit solve of eqs (31)-(33): u = Re F^{-1}( F(rhs) / (1 - tau mu
  * (2 cos z1 + 2 cos z2 - 4)) ), i.e. (1 - tau mu Lap) u = rhs on the periodic
- * grid, through the library's LDS-staged radix-4/2 Stockham FFTs. */
+ * grid, through the library's LDS-staged Stockham FFTs (radix 16/8/4/2);
+ * with bc = 1 the same solve for the mirrored Laplacian through DCT-II
+ * passes built on those FFTs. */
 int sr_implicit_solve(sr_ctx* ctx, const float* rhs, float* u_out, uint32_t flags);
 
 /* The solve of sr_implicit_solve for callers that cannot allocate device

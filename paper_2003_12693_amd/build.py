@@ -23,7 +23,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsr.so")
 ARCH = os.environ.get("SR_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["sr_kernels.hip", "sr_aos.hip", "sr_api.hip", "sr_noalloc.hip", "sr3d.hip", "cnn.hip"]
+SOURCES = ["sr_kernels.hip", "sr_fused.hip", "sr_fused_small.hip", "sr_fused_512.hip", "sr_fused_1024.hip",
+           "sr_dct.hip", "sr_aos.hip", "sr_api.hip", "sr_noalloc.hip", "sr3d.hip", "cnn.hip"]
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -106,13 +106,6 @@ static int validate(int32_t M, int32_t N, const sr_params* p) {
     if (p->w_sweeps < 1 || p->w_sweeps > 16) return fail(SR_EINVAL, "w_sweeps must be in [1, 16]");
     if (p->phi_solver != 0 && p->phi_solver != 1) return fail(SR_EINVAL, "phi_solver must be 0 or 1");
     if (p->bc != 0 && p->bc != 1) return fail(SR_EINVAL, "bc must be 0 (periodic) or 1 (Neumann)");
-    if (p->bc == 1 && p->phi_solver == 0) {
-        if (2 * M > 4096 || 2 * N > 4096)
-            return fail(SR_EUNSUPPORTED, "Neumann boundaries with the FFT solve need M, N <= 2048 (the solve runs on "
-                        "the 2M x 2N mirror extension)");
-        if (p->tol_inner > 0)
-            return fail(SR_EUNSUPPORTED, "Neumann boundaries with the FFT solve run a fixed S (tol_inner = 0)");
-    }
     if (p->phi_solver == 1) {
         if (p->tol_inner > 0) return fail(SR_EUNSUPPORTED, "the AOS phi solver runs a fixed S (tol_inner = 0)");
         std::vector<float> taps(sr::kAosTapFloats);
@@ -128,8 +121,8 @@ static int validate(int32_t M, int32_t N, const sr_params* p) {
 // workspace layout
 // ---------------------------------------------------------------------------
 struct Layout {
-    size_t twM, twN, stM, stN, aos, g, P0, P1, P2, W0, W1, B0, B1, D, Rb, spec, part, scal, rhist, X0, X1;
-    size_t xtwM, xtwN, xstM, xstN, xr, xd, xspec;   // Neumann FFT solve on the 2M x 2N mirror extension
+    size_t twM, twN, stM, stN, dtM, dtN, cM, cN, aos, g, P0, P1, P2, W0, W1, B0, B1, D, Rb, spec, part, scal, rhist;
+    size_t X0, X1;
     size_t total;
 };
 
@@ -140,11 +133,8 @@ static int sweep_buffers(const sr_params& p) {
     return p.w_solver == 1 ? std::min(2, p.w_sweeps - 1) : 0;
 }
 
-// Neumann boundaries with the FFT solve: work on the 2M x 2N mirror extension.
-static bool neumann_fft(const sr_params& p) { return p.bc == 1 && p.phi_solver == 0; }
-
 // nz instances of one size class laid out plane-by-plane ([nz][M][N] each).
-static Layout make_layout(int M, int N, int nz, int xbufs = 0, bool ext = false) {
+static Layout make_layout(int M, int N, int nz, int xbufs = 0) {
     Layout L{};
     const size_t MN = (size_t)M * N, pl = MN * 4 * nz, vec = 2 * pl;
     size_t o = 0;
@@ -153,6 +143,10 @@ static Layout make_layout(int M, int N, int nz, int xbufs = 0, bool ext = false)
     L.twN = take(sizeof(float2) * N);
     L.stM = take(sizeof(float2) * sr::fft_stage_table_len(M, true));
     L.stN = take(sizeof(float2) * sr::fft_stage_table_len(N, false));
+    L.dtM = take(sizeof(float2) * M);
+    L.dtN = take(sizeof(float2) * N);
+    L.cM = take(sizeof(float) * M);
+    L.cN = take(sizeof(float) * N);
     L.aos = take(sizeof(float) * sr::kAosTapFloats);
     L.g = take(pl);
     L.P0 = take(pl);
@@ -171,15 +165,6 @@ static Layout make_layout(int M, int N, int nz, int xbufs = 0, bool ext = false)
     L.rhist = take(sizeof(double) * sr::kRHist * nz);
     L.X0 = xbufs > 0 ? take(vec) : 0;
     L.X1 = xbufs > 1 ? take(vec) : 0;
-    if (ext) {
-        L.xtwM = take(sizeof(float2) * 2 * M);
-        L.xtwN = take(sizeof(float2) * 2 * N);
-        L.xstM = take(sizeof(float2) * sr::fft_stage_table_len(2 * M, true));
-        L.xstN = take(sizeof(float2) * sr::fft_stage_table_len(2 * N, false));
-        L.xr = take(4 * pl);
-        L.xd = take(4 * pl);
-        L.xspec = take(4 * pl);
-    }
     L.total = o;
     return L;
 }
@@ -188,7 +173,8 @@ static Layout make_layout(int M, int N, int nz, int xbufs = 0, bool ext = false)
 // context
 // ---------------------------------------------------------------------------
 struct Bufs {
-    float2 *twM, *twN, *stM, *stN;
+    float2 *twM, *twN, *stM, *stN, *dtM, *dtN;
+    float *cM, *cN;
     float* aos;    // AOS tap buffer (sr::aos_tap_buffer layout)
     float *g, *P0, *P1, *P2, *W[2], *B[2], *D, *Rb;
     float2* spec;
@@ -196,9 +182,6 @@ struct Bufs {
     DevScal* scal;
     double* rhist;
     float* X[2];   // intermediate w of the fixed-point sweeps (when allocated)
-    float2 *xtwM, *xtwN, *xstM, *xstN;   // Neumann FFT solve (when allocated)
-    float *xr, *xd;
-    float2* xspec;
 };
 
 struct sr_ctx {
@@ -206,7 +189,6 @@ struct sr_ctx {
     sr_params p;
     KParams kp;
     Geometry geo;
-    Geometry xgeo;             // 2M x 2N periodic geometry of the Neumann FFT solve
     Bufs b;
     hipStream_t stream;
     hipStream_t cap;           // capture stream (graphs are replayed on `stream`)
@@ -228,6 +210,10 @@ static void carve(Bufs& b, char* base, const Layout& L) {
     b.twN = (float2*)(base + L.twN);
     b.stM = (float2*)(base + L.stM);
     b.stN = (float2*)(base + L.stN);
+    b.dtM = (float2*)(base + L.dtM);
+    b.dtN = (float2*)(base + L.dtN);
+    b.cM = (float*)(base + L.cM);
+    b.cN = (float*)(base + L.cN);
     b.aos = (float*)(base + L.aos);
     b.g = (float*)(base + L.g);
     b.P0 = (float*)(base + L.P0);
@@ -245,26 +231,6 @@ static void carve(Bufs& b, char* base, const Layout& L) {
     b.rhist = (double*)(base + L.rhist);
     b.X[0] = L.X0 ? (float*)(base + L.X0) : nullptr;
     b.X[1] = L.X1 ? (float*)(base + L.X1) : nullptr;
-    b.xtwM = L.xr ? (float2*)(base + L.xtwM) : nullptr;
-    b.xtwN = L.xr ? (float2*)(base + L.xtwN) : nullptr;
-    b.xstM = L.xr ? (float2*)(base + L.xstM) : nullptr;
-    b.xstN = L.xr ? (float2*)(base + L.xstN) : nullptr;
-    b.xr = L.xr ? (float*)(base + L.xr) : nullptr;
-    b.xd = L.xr ? (float*)(base + L.xd) : nullptr;
-    b.xspec = L.xr ? (float2*)(base + L.xspec) : nullptr;
-}
-
-// The 2M x 2N geometry of the Neumann FFT solve (periodic on the extension).
-static void make_xgeo(const Bufs& b, int M, int N, float taumu, Geometry& x) {
-    x = Geometry{};
-    x.M = 2 * M;
-    x.N = 2 * N;
-    x.twM = b.xtwM;
-    x.twN = b.xtwN;
-    x.stM = b.xstM;
-    x.stN = b.xstN;
-    x.taumu = taumu;
-    x.bc = 0;
 }
 
 // The fused right-hand-side + row FFT kernel replaces the rhs kernel and the
@@ -275,7 +241,7 @@ static bool use_fused(const sr_params& p, const Geometry& geo, const KParams& kp
         const char* s = std::getenv("SR_NO_FUSE");
         return s && s[0] == '1';
     }();
-    return !off && p.phi_solver == 0 && p.bc == 0 && sr::fused_rhs_supported(geo, kp);
+    return !off && p.phi_solver == 0 && sr::fused_rhs_supported(geo, kp);
 }
 
 static void make_kparams(const sr_params& p, KParams& kp) {
@@ -337,9 +303,29 @@ static hipError_t upload_tables_to(float2* twM, float2* twN, float2* stM, float2
     return e;
 }
 
+// Tables of the Neumann (DCT-II) solve: exp(-i pi k / (2L)) and 2 cos(pi k / L), k < L.
+static void dct_tables(int L, std::vector<float2>& dt, std::vector<float>& cs) {
+    const double pi = 3.14159265358979323846264338327950288;
+    dt.resize(L);
+    cs.resize(L);
+    for (int k = 0; k < L; ++k) {
+        const double a = pi * (double)k / (2.0 * L);
+        dt[k] = make_float2((float)std::cos(a), (float)-std::sin(a));
+        cs[k] = (float)(2.0 * std::cos(pi * (double)k / (double)L));
+    }
+}
+
 static hipError_t upload_tables(const Bufs& b, int M, int N, hipStream_t st) {
     hipError_t e = upload_tables_to(b.twM, b.twN, b.stM, b.stN, M, N, st);
-    if (e == hipSuccess && b.xr) e = upload_tables_to(b.xtwM, b.xtwN, b.xstM, b.xstN, 2 * M, 2 * N, st);
+    std::vector<float2> dm, dn;
+    std::vector<float> cm, cn;
+    dct_tables(M, dm, cm);
+    dct_tables(N, dn, cn);
+    if (e == hipSuccess) e = hipMemcpyAsync(b.dtM, dm.data(), sizeof(float2) * M, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(b.dtN, dn.data(), sizeof(float2) * N, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(b.cM, cm.data(), sizeof(float) * M, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(b.cN, cn.data(), sizeof(float) * N, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);   // the host vectors are released on return
     return e;
 }
 
@@ -388,12 +374,7 @@ static void enqueue_iteration(sr_ctx* c, int p, hipStream_t st, Hook&& before = 
             before(2);
             sr::launch_aos(c->M, c->N, c->p.bc, b.Rb, in, out, b.aos, c->aosKx, c->aosKy,
                            c->geo.taumu, c->nz, b.scal, st, t_aos_ev[0], t_aos_ev[1]);
-        } else if (c->p.bc == 1) {   // DCT solve as the periodic solve of the mirror extension
-            for (int pass = 0; pass < 3; ++pass) {
-                before(1 + pass);
-                sr::launch_solve_neumann_pass(pass, c->xgeo, b.Rb, in, out, b.xr, b.xd, b.xspec, c->nz, b.scal, st);
-            }
-        } else {
+        } else {   // FFT solve (periodic) or DCT-II solve (Neumann), by geo.bc
             for (int pass = c->fused ? 1 : 0; pass < 3; ++pass) {
                 before(1 + pass);
                 sr::launch_solve_pass(pass, c->geo, b.Rb, in, out, b.spec, c->kp.tol_inner, b.part, c->nz, b.scal,
@@ -580,7 +561,7 @@ int sr_workspace_size(int32_t M, int32_t N, const sr_params* p, size_t* bytes) {
     if (!bytes) return fail(SR_EINVAL, "bytes is NULL");
     int rc = validate(M, N, p);
     if (rc) return rc;
-    *bytes = make_layout(M, N, 1, sweep_buffers(*p), neumann_fft(*p)).total;
+    *bytes = make_layout(M, N, 1, sweep_buffers(*p)).total;
     return SR_OK;
 }
 
@@ -592,7 +573,7 @@ int sr_create(sr_ctx** out, int32_t M, int32_t N, const sr_params* p, void* work
     if (rc) return rc;
     if (!workspace) return fail(SR_EINVAL, "workspace is NULL");
     if ((uintptr_t)workspace & 255) return fail(SR_EWORKSPACE, "workspace must be 256-byte aligned");
-    const Layout L = make_layout(M, N, 1, sweep_buffers(*p), neumann_fft(*p));
+    const Layout L = make_layout(M, N, 1, sweep_buffers(*p));
     if (bytes < L.total) return fail(SR_EWORKSPACE, "workspace has %zu bytes, needs %zu", bytes, L.total);
 
     sr::configure_kernels();
@@ -612,10 +593,13 @@ int sr_create(sr_ctx** out, int32_t M, int32_t N, const sr_params* p, void* work
     c->geo.twN = c->b.twN;
     c->geo.stM = c->b.stM;
     c->geo.stN = c->b.stN;
+    c->geo.dtM = c->b.dtM;
+    c->geo.dtN = c->b.dtN;
+    c->geo.cM = c->b.cM;
+    c->geo.cN = c->b.cN;
     c->geo.taumu = (float)(c->p.tau * c->p.mu);
     c->geo.bc = c->p.bc;
     c->fused = use_fused(c->p, c->geo, c->kp);
-    make_xgeo(c->b, M, N, c->geo.taumu, c->xgeo);
     const char* ng = std::getenv("SR_NO_GRAPH");
     c->use_graphs = !(ng && ng[0] == '1');
     const char* th = std::getenv("SR_TILE_TH");
@@ -827,15 +811,7 @@ int sr_implicit_solve(sr_ctx* c, const float* rhs, float* u_out, uint32_t flags)
         rd = c->b.P1;
         ud = c->b.P2;
     }
-    if (c->p.bc == 1 && c->b.xr) {
-        for (int pass = 0; pass < 3; ++pass)
-            sr::launch_solve_neumann_pass(pass, c->xgeo, rd, nullptr, ud, c->b.xr, c->b.xd, c->b.xspec, 1, c->b.scal,
-                                          c->stream);
-    } else if (c->p.bc == 1) {
-        return fail(SR_EUNSUPPORTED, "the Neumann FFT solve is set up only with phi_solver = 0");
-    } else {
-        sr::launch_solve(c->geo, rd, nullptr, ud, c->b.spec, 0.0f, c->b.part, 1, c->b.scal, c->stream);
-    }
+    sr::launch_solve(c->geo, rd, nullptr, ud, c->b.spec, 0.0f, c->b.part, 1, c->b.scal, c->stream);
     HIP_TRY(hipGetLastError());
     if (flags & SR_HOST) return copy_out(c, u_out, ud, bytes, flags);
     return SR_OK;
@@ -964,8 +940,7 @@ static int plan_batch(const sr_batch_item* items, int32_t n, BatchPlan& plan) {
     size_t o = 0;
     for (auto& g : plan.groups) {
         plan.offset.push_back(o);
-        o += align256(make_layout(items[g[0]].M, items[g[0]].N, (int)g.size(), sweep_buffers(items[g[0]].params),
-                                  neumann_fft(items[g[0]].params))
+        o += align256(make_layout(items[g[0]].M, items[g[0]].N, (int)g.size(), sweep_buffers(items[g[0]].params))
                           .total);
     }
     plan.total = o;
@@ -1009,13 +984,13 @@ int sr_solve_batch(sr_batch_item* items, int32_t n, void* workspace, size_t byte
         make_kparams(c.p, c.kp);
         make_gauss(c.p.sigma, c.gauss, c.gauss_r);
         carve(c.b, (char*)workspace + plan.offset[gi],
-              make_layout(c.M, c.N, c.nz, sweep_buffers(c.p), neumann_fft(c.p)));
+              make_layout(c.M, c.N, c.nz, sweep_buffers(c.p)));
         c.geo.M = c.M; c.geo.N = c.N; c.geo.twM = c.b.twM; c.geo.twN = c.b.twN;
         c.geo.stM = c.b.stM; c.geo.stN = c.b.stN;
+        c.geo.dtM = c.b.dtM; c.geo.dtN = c.b.dtN; c.geo.cM = c.b.cM; c.geo.cN = c.b.cN;
         c.geo.taumu = (float)(c.p.tau * c.p.mu);
         c.geo.bc = c.p.bc;
         c.fused = use_fused(c.p, c.geo, c.kp);
-        make_xgeo(c.b, c.M, c.N, c.geo.taumu, c.xgeo);
         HIP_TRY(upload_tables(c.b, c.M, c.N, st));
         HIP_TRY(upload_aos(&c, st));
         HIP_TRY(hipStreamSynchronize(st));

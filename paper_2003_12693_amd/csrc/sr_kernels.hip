@@ -25,6 +25,7 @@
 
 #include "sr_device.hpp"
 #include "sr_kernels.hpp"
+#include "sr_pass.hpp"
 
 namespace sr {
 
@@ -134,31 +135,6 @@ __global__ __launch_bounds__(256) void k_set_D(const float* __restrict__ W, cons
     D[o] = mu * ((e1 - e1u) + (e2 - e2l));
 }
 
-// Neumann solve through the periodic one: the half-sample mirror extension
-// of an M x N plane to 2M x 2N (its periodic FFT solve, restricted to the
-// first M x N block, is the DCT-II solve of the mirrored Laplacian).
-__global__ __launch_bounds__(256) void k_mirror_ext(const float* __restrict__ src, float* __restrict__ dst, int M,
-                                                    int N, DevScal* sc) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    const int i = blockIdx.y;
-    const int z = blockIdx.z;
-    if (j >= 2 * N || !sc[z].active || sc[z].inner_done) return;
-    const size_t MN = (size_t)M * N;
-    dst[4 * MN * z + (size_t)i * 2 * N + j] = src[MN * z + (size_t)bidx<1>(i, M) * N + bidx<1>(j, N)];
-}
-
-// out = base + ext restricted to the first M x N block (base nullable: copy).
-__global__ __launch_bounds__(256) void k_restrict_add(const float* __restrict__ ext, const float* __restrict__ base,
-                                                      float* __restrict__ out, int M, int N, DevScal* sc) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    const int i = blockIdx.y;
-    const int z = blockIdx.z;
-    if (j >= N || !sc[z].active || sc[z].inner_done) return;
-    const size_t MN = (size_t)M * N, o = MN * z + (size_t)i * N + j;
-    const float v = ext[4 * MN * z + (size_t)i * 2 * N + j];
-    out[o] = base ? base[o] + v : v;
-}
-
 __global__ void k_reset_scal(DevScal* sc, int n, int active) {
     const int z = blockIdx.x * blockDim.x + threadIdx.x;
     if (z >= n) return;
@@ -220,24 +196,6 @@ __device__ __forceinline__ void xcd_tile(int& tx, int& ty) {
     if ((nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);
     ty = b / gx;
     tx = b - ty * gx;
-}
-
-// Outer-iteration finalize of instance z, by every thread of one workgroup.
-__device__ __forceinline__ void fin_outer_body(const double* __restrict__ part, int nb, double* __restrict__ rhist,
-                                               DevScal& S, int z, double* red) {
-    double v[2];
-    sum_partials<2>(part + (size_t)z * 2 * nb, nb, v, red);
-    if (threadIdx.x == 0) {
-        const double r = sqrt(v[0]) / (sqrt(v[1]) + 1e-6);
-        S.r_last = r;
-        rhist[(size_t)z * kRHist + (S.k % kRHist)] = r;
-        S.k += 1;
-        if (S.inner_done) S.inner_done = 0;   // (a folded finalize never finds it set)
-        // batched solves retire an instance on the device: cap, tolerance, NaN
-        if (!(r == r) || r > 1e30) { S.nonfinite = 1; S.active = 0; }
-        else if (S.tol_outer > 0.0 && S.k >= S.min_iter && r < S.tol_outer) { S.converged = 1; S.active = 0; }
-        else if (S.max_iter > 0 && S.k >= S.max_iter) S.active = 0;
-    }
 }
 
 template <int TH, int R>
@@ -447,28 +405,6 @@ __global__ __launch_bounds__(kTileThreads) void k_repulsion(KParams kp, int M, i
 // ---------------------------------------------------------------------------
 // FFT passes of the semi-implicit solve (eqs 31-33)
 // ---------------------------------------------------------------------------
-// Rows 2m and 2m+1 of the real field r are transformed together as one
-// complex row z = r_a + i r_b.  Each row's half spectrum X[k], k < N/2 (the
-// DC slot carrying (X[0], X[N/2]) as its real and imaginary parts) is stored
-// in 8-row tiles: element (row i, k) at ((i / 8) * (N/2) + k) * 8 + i % 8.
-// Row passes then write / read 64-byte runs (8 rows of one frequency) and
-// the column pass reads 64-byte runs (8 rows of one column; the two columns
-// of a 128-byte run are read by workgroups on one XCD).
-constexpr int kSpecTile = 8;
-
-// First row of workgroup b's rows (2^lrpw of them; nb workgroups).  When a
-// workgroup holds fewer than the 8 rows of a spectrum tile, the pieces of one
-// tile go to workgroups b, b + 8, ... which the dispatcher sends to the same
-// XCD (it deals workgroups to the 8 XCDs in turn), so each tile's 64-byte
-// runs are completed (written, or re-read) in one L2.
-__device__ __forceinline__ int row_piece0(int b, int nb, int lrpw) {
-    if (lrpw >= 3) return b << lrpw;
-    const int P = 8 >> lrpw;                 // pieces per tile
-    if (nb % (8 * P)) return b << lrpw;      // small grids: linear order
-    const int x = b & 7, s = b >> 3;
-    return ((s / P) * 8 + x) * 8 + ((s % P) << lrpw);
-}
-
 // RT tiles (8 RT rows, 4 RT complex transforms) per workgroup.  LR > 0 fixes
 // log2(rows per workgroup) at compile time (the common launch shapes, so the
 // index arithmetic folds); LR = 0 takes it from lrpw.
@@ -517,219 +453,6 @@ __global__ __launch_bounds__(1024) void k_row_fwd(const float* __restrict__ src,
         } else {
             r = o & ((1 << lrpw) - 1);
             kk = o >> lrpw;
-            di = ((size_t)(row0 >> 3) * H + kk) * 8 + (row0 & 7) + r;
-        }
-        const float2* xz = xs + (r >> 1) * LX;
-        const float2 Zk = xz[sk(kk)];
-        float2 out;
-        if (kk == 0) {
-            const float2 ZH = xz[sk(H)];
-            out = (r & 1) ? make_float2(Zk.y, ZH.y) : make_float2(Zk.x, ZH.x);
-        } else {
-            const float2 Zm = xz[sk(N - kk)];
-            out = (r & 1) ? make_float2(0.5f * (Zk.y + Zm.y), -0.5f * (Zk.x - Zm.x))
-                          : make_float2(0.5f * (Zk.x + Zm.x), 0.5f * (Zk.y - Zm.y));
-        }
-        spec[di] = out;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Inner right-hand side of eq (37) fused into the forward row FFT of its
-// solve (eqs 31-33): a workgroup owns RW = 2^LR whole rows and computes
-//   F = tau ( -gamma g |w| delta'(phi) + alpha g delta(phi)
-//             + 2 beta h'(phi) w . v + D + mu Lap phi )       (increment form)
-// on them, then transforms them (RW / 2 complex FFTs of two rows each) and
-// stores the half spectra, so the right-hand side never goes to memory.
-// Each thread owns whole columns of the strip: it loads phi on the RW rows
-// plus a halo of max(R, 1) rows above and below, forms u = w h(phi) on the
-// window's rows and sums them vertically in registers (the column factor of
-// the separable window K_pq = a_p a_q); the vertical sums and phi go through
-// LDS once for the horizontal factor and the Laplacian's left / right
-// neighbours (a whole row is in the workgroup, so the column halo is the
-// row itself, periodic or mirrored).  w and g are only read where the pixel
-// lies in the band |phi| <= l + eps: outside it h, h', delta and delta'
-// vanish, so u and the force are exactly zero there.
-// ---------------------------------------------------------------------------
-template <int N, int LR, int R>
-struct RhsFwdShape {
-    static constexpr int RW = 1 << LR, NTR = RW / 2;
-    static constexpr int E = FftShape<N>::E, NT = FftShape<N>::NT, T = NTR * NT;
-    static constexpr int CPT = N / T;                     // columns per thread
-    static constexpr int RH = R > 0 ? R : 1;              // halo rows of phi
-    static constexpr int NR = RW + 2 * RH;                // rows of phi a column reads
-    static constexpr int NU = RW + 2 * R;                 // rows of u a column sums
-    static constexpr int LX = LdsLen<N>::v;
-    static constexpr size_t lds_win = sizeof(float) * 3 * RW * N;
-    static constexpr size_t lds_fft = sizeof(float2) * NTR * LX;
-    static constexpr size_t lds_bytes = lds_win > lds_fft ? lds_win : lds_fft;
-    static_assert(CPT >= 1 && CPT * T == N, "a thread owns whole columns");
-    static_assert(E <= 4, "stage twiddles preloaded into registers");
-};
-
-// First row of workgroup b's strip of 2^lrpw rows.  Workgroups are dealt to
-// the 8 XCDs in turn, so XCD x = b % 8 is given a contiguous band of 8-row
-// spectrum tiles (the halo rows of neighbouring strips then meet in one L2),
-// and the pieces of one tile stay on one XCD.
-__device__ __forceinline__ int strip_row0(int b, int nb, int lrpw) {
-    const int P = lrpw >= 3 ? 1 : 8 >> lrpw;          // workgroups per 8-row tile
-    const int per = lrpw >= 3 ? 1 << (lrpw - 3) : 1;  // tiles per workgroup
-    if (nb & 7) return b << lrpw;
-    const int x = b & 7, s = b >> 3, nx = nb >> 3;    // s-th workgroup on XCD x
-    if (P == 1) return (x * nx + s) * per * 8;
-    if (nx % P) return b << lrpw;
-    const int tile = x * (nx / P) + s / P;
-    return tile * 8 + ((s % P) << lrpw);
-}
-
-template <int N, int LR, int R, int BC>
-__global__ __launch_bounds__((RhsFwdShape<N, LR, R>::T)) void k_rhs_fwd(KParams kp, int M,
-                                                                     const float* __restrict__ phi_s,
-                                                                     const float* __restrict__ W,
-                                                                     const float* __restrict__ g,
-                                                                     const float* __restrict__ D,
-                                                                     float2* __restrict__ spec,
-                                                                     const float2* __restrict__ stN,
-                                                                     const double* __restrict__ fin_part, int fin_nb,
-                                                                     double* __restrict__ fin_rhist, DevScal* sc) {
-    using C = RhsFwdShape<N, LR, R>;
-    constexpr int RW = C::RW, T = C::T, CPT = C::CPT, RH = C::RH, NR = C::NR, NU = C::NU;
-    constexpr int NT = C::NT, E = C::E, LX = C::LX, H = N / 2;
-    const int z = blockIdx.z;
-    if (!sc[z].active || sc[z].inner_done) return;
-    if (fin_part != nullptr && blockIdx.x == 0) {   // folded finalize (FinFold)
-        __shared__ double fred[2 * 16];
-        fin_outer_body(fin_part, fin_nb, fin_rhist, sc[z], z, fred);
-    }
-    const size_t MN = (size_t)M * N;
-    phi_s += z * MN; W += 2 * z * MN; g += z * MN; D += z * MN;
-    spec += (size_t)z * M * H;
-    extern __shared__ float lds[];
-    float* sv1 = lds;             // vertical window sums, RW rows x N
-    float* sv2 = sv1 + RW * N;
-    float* sph = sv2 + RW * N;    // phi on the RW rows
-    const int row0 = strip_row0(blockIdx.x, gridDim.x, LR);
-    const int tid = threadIdx.x;
-    const float lim = kp.band_l + kp.eps;
-    // the transform's stage twiddles, loaded now so that they arrive with phi
-    const int gq = tid / NT, t = tid - gq * NT;
-    float2 twr[TwN<N, E>::v];
-    tw_preload<N, E>(stN, t, twr);
-
-    // phase 1 (per owned column): loads, u = w h(phi), vertical sums
-    float ph[CPT][RW], lv[CPT][RW], dv[CPT][RW], w1o[CPT][RW], w2o[CPT][RW], go[CPT][RW];
-#pragma unroll
-    for (int q = 0; q < CPT; ++q) {
-        const int c = tid + q * T;
-        float p[NR];
-#pragma unroll
-        for (int rr = 0; rr < NR; ++rr) p[rr] = phi_s[(size_t)bidx<BC>(row0 - RH + rr, M) * N + c];
-#pragma unroll
-        for (int r = 0; r < RW; ++r) dv[q][r] = D[(size_t)(row0 + r) * N + c];
-        float a1[NU], a2[NU];
-#pragma unroll
-        for (int m = 0; m < NU; ++m) {
-            const float pv = p[RH - R + m];
-            a1[m] = 0.0f;
-            a2[m] = 0.0f;
-            if (pv <= lim && pv >= -lim) {
-                const size_t o = (size_t)bidx<BC>(row0 - R + m, M) * N + c;
-                a1[m] = W[o];
-                a2[m] = W[MN + o];
-            }
-        }
-#pragma unroll
-        for (int r = 0; r < RW; ++r) {
-            const float pv = p[RH + r];
-            go[q][r] = 0.0f;
-            if (pv <= lim && pv >= -lim) go[q][r] = g[(size_t)(row0 + r) * N + c];
-            w1o[q][r] = a1[R + r];
-            w2o[q][r] = a2[R + r];
-            ph[q][r] = pv;
-            lv[q][r] = p[RH + r - 1] + p[RH + r + 1];
-        }
-        float u1[NU], u2[NU];
-#pragma unroll
-        for (int m = 0; m < NU; ++m) {
-            const float h = band_h(p[RH - R + m], kp);
-            u1[m] = a1[m] * h;
-            u2[m] = a2[m] * h;
-        }
-#pragma unroll
-        for (int r = 0; r < RW; ++r) {
-            float s1 = 0.0f, s2 = 0.0f;
-#pragma unroll
-            for (int pp = 0; pp <= 2 * R; ++pp) {
-                s1 += kp.taps[pp] * u1[r + pp];
-                s2 += kp.taps[pp] * u2[r + pp];
-            }
-            sv1[r * N + c] = s1;
-            sv2[r * N + c] = s2;
-            sph[r * N + c] = ph[q][r];
-        }
-    }
-    __syncthreads();
-    // phase 2: horizontal window factor, Laplacian, force, F
-    float F[CPT][RW];
-#pragma unroll
-    for (int q = 0; q < CPT; ++q) {
-        const int c = tid + q * T;
-#pragma unroll
-        for (int r = 0; r < RW; ++r) {
-            const float p = ph[q][r];
-            float force = 0.0f;
-            if (p <= lim && p >= -lim) {
-                float v1 = 0.0f, v2 = 0.0f;
-#pragma unroll
-                for (int qq = 0; qq <= 2 * R; ++qq) {
-                    const int cc = bidx<BC>(c - R + qq, N);
-                    v1 += kp.taps[qq] * sv1[r * N + cc];
-                    v2 += kp.taps[qq] * sv2[r * N + cc];
-                }
-                float dl, ddl, h, dh;
-                dirac_d(p, kp, dl, ddl);
-                band_h_dh(p, kp, h, dh);
-                const float w1 = w1o[q][r], w2 = w2o[q][r], gg = go[q][r];
-                const float wn = sqrtf(w1 * w1 + w2 * w2);
-                force = -kp.gamma * gg * wn * ddl + kp.alpha * gg * dl + 2.0f * kp.beta * dh * (w1 * v1 + w2 * v2);
-            }
-            const float left = sph[r * N + bidx<BC>(c - 1, N)], right = sph[r * N + bidx<BC>(c + 1, N)];
-            const float lap = lv[q][r] + (left + right) - 4.0f * p;
-            F[q][r] = kp.tau * (force + dv[q][r] + kp.mu * lap);
-        }
-    }
-    __syncthreads();   // the FFT buffers alias the window buffers
-    // phase 3: rows 2m, 2m + 1 as one complex row, forward FFT, R2C split, store
-    extern __shared__ float2 xs[];
-    float2* x = xs + gq * LX;
-    float2 io[E];
-    if constexpr (C::NTR == 1) {
-        // one transform: thread t's columns t + q NT are its first-stage inputs
-#pragma unroll
-        for (int q = 0; q < CPT; ++q) io[q] = make_float2(F[q][0], F[q][1]);
-        fft_lds_pre<N, E, false, true, false>(x, twr, t, io);
-    } else {
-#pragma unroll
-        for (int q = 0; q < CPT; ++q) {
-            const int c = tid + q * T;
-#pragma unroll
-            for (int r = 0; r < RW; r += 2) xs[(r >> 1) * LX + sk(c)] = make_float2(F[q][r], F[q][r + 1]);
-        }
-        fft_lds_pre<N, E, false>(x, twr, t, io);
-    }
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int o = tid + e * T;
-        int r, kk;
-        size_t di;
-        if constexpr (LR >= 3) {
-            r = o & 7;
-            kk = (o >> 3) & (H - 1);
-            r += ((o >> 3) / H) * 8;
-            di = (size_t)row0 * H + o;
-        } else {
-            r = o & (RW - 1);
-            kk = o >> LR;
             di = ((size_t)(row0 >> 3) * H + kk) * 8 + (row0 & 7) + r;
         }
         const float2* xz = xs + (r >> 1) * LX;
@@ -1386,13 +1109,11 @@ void set_launch_events(hipEvent_t start, hipEvent_t stop) {
     t_ev_start = start;
     t_ev_stop = stop;
 }
-template <typename... KArgs, typename... Args>
-static void launch_iter(void (*kernel)(KArgs...), dim3 grid, dim3 block, size_t lds, hipStream_t st, Args... args) {
+void launch_kernel_ev(const void* fn, dim3 grid, dim3 block, void** args, size_t lds, hipStream_t st) {
     if (t_ev_start)
-        hipExtLaunchKernelGGL(kernel, grid, block, (std::uint32_t)lds, st, t_ev_start, t_ev_stop, 0u,
-                              static_cast<KArgs>(args)...);
+        (void)hipExtLaunchKernel(fn, grid, block, args, lds, st, t_ev_start, t_ev_stop, 0);
     else
-        hipLaunchKernelGGL(kernel, grid, block, lds, st, static_cast<KArgs>(args)...);
+        (void)hipLaunchKernel(fn, grid, block, args, lds, st);
 }
 
 // Elements per thread of the row (col = false) or column transforms of length L.
@@ -1473,7 +1194,7 @@ static void launch_row_inv_t(const float2* spec, const float* phi_in, float* phi
     auto k = lr == 3 ? k_row_inv<N, 3> : lr == 2 ? k_row_inv<N, 2> : k_row_inv<N, 0>;
     launch_iter(k, dim3(nb, 1, nz), dim3(((1 << lr) / 2) * NT), lds, st, spec, phi_in, phi_out, stN, M, lr, tol, part,
                 sc);
-    if (tol > 0.0f) hipLaunchKernelGGL(k_fin_inner, dim3(nz), dim3(1024), 0, st, part, nb, tol, sc);
+    if (tol > 0.0f) launch_fin_inner(part, nb, tol, nz, sc, st);
 }
 
 template <int L>
@@ -1486,8 +1207,16 @@ static void set_fft_attrs() {
     for (const void* f : fns) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
+void launch_fin_inner(const double* part, int nb, float tol, int nz, DevScal* sc, hipStream_t st) {
+    hipLaunchKernelGGL(k_fin_inner, dim3(nz), dim3(1024), 0, st, part, nb, tol, sc);
+}
+
 void launch_solve_pass(int pass, const Geometry& geo, const float* rhs, const float* phi_in, float* phi_out,
                        float2* spec, float tol_inner, double* part, int nz, DevScal* sc, hipStream_t st) {
+    if (geo.bc == 1) {   // the DCT-II solve of the mirrored Laplacian (sr_dct.hip)
+        launch_dct_solve_pass(pass, geo, rhs, phi_in, phi_out, spec, tol_inner, part, nz, sc, st);
+        return;
+    }
     const int M = geo.M, N = geo.N;
     if (pass == 0) {
         SR_FFT_DISPATCH(launch_row_fwd_t, N, rhs, spec, geo.stN, M, nz, sc, st);
@@ -1503,92 +1232,6 @@ void launch_solve(const Geometry& geo, const float* rhs, const float* phi_in, fl
                   float tol_inner, double* part, int nz, DevScal* sc, hipStream_t st) {
     for (int pass = 0; pass < 3; ++pass)
         launch_solve_pass(pass, geo, rhs, phi_in, phi_out, spec, tol_inner, part, nz, sc, st);
-}
-
-// ---------------------------------------------------------------------------
-// fused right-hand side + forward row FFT (k_rhs_fwd)
-// ---------------------------------------------------------------------------
-// log2 of the rows per workgroup: 4-row strips (2 transforms) where their
-// workgroup fills a wave (N >= 128), else 8; SR_FUSED_LR (1..3) overrides
-// where the workgroup still holds at least 32 threads.  Measured at 1024^2
-// (per launch): 2 rows 14.7 us, 4 rows 13.3 us, 8 rows 17.0 us (the separate
-// rhs and row-FFT kernels: 11.0 + 5.6 us).
-static int fused_lr(int N) {
-    static const int env = [] {
-        const char* s = std::getenv("SR_FUSED_LR");
-        return s ? std::atoi(s) : 0;
-    }();
-    const int lo = N >= 256 ? 1 : N == 128 ? 2 : 3;
-    const int base = N >= 128 ? 2 : 3;
-    return (env >= lo && env <= 3) ? env : base;
-}
-bool fused_rhs_supported(const Geometry& geo, const KParams& kp) {
-    return geo.bc == 0 && geo.N >= 64 && geo.N <= 1024 && geo.M >= 8 && kp.R >= 0 && kp.R <= kMaxR;
-}
-template <int N, int LR, int R>
-static void launch_rhs_fwd_nlr(const Geometry& geo, const KParams& kp, const float* phi_s, const float* W,
-                               const float* g, const float* D, float2* spec, int nz, DevScal* sc, hipStream_t st,
-                               const FinFold* fold) {
-    using Cs = RhsFwdShape<N, LR, R>;
-    launch_iter(k_rhs_fwd<N, LR, R, 0>, dim3(geo.M >> LR, 1, nz), dim3(Cs::T), Cs::lds_bytes, st, kp, geo.M, phi_s,
-                W, g, D, spec, geo.stN, fold ? fold->part : nullptr, fold ? fold->nb : 0,
-                fold ? fold->rhist : nullptr, sc);
-}
-template <int N, int R>
-static void launch_rhs_fwd_n(const Geometry& geo, const KParams& kp, const float* phi_s, const float* W,
-                             const float* g, const float* D, float2* spec, int nz, DevScal* sc, hipStream_t st,
-                             const FinFold* fold) {
-    const int lr = fused_lr(N);
-    if constexpr (N >= 256) {
-        if (lr == 1) return launch_rhs_fwd_nlr<N, 1, R>(geo, kp, phi_s, W, g, D, spec, nz, sc, st, fold);
-    }
-    if constexpr (N >= 128) {
-        if (lr == 2) return launch_rhs_fwd_nlr<N, 2, R>(geo, kp, phi_s, W, g, D, spec, nz, sc, st, fold);
-    }
-    launch_rhs_fwd_nlr<N, 3, R>(geo, kp, phi_s, W, g, D, spec, nz, sc, st, fold);
-}
-template <int N>
-static void launch_rhs_fwd_r(const Geometry& geo, const KParams& kp, const float* phi_s, const float* W,
-                             const float* g, const float* D, float2* spec, int nz, DevScal* sc, hipStream_t st,
-                             const FinFold* fold) {
-    switch (kp.R) {
-        case 0: launch_rhs_fwd_n<N, 0>(geo, kp, phi_s, W, g, D, spec, nz, sc, st, fold); break;
-        case 1: launch_rhs_fwd_n<N, 1>(geo, kp, phi_s, W, g, D, spec, nz, sc, st, fold); break;
-        case 2: launch_rhs_fwd_n<N, 2>(geo, kp, phi_s, W, g, D, spec, nz, sc, st, fold); break;
-        case 3: launch_rhs_fwd_n<N, 3>(geo, kp, phi_s, W, g, D, spec, nz, sc, st, fold); break;
-        case 4: launch_rhs_fwd_n<N, 4>(geo, kp, phi_s, W, g, D, spec, nz, sc, st, fold); break;
-        case 5: launch_rhs_fwd_n<N, 5>(geo, kp, phi_s, W, g, D, spec, nz, sc, st, fold); break;
-        case 6: launch_rhs_fwd_n<N, 6>(geo, kp, phi_s, W, g, D, spec, nz, sc, st, fold); break;
-        case 7: launch_rhs_fwd_n<N, 7>(geo, kp, phi_s, W, g, D, spec, nz, sc, st, fold); break;
-        case 8: launch_rhs_fwd_n<N, 8>(geo, kp, phi_s, W, g, D, spec, nz, sc, st, fold); break;
-        default: break;
-    }
-}
-void launch_rhs_fwd(const Geometry& geo, const KParams& kp, const float* phi_s, const float* W, const float* g,
-                    const float* D, float2* spec, int nz, DevScal* sc, hipStream_t st, const FinFold* fold) {
-    switch (geo.N) {
-        case 64: launch_rhs_fwd_r<64>(geo, kp, phi_s, W, g, D, spec, nz, sc, st, fold); break;
-        case 128: launch_rhs_fwd_r<128>(geo, kp, phi_s, W, g, D, spec, nz, sc, st, fold); break;
-        case 256: launch_rhs_fwd_r<256>(geo, kp, phi_s, W, g, D, spec, nz, sc, st, fold); break;
-        case 512: launch_rhs_fwd_r<512>(geo, kp, phi_s, W, g, D, spec, nz, sc, st, fold); break;
-        case 1024: launch_rhs_fwd_r<1024>(geo, kp, phi_s, W, g, D, spec, nz, sc, st, fold); break;
-        default: break;
-    }
-}
-template <int N, int R>
-static void set_fused_attrs_nr() {
-    const int bytes = 160 * 1024 - 1024;
-    if constexpr (N >= 256)
-        (void)hipFuncSetAttribute((const void*)k_rhs_fwd<N, 1, R, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    if constexpr (N >= 128)
-        (void)hipFuncSetAttribute((const void*)k_rhs_fwd<N, 2, R, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    (void)hipFuncSetAttribute((const void*)k_rhs_fwd<N, 3, R, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-}
-template <int N>
-static void set_fused_attrs() {
-    set_fused_attrs_nr<N, 0>(); set_fused_attrs_nr<N, 1>(); set_fused_attrs_nr<N, 2>();
-    set_fused_attrs_nr<N, 3>(); set_fused_attrs_nr<N, 4>(); set_fused_attrs_nr<N, 5>();
-    set_fused_attrs_nr<N, 6>(); set_fused_attrs_nr<N, 7>(); set_fused_attrs_nr<N, 8>();
 }
 
 // Tile height of the right-hand-side kernel: the context's (from the
@@ -1749,18 +1392,6 @@ void launch_set_D(const Geometry& geo, const float* W, const float* B, float* D,
     hipLaunchKernelGGL(kern, grd, blk, 0, st, W, B, D, geo.M, geo.N, mu);
 }
 
-void launch_solve_neumann_pass(int pass, const Geometry& xgeo, const float* rhs, const float* phi_in,
-                               float* phi_out, float* xr, float* xd, float2* xspec, int nz, DevScal* sc,
-                               hipStream_t st) {
-    const int M = xgeo.M / 2, N = xgeo.N / 2;
-    if (pass == 0)
-        hipLaunchKernelGGL(k_mirror_ext, dim3((2 * N + 255) / 256, 2 * M, nz), dim3(256), 0, st, rhs, xr, M, N, sc);
-    launch_solve_pass(pass, xgeo, xr, nullptr, xd, xspec, 0.0f, nullptr, nz, sc, st);
-    if (pass == 2)
-        hipLaunchKernelGGL(k_restrict_add, dim3((N + 255) / 256, M, nz), dim3(256), 0, st, xd, phi_in, phi_out, M, N,
-                           sc);
-}
-
 void launch_reset_scal(DevScal* sc, int n, int active, hipStream_t st) {
     hipLaunchKernelGGL(k_reset_scal, dim3((n + 63) / 64), dim3(64), 0, st, sc, n, active);
 }
@@ -1788,8 +1419,8 @@ void configure_kernels() {
     (void)hipFuncSetAttribute((const void*)k_repulsion<kTH, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     set_fft_attrs<8>(); set_fft_attrs<16>(); set_fft_attrs<32>(); set_fft_attrs<64>(); set_fft_attrs<128>();
     set_fft_attrs<256>(); set_fft_attrs<512>(); set_fft_attrs<1024>(); set_fft_attrs<2048>(); set_fft_attrs<4096>();
-    set_fused_attrs<64>(); set_fused_attrs<128>(); set_fused_attrs<256>(); set_fused_attrs<512>();
-    set_fused_attrs<1024>();
+    configure_fused();
+    configure_dct();
     done = true;
 }
 }  // namespace sr

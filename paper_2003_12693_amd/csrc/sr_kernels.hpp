@@ -19,6 +19,11 @@ struct Geometry {
     float taumu;
     int tile_th = 0;   // stencil tile height (16 or 32); 0 = size heuristic
     int bc = 0;        // boundaries: 0 periodic, 1 Neumann (mirror ghosts)
+    // Neumann (DCT-II) solve: exp(-i pi k / (2L)) for k < L, and 2 cos(pi k / L)
+    const float2* dtM = nullptr;
+    const float2* dtN = nullptr;
+    const float* cM = nullptr;
+    const float* cN = nullptr;
 };
 
 int tile_blocks(int M, int N);
@@ -58,16 +63,22 @@ void launch_rhs(const Geometry& geo, const KParams& kp, const float* phi_s, cons
 // launch_solve_pass would from the rhs plane).  Only where
 // fused_rhs_supported (periodic, 64 <= N <= 1024).
 bool fused_rhs_supported(const Geometry& geo, const KParams& kp);
+void configure_fused();   // dynamic LDS limits of the fused kernels (once per process)
 void launch_rhs_fwd(const Geometry& geo, const KParams& kp, const float* phi_s, const float* W, const float* g,
                     const float* D, float2* spec, int nz, DevScal* sc, hipStream_t st, const FinFold* fold = nullptr);
 // Pass `pass` (0..2) of the Neumann solve (phi_out = phi_in + u, phi_in
-// nullable, with (1 - tau mu Lap) u = rhs for the mirrored Laplacian) as the
-// periodic solve on the 2M x 2N mirror extension: xgeo is the 2M x 2N
-// geometry, xr / xd two 4MN-float planes per instance, xspec its spectrum;
-// pass 0 also writes the extension, pass 2 also the restriction.
-void launch_solve_neumann_pass(int pass, const Geometry& xgeo, const float* rhs, const float* phi_in,
-                               float* phi_out, float* xr, float* xd, float2* xspec, int nz, DevScal* sc,
-                               hipStream_t st);
+// nullable, with (1 - tau mu Lap) u = rhs for the mirrored Laplacian): the
+// DCT-II passes of sr_dct.hip, same shapes and spectrum layout as the
+// periodic passes.  launch_solve_pass calls it when geo.bc = 1.
+void launch_dct_solve_pass(int pass, const Geometry& geo, const float* rhs, const float* phi_in, float* phi_out,
+                           float2* spec, float tol_inner, double* part, int nz, DevScal* sc, hipStream_t st);
+void configure_dct();
+// Shapes of the FFT passes: log2 rows per workgroup of the row passes, and
+// columns per workgroup of the column pass.
+int fft_row_split(int M, int N, int nz, int min_wg, int min_lr);
+int fft_col_group(int M, int N, int nz);
+// The inner stop rule's finalize after an inverse row pass's partial sums.
+void launch_fin_inner(const double* part, int nb, float tol, int nz, DevScal* sc, hipStream_t st);
 void launch_solve(const Geometry& geo, const float* rhs, const float* phi_in, float* phi_out, float2* spec,
                   float tol_inner, double* part, int nz, DevScal* sc, hipStream_t st);
 // The three passes of launch_solve separately (pass 0: forward rows,

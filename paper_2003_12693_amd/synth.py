@@ -241,23 +241,47 @@ def annuli(M=4096, N=4096, seed=3, n_shapes=64, axis_lo=60.0, axis_hi=240.0,
 BATCH_SIZES = ((128, 128), (256, 256), (512, 512), (256, 512), (512, 1024))
 
 
-def batch_items(count=256, size_seed=4999, seed0=4000):
-    """Instance list: (M, N, R, f, phi0) with sizes drawn uniformly from
-    BATCH_SIZES, R ~ U{3, 4, 5}, and an ``ellipses`` image whose shape count and
-    axes scale with the area."""
+def batch_sizes(count=256, size_seed=4999):
+    """(M, N, R) of the first `count` instances of the batched workload:
+    sizes drawn uniformly from BATCH_SIZES, R ~ U{3, 4, 5}."""
     rs = _rng(size_seed)
-    items = []
-    for k in range(count):
+    out = []
+    for _ in range(count):
         M, N = BATCH_SIZES[rs.integers(len(BATCH_SIZES))]
-        R = int(rs.integers(3, 6))
-        area = M * N / (1024.0 * 1024.0)
-        n = max(1, int(round(12 * area)))
-        s = math.sqrt(area)
-        lo = min(max(30.0 * s, 8.0), 0.3 * min(M, N))
-        hi = min(max(120.0 * s, 8.0), 0.3 * min(M, N))
-        f, phi0 = ellipses(M, N, seed=seed0 + k, n_shapes=n, axis_lo=lo, axis_hi=hi)
-        items.append((M, N, R, f, phi0))
-    return items
+        out.append((M, N, int(rs.integers(3, 6))))
+    return out
+
+
+def batch_instance(k, M, N, seed0=4000):
+    """Image and initial level set of instance k (size M x N): an
+    ``ellipses`` image whose shape count and axes scale with the area."""
+    area = M * N / (1024.0 * 1024.0)
+    n = max(1, int(round(12 * area)))
+    s = math.sqrt(area)
+    lo = min(max(30.0 * s, 8.0), 0.3 * min(M, N))
+    hi = min(max(120.0 * s, 8.0), 0.3 * min(M, N))
+    return ellipses(M, N, seed=seed0 + k, n_shapes=n, axis_lo=lo, axis_hi=hi)
+
+
+def batch_items(count=256, size_seed=4999, seed0=4000):
+    """Instance list: (M, N, R, f, phi0) of the batched workload."""
+    return [(M, N, R) + tuple(batch_instance(k, M, N, seed0))
+            for k, (M, N, R) in enumerate(batch_sizes(count, size_seed))]
+
+
+def batch_subset(n=32, count=256, size_seed=4999):
+    """Indices of a size-stratified subset of the batched workload: the
+    first instances of each size class in turn (round robin over the
+    classes in the order of BATCH_SIZES), n in all."""
+    sizes = batch_sizes(count, size_seed)
+    by = {sz: [k for k, (M, N, R) in enumerate(sizes) if (M, N) == sz] for sz in BATCH_SIZES}
+    out, r = [], 0
+    while len(out) < n:
+        for sz in BATCH_SIZES:
+            if r < len(by[sz]) and len(out) < n:
+                out.append(by[sz][r])
+        r += 1
+    return sorted(out)
 
 
 # --------------------------------------------------------------------------

@@ -172,21 +172,20 @@ def test_aos_phi_solver_parameters(sr):
 
 
 def test_boundary_parameter(sr):
-    """bc is validated before any HIP call: 0 (periodic) / 1 (Neumann) only;
-    the Neumann FFT solve runs on the 2M x 2N mirror extension (M, N <= 2048,
-    fixed S, workspace for the extension), the Neumann AOS solve needs none."""
+    """bc is validated before any HIP call: 0 (periodic) / 1 (Neumann) only.
+    The Neumann solve is the DCT-II one on the grid itself: every size the
+    periodic solve takes (up to 4096 per side, the inner stop rule allowed),
+    and the same workspace as the periodic solve."""
     assert sr.sr_params_default().bc == 0
     with pytest.raises(sr.SRError) as e:
         sr.sr_workspace_size(64, 64, sr.sr_params_default(bc=2))
     assert e.value.code == sr.SR_EINVAL
-    for M, N, kw in ((4096, 64, {}), (64, 4096, {}), (64, 64, dict(tol_inner=1e-3))):
-        with pytest.raises(sr.SRError) as e:
-            sr.sr_workspace_size(M, N, sr.sr_params_default(bc=1, **kw))
-        assert e.value.code == sr.SR_EUNSUPPORTED
     base = sr.sr_workspace_size(64, 64, sr.sr_params_default())
     assert sr.sr_workspace_size(64, 64, sr.sr_params_default(bc=1, phi_solver=1)) == base
-    assert sr.sr_workspace_size(64, 64, sr.sr_params_default(bc=1)) >= base + 3 * 4 * 64 * 64 * 4
-    assert sr.sr_workspace_size(2048, 2048, sr.sr_params_default(bc=1)) > 0
+    assert sr.sr_workspace_size(64, 64, sr.sr_params_default(bc=1)) == base
+    assert sr.sr_workspace_size(64, 64, sr.sr_params_default(bc=1, tol_inner=1e-3)) == base
+    assert sr.sr_workspace_size(4096, 4096, sr.sr_params_default(bc=1)) == sr.sr_workspace_size(
+        4096, 4096, sr.sr_params_default())
 
 
 def test_every_3d_symbol_is_exported_and_validated(sr):

@@ -104,6 +104,42 @@ def test_batch_against_oracle(sr, k):
         _note(f"  {M}x{N} R{R}: worst phi error {ratio:.3f} of the bar, {int(flips.sum())} gate flips")
 
 
+def test_batch_stratified_subset_against_oracle(sr):
+    """32 instances of the 256-instance batched workload itself (7, 7, 6, 6, 6
+    of the five sizes, R 3-5, the workload's seeds), solved together for 5
+    iterations and for 6; each instance's sixth iteration is compared with
+    one oracle iteration from its state after 5 (teacher forcing through the
+    batch) by the element-wise bars."""
+    _note("batch stratified 32-instance subset vs oracle")
+    from tests.parity import check_phi, check_w_b, phi_tol
+    sizes = synth.batch_sizes(256)
+    sub = synth.batch_subset(32)
+    inst = [sizes[k] + tuple(synth.batch_instance(k, sizes[k][0], sizes[k][1])) for k in sub]
+    k = 5
+
+    def run(n):
+        items = [dict(f=_cuda(f), phi0=_cuda(p), max_iter=n, params=gpu_params(R=R, d=float(R)), want_state=True)
+                 for (M, N, R, f, p) in inst]
+        rc, res = sr.solve_batch(items)
+        assert rc == 0 and all(r["iters"] == n for r in res)
+        return [(r["phi"].cpu().numpy(), r["w"].cpu().numpy(), r["b"].cpu().numpy()) for r in res]
+
+    before, after = run(k), run(k + 1)
+    worst, flips_total = 0.0, 0
+    for (M, N, R, f, p), (phi, w, b), (gphi, gw, gb) in zip(inst, before, after):
+        P = oracle_params(R=R, d=float(R))
+        g = O.edge_map(as64(f), P.sigma, P.rho, P.s_exp)
+        start = O.State(as64(phi), as64(w[0]), as64(w[1]), as64(b[0]), as64(b[1]), k)
+        ref, _ = O.sb_iteration(start, g, P)
+        worst = max(worst, check_phi(gphi, ref.phi, start.phi, what=f"{M}x{N} R{R}"))
+        B1, B2, t = O.shrink_input(ref.phi, start.w1, start.w2, start.b1, start.b2, g, P)
+        flips = check_w_b([gw[0], gw[1]], [gb[0], gb[1]], [ref.w1, ref.w2], [ref.b1, ref.b2],
+                          [start.b1, start.b2], [B1, B2], t, P.zero_tol, g, O.dirac(ref.phi, P.eps),
+                          np.pi / (2 * P.eps ** 2), P.gamma / P.mu, phi_tol(ref.phi, start.phi))
+        flips_total += int(flips.sum())
+    _note(f"  32 instances: worst phi error {worst:.3f} of the bar, {flips_total} gate flips in all")
+
+
 def test_batch_tolerance_and_caps(sr):
     _note("batch tolerance")
     inst = _instances()

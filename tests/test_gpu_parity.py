@@ -396,17 +396,24 @@ def test_energy_matches_oracle(sr):
     assert abs(E - sum(ref)) <= 1e-5 * abs(sum(ref))
 
 
-def test_inner_tolerance_matches_oracle(sr):
-    _note("inner tol")
+@pytest.mark.parametrize("bc", [0, 1])
+def test_inner_tolerance_matches_oracle(sr, bc):
+    """The inner stop rule (Sec. 4 after eq 37) takes the same number of inner
+    steps as the oracle, with periodic and with Neumann boundaries (at
+    tol_inner = 1e-3 the oracle stops after 2-4 of the 6 steps; its relative
+    changes stay at least 0.8% away from the tolerance, far outside FP32
+    rounding of that ratio)."""
+    _note(f"inner tol bc={bc}")
     f, phi0 = synth.two_disks()
-    P = oracle_params(tol_inner=2e-4, S=6)
-    st, g, _ = O.solve(as64(f), as64(phi0), P, 5)
+    P = oracle_params(tol_inner=1e-3, S=6, bc=bc)
+    g = O.edge_map(as64(f), P.sigma, P.rho, P.s_exp, bc)
     steps_ref = []
-    st2 = O.initial_state(as64(phi0))
+    st = O.initial_state(as64(phi0), bc)
     for _ in range(5):
-        st2, info = O.sb_iteration(st2, g, P)
+        st, info = O.sb_iteration(st, g, P)
         steps_ref.append(info["inner_steps"])
-    s = sr.Solver(128, 128, gpu_params(tol_inner=2e-4, S=6))
+    assert min(steps_ref) < 6
+    s = sr.Solver(128, 128, gpu_params(tol_inner=1e-3, S=6, bc=bc))
     s.set_image(_cuda(f), _cuda(phi0))
     res = s.step(5)
     assert res["inner_steps"] == sum(steps_ref), (res, steps_ref)
@@ -576,11 +583,11 @@ def test_repulsion_neumann(sr, shape, R, d):
 
 
 @pytest.mark.parametrize("shape", [(8, 8), (8, 16), (16, 8), (32, 32), (128, 128), (64, 2048), (2048, 64),
-                                   (256, 512), (1024, 1024)])
+                                   (256, 512), (1024, 1024), (4096, 8), (8, 4096), (4096, 4096)])
 @pytest.mark.parametrize("tau,mu", [(0.1, 8.0), (0.4, 0.1)])
 def test_implicit_solve_neumann(sr, shape, tau, mu):
-    """The Neumann (DCT-II) solve of (1 - tau mu Lap) u = F, run as the
-    periodic FFT solve of the mirror extension, against the oracle's DCT."""
+    """The Neumann (DCT-II) solve of (1 - tau mu Lap) u = F through the
+    reordered-FFT DCT passes, against the oracle's DCT (SciPy)."""
     _note(f"implicit_solve neumann {shape} tau={tau} mu={mu}")
     M, N = shape
     rng = np.random.default_rng(M * 11 + N)
@@ -616,7 +623,8 @@ def test_teacher_forced_neumann(sr, kw, k, solver, monkeypatch):
 
 
 @pytest.mark.parametrize("solver", ["fft", "gather", "slide"])
-@pytest.mark.parametrize("shape", [(64, 64), (256, 128), (64, 512), (32, 1024), (8, 8), (16, 128)])
+@pytest.mark.parametrize("shape", [(64, 64), (256, 128), (64, 512), (32, 1024), (8, 8), (16, 128), (4096, 8),
+                                   (8, 4096), (2048, 32)])
 def test_teacher_forced_neumann_shapes(sr, shape, solver, monkeypatch):
     """Neumann boundaries on non-square and tiny grids, with contour and noise
     touching the edges, so that every boundary rule is exercised."""
@@ -638,6 +646,21 @@ def test_teacher_forced_neumann_shapes(sr, shape, solver, monkeypatch):
     st.b2 = 0.2 * rng.normal(size=shape)
     tf = _teacher_forced(sr, f, P, st, kw, M, N)
     _verify(tf, P, frac=2e-3)
+
+
+def test_teacher_forced_neumann_c2_full_size(sr):
+    """The 1024 x 1024 benchmark workload with Neumann boundaries: one outer
+    iteration (fused right-hand side with the row DCT, column DCT solve,
+    inverse row DCT) from the oracle's state after two iterations."""
+    _note("teacher forced neumann 1024^2")
+    f, phi0 = synth.ellipses()
+    P = oracle_params(bc=1)
+    g = O.edge_map(as64(f), P.sigma, P.rho, P.s_exp, P.bc)
+    st = O.initial_state(as64(phi0), 1)
+    for _ in range(2):
+        st, _ = O.sb_iteration(st, g, P)
+    tf = _teacher_forced(sr, f, P, st, dict(bc=1), 1024, 1024)
+    _verify(tf, P)
 
 
 @pytest.mark.parametrize("phi_solver", [0, 1])
