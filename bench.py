@@ -217,6 +217,37 @@ def volume_bench(S, steps, warmup, cpu):
     return out
 
 
+def converge_bench(name, tol, cap, min_iter, check_every):
+    """Time-to-converge of one workload under Algorithm 1's stop rule read as
+    the relative phi change r_k < tol (after min_iter), checked every
+    check_every iterations, capped at cap: set_image (edge map, initial
+    state) plus the iterations, with f and phi0 already in HBM."""
+    import torch
+    from paper_2003_12693_amd import sr
+    wl = dict(WORKLOADS[name])
+    M, N = wl["M"], wl["N"]
+    f, phi0 = make_input(name)
+    kw = dict(params_kw(wl), tol_outer=tol, min_iter=min_iter, check_every=check_every)
+    s = sr.Solver(M, N, device="cuda:0", **kw)
+    ft = torch.from_numpy(f.astype(np.float32)).cuda()
+    pt = torch.from_numpy(phi0.astype(np.float32)).cuda()
+    s.set_image(ft, pt)          # warm-up: code objects and graphs
+    s.step(check_every)
+    s.prepare()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.set_image(ft, pt)
+    info = s.step(cap)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    E, _ = s.energy()
+    return {"metric": f"time-to-converge at {M}x{N} (r_k < {tol} after {min_iter}, checked every {check_every}, "
+                      f"cap {cap})", "value": round(t, 4), "unit": "s", "higher_is_better": False,
+            "iterations": info["k"], "converged": info["converged"], "r_last": info["r_last"],
+            "ms_per_iteration": round(t * 1e3 / max(info["k"], 1), 4), "energy": E,
+            "n_gpus": 1, "dtype": "f32", "data": "synthetic", "config": {"workload": wl["text"]}}
+
+
 def batch_bench(count, cap, tol, cpu):
     """Time-to-converge of `count` uneven instances: one sr_solve_batch call
     against sequential plain solves (sr_step with the same stop rule).  With
@@ -461,6 +492,8 @@ def main():
                     help="boundaries: periodic, or Neumann (mirror ghosts; the FFT solve then runs on the "
                          "2M x 2N mirror extension)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB")
+    ap.add_argument("--converge", action="store_true",
+                    help="time-to-converge of the workload: r_k < 1e-4 after 20 iterations, cap 2000")
     ap.add_argument("--batch", type=int, default=0, metavar="COUNT",
                     help="time-to-converge of COUNT uneven instances, batched vs plain")
     ap.add_argument("--cnn", type=int, default=0, metavar="BATCH",
@@ -478,6 +511,9 @@ def main():
         sys.exit(2)
     if args.copy_probe:
         copy_probe(args.copy_probe)
+        return
+    if args.converge:
+        print(json.dumps(converge_bench(args.workload, 1e-4, 2000, 20, 10)), flush=True)
         return
     if args.batch:
         print(json.dumps(batch_bench(args.batch, 500, 1e-4, not args.no_cpu_baseline)), flush=True)

@@ -278,7 +278,7 @@ def test_teacher_forced_aos_2048(sr):
     _verify(tf, P)
 
 
-@pytest.mark.parametrize("shape", [(8, 8), (16, 128), (64, 32), (256, 512)])
+@pytest.mark.parametrize("shape", [(8, 8), (16, 128), (64, 32), (256, 512), (8, 4096), (32, 2048), (16, 1024)])
 def test_teacher_forced_shapes(sr, shape):
     """Ragged / tiny grids: tiles larger than the image, wrap-around halos."""
     _note(f"teacher forced shape {shape}")
@@ -294,6 +294,22 @@ def test_teacher_forced_shapes(sr, shape):
     st.b2 = 0.2 * rng.normal(size=shape)
     tf = _teacher_forced(sr, f, P, st, {}, M, N)
     _verify(tf, P, frac=2e-3)
+
+
+@pytest.mark.parametrize("bc", [0, 1])
+def test_teacher_forced_2048_wide_window(sr, bc):
+    """2048 x 2048 ellipses with the 4096^2 workload's window (R = 5,
+    eps = 2): the fused right-hand-side kernel in its column-chunk form for
+    long rows, then the column and inverse row passes, one teacher-forced
+    iteration, periodic and Neumann."""
+    _note(f"teacher forced 2048^2 R=5 bc={bc}")
+    f, phi0 = synth.ellipses(2048, 2048, seed=8)
+    kw = dict(R=5, eps=2.0, d=5.0, bc=bc)
+    P = oracle_params(**kw)
+    g = O.edge_map(as64(f), P.sigma, P.rho, P.s_exp, bc)
+    st, _ = O.sb_iteration(O.initial_state(as64(phi0), bc), g, P)
+    tf = _teacher_forced(sr, f, P, st, kw, 2048, 2048)
+    _verify(tf, P)
 
 
 def test_teacher_forced_c2_full_size(sr):
