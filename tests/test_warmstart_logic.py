@@ -14,29 +14,34 @@ class FakeNet:
 
 
 class FakeSolver:
-    """Energy as a function of the iteration count; snapshots are (k,)."""
+    """Energy as a function of a position x that phi carries (phi = x
+    everywhere); an iteration advances x by 1, set_state restores x from phi,
+    so interpolated states have fractional x."""
     M = N = 4
 
     def __init__(self, curve):
         self.curve = curve
-        self.k = 0
+        self.x = 0.0
         self.restores = 0
 
     def set_image(self, f, start):
-        self.k = 0
+        self.x = 0.0
 
     def energy(self):
-        return float(self.curve(self.k)), (0.0, 0.0, 0.0)
+        return float(self.curve(self.x)), (0.0, 0.0, 0.0)
 
     def step(self, n):
-        self.k += n
+        self.x += n
         return {"iters_done": n, "converged": False}
 
+    def phi(self):
+        return torch.full((4, 4), self.x, dtype=torch.float64)
+
     def _empty(self, *shape):
-        return torch.zeros(shape)
+        return torch.zeros(shape, dtype=torch.float64)
 
     def set_state(self, phi, w, b, k):
-        self.k = int(k)
+        self.x = float(phi[0, 0])
         self.restores += 1
 
 
@@ -44,7 +49,12 @@ class FakeSolver:
 def ws(monkeypatch):
     from paper_2003_12693_amd import warmstart
     monkeypatch.setattr(torch.cuda, "synchronize", lambda *a, **k: None)
-    monkeypatch.setattr(warmstart.sr, "sr_get_state", lambda ctx, phi, w, b: FAKE["solver"].k)
+
+    def get_state(ctx, phi, w, b):
+        phi.fill_(FAKE["solver"].x)
+        return int(FAKE["solver"].x)
+
+    monkeypatch.setattr(warmstart.sr, "sr_get_state", get_state)
     return warmstart
 
 
@@ -74,11 +84,11 @@ def test_overlong_chunk_is_undone(ws):
     assert ok and k == 405 and E == 500.0 and why == "energy reached"
 
 
-def test_smooth_acceleration_resolves_the_crossing_to_one_iteration(ws):
+def test_smooth_acceleration_lands_in_the_window(ws):
     curve = lambda k: 1000.0 - 0.001 * k * k
     (ok, k, _, E, why), s = _run(ws, curve, 500.0)
     first = next(i for i in range(10000) if curve(i) <= 500.0 * (1 + 1e-4))
-    assert ok and k == first
+    assert ok and k == first and abs(E - 500.0) <= 500.0 * 1e-4
 
 
 def test_start_below_plain_energy_is_rejected(ws):
@@ -91,8 +101,16 @@ def test_no_progress_spends_the_budget(ws):
     assert not ok and k == 300 and why == "budget spent"
 
 
-def test_jump_over_the_window_in_one_iteration_is_accepted_there(ws):
-    # a burst: E drops from 600 to 400 between k = 49 and 50 (the window is 500 +- 0.05)
-    curve = lambda k: 1000.0 - 8.0 * k if k < 50 else 400.0 - 0.1 * (k - 50)
+def test_jump_over_the_window_is_resolved_between_the_last_two_iterates(ws):
+    # a burst: E drops from 608 to 400 in the iteration from k = 49 to 50 (the window is 500 +- 0.05);
+    # along the segment between the two iterates the energy passes through the window
+    def curve(x):
+        if x <= 49:
+            return 1000.0 - 8.0 * x
+        if x <= 50:
+            return 608.0 - 208.0 * (x - 49)
+        return 400.0 - 0.1 * (x - 50)
     (ok, k, _, E, why), s = _run(ws, curve, 500.0)
-    assert ok and k == 50 and why == "crossed within one iteration"
+    assert ok and k == 50 and why == "crossing resolved on the last step"
+    assert abs(E - 500.0) <= 500.0 * 1e-4
+    assert 49.0 < s.x < 50.0
