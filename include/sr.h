@@ -260,9 +260,10 @@ int sr_profile_kernels(sr_ctx* ctx, int32_t n_iter, double ms[SR_NUM_KERNEL_KIND
 int sr_autotune(sr_ctx* ctx, int32_t reps, int32_t* tile_th, double us_out[3]);
 
 /* ---- launch preparation -------------------------------------------------
- * sr_step replays HIP graphs of one, two and eight outer iterations (one
- * set per parity of the w / b ping-pong), capturing each the first time it
- * is needed.  sr_prepare captures and instantiates all six now, without
+ * sr_step replays HIP graphs of 1, 2, 4, 8 and 16 outer iterations (one
+ * set per parity of the w / b ping-pong; n iterations are split into powers
+ * of two, largest first), capturing each the first time it is needed.
+ * sr_prepare captures and instantiates all ten now, without
  * running any kernel or changing the state, so that a later sr_step spends
  * no time on capture (e.g. before a timed region).  sr_autotune drops the
  * graphs when it changes the tile height; call sr_prepare after it.

@@ -184,6 +184,8 @@ struct Bufs {
     float* X[2];   // intermediate w of the fixed-point sweeps (when allocated)
 };
 
+constexpr int kGraphLevels = 5;   // graphs of 1, 2, 4, 8 and 16 iterations
+
 struct sr_ctx {
     int M, N, nz;
     sr_params p;
@@ -192,9 +194,9 @@ struct sr_ctx {
     Bufs b;
     hipStream_t stream;
     hipStream_t cap;           // capture stream (graphs are replayed on `stream`)
-    hipGraphExec_t g1[2] = {nullptr, nullptr};   // one iteration from parity p
-    hipGraphExec_t g2[2] = {nullptr, nullptr};   // two iterations from parity p
-    hipGraphExec_t g8[2] = {nullptr, nullptr};   // eight iterations from parity p
+    // graphs of 2^j outer iterations (j = 0..kGraphLevels-1) from parity p
+    hipGraphExec_t gr[kGraphLevels][2] = {};
+    DevScal* hscal = nullptr;  // pinned host copy of the scalar block (read back after every sr_step)
     bool use_graphs = true;
     bool fused = false;        // rhs fused with the forward row FFT (sr::fused_rhs_supported)
     int parity = 0;            // state in W[parity], B[parity]
@@ -416,6 +418,9 @@ static int capture(sr_ctx* c, int p, int iters, hipGraphExec_t* out) {
     e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e != hipSuccess) return fail(SR_EHIP, "graph instantiate: %s", hipGetErrorString(e));
+    // upload now, so that the first replay does not pay for it
+    e = hipGraphUpload(*out, c->stream);
+    if (e != hipSuccess) return fail(SR_EHIP, "graph upload: %s", hipGetErrorString(e));
     return SR_OK;
 }
 
@@ -462,15 +467,17 @@ static int tune_tiles(sr_ctx* c, int reps, double us_out[3]) {
 }
 
 static void drop_graphs(sr_ctx* c) {
-    for (int p = 0; p < 2; ++p) {
-        if (c->g1[p]) (void)hipGraphExecDestroy(c->g1[p]);
-        if (c->g2[p]) (void)hipGraphExecDestroy(c->g2[p]);
-        if (c->g8[p]) (void)hipGraphExecDestroy(c->g8[p]);
-        c->g1[p] = c->g2[p] = c->g8[p] = nullptr;
-    }
+    for (int j = 0; j < kGraphLevels; ++j)
+        for (int p = 0; p < 2; ++p) {
+            if (c->gr[j][p]) (void)hipGraphExecDestroy(c->gr[j][p]);
+            c->gr[j][p] = nullptr;
+        }
 }
 
-// Enqueue n outer iterations on the context's stream.
+// Enqueue n outer iterations on the context's stream: n split into powers of
+// two, largest first, one graph replay each (20 iterations: 16 + 4).  The
+// w / b ping-pong keeps its parity across an even-length graph; only the
+// one-iteration graph flips it.
 static int enqueue_iters(sr_ctx* c, int n) {
     while (n > 0) {
         const int p = c->parity;
@@ -482,23 +489,13 @@ static int enqueue_iters(sr_ctx* c, int n) {
             n -= 1;
             continue;
         }
-        if (n >= 8) {
-            if (!c->g8[p]) { int rc = capture(c, p, 8, &c->g8[p]); if (rc) return rc; }
-            HIP_TRY(hipGraphLaunch(c->g8[p], c->stream));
-            c->k += 8;
-            n -= 8;
-        } else if (n >= 2) {
-            if (!c->g2[p]) { int rc = capture(c, p, 2, &c->g2[p]); if (rc) return rc; }
-            HIP_TRY(hipGraphLaunch(c->g2[p], c->stream));
-            c->k += 2;
-            n -= 2;
-        } else {
-            if (!c->g1[p]) { int rc = capture(c, p, 1, &c->g1[p]); if (rc) return rc; }
-            HIP_TRY(hipGraphLaunch(c->g1[p], c->stream));
-            c->parity ^= 1;
-            c->k += 1;
-            n -= 1;
-        }
+        int j = kGraphLevels - 1;
+        while ((1 << j) > n) --j;
+        if (!c->gr[j][p]) { int rc = capture(c, p, 1 << j, &c->gr[j][p]); if (rc) return rc; }
+        HIP_TRY(hipGraphLaunch(c->gr[j][p], c->stream));
+        if (j == 0) c->parity ^= 1;
+        c->k += 1 << j;
+        n -= 1 << j;
     }
     return SR_OK;
 }
@@ -517,8 +514,9 @@ static int copy_out(sr_ctx* c, void* dst, const void* src, size_t bytes, uint32_
 }
 
 static int read_scal(sr_ctx* c, DevScal* out) {
-    HIP_TRY(hipMemcpyAsync(out, c->b.scal, sizeof(DevScal), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->hscal, c->b.scal, sizeof(DevScal), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
+    *out = *c->hscal;
     return SR_OK;
 }
 
@@ -605,14 +603,21 @@ int sr_create(sr_ctx** out, int32_t M, int32_t N, const sr_params* p, void* work
     const char* th = std::getenv("SR_TILE_TH");
     c->geo.tile_th = th ? std::atoi(th) : tuned_tile_height(M, N, c->kp.R, 1);
 
-    hipError_t e = hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking);
-    if (e != hipSuccess) { delete c; return fail(SR_EHIP, "hipStreamCreate: %s", hipGetErrorString(e)); }
+    hipError_t e = hipHostMalloc((void**)&c->hscal, sizeof(DevScal), hipHostMallocDefault);
+    if (e != hipSuccess) { delete c; return fail(SR_EHIP, "hipHostMalloc: %s", hipGetErrorString(e)); }
+    e = hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        (void)hipHostFree(c->hscal);
+        delete c;
+        return fail(SR_EHIP, "hipStreamCreate: %s", hipGetErrorString(e));
+    }
     e = upload_tables(c->b, M, N, c->stream);
     if (e == hipSuccess) e = upload_aos(c, c->stream);
     if (e == hipSuccess) { sr::launch_reset_scal(c->b.scal, 1, 1, c->stream); e = hipGetLastError(); }
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {
         (void)hipStreamDestroy(c->cap);
+        (void)hipHostFree(c->hscal);
         delete c;
         return fail(SR_EHIP, "sr_create upload: %s", hipGetErrorString(e));
     }
@@ -622,12 +627,9 @@ int sr_create(sr_ctx** out, int32_t M, int32_t N, const sr_params* p, void* work
 
 void sr_destroy(sr_ctx* c) {
     if (!c) return;
-    for (int i = 0; i < 2; ++i) {
-        if (c->g1[i]) (void)hipGraphExecDestroy(c->g1[i]);
-        if (c->g2[i]) (void)hipGraphExecDestroy(c->g2[i]);
-        if (c->g8[i]) (void)hipGraphExecDestroy(c->g8[i]);
-    }
+    drop_graphs(c);
     (void)hipStreamDestroy(c->cap);
+    (void)hipHostFree(c->hscal);
     delete c;
 }
 
@@ -834,9 +836,8 @@ int sr_prepare(sr_ctx* c) {
     if (!c->use_graphs) return SR_OK;
     for (int p = 0; p < 2; ++p) {
         int rc = SR_OK;
-        if (!c->g1[p]) rc = capture(c, p, 1, &c->g1[p]);
-        if (!rc && !c->g2[p]) rc = capture(c, p, 2, &c->g2[p]);
-        if (!rc && !c->g8[p]) rc = capture(c, p, 8, &c->g8[p]);
+        for (int j = 0; j < kGraphLevels && rc == SR_OK; ++j)
+            if (!c->gr[j][p]) rc = capture(c, p, 1 << j, &c->gr[j][p]);
         if (rc) return rc;
     }
     return SR_OK;
