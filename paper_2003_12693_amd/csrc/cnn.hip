@@ -181,6 +181,12 @@ __global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a, int tiles_per_bloc
     constexpr int NKS = (9 * KC + 31) / 32;
     constexpr int ITEMS = (SR * SC * G8 + 255) / 256;   // staged 16-byte items per thread
     __shared__ __attribute__((aligned(16))) uint16_t tile[SR * SC * PITCH];
+    // the block's weight panel for one channel chunk: row = output channel
+    // (16 NT of them), column = reduction index tap * KC + ci; a 16-byte pad
+    // per row spreads neighbouring rows over the LDS banks
+    constexpr int WP = 9 * KC + 8, WG8 = 9 * KC / 8, WN = 16 * NT * WG8;
+    constexpr int WITEMS = (WN + 255) / 256;   // staged 16-byte items per thread
+    __shared__ __attribute__((aligned(16))) uint16_t wpan[16 * NT * WP];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int g = lane >> 4, r = lane & 15;
     const int tiles_w = a.W / kTileC, tiles_h = (a.H + kTileR - 1) / kTileR;
@@ -198,9 +204,19 @@ __global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a, int tiles_per_bloc
     for (int m = 0; m < 4; ++m)
 #pragma unroll
         for (int u = 0; u < NT; ++u) acc[m][u] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const uint16_t* wrow[NT];
+    // global -> LDS: the weight panel of channel chunk c0
+    auto wstage = [&](int c0) {
 #pragma unroll
-    for (int u = 0; u < NT; ++u) wrow[u] = a.w + (size_t)(cbase + u * 16 + r) * a.kpad;
+        for (int it = 0; it < WITEMS; ++it) {
+            const int e = t + 256 * it;
+            if (e < WN) {
+                const int row = e / WG8, kk = 8 * (e - row * WG8);
+                const int tap = kk / KC, ci = kk - tap * KC;
+                *(uint4*)&wpan[row * WP + kk] =
+                    *(const uint4*)(a.w + (size_t)(cbase + row) * a.kpad + tap * cin + c0 + ci);
+            }
+        }
+    };
 
     // global -> registers for step `step` (tile tl0 + step / nch, channel chunk step % nch)
     uint4 pre[ITEMS];
@@ -250,6 +266,7 @@ __global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a, int tiles_per_bloc
                 *(uint4*)&tile[px * PITCH + 8 * cg] = pre[it];
             }
         }
+        if (nch > 1 || step == 0) wstage(c0);   // one chunk: the panel stays for every tile
         __syncthreads();
         if (step + 1 < nsteps) fetch(step + 1);   // in flight during the MFMAs below
         if (i0 + row0 < a.H) {
@@ -263,7 +280,7 @@ __global__ __launch_bounds__(256) void k_conv_lds(ConvArgs a, int tiles_per_bloc
 #pragma unroll
                 for (int u = 0; u < NT; ++u) {
                     uint4 w = make_uint4(0u, 0u, 0u, 0u);
-                    if (tv) w = *(const uint4*)(wrow[u] + tap * cin + c0 + cc);
+                    if (tv) w = *(const uint4*)&wpan[(u * 16 + r) * WP + kk];
                     bv[u] = as_bf16x8(w);
                 }
 #pragma unroll
