@@ -150,6 +150,18 @@ k_col_dct_solve(float2* __restrict__ spec, const float* __restrict__ cM, const f
     const int g = threadIdx.x / NT, t = threadIdx.x - g * NT;
     const int col = k0 + g;   // float2 column m: real columns 2m and 2m + 1
     float2* x = xs + g * LD;
+    // the tables the frequency pairs need, loaded with the data (the
+    // transform's barriers would hold them back until after it)
+    const float ca = 4.0f - cN[2 * col], cb = 4.0f - cN[2 * col + 1];
+    float2 dtv[E / 2 + 1];
+    float cl[E / 2 + 1], cr[E / 2 + 1];
+#pragma unroll
+    for (int e = 0; e <= E / 2; ++e) {
+        const int l = e < E / 2 ? t + e * NT : M / 2, lm = (M - l) & (M - 1);
+        dtv[e] = dtM[l];
+        cl[e] = cM[l];
+        cr[e] = cM[lm];
+    }
     constexpr bool PRE = E <= 4;
     float2 twr[TwN<M, E>::v];
     if constexpr (PRE) {
@@ -160,19 +172,17 @@ k_col_dct_solve(float2* __restrict__ spec, const float* __restrict__ cM, const f
     }
     // frequency pair (l, M - l) of both real columns: forward post-twiddle,
     // division by the eigenvalues (1/(MN) folded in), inverse pre-twiddle
-    const float ca = 4.0f - cN[2 * col], cb = 4.0f - cN[2 * col + 1];
-    auto solve_pair = [&](int l) {
+    auto solve_pair = [&](int l, float2 c, float cml, float cmm) {
         const int lm = (M - l) & (M - 1);
         const float2 Zl = x[sk(l)], Zm = x[sk(lm)];
         const float2 Va = make_float2(0.5f * (Zl.x + Zm.x), 0.5f * (Zl.y - Zm.y));
         const float2 Vb = make_float2(0.5f * (Zl.y + Zm.y), -0.5f * (Zl.x - Zm.x));
-        const float2 c = dtM[l];
         const float2 pa = cmul(c, Va), pb = cmul(c, Vb);
         // coefficients Y[l] = Re(c V[l]) and Y[M - l] = -Im(c V[l]) (none for l = 0)
-        const float sl_a = inv_mn * __builtin_amdgcn_rcpf(1.0f + taumu * (ca - cM[l]));
-        const float sl_b = inv_mn * __builtin_amdgcn_rcpf(1.0f + taumu * (cb - cM[l]));
-        const float sm_a = inv_mn * __builtin_amdgcn_rcpf(1.0f + taumu * (ca - cM[lm]));
-        const float sm_b = inv_mn * __builtin_amdgcn_rcpf(1.0f + taumu * (cb - cM[lm]));
+        const float sl_a = inv_mn * __builtin_amdgcn_rcpf(1.0f + taumu * (ca - cml));
+        const float sl_b = inv_mn * __builtin_amdgcn_rcpf(1.0f + taumu * (cb - cml));
+        const float sm_a = inv_mn * __builtin_amdgcn_rcpf(1.0f + taumu * (ca - cmm));
+        const float sm_b = inv_mn * __builtin_amdgcn_rcpf(1.0f + taumu * (cb - cmm));
         const float ua = pa.x * sl_a, ub = pb.x * sl_b;
         const float uam = l ? -pa.y * sm_a : 0.0f, ubm = l ? -pb.y * sm_b : 0.0f;
         // P[l] = conj(c) (U[l] - i U[M - l]) per column, packed a + i b
@@ -182,8 +192,8 @@ k_col_dct_solve(float2* __restrict__ spec, const float* __restrict__ cM, const f
         if (l != lm) x[sk(lm)] = make_float2(Pa.x + Pb.y, Pb.x - Pa.y);
     };
 #pragma unroll
-    for (int e = 0; e < E / 2; ++e) solve_pair(t + e * NT);   // l in [0, M/2)
-    if (t == 0) solve_pair(M / 2);
+    for (int e = 0; e < E / 2; ++e) solve_pair(t + e * NT, dtv[e], cl[e], cr[e]);   // l in [0, M/2)
+    if (t == 0) solve_pair(M / 2, dtv[E / 2], cl[E / 2], cr[E / 2]);
     int t_inv = t;
     asm volatile("" : "+v"(t_inv));
     if constexpr (PRE) fft_lds_pre<M, E, true, false, ONE>(x, twr, t_inv, io);

@@ -525,6 +525,14 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, 1024), amdgpu_waves_per
     const int g = threadIdx.x / NT, t = threadIdx.x - g * NT;
     const int col = k0 + g;
     float2* x = xs + g * LD;
+    // The cosines of the symbol, loaded with the data: the transform's
+    // barriers would keep the compiler from issuing them any earlier than
+    // their use, after the forward transform.
+    const float cn = 2.0f * twN[col].x;
+    float cmv[E / 2 + 1];
+#pragma unroll
+    for (int e = 0; e < E / 2; ++e) cmv[e] = 2.0f * twM[t + e * NT].x;
+    cmv[E / 2] = 2.0f * twM[M / 2].x;
     // up to 2048 points every stage twiddle is loaded once into registers
     // and serves the forward and the inverse transform
     constexpr bool PRE = E <= 4;
@@ -538,10 +546,8 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, 1024), amdgpu_waves_per
     // Divide by the symbol.  The symbol is even in l1, so each thread owns the
     // mirror pair (l, M - l): column 0's two packed real spectra mix Z[l]
     // with conj(Z[M - l]), every other column scales pointwise.
-    const float cn = 2.0f * twN[col].x;
-    auto scale_pair = [&](int l) {
+    auto scale_pair = [&](int l, float cm) {
         const int m = (M - l) & (M - 1);
-        const float cm = 2.0f * twM[l].x;
         float hp, hm;
         // v_rcp_f32 (1 ulp) in place of an IEEE division: the symbol is >= 1
         if (col != 0) {
@@ -558,8 +564,8 @@ __global__ __attribute__((amdgpu_flat_work_group_size(1, 1024), amdgpu_waves_per
         if (m != l) x[sk(m)] = make_float2(hp * zm.x + hm * zl.x, hp * zm.y - hm * zl.y);
     };
 #pragma unroll
-    for (int e = 0; e < E / 2; ++e) scale_pair(t + e * NT);   // l in [0, M/2)
-    if (t == 0) scale_pair(M / 2);
+    for (int e = 0; e < E / 2; ++e) scale_pair(t + e * NT, cmv[e]);   // l in [0, M/2)
+    if (t == 0) scale_pair(M / 2, cmv[E / 2]);
     // A fresh copy of t (through an empty asm) keeps the compiler from holding
     // the forward transform's LDS addresses live across the division.
     int t_inv = t;
