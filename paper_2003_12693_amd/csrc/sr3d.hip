@@ -309,13 +309,27 @@ __global__ __launch_bounds__(fft3_threads(L, G)) void k3_fft(const float* __rest
                                                              const float2* __restrict__ twP, int M, int N, int P,
                                                              int axis, int mode, float taumu, float scale) {
     using S = FftShape3<L, G>;
+    static_assert(S::T % G == 0, "a thread's elements share one line of the block");
     extern __shared__ float2 lds3[];
     constexpr int LP = L + 1;   // line pitch in LDS: strided loads of G lines hit distinct banks
     float2* s0 = lds3;
     float2* s1 = lds3 + G * LP;
+    float2* stw = lds3 + 2 * G * LP;   // this axis's twiddle table, L entries
     const int tid = threadIdx.x;
     const int line0 = blockIdx.x * G;
     const float2* tw = axis == 0 ? twM : axis == 1 ? twN : twP;
+    // The stages read their twiddles from LDS: from memory, each stage would
+    // wait for an L2 round trip before its butterflies.
+    for (int i = tid; i < L; i += S::T) stw[i] = tw[i];
+    // mode 2 (axis 0): this thread's elements all lie on line line0 + tid % G
+    // (the thread count is a multiple of G); the j and k cosines of that line
+    // are loaded with the data
+    float cj = 0.0f, ck = 0.0f;
+    if (mode == 2) {
+        const int l = line0 + tid % G;
+        cj = twN[l / P].x;
+        ck = twP[l % P].x;
+    }
     // element e of the block -> (line g, position n) and its address
     auto addr = [&](int e, int& g, int& pos) -> size_t {
         if (axis == 2) {
@@ -337,7 +351,7 @@ __global__ __launch_bounds__(fft3_threads(L, G)) void k3_fft(const float* __rest
         s0[g * LP + pos] = mode == 0 ? make_float2(rin[o], 0.0f) : C[o];
     }
     __syncthreads();
-    float2* res = stockham<L, G>(s0, s1, tw, mode >= 3);
+    float2* res = stockham<L, G>(s0, s1, stw, mode >= 3);
     if (mode == 2) {
         // line l = j P + k holds frequencies (n, j, k): symbol
         // 1 + tau mu (6 - 2 cos(2 pi n / M) - 2 cos(2 pi j / N) - 2 cos(2 pi k / P))
@@ -346,14 +360,13 @@ __global__ __launch_bounds__(fft3_threads(L, G)) void k3_fft(const float* __rest
         for (int m = 0; m < S::NE; ++m) {
             const int e = tid + m * S::T;
             const int pos = e / G, gg = e - pos * G;
-            const int l = line0 + gg;
-            const float cs = twM[pos].x + twN[l / P].x + twP[l % P].x;
+            const float cs = stw[pos].x + cj + ck;
             const float sym = 1.0f + taumu * (6.0f - 2.0f * cs);
             const float2 z = res[gg * LP + pos];
             res[gg * LP + pos] = make_float2(z.x / sym, z.y / sym);
         }
         __syncthreads();
-        res = stockham<L, G>(res, other, tw, true);
+        res = stockham<L, G>(res, other, stw, true);
     }
 #pragma unroll
     for (int m = 0; m < S::NE; ++m) {
@@ -458,7 +471,7 @@ template <int L, int G>
 void fft_pass_g(sr3_ctx* c, int axis, int mode, const float* rin, float* rout, const float* radd) {
     const int lines = (int)(c->n / L);
     const float scale = 1.0f / (float)c->n;
-    const size_t lds = sizeof(float2) * 2 * G * (L + 1);
+    const size_t lds = sizeof(float2) * (2 * G * (L + 1) + L);
     launch(k3_fft<L, G>, dim3(lines / G), dim3(FftShape3<L, G>::T), lds, c->st, rin, c->C, rout, radd, c->twM,
            c->twN, c->twP, c->M, c->N, c->P, axis, mode, c->taumu, scale);
 }
@@ -474,9 +487,9 @@ void fft_pass_t(sr3_ctx* c, int axis, int mode, const float* rin, float* rout, c
 template <int L>
 void fft_attrs() {
     (void)hipFuncSetAttribute((const void*)k3_fft<L, kLines>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)(sizeof(float2) * 2 * kLines * (L + 1)));
+                              (int)(sizeof(float2) * (2 * kLines * (L + 1) + L)));
     (void)hipFuncSetAttribute((const void*)k3_fft<L, kStridedLines>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)(sizeof(float2) * 2 * kStridedLines * (L + 1)));
+                              (int)(sizeof(float2) * (2 * kStridedLines * (L + 1) + L)));
 }
 
 }  // namespace
