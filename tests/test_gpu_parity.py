@@ -517,10 +517,12 @@ def test_profile_kernels_advance_like_step(sr):
 
 
 def test_graph_replay_matches_direct_launches(sr):
-    """Graph replays (8-, 2- and 1-iteration graphs, the outer-iteration
-    finalize folded into the next iteration's first rhs launch) against
-    direct launches without graphs: bitwise the same phi, and the same k and
-    r_k, with and without the outer stop rule."""
+    """Graph replays (16-, 8-, 4-, 2- and 1-iteration graphs from both
+    parities of the w / b ping-pong: 21 = 16 + 4 + 1, then 11 = 8 + 2 + 1,
+    then 7 = 4 + 2 + 1; the outer-iteration finalize folded into the next
+    iteration's first rhs launch) against direct launches without graphs:
+    bitwise the same phi, and the same k and r_k, with and without the outer
+    stop rule."""
     _note("graph replay vs direct launches")
     import os
     f, phi0 = synth.two_disks(seed=3)
@@ -534,7 +536,8 @@ def test_graph_replay_matches_direct_launches(sr):
             finally:
                 os.environ.pop("SR_NO_GRAPH", None)
             s.set_image(_cuda(f), _cuda(phi0))
-            info = s.step(21)
+            for n in (21, 11, 7):
+                info = s.step(n)
             res[mode] = (s.phi().cpu().numpy(), info["k"], info["r_last"], info["converged"])
         a, b = res["direct"], res["graph"]
         assert np.array_equal(a[0], b[0]), kw
