@@ -176,7 +176,11 @@ struct Bufs {
     float2 *twM, *twN, *stM, *stN, *dtM, *dtN;
     float *cM, *cN;
     float* aos;    // AOS tap buffer (sr::aos_tap_buffer layout)
-    float *g, *P0, *P1, *P2, *W[2], *B[2], *D, *Rb;
+    float *g, *W[2], *B[2], *D, *Rb;
+    // phi^k in Ph[parity]: the last inner step of an outer iteration writes
+    // phi^{k+1} into Ph[parity ^ 1] (no copy back); Ph[2] is the spare inner
+    // iterate
+    float* Ph[3];
     float2* spec;
     double* part;
     DevScal* scal;
@@ -199,13 +203,19 @@ struct sr_ctx {
     DevScal* hscal = nullptr;  // pinned host copy of the scalar block (read back after every sr_step)
     bool use_graphs = true;
     bool fused = false;        // rhs fused with the forward row FFT (sr::fused_rhs_supported)
-    int parity = 0;            // state in W[parity], B[parity]
+    int parity = 0;            // state in Ph[parity], W[parity], B[parity]
     long long k = 0;
     bool image_set = false;
     int aosKx = 0, aosKy = 0;  // AOS truncation radii (phi_solver = 1)
     std::vector<float> gauss;  // Gaussian taps
     int gauss_r = 0;
 };
+
+// phi^k of the current state, and the phi planes that hold no state (host
+// staging for the component operators): i = 0 the other half of the pair,
+// i = 1 the spare.
+static float* phi_state(sr_ctx* c) { return c->b.Ph[c->parity]; }
+static float* phi_free(sr_ctx* c, int i) { return i == 0 ? c->b.Ph[c->parity ^ 1] : c->b.Ph[2]; }
 
 static void carve(Bufs& b, char* base, const Layout& L) {
     b.twM = (float2*)(base + L.twM);
@@ -218,9 +228,9 @@ static void carve(Bufs& b, char* base, const Layout& L) {
     b.cN = (float*)(base + L.cN);
     b.aos = (float*)(base + L.aos);
     b.g = (float*)(base + L.g);
-    b.P0 = (float*)(base + L.P0);
-    b.P1 = (float*)(base + L.P1);
-    b.P2 = (float*)(base + L.P2);
+    b.Ph[0] = (float*)(base + L.P0);
+    b.Ph[1] = (float*)(base + L.P1);
+    b.Ph[2] = (float*)(base + L.P2);
     b.W[0] = (float*)(base + L.W0);
     b.W[1] = (float*)(base + L.W1);
     b.B[0] = (float*)(base + L.B0);
@@ -360,8 +370,12 @@ static void enqueue_iteration(sr_ctx* c, int p, hipStream_t st, Hook&& before = 
                               bool fin_out = true) {
     Bufs& b = c->b;
     const int S = c->p.S;
-    const float* in = b.P0;
-    float* outs[2] = {b.P1, b.P2};
+    // phi^k in Ph[p]; the inner iterates alternate between Ph[p ^ 1] and the
+    // spare so that the last one, phi^{k+1}, lands in Ph[p ^ 1]
+    const float* in = b.Ph[p];
+    float* outs[2];
+    outs[(S - 1) & 1] = b.Ph[p ^ 1];
+    outs[S & 1] = b.Ph[2];
     const sr::FinFold fold{b.part, sr::wstep_blocks(c->geo, c->nz), b.rhist};
     for (int s = 0; s < S; ++s) {
         float* out = outs[s & 1];
@@ -392,12 +406,12 @@ static void enqueue_iteration(sr_ctx* c, int p, hipStream_t st, Hook&& before = 
         for (int r = 0; r + 1 < c->p.w_sweeps; ++r) {
             float* w_out = b.X[r & 1];
             before(4);
-            sr::launch_wstep(c->geo, c->kp, in, b.P0, w_in, b.B[p], b.g, w_out, nullptr, nullptr, nullptr,
+            sr::launch_wstep(c->geo, c->kp, in, b.Ph[p], w_in, b.B[p], b.g, w_out, nullptr, nullptr, nullptr,
                              nullptr, c->nz, b.scal, st, false, true);
             w_in = w_out;
         }
     before(4);
-    sr::launch_wstep(c->geo, c->kp, in, b.P0, w_in, b.B[p], b.g, b.W[1 - p], b.B[1 - p], b.D, b.part, b.rhist,
+    sr::launch_wstep(c->geo, c->kp, in, b.Ph[p], w_in, b.B[p], b.g, b.W[1 - p], b.B[1 - p], b.D, b.part, b.rhist,
                      c->nz, b.scal, st, fin_out);
 }
 
@@ -436,10 +450,10 @@ static int tune_tiles(sr_ctx* c, int reps, double us_out[3]) {
     hipError_t e = hipSuccess;
     for (int i = 0; i < 3 && e == hipSuccess; ++i) {
         c->geo.tile_th = kTileHeights[i];
-        sr::launch_rhs(c->geo, c->kp, b.P0, b.W[p], b.g, b.D, b.Rb, c->nz, b.scal, c->stream);
+        sr::launch_rhs(c->geo, c->kp, b.Ph[p], b.W[p], b.g, b.D, b.Rb, c->nz, b.scal, c->stream);
         e = hipEventRecord(e0, c->stream);
         for (int r = 0; r < reps && e == hipSuccess; ++r)
-            sr::launch_rhs(c->geo, c->kp, b.P0, b.W[p], b.g, b.D, b.Rb, c->nz, b.scal, c->stream);
+            sr::launch_rhs(c->geo, c->kp, b.Ph[p], b.W[p], b.g, b.D, b.Rb, c->nz, b.scal, c->stream);
         if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
         if (e == hipSuccess) e = hipEventSynchronize(e1);
         float ms = 0.f;
@@ -641,16 +655,16 @@ int sr_set_image(sr_ctx* c, const float* f, const float* phi0, uint32_t flags) {
     const float* fd = f;
     const float* pd = phi0;
     if (flags & SR_HOST) {
-        int rc = copy_in(c, c->b.P2, f, bytes, flags);
-        if (!rc) rc = copy_in(c, c->b.P1, phi0, bytes, flags);
+        int rc = copy_in(c, c->b.Ph[2], f, bytes, flags);
+        if (!rc) rc = copy_in(c, c->b.Ph[1], phi0, bytes, flags);
         if (rc) return rc;
-        fd = c->b.P2;
-        pd = c->b.P1;
+        fd = c->b.Ph[2];
+        pd = c->b.Ph[1];
     }
     sr::launch_reset_scal(c->b.scal, 1, 1, c->stream);
     sr::launch_edge(c->geo, fd, c->b.Rb, (float*)c->b.spec, c->b.g, c->gauss.data(), c->gauss_r, (float)c->p.rho,
                     c->p.s_exp, c->b.scal, c->stream);
-    sr::launch_init(c->geo, pd, c->b.P0, c->b.W[0], c->b.B[0], c->b.D, (float)c->p.mu, c->p.w0_mode, c->b.scal,
+    sr::launch_init(c->geo, pd, c->b.Ph[0], c->b.W[0], c->b.B[0], c->b.D, (float)c->p.mu, c->p.w0_mode, c->b.scal,
                     c->stream);
     HIP_TRY(hipGetLastError());
     c->parity = 0;
@@ -712,7 +726,7 @@ int sr_step(sr_ctx* c, int32_t n_iter, sr_step_info* info) {
 
 int sr_get_phi(sr_ctx* c, float* phi_out, uint32_t flags) {
     if (!c || !phi_out) return fail(SR_EINVAL, "NULL argument");
-    return copy_out(c, phi_out, c->b.P0, sizeof(float) * c->M * c->N, flags);
+    return copy_out(c, phi_out, phi_state(c), sizeof(float) * c->M * c->N, flags);
 }
 
 int sr_get_g(sr_ctx* c, float* g_out, uint32_t flags) {
@@ -724,7 +738,7 @@ int sr_get_g(sr_ctx* c, float* g_out, uint32_t flags) {
 int sr_energy(sr_ctx* c, double* E_total, double terms[3]) {
     if (!c || !E_total) return fail(SR_EINVAL, "NULL argument");
     if (!c->image_set) return fail(SR_ESTATE, "sr_energy before sr_set_image");
-    sr::launch_energy(c->geo, c->kp, c->b.P0, c->b.g, c->b.part, 1, c->b.scal, c->stream);
+    sr::launch_energy(c->geo, c->kp, phi_state(c), c->b.g, c->b.part, 1, c->b.scal, c->stream);
     HIP_TRY(hipGetLastError());
     DevScal s;
     int rc = read_scal(c, &s);
@@ -737,7 +751,7 @@ int sr_energy(sr_ctx* c, double* E_total, double terms[3]) {
 int sr_get_state(sr_ctx* c, float* phi, float* w, float* b, int64_t* k, uint32_t flags) {
     if (!c || !phi || !w || !b) return fail(SR_EINVAL, "NULL argument");
     const size_t MN = (size_t)c->M * c->N;
-    int rc = copy_out(c, phi, c->b.P0, sizeof(float) * MN, flags, false);
+    int rc = copy_out(c, phi, phi_state(c), sizeof(float) * MN, flags, false);
     if (!rc) rc = copy_out(c, w, c->b.W[c->parity], 2 * sizeof(float) * MN, flags, false);
     if (!rc) rc = copy_out(c, b, c->b.B[c->parity], 2 * sizeof(float) * MN, flags);
     if (rc) return rc;
@@ -751,7 +765,7 @@ int sr_set_state(sr_ctx* c, const float* phi, const float* w, const float* b, in
     if (k < 0) return fail(SR_EINVAL, "k must be >= 0");
     const size_t MN = (size_t)c->M * c->N;
     c->parity = 0;
-    int rc = copy_in(c, c->b.P0, phi, sizeof(float) * MN, flags);
+    int rc = copy_in(c, c->b.Ph[0], phi, sizeof(float) * MN, flags);
     if (!rc) rc = copy_in(c, c->b.W[0], w, 2 * sizeof(float) * MN, flags);
     if (!rc) rc = copy_in(c, c->b.B[0], b, 2 * sizeof(float) * MN, flags);
     if (rc) return rc;
@@ -769,10 +783,10 @@ int sr_edge_map(sr_ctx* c, const float* f, float* g_out, uint32_t flags) {
     const float* fd = f;
     float* gd = g_out;
     if (flags & SR_HOST) {
-        int rc = copy_in(c, c->b.P2, f, bytes, flags);
+        int rc = copy_in(c, phi_free(c, 1), f, bytes, flags);
         if (rc) return rc;
-        fd = c->b.P2;
-        gd = c->b.P1;
+        fd = phi_free(c, 1);
+        gd = phi_free(c, 0);
     }
     sr::launch_edge(c->geo, fd, c->b.Rb, (float*)c->b.spec, gd, c->gauss.data(), c->gauss_r, (float)c->p.rho,
                     c->p.s_exp, c->b.scal, c->stream);
@@ -790,10 +804,10 @@ int sr_repulsion(sr_ctx* c, const float* w, const float* phi, float* v_out, uint
     float* vd = v_out;
     if (flags & SR_HOST) {
         int rc = copy_in(c, c->b.W[q], w, 2 * sizeof(float) * MN, flags);
-        if (!rc) rc = copy_in(c, c->b.P1, phi, sizeof(float) * MN, flags);
+        if (!rc) rc = copy_in(c, phi_free(c, 0), phi, sizeof(float) * MN, flags);
         if (rc) return rc;
         wd = c->b.W[q];
-        pd = c->b.P1;
+        pd = phi_free(c, 0);
         vd = c->b.B[q];
     }
     sr::launch_repulsion(c->geo, c->kp, pd, wd, vd, c->stream);
@@ -808,10 +822,10 @@ int sr_implicit_solve(sr_ctx* c, const float* rhs, float* u_out, uint32_t flags)
     const float* rd = rhs;
     float* ud = u_out;
     if (flags & SR_HOST) {
-        int rc = copy_in(c, c->b.P1, rhs, bytes, flags);
+        int rc = copy_in(c, phi_free(c, 0), rhs, bytes, flags);
         if (rc) return rc;
-        rd = c->b.P1;
-        ud = c->b.P2;
+        rd = phi_free(c, 0);
+        ud = phi_free(c, 1);
     }
     sr::launch_solve(c->geo, rd, nullptr, ud, c->b.spec, 0.0f, c->b.part, 1, c->b.scal, c->stream);
     HIP_TRY(hipGetLastError());
@@ -1010,12 +1024,12 @@ int sr_solve_batch(sr_batch_item* items, int32_t n, void* workspace, size_t byte
         HIP_TRY(hipMemcpy(c.b.scal, hs[gi].data(), sizeof(DevScal) * c.nz, hipMemcpyHostToDevice));
         const size_t MN = (size_t)c.M * c.N;
         for (int z = 0; z < c.nz; ++z) {
-            HIP_TRY(hipMemcpyAsync(c.b.P2 + z * MN, items[idx[z]].f, MN * 4, hipMemcpyDeviceToDevice, st));
-            HIP_TRY(hipMemcpyAsync(c.b.P1 + z * MN, items[idx[z]].phi0, MN * 4, hipMemcpyDeviceToDevice, st));
+            HIP_TRY(hipMemcpyAsync(c.b.Ph[2] + z * MN, items[idx[z]].f, MN * 4, hipMemcpyDeviceToDevice, st));
+            HIP_TRY(hipMemcpyAsync(c.b.Ph[1] + z * MN, items[idx[z]].phi0, MN * 4, hipMemcpyDeviceToDevice, st));
         }
-        sr::launch_edge(c.geo, c.b.P2, c.b.Rb, (float*)c.b.spec, c.b.g, c.gauss.data(), c.gauss_r, (float)c.p.rho,
+        sr::launch_edge(c.geo, c.b.Ph[2], c.b.Rb, (float*)c.b.spec, c.b.g, c.gauss.data(), c.gauss_r, (float)c.p.rho,
                         c.p.s_exp, c.b.scal, st, c.nz);
-        sr::launch_init(c.geo, c.b.P1, c.b.P0, c.b.W[0], c.b.B[0], c.b.D, (float)c.p.mu, c.p.w0_mode, c.b.scal, st,
+        sr::launch_init(c.geo, c.b.Ph[1], c.b.Ph[0], c.b.W[0], c.b.B[0], c.b.D, (float)c.p.mu, c.p.w0_mode, c.b.scal, st,
                         c.nz);
         HIP_TRY(hipGetLastError());
     }
@@ -1102,16 +1116,20 @@ int sr_solve_batch(sr_batch_item* items, int32_t n, void* workspace, size_t byte
     int worst = SR_OK;
     for (int gi = 0; gi < G; ++gi) {
         sr_ctx& c = ctx[gi];
-        sr::launch_energy(c.geo, c.kp, c.b.P0, c.b.g, c.b.part, c.nz, c.b.scal, st);
+        const size_t MN = (size_t)c.M * c.N;
+        // an instance's state is in the ping-pong half of its own iteration
+        // count (retired instances are not advanced further); the energy
+        // kernel reads phi from Ph[0] for every instance
+        for (int z = 0; z < c.nz; ++z)
+            if (hs[gi][z].k & 1)
+                HIP_TRY(hipMemcpyAsync(c.b.Ph[0] + z * MN, c.b.Ph[1] + z * MN, MN * 4, hipMemcpyDeviceToDevice, st));
+        sr::launch_energy(c.geo, c.kp, c.b.Ph[0], c.b.g, c.b.part, c.nz, c.b.scal, st);
         HIP_TRY(hipGetLastError());
         HIP_TRY(hipMemcpyAsync(hs[gi].data(), c.b.scal, sizeof(DevScal) * c.nz, hipMemcpyDeviceToHost, st));
-        const size_t MN = (size_t)c.M * c.N;
         const auto& idx = plan.groups[gi];
         for (int z = 0; z < c.nz; ++z) {
             const sr_batch_item& it = items[idx[z]];
-            HIP_TRY(hipMemcpyAsync(it.phi_out, c.b.P0 + z * MN, MN * 4, hipMemcpyDeviceToDevice, st));
-            // an instance's state is in the ping-pong half of its own iteration
-            // count (retired instances are not advanced further)
+            HIP_TRY(hipMemcpyAsync(it.phi_out, c.b.Ph[0] + z * MN, MN * 4, hipMemcpyDeviceToDevice, st));
             const int par = (int)(hs[gi][z].k & 1);
             if (it.w_out)
                 HIP_TRY(hipMemcpyAsync(it.w_out, c.b.W[par] + 2 * z * MN, 2 * MN * 4, hipMemcpyDeviceToDevice, st));

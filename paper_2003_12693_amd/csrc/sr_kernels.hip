@@ -341,22 +341,25 @@ __global__ __launch_bounds__(kRhsThreads) void k_rhs(KParams kp, int M, int N,
         const int e = tid + u * T;
         const int i = e / TW, j = e - i * TW;
         const int gi = i0 + i, gj = j0 + j;
-        float v1 = 0.0f, v2 = 0.0f;
-#pragma unroll
-        for (int pp = 0; pp <= 2 * R; ++pp) {
-            v1 += kp.taps[pp] * sh1[(i + pp) * TW + j];
-            v2 += kp.taps[pp] * sh2[(i + pp) * TW + j];
-        }
         const float* sp = sphi + (i + 1) * PW + (j + 1);
         const float p = sp[0];
         const float lap = (sp[-PW] + sp[PW]) + (sp[-1] + sp[1]) - 4.0f * p;
-        float dl, ddl, h, dh;
-        dirac_d(p, kp, dl, ddl);
-        band_h_dh(p, kp, h, dh);
-        const float w1 = w1v[u], w2 = w2v[u], gg = gv[u];
-        const float wn = sqrtf(w1 * w1 + w2 * w2);
-        const float force = -kp.gamma * gg * wn * ddl + kp.alpha * gg * dl
-                            + 2.0f * kp.beta * dh * (w1 * v1 + w2 * v2);
+        // the force vanishes outside the band (delta, delta' and h' are 0)
+        float force = 0.0f;
+        if (p <= lim && p >= -lim) {
+            float v1 = 0.0f, v2 = 0.0f;
+#pragma unroll
+            for (int pp = 0; pp <= 2 * R; ++pp) {
+                v1 += kp.taps[pp] * sh1[(i + pp) * TW + j];
+                v2 += kp.taps[pp] * sh2[(i + pp) * TW + j];
+            }
+            float dl, ddl, h, dh;
+            dirac_d(p, kp, dl, ddl);
+            band_h_dh(p, kp, h, dh);
+            const float w1 = w1v[u], w2 = w2v[u], gg = gv[u];
+            const float wn = sqrtf(w1 * w1 + w2 * w2);
+            force = -kp.gamma * gg * wn * ddl + kp.alpha * gg * dl + 2.0f * kp.beta * dh * (w1 * v1 + w2 * v2);
+        }
         if (gi < M && gj < N) out[(size_t)gi * N + gj] = kp.tau * (force + dv[u] + kp.mu * lap);
     }
 }
@@ -717,7 +720,9 @@ __global__ __launch_bounds__(1024) void k_fin_inner(const double* __restrict__ p
 
 // ---------------------------------------------------------------------------
 // w step: B (eq 41), shrink (eq 42) + projection (eq 40) in gate form,
-// Bregman (eq 23), next D = mu div(b - w), outer residual r_k, phi^k <- phi^{k+1}.
+// Bregman (eq 23), next D = mu div(b - w), outer residual r_k.  phi^{k+1}
+// stays where the last inner step wrote it (the caller alternates the phi^k
+// and phi^{k+1} planes with the iteration's parity, as it does w and b).
 // The tile computes w, b on one extra row above and column left so that the
 // backward divergence of its own pixels is local.
 // ---------------------------------------------------------------------------
@@ -736,7 +741,7 @@ struct WTile {
 template <int TH, int R, int TT, int BC>
 __global__ __launch_bounds__(TT) void k_wstep(KParams kp, int M, int N,
                                                         const float* __restrict__ phin,
-                                                        float* __restrict__ P0,
+                                                        const float* __restrict__ Pk,
                                                         const float* __restrict__ Wold,
                                                         const float* __restrict__ Bold,
                                                         const float* __restrict__ g,
@@ -750,7 +755,7 @@ __global__ __launch_bounds__(TT) void k_wstep(KParams kp, int M, int N,
     DevScal& S = sc[z];
     if (!S.active) return;
     const size_t MN = (size_t)M * N;
-    phin += z * MN; P0 += z * MN; Wold += 2 * z * MN; Bold += 2 * z * MN; g += z * MN;
+    phin += z * MN; Pk += z * MN; Wold += 2 * z * MN; Bold += 2 * z * MN; g += z * MN;
     Wnew += 2 * z * MN; Bnew += 2 * z * MN; D += z * MN;
 
     extern __shared__ float lds[];
@@ -792,7 +797,7 @@ __global__ __launch_bounds__(TT) void k_wstep(KParams kp, int M, int N,
 #pragma unroll
     for (int u = 0; u < C::NO; ++u) {
         const int e = tid + u * T;
-        pold[u] = P0[(size_t)bidx<BC>(i0 + e / TW, M) * N + bidx<BC>(j0 + (e % TW), N)];
+        pold[u] = Pk[(size_t)bidx<BC>(i0 + e / TW, M) * N + bidx<BC>(j0 + (e % TW), N)];
     }
     int inband = 0;
 #pragma unroll
@@ -941,7 +946,6 @@ __global__ __launch_bounds__(TT) void k_wstep(KParams kp, int M, int N,
             D[o] = kp.mu * dvv;
             const float pn = sphi[(i + 1) * PW + (j + 1)];
             const float po = pold[u];
-            P0[o] = pn;
             const double df = (double)pn - (double)po;
             sdiff += df * df;
             sold += (double)po * po;
@@ -1256,29 +1260,29 @@ static void launch_rhs_t(const Geometry& geo, const KParams& kp, const float* ph
                 fold ? fold->part : nullptr, fold ? fold->nb : 0, fold ? fold->rhist : nullptr, sc);
 }
 template <int TH, int R, int TT>
-static void launch_wstep_t(const Geometry& geo, const KParams& kp, const float* phin, float* P0, const float* Wold,
+static void launch_wstep_t(const Geometry& geo, const KParams& kp, const float* phin, const float* Pk, const float* Wold,
                            const float* Bold, const float* g, float* Wnew, float* Bnew, float* D, double* part,
                            double* rhist, int sweep, int nz, DevScal* sc, hipStream_t st) {
     launch_iter(geo.bc ? k_wstep<TH, R, TT, 1> : k_wstep<TH, R, TT, 0>, tile_grid(geo.M, geo.N, TH, nz), dim3(TT),
-                sizeof(float) * WTile<TH, R, TT>::lds_floats, st, kp, geo.M, geo.N, phin, P0, Wold, Bold, g, Wnew,
+                sizeof(float) * WTile<TH, R, TT>::lds_floats, st, kp, geo.M, geo.N, phin, Pk, Wold, Bold, g, Wnew,
                 Bnew, D, part, rhist, sweep, sc);
 }
 // The two w-step tile shapes in use: 64 x 32 on 512 threads up to 4 Mpx per
 // launch, 64 x 16 on 256 threads above (measured 16.0 / 171 us against
 // 17.8 / 160 us at 1024^2 / 4096^2).
 template <int TH, int R>
-static void launch_wstep_small(const Geometry& geo, const KParams& kp, const float* phin, float* P0,
+static void launch_wstep_small(const Geometry& geo, const KParams& kp, const float* phin, const float* Pk,
                                const float* Wold, const float* Bold, const float* g, float* Wnew, float* Bnew,
                                float* D, double* part, double* rhist, int sweep, int nz, DevScal* sc,
                                hipStream_t st) {
-    launch_wstep_t<TH, R, 512>(geo, kp, phin, P0, Wold, Bold, g, Wnew, Bnew, D, part, rhist, sweep, nz, sc, st);
+    launch_wstep_t<TH, R, 512>(geo, kp, phin, Pk, Wold, Bold, g, Wnew, Bnew, D, part, rhist, sweep, nz, sc, st);
 }
 template <int TH, int R>
-static void launch_wstep_large(const Geometry& geo, const KParams& kp, const float* phin, float* P0,
+static void launch_wstep_large(const Geometry& geo, const KParams& kp, const float* phin, const float* Pk,
                                const float* Wold, const float* Bold, const float* g, float* Wnew, float* Bnew,
                                float* D, double* part, double* rhist, int sweep, int nz, DevScal* sc,
                                hipStream_t st) {
-    launch_wstep_t<TH, R, 256>(geo, kp, phin, P0, Wold, Bold, g, Wnew, Bnew, D, part, rhist, sweep, nz, sc, st);
+    launch_wstep_t<TH, R, 256>(geo, kp, phin, Pk, Wold, Bold, g, Wnew, Bnew, D, part, rhist, sweep, nz, sc, st);
 }
 
 #define SR_R_DISPATCH(FN, TH, R, ...)                                                          \
@@ -1313,17 +1317,17 @@ int wstep_blocks(const Geometry& geo, int nz) {
     return ((geo.N + kTileW - 1) / kTileW) * ((geo.M + TH - 1) / TH);
 }
 
-void launch_wstep(const Geometry& geo, const KParams& kp, const float* phin, float* P0, const float* Wold,
+void launch_wstep(const Geometry& geo, const KParams& kp, const float* phin, const float* Pk, const float* Wold,
                   const float* Bold, const float* g, float* Wnew, float* Bnew, float* D, double* part,
                   double* rhist, int nz, DevScal* sc, hipStream_t st, bool finalize, bool sweep) {
     // Fixed shapes, whatever tile height the autotuner picks for the right-hand
     // side (on 256 threads, 8 and 32 rows measured 18.8 / 180 and 19.5 / 194 us).
     const bool small = wstep_small(geo, nz);
     if (small) {
-        SR_R_DISPATCH(launch_wstep_small, 32, kp.R, geo, kp, phin, P0, Wold, Bold, g, Wnew, Bnew, D, part, rhist,
+        SR_R_DISPATCH(launch_wstep_small, 32, kp.R, geo, kp, phin, Pk, Wold, Bold, g, Wnew, Bnew, D, part, rhist,
                       (int)sweep, nz, sc, st);
     } else {
-        SR_R_DISPATCH(launch_wstep_large, 16, kp.R, geo, kp, phin, P0, Wold, Bold, g, Wnew, Bnew, D, part, rhist,
+        SR_R_DISPATCH(launch_wstep_large, 16, kp.R, geo, kp, phin, Pk, Wold, Bold, g, Wnew, Bnew, D, part, rhist,
                       (int)sweep, nz, sc, st);
     }
     if (!finalize || sweep) return;

@@ -87,9 +87,9 @@ void launch_solve_pass(int pass, const Geometry& geo, const float* rhs, const fl
                        float2* spec, float tol_inner, double* part, int nz, DevScal* sc, hipStream_t st);
 // finalize = false leaves the outer-iteration finalize to a FinFold in the
 // next right-hand-side launch.  sweep = true: one sweep of the fixed-point w
-// solver only, w from Wold into Wnew (Bnew, D, part, rhist unused; P0 not
-// written; no finalize).
-void launch_wstep(const Geometry& geo, const KParams& kp, const float* phin, float* P0, const float* Wold,
+// solver only, w from Wold into Wnew (Bnew, D, part, rhist unused; no
+// finalize).  phin is phi^{k+1}, Pk phi^k (read for the outer residual only).
+void launch_wstep(const Geometry& geo, const KParams& kp, const float* phin, const float* Pk, const float* Wold,
                   const float* Bold, const float* g, float* Wnew, float* Bnew, float* D, double* part,
                   double* rhist, int nz, DevScal* sc, hipStream_t st, bool finalize = true, bool sweep = false);
 // Residual partials per instance written by launch_wstep.
