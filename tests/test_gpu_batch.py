@@ -211,6 +211,43 @@ def test_autotune_leaves_state_and_results_unchanged(sr):
         assert np.array_equal(t.phi().cpu().numpy(), want), forced
 
 
+def test_component_operators_leave_solver_state_unchanged(sr):
+    """The component operators (edge map, repulsion field, implicit solve)
+    called with host arrays stage them in the context's free planes: the
+    phi plane of the pair that does not hold phi^k, the spare inner
+    iterate, the free w / b halves.  Called at an odd and at an even
+    iteration count, they leave the state (phi, w, b, k) bitwise unchanged,
+    and the solve then continues bitwise like one that never called them."""
+    _note("component operators with host staging mid-solve")
+    M, N = 128, 256
+    f, p = synth.ellipses(M, N, seed=21, n_shapes=3, axis_lo=10.0, axis_hi=30.0, inset=8)
+    kw = gpu_params(R=3, d=4.0)
+    ref = sr.Solver(M, N, kw)
+    ref.set_image(_cuda(f), _cuda(p))
+    ref.step(7)
+    want = [t.cpu().numpy() for t in ref.get_state()[:3]]
+    s = sr.Solver(M, N, kw)
+    s.set_image(_cuda(f), _cuda(p))
+    rng = np.random.default_rng(3)
+    host = lambda *shape: rng.normal(size=shape).astype(np.float32)
+    for k in (3, 6):   # operators at an odd, then an even iteration count
+        s.step(3)
+        before = [t.cpu().numpy() for t in s.get_state()[:3]]
+        g = sr.sr_edge_map(s.ctx, host(M, N), np.empty((M, N), np.float32))
+        v = sr.sr_repulsion(s.ctx, host(2, M, N), host(M, N), np.empty((2, M, N), np.float32))
+        u = sr.sr_implicit_solve(s.ctx, host(M, N), np.empty((M, N), np.float32))
+        assert all(np.isfinite(x).all() for x in (g, v, u))
+        after = s.get_state()
+        assert after[3] == k
+        for a, b in zip(before, after[:3]):
+            assert np.array_equal(a, b.cpu().numpy())
+    s.step(1)
+    got = s.get_state()
+    assert got[3] == 7
+    for a, b in zip(want, got[:3]):
+        assert np.array_equal(a, b.cpu().numpy())
+
+
 def test_fixed_point_w_batch_matches_single(sr):
     """17 instances of 512^2 with the fixed-point w solver (3 sweeps): the
     batch (above 4 Mpx per launch: 64x16 w-step tiles on 256 threads) gives
