@@ -165,10 +165,18 @@ PARAMS_3D = dict(gamma=5.0, alpha=4.0, beta=0.2, mu=3.0, tau=0.05, eps=1.0, band
 #   window: the k pass reads w (12) and phi (4) and writes 3 components
 #           (12); the j and i passes read and write 3 components (24): mean of 3
 #   rhs: reads phi, w, b, g, v (4 + 12 + 12 + 4 + 12), writes r (4)
-#   fft: first pass reads r (4), writes complex (8); three complex passes
-#        read and write 8 each; the last reads 8 + phi_s 4, writes 4: mean of 5
+#   fft: the spectrum holds k frequencies 0..P/2, h = 8 (P/2 + 1) / P bytes
+#        per voxel; the first pass reads r (4) and writes h; three passes
+#        read and write h each; the last reads h + phi_s 4, writes 4: mean of 5
 #   w step: reads phi, b, g, v (4 + 12 + 4 + 12), writes w and b (24)
-BYTES_PER_VOX_3D = {"window": (28 + 2 * 24) / 3, "rhs": 48, "fft": (12 + 3 * 16 + 16) / 5, "w_step": 56}
+BYTES_PER_VOX_3D = {"window": (28 + 2 * 24) / 3, "rhs": 48, "w_step": 56}
+
+
+def bytes_per_vox_3d(kind, P):
+    if kind != "fft":
+        return BYTES_PER_VOX_3D[kind]
+    h = 8.0 * (P // 2 + 1) / P
+    return (4 + h + 3 * 2 * h + h + 8) / 5
 
 
 def volume_bench(S, steps, warmup, cpu):
@@ -188,7 +196,7 @@ def volume_bench(S, steps, warmup, cpu):
     prof = sr.sr3_profile(s.ctx, 3)
     per_iter_ms = {k: v[0] * v[1] / 3 for k, v in prof.items()}
     dom = max(per_iter_ms, key=per_iter_ms.get)
-    achieved = BYTES_PER_VOX_3D[dom] * S ** 3 / (prof[dom][0] * 1e-3) / 1e9
+    achieved = bytes_per_vox_3d(dom, S) * S ** 3 / (prof[dom][0] * 1e-3) / 1e9
     out = {"metric": f"3-D SB megavoxel-iters/s at {S}^3", "value": round(value, 2), "unit": "MVox-it/s",
            "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": round((t1 - t0) * 1e3 / steps, 4),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
@@ -197,7 +205,7 @@ def volume_bench(S, steps, warmup, cpu):
                                   "S 5)"},
            "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                        "alg_bytes_per_launch": BYTES_PER_VOX_3D[dom] * S ** 3},
+                        "alg_bytes_per_launch": bytes_per_vox_3d(dom, S) * S ** 3},
            "kernels_ms": {k: round(v[0], 5) for k, v in prof.items()},
            "iteration_ms_sum_of_kernels": round(sum(per_iter_ms.values()), 4)}
     if cpu:

@@ -261,7 +261,7 @@ int sr_autotune(sr_ctx* ctx, int32_t reps, int32_t* tile_th, double us_out[3]);
 
 /* ---- launch preparation -------------------------------------------------
  * sr_step replays HIP graphs of 1, 2, 4, 8 and 16 outer iterations (one
- * set per parity of the w / b ping-pong; n iterations are split into powers
+ * set per parity of the phi / w / b ping-pong; n iterations are split into powers
  * of two, largest first), capturing each the first time it is needed.
  * sr_prepare captures and instantiates all ten now, without
  * running any kernel or changing the state, so that a later sr_step spends

@@ -231,7 +231,10 @@ __global__ __launch_bounds__(kT) void k3_wstep(const float* __restrict__ phi, fl
 // butterflies of the block per stage.
 // mode 0: forward, real input; 1: forward; 2: forward, divide by the
 // symbol of (1 - tau mu Lap), inverse; 3: inverse; 4: inverse, real output
-// out = add + scale Re.  Lines of axis 2 are contiguous (kLines per
+// out = add + scale Re.  The volume is real, so the spectrum is kept for k
+// frequencies 0..P/2 only: the k pass stores those, the i and j passes
+// transform only those lines, and the inverse k pass restores the others as
+// complex conjugates.  Lines of axis 2 are contiguous (kLines per
 // workgroup); lines of axes 0 and 1 are strided, and kStridedLines
 // neighbours along k share a workgroup so that each load and store touches
 // 128-byte runs.
@@ -307,7 +310,7 @@ __global__ __launch_bounds__(fft3_threads(L, G)) void k3_fft(const float* __rest
                                                              const float2* __restrict__ twM,
                                                              const float2* __restrict__ twN,
                                                              const float2* __restrict__ twP, int M, int N, int P,
-                                                             int axis, int mode, float taumu, float scale) {
+                                                             int Hp, int axis, int mode, float taumu, float scale) {
     using S = FftShape3<L, G>;
     static_assert(S::T % G == 0, "a thread's elements share one line of the block");
     extern __shared__ float2 lds3[];
@@ -324,31 +327,52 @@ __global__ __launch_bounds__(fft3_threads(L, G)) void k3_fft(const float* __rest
     // mode 2 (axis 0): this thread's elements all lie on line line0 + tid % G
     // (the thread count is a multiple of G); the j and k cosines of that line
     // are loaded with the data
+    // The spectrum C holds k frequencies 0..P/2 only (the rest follow from
+    // those by conjugate symmetry, the volume being real), Hp >= P/2 + 1
+    // slots per k-line.  Lines of the strided passes run over every slot;
+    // those past P/2 carry zeros and are not stored.
+    const int H = P / 2 + 1;
     float cj = 0.0f, ck = 0.0f;
     if (mode == 2) {
-        const int l = line0 + tid % G;
-        cj = twN[l / P].x;
-        ck = twP[l % P].x;
+        const int l = line0 + tid % G, kk = l % Hp;
+        cj = twN[l / Hp].x;
+        ck = kk < H ? twP[kk].x : 0.0f;
     }
-    // element e of the block -> (line g, position n) and its address
-    auto addr = [&](int e, int& g, int& pos) -> size_t {
+    // element e of the block -> (line g, position pos), the line's k slot
+    // (strided passes) and the element's address in C (in the real plane
+    // for the k pass)
+    auto addr = [&](int e, int& g, int& pos, int& kk) -> size_t {
         if (axis == 2) {
             g = e / L;
             pos = e - g * L;
+            kk = 0;
             return (size_t)(line0 + g) * P + pos;
         }
         pos = e / G;
         g = e - pos * G;
         const int l = line0 + g;
-        if (axis == 1) return (size_t)(l / P) * N * P + (size_t)pos * P + (l % P);
-        return (size_t)pos * N * P + l;
+        kk = l % Hp;
+        if (axis == 1) return (size_t)(l / Hp) * N * Hp + (size_t)pos * Hp + kk;
+        return (size_t)pos * N * Hp + l;
     };
 #pragma unroll
     for (int m = 0; m < S::NE; ++m) {
         const int e = tid + m * S::T;
-        int g, pos;
-        const size_t o = addr(e, g, pos);
-        s0[g * LP + pos] = mode == 0 ? make_float2(rin[o], 0.0f) : C[o];
+        int g, pos, kk;
+        const size_t o = addr(e, g, pos, kk);
+        float2 v;
+        if (axis == 2) {
+            const size_t line = (size_t)(line0 + g);
+            if (mode == 0) {
+                v = make_float2(rin[o], 0.0f);
+            } else {   // mode 4: frequencies above P/2 by conjugate symmetry
+                v = pos < H ? C[line * Hp + pos] : C[line * Hp + (L - pos)];
+                if (pos >= H) v.y = -v.y;
+            }
+        } else {
+            v = kk < H ? C[o] : make_float2(0.0f, 0.0f);
+        }
+        s0[g * LP + pos] = v;
     }
     __syncthreads();
     float2* res = stockham<L, G>(s0, s1, stw, mode >= 3);
@@ -371,13 +395,17 @@ __global__ __launch_bounds__(fft3_threads(L, G)) void k3_fft(const float* __rest
 #pragma unroll
     for (int m = 0; m < S::NE; ++m) {
         const int e = tid + m * S::T;
-        int gg, pos;
-        const size_t o = addr(e, gg, pos);
+        int gg, pos, kk;
+        const size_t o = addr(e, gg, pos, kk);
         const float2 z = res[gg * LP + pos];
-        if (mode == 4)
-            rout[o] = radd[o] + scale * z.x;
-        else
+        if (axis == 2) {
+            if (mode == 4)
+                rout[o] = radd[o] + scale * z.x;
+            else if (pos < H)
+                C[(size_t)(line0 + gg) * Hp + pos] = z;
+        } else if (kk < H) {
             C[o] = z;
+        }
     }
 }
 
@@ -392,6 +420,11 @@ std::vector<float2> host_twiddles(int L) {
 }
 
 bool pow2_in(int x) { return x >= 8 && x <= 256 && (x & (x - 1)) == 0; }
+
+// k slots per line of the half spectrum: P/2 + 1 frequencies, rounded up to
+// whole groups of strided lines (so that a strided workgroup's lines start
+// a 128-byte run)
+int half_pitch(int P) { return (P / 2 + 1 + kStridedLines - 1) / kStridedLines * kStridedLines; }
 
 struct Layout3 {
     size_t g, pa, pb, W, B, U, T, R, C, twM, twN, twP, total;
@@ -410,7 +443,7 @@ Layout3 layout3(int M, int N, int P) {
     L.U = take(3 * pl);
     L.T = take(3 * pl);
     L.R = take(pl);
-    L.C = take(2 * pl);
+    L.C = take(sizeof(float2) * (size_t)M * N * half_pitch(P));
     L.twM = take(sizeof(float2) * M);
     L.twN = take(sizeof(float2) * N);
     L.twP = take(sizeof(float2) * P);
@@ -469,11 +502,14 @@ unsigned vblocks(size_t n) { return (unsigned)((n + kT - 1) / kT); }
 
 template <int L, int G>
 void fft_pass_g(sr3_ctx* c, int axis, int mode, const float* rin, float* rout, const float* radd) {
-    const int lines = (int)(c->n / L);
+    // the k pass: one line per (i, j); the strided passes: one line per k
+    // slot of the half spectrum and (j, or i)
+    const int Hp = half_pitch(c->P);
+    const int lines = axis == 2 ? c->M * c->N : (axis == 1 ? c->M : c->N) * Hp;
     const float scale = 1.0f / (float)c->n;
     const size_t lds = sizeof(float2) * (2 * G * (L + 1) + L);
     launch(k3_fft<L, G>, dim3(lines / G), dim3(FftShape3<L, G>::T), lds, c->st, rin, c->C, rout, radd, c->twM,
-           c->twN, c->twP, c->M, c->N, c->P, axis, mode, c->taumu, scale);
+           c->twN, c->twP, c->M, c->N, c->P, Hp, axis, mode, c->taumu, scale);
 }
 
 template <int L>
