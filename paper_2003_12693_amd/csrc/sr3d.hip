@@ -234,7 +234,11 @@ __global__ __launch_bounds__(kT) void k3_wstep(const float* __restrict__ phi, fl
 // out = add + scale Re.  The volume is real, so the spectrum is kept for k
 // frequencies 0..P/2 only: the k pass stores those, the i and j passes
 // transform only those lines, and the inverse k pass restores the others as
-// complex conjugates.  Lines of axis 2 are contiguous (kLines per
+// complex conjugates.  Along k a line of P real samples runs as a P/2-point
+// complex transform of its even (real part) and odd (imaginary part)
+// samples, split into the P-point spectrum after it (and joined before the
+// inverse).
+// Lines of axis 2 are contiguous (kLines per
 // workgroup); lines of axes 0 and 1 are strided, and kStridedLines
 // neighbours along k share a workgroup so that each load and store touches
 // 128-byte runs.
@@ -323,7 +327,9 @@ __global__ __launch_bounds__(fft3_threads(L, G)) void k3_fft(const float* __rest
     const float2* tw = axis == 0 ? twM : axis == 1 ? twN : twP;
     // The stages read their twiddles from LDS: from memory, each stage would
     // wait for an L2 round trip before its butterflies.
-    for (int i = tid; i < L; i += S::T) stw[i] = tw[i];
+    // (the k pass runs L = P/2-point transforms: every second entry of the
+    // P-point table)
+    for (int i = tid; i < L; i += S::T) stw[i] = tw[axis == 2 ? 2 * i : i];
     // mode 2 (axis 0): this thread's elements all lie on line line0 + tid % G
     // (the thread count is a multiple of G); the j and k cosines of that line
     // are loaded with the data
@@ -338,15 +344,14 @@ __global__ __launch_bounds__(fft3_threads(L, G)) void k3_fft(const float* __rest
         cj = twN[l / Hp].x;
         ck = kk < H ? twP[kk].x : 0.0f;
     }
-    // element e of the block -> (line g, position pos), the line's k slot
-    // (strided passes) and the element's address in C (in the real plane
-    // for the k pass)
+    // element e of the block -> (line g, position pos), and for the strided
+    // passes the line's k slot and the element's address in C
     auto addr = [&](int e, int& g, int& pos, int& kk) -> size_t {
         if (axis == 2) {
             g = e / L;
             pos = e - g * L;
             kk = 0;
-            return (size_t)(line0 + g) * P + pos;
+            return 0;
         }
         pos = e / G;
         g = e - pos * G;
@@ -362,12 +367,19 @@ __global__ __launch_bounds__(fft3_threads(L, G)) void k3_fft(const float* __rest
         const size_t o = addr(e, g, pos, kk);
         float2 v;
         if (axis == 2) {
+            // k-line g of P = 2L real samples as L complex ones z_n = x_2n + i x_2n+1
             const size_t line = (size_t)(line0 + g);
             if (mode == 0) {
-                v = make_float2(rin[o], 0.0f);
-            } else {   // mode 4: frequencies above P/2 by conjugate symmetry
-                v = pos < H ? C[line * Hp + pos] : C[line * Hp + (L - pos)];
-                if (pos >= H) v.y = -v.y;
+                v = *reinterpret_cast<const float2*>(rin + line * P + 2 * pos);
+            } else {
+                // mode 4: Z_m = E_m + i O_m with E_m = X_m + conj X_L-m (2x the
+                // even samples' spectrum) and O_m = (X_m - conj X_L-m) W_P^-m
+                const float2 xm = C[line * Hp + pos], xq = C[line * Hp + (L - pos)];
+                const float2 e = make_float2(xm.x + xq.x, xm.y - xq.y);
+                const float2 d = make_float2(xm.x - xq.x, xm.y + xq.y);
+                const float2 t = twP[pos];
+                const float2 o = make_float2(d.x * t.x + d.y * t.y, d.y * t.x - d.x * t.y);
+                v = make_float2(e.x - o.y, e.y + o.x);
             }
         } else {
             v = kk < H ? C[o] : make_float2(0.0f, 0.0f);
@@ -399,10 +411,22 @@ __global__ __launch_bounds__(fft3_threads(L, G)) void k3_fft(const float* __rest
         const size_t o = addr(e, gg, pos, kk);
         const float2 z = res[gg * LP + pos];
         if (axis == 2) {
-            if (mode == 4)
-                rout[o] = radd[o] + scale * z.x;
-            else if (pos < H)
-                C[(size_t)(line0 + gg) * Hp + pos] = z;
+            const size_t line = (size_t)(line0 + gg);
+            if (mode == 4) {   // z_n = P (x_2n + i x_2n+1) up to the other axes' factors
+                const size_t r = line * P + 2 * pos;
+                const float2 ad = *reinterpret_cast<const float2*>(radd + r);
+                *reinterpret_cast<float2*>(rout + r) = make_float2(ad.x + scale * z.x, ad.y + scale * z.y);
+            } else {
+                // X_m = E_m + W_P^m O_m (m = 0..L) from the spectra of the even
+                // and odd samples, E_m = (Z_m + conj Z_L-m) / 2 and
+                // O_m = (Z_m - conj Z_L-m) / 2i (indices mod L); X_L = E_0 - O_0
+                const float2 zq = res[gg * LP + ((L - pos) & (L - 1))];
+                const float2 e = make_float2(0.5f * (z.x + zq.x), 0.5f * (z.y - zq.y));
+                const float2 o = make_float2(0.5f * (z.y + zq.y), -0.5f * (z.x - zq.x));
+                const float2 wo = sr::cmul(twP[pos], o);
+                C[line * Hp + pos] = sr::cadd(e, wo);
+                if (pos == 0) C[line * Hp + L] = sr::csub(e, o);
+            }
         } else if (kk < H) {
             C[o] = z;
         }
@@ -512,18 +536,19 @@ void fft_pass_g(sr3_ctx* c, int axis, int mode, const float* rin, float* rout, c
            c->twN, c->twP, c->M, c->N, c->P, Hp, axis, mode, c->taumu, scale);
 }
 
+// L is the axis length; the k pass runs L/2-point transforms
 template <int L>
 void fft_pass_t(sr3_ctx* c, int axis, int mode, const float* rin, float* rout, const float* radd) {
     if (axis == 2)
-        fft_pass_g<L, kLines>(c, axis, mode, rin, rout, radd);
+        fft_pass_g<L / 2, kLines>(c, axis, mode, rin, rout, radd);
     else
         fft_pass_g<L, kStridedLines>(c, axis, mode, rin, rout, radd);
 }
 
 template <int L>
 void fft_attrs() {
-    (void)hipFuncSetAttribute((const void*)k3_fft<L, kLines>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)(sizeof(float2) * (2 * kLines * (L + 1) + L)));
+    (void)hipFuncSetAttribute((const void*)k3_fft<L / 2, kLines>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)(sizeof(float2) * (2 * kLines * (L / 2 + 1) + L / 2)));
     (void)hipFuncSetAttribute((const void*)k3_fft<L, kStridedLines>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)(sizeof(float2) * (2 * kStridedLines * (L + 1) + L)));
 }
