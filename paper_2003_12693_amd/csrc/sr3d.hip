@@ -166,10 +166,14 @@ __global__ __launch_bounds__(kT) void k3_win_tile(const float* __restrict__ src,
 }
 
 // r = tau (-gamma g |w| delta' + alpha g delta + 2 beta h' w.v + mu div(b - w) + mu Lap phi).
+// w and b are fixed over the inner steps of an outer iteration: the first
+// inner step (first = 1) forms D = div(b - w) and stores it, the others
+// read it.  The force vanishes outside the band |phi| <= l + eps (delta,
+// delta' and h' are 0 there), where w, g and v are not read.
 __global__ __launch_bounds__(kT) void k3_rhs(const float* __restrict__ phi, const float* __restrict__ W,
-                                             const float* __restrict__ B, const float* __restrict__ g,
-                                             const float* __restrict__ V, float* __restrict__ r, int M, int N,
-                                             int P, KParams kp) {
+                                             const float* __restrict__ B, float* __restrict__ D,
+                                             const float* __restrict__ g, const float* __restrict__ V,
+                                             float* __restrict__ r, int M, int N, int P, int first, KParams kp) {
     const size_t n = (size_t)M * N * P, v = (size_t)blockIdx.x * kT + threadIdx.x;
     if (v >= n) return;
     const int k = (int)(v % P), j = (int)((v / P) % N), i = (int)(v / ((size_t)N * P));
@@ -178,16 +182,26 @@ __global__ __launch_bounds__(kT) void k3_rhs(const float* __restrict__ phi, cons
     const float p = phi[v];
     const float lap = (phi[vox(wrp(i + 1, M), j, k, N, P)] + phi[oi]) + (phi[vox(i, wrp(j + 1, N), k, N, P)] + phi[oj]) +
                       (phi[vox(i, j, wrp(k + 1, P), N, P)] + phi[ok]) - 6.0f * p;
-    const float w0 = W[v], w1 = W[n + v], w2 = W[2 * n + v];
-    const float dv = ((B[v] - w0) - (B[oi] - W[oi])) + ((B[n + v] - w1) - (B[n + oj] - W[n + oj])) +
-                     ((B[2 * n + v] - w2) - (B[2 * n + ok] - W[2 * n + ok]));
-    float dl, ddl, h, dh;
-    sr::dirac_d(p, kp, dl, ddl);
-    sr::band_h_dh(p, kp, h, dh);
-    const float gv = g[v];
-    const float wn = sqrtf(w0 * w0 + w1 * w1 + w2 * w2);
-    const float wv = w0 * V[v] + w1 * V[n + v] + w2 * V[2 * n + v];
-    const float force = -kp.gamma * gv * wn * ddl + kp.alpha * gv * dl + 2.0f * kp.beta * dh * wv;
+    float dv;
+    if (first) {
+        dv = ((B[v] - W[v]) - (B[oi] - W[oi])) + ((B[n + v] - W[n + v]) - (B[n + oj] - W[n + oj])) +
+             ((B[2 * n + v] - W[2 * n + v]) - (B[2 * n + ok] - W[2 * n + ok]));
+        D[v] = dv;
+    } else {
+        dv = D[v];
+    }
+    const float lim = kp.band_l + kp.eps;
+    float force = 0.0f;
+    if (p <= lim && p >= -lim) {
+        const float w0 = W[v], w1 = W[n + v], w2 = W[2 * n + v];
+        float dl, ddl, h, dh;
+        sr::dirac_d(p, kp, dl, ddl);
+        sr::band_h_dh(p, kp, h, dh);
+        const float gv = g[v];
+        const float wn = sqrtf(w0 * w0 + w1 * w1 + w2 * w2);
+        const float wv = w0 * V[v] + w1 * V[n + v] + w2 * V[2 * n + v];
+        force = -kp.gamma * gv * wn * ddl + kp.alpha * gv * dl + 2.0f * kp.beta * dh * wv;
+    }
     r[v] = kp.tau * (force + kp.mu * dv + kp.mu * lap);
 }
 
@@ -451,7 +465,7 @@ bool pow2_in(int x) { return x >= 8 && x <= 256 && (x & (x - 1)) == 0; }
 int half_pitch(int P) { return (P / 2 + 1 + kStridedLines - 1) / kStridedLines * kStridedLines; }
 
 struct Layout3 {
-    size_t g, pa, pb, W, B, U, T, R, C, twM, twN, twP, total;
+    size_t g, pa, pb, W, B, U, T, R, D, C, twM, twN, twP, total;
 };
 
 Layout3 layout3(int M, int N, int P) {
@@ -467,6 +481,7 @@ Layout3 layout3(int M, int N, int P) {
     L.U = take(3 * pl);
     L.T = take(3 * pl);
     L.R = take(pl);
+    L.D = take(pl);
     L.C = take(sizeof(float2) * (size_t)M * N * half_pitch(P));
     L.twM = take(sizeof(float2) * M);
     L.twN = take(sizeof(float2) * N);
@@ -496,7 +511,7 @@ struct sr3_ctx {
     KParams kp;
     Gauss3 gauss;
     hipStream_t st;
-    float *g, *phi, *alt, *W, *B, *U, *T, *R;
+    float *g, *phi, *alt, *W, *B, *U, *T, *R, *D;   // D = div(b - w) of the current outer iteration
     float2 *C, *twM, *twN, *twP;
     float taumu;
     long long k = 0;
@@ -603,7 +618,8 @@ void iteration(sr3_ctx* c) {
     for (int s = 0; s < c->p.S; ++s) {
         window(c, c->phi);
         arm(c, 1);
-        launch(k3_rhs, dim3(nb), dim3(kT), 0, c->st, c->phi, c->W, c->B, c->g, c->T, c->R, c->M, c->N, c->P, c->kp);
+        launch(k3_rhs, dim3(nb), dim3(kT), 0, c->st, c->phi, c->W, c->B, c->D, c->g, c->T, c->R, c->M, c->N, c->P,
+               s == 0 ? 1 : 0, c->kp);
         disarm();
         solve(c, c->R, c->phi, c->alt);
         float* t = c->phi;
@@ -702,6 +718,7 @@ int sr3_create(sr3_ctx** out, int32_t M, int32_t N, int32_t P, const sr_params* 
     c->U = (float*)(base + L.U);
     c->T = (float*)(base + L.T);
     c->R = (float*)(base + L.R);
+    c->D = (float*)(base + L.D);
     c->C = (float2*)(base + L.C);
     c->twM = (float2*)(base + L.twM);
     c->twN = (float2*)(base + L.twN);
