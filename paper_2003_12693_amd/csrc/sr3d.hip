@@ -217,14 +217,23 @@ __global__ __launch_bounds__(kT) void k3_wstep(const float* __restrict__ phi, fl
     const float G0 = phi[vox(wrp(i + 1, M), j, k, N, P)] - p;
     const float G1 = phi[vox(i, wrp(j + 1, N), k, N, P)] - p;
     const float G2 = phi[vox(i, j, wrp(k + 1, P), N, P)] - p;
-    const float h = sr::band_h(p, kp);
-    float H_, dl;
-    sr::heav_dirac(p, kp.eps, kp.inv_eps, H_, dl);
     const float b0 = B[v], b1 = B[n + v], b2 = B[2 * n + v];
-    const float B0 = G0 + b0 + kp.c_rep * h * V[v];
-    const float B1 = G1 + b1 + kp.c_rep * h * V[n + v];
-    const float B2 = G2 + b2 + kp.c_rep * h * V[2 * n + v];
-    const float thr = kp.c_thr * g[v] * dl;
+    // outside the band |phi| <= l + eps h and delta vanish: B = grad phi + b
+    // and the threshold is 0, so v and g are read only inside it
+    float v0 = 0.0f, v1 = 0.0f, v2 = 0.0f, h = 0.0f, thr = 0.0f;
+    const float lim = kp.band_l + kp.eps;
+    if (p <= lim && p >= -lim) {
+        h = sr::band_h(p, kp);
+        float H_, dl;
+        sr::heav_dirac(p, kp.eps, kp.inv_eps, H_, dl);
+        v0 = V[v];
+        v1 = V[n + v];
+        v2 = V[2 * n + v];
+        thr = kp.c_thr * g[v] * dl;
+    }
+    const float B0 = G0 + b0 + kp.c_rep * h * v0;
+    const float B1 = G1 + b1 + kp.c_rep * h * v1;
+    const float B2 = G2 + b2 + kp.c_rep * h * v2;
     const float nb = sqrtf(B0 * B0 + B1 * B1 + B2 * B2);
     float w0 = 0.0f, w1 = 0.0f, w2 = 0.0f;
     if (nb > thr && nb > kp.zero_tol) { w0 = B0 / nb; w1 = B1 / nb; w2 = B2 / nb; }
