@@ -164,21 +164,23 @@ PARAMS_3D = dict(gamma=5.0, alpha=4.0, beta=0.2, mu=3.0, tau=0.05, eps=1.0, band
 # algorithmic bytes per voxel per launch of each 3-D kernel kind (FP32):
 #   window: the k pass reads w (12) and phi (4) and writes 3 components
 #           (12); the j and i passes read and write 3 components (24): mean of 3
-#   rhs: reads phi, w, g, v, D (4 + 12 + 4 + 12 + 4), writes r (4); the first
-#        of the S inner steps reads b (12) and writes D (4) instead of reading
-#        D: mean over S = 5 steps 40 + 12 / 5
-#   fft: the spectrum holds k frequencies 0..P/2, h = 8 (P/2 + 1) / P bytes
-#        per voxel; the first pass reads r (4) and writes h; three passes
-#        read and write h each; the last reads h + phi_s 4, writes 4: mean of 5
+#   The spectrum holds k frequencies 0..P/2: h = 8 (P/2 + 1) / P bytes per voxel.
+#   rhs (with the forward k transform): reads phi, w, g, v, D (4 + 12 + 4 +
+#        12 + 4), writes the spectrum (h); the first of the S = 5 inner steps
+#        reads b (12) and writes D (4) instead of reading D: + 12 / 5
+#   fft: three passes read and write h each; the last reads h + phi_s 4,
+#        writes 4: mean of 4
 #   w step: reads phi, b, g, v (4 + 12 + 4 + 12), writes w and b (24)
-BYTES_PER_VOX_3D = {"window": (28 + 2 * 24) / 3, "rhs": 40 + 12 / 5, "w_step": 56}
+BYTES_PER_VOX_3D = {"window": (28 + 2 * 24) / 3, "w_step": 56}
 
 
 def bytes_per_vox_3d(kind, P):
-    if kind != "fft":
-        return BYTES_PER_VOX_3D[kind]
     h = 8.0 * (P // 2 + 1) / P
-    return (4 + h + 3 * 2 * h + h + 8) / 5
+    if kind == "rhs":
+        return 36 + h + 12 / 5
+    if kind == "fft":
+        return (3 * 2 * h + h + 8) / 4
+    return BYTES_PER_VOX_3D[kind]
 
 
 def volume_bench(S, steps, warmup, cpu):

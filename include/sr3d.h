@@ -53,8 +53,9 @@ int sr3_get_state(sr3_ctx* ctx, float* phi, float* w, float* b, float* g);
 
 /* Per-kernel-kind average duration (ms) over n_iter further iterations,
  * each kernel launch timed with its own events: [0] the three window
- * passes (the first forms u = w h(phi)), [1] right-hand side, [2] FFT passes (five per solve),
- * [3] w step; count[] the launches per kind.  Synchronises. */
+ * passes (the first forms u = w h(phi)), [1] right-hand side with the
+ * forward k transform, [2] the other FFT passes (four per solve), [3] w
+ * step; count[] the launches per kind.  Synchronises. */
 int sr3_profile(sr3_ctx* ctx, int32_t n_iter, double ms[4], int64_t count[4]);
 
 void sr3_destroy(sr3_ctx* ctx);

@@ -170,13 +170,13 @@ __global__ __launch_bounds__(kT) void k3_win_tile(const float* __restrict__ src,
 // inner step (first = 1) forms D = div(b - w) and stores it, the others
 // read it.  The force vanishes outside the band |phi| <= l + eps (delta,
 // delta' and h' are 0 there), where w, g and v are not read.
-__global__ __launch_bounds__(kT) void k3_rhs(const float* __restrict__ phi, const float* __restrict__ W,
-                                             const float* __restrict__ B, float* __restrict__ D,
-                                             const float* __restrict__ g, const float* __restrict__ V,
-                                             float* __restrict__ r, int M, int N, int P, int first, KParams kp) {
-    const size_t n = (size_t)M * N * P, v = (size_t)blockIdx.x * kT + threadIdx.x;
-    if (v >= n) return;
-    const int k = (int)(v % P), j = (int)((v / P) % N), i = (int)(v / ((size_t)N * P));
+// Evaluated at voxel (i, j, k) by the forward k transform, which takes r
+// as its input.
+__device__ __forceinline__ float rhs_voxel(const float* __restrict__ phi, const float* __restrict__ W,
+                                           const float* __restrict__ B, float* __restrict__ D,
+                                           const float* __restrict__ g, const float* __restrict__ V, int M, int N,
+                                           int P, int i, int j, int k, int first, const KParams& kp) {
+    const size_t n = (size_t)M * N * P, v = vox(i, j, k, N, P);
     const size_t oi = vox(wrp(i - 1, M), j, k, N, P), oj = vox(i, wrp(j - 1, N), k, N, P),
                  ok = vox(i, j, wrp(k - 1, P), N, P);
     const float p = phi[v];
@@ -202,7 +202,7 @@ __global__ __launch_bounds__(kT) void k3_rhs(const float* __restrict__ phi, cons
         const float wv = w0 * V[v] + w1 * V[n + v] + w2 * V[2 * n + v];
         force = -kp.gamma * gv * wn * ddl + kp.alpha * gv * dl + 2.0f * kp.beta * dh * wv;
     }
-    r[v] = kp.tau * (force + kp.mu * dv + kp.mu * lap);
+    return kp.tau * (force + kp.mu * dv + kp.mu * lap);
 }
 
 // w step: B = grad phi + b + (2 beta / mu) h v, gate (eq 42) and projection
@@ -252,9 +252,9 @@ __global__ __launch_bounds__(kT) void k3_wstep(const float* __restrict__ phi, fl
 // W_L^{r (j mod Ns) L / (R Ns)}, applies the R-point DFT and writes output r
 // to y[(j div Ns) R Ns + j mod Ns + r Ns].  A thread runs several
 // butterflies of the block per stage.
-// mode 0: forward, real input; 1: forward; 2: forward, divide by the
-// symbol of (1 - tau mu Lap), inverse; 3: inverse; 4: inverse, real output
-// out = add + scale Re.  The volume is real, so the spectrum is kept for k
+// mode 1: forward; 2: forward, divide by the symbol of (1 - tau mu Lap),
+// inverse; 3: inverse; 4: inverse, real output out = add + scale Re (the
+// forward k transform, with real input, is k3_rhs_kfwd).  The volume is real, so the spectrum is kept for k
 // frequencies 0..P/2 only: the k pass stores those, the i and j passes
 // transform only those lines, and the inverse k pass restores the others as
 // complex conjugates.  Along k a line of P real samples runs as a P/2-point
@@ -331,8 +331,24 @@ __device__ float2* stockham(float2* a, float2* b, const float2* __restrict__ tw,
     return x;
 }
 
+// Forward k transform of a real line of P = 2L samples run as the L-point
+// transform Z of z_n = x_2n + i x_2n+1 (line in LDS after the transform):
+// X_m = E_m + W_P^m O_m (m = 0..L) from the spectra of the even and odd
+// samples, E_m = (Z_m + conj Z_L-m) / 2 and O_m = (Z_m - conj Z_L-m) / 2i
+// (indices mod L); X_L = E_0 - O_0.  Cline: the line's half spectrum.
+template <int L>
+__device__ __forceinline__ void store_k_half(const float2* zline, int pos, float2* __restrict__ Cline,
+                                             const float2* __restrict__ twP) {
+    const float2 z = zline[pos], zq = zline[(L - pos) & (L - 1)];
+    const float2 e = make_float2(0.5f * (z.x + zq.x), 0.5f * (z.y - zq.y));
+    const float2 o = make_float2(0.5f * (z.y + zq.y), -0.5f * (z.x - zq.x));
+    const float2 wo = sr::cmul(twP[pos], o);
+    Cline[pos] = sr::cadd(e, wo);
+    if (pos == 0) Cline[L] = sr::csub(e, o);
+}
+
 template <int L, int G>
-__global__ __launch_bounds__(fft3_threads(L, G)) void k3_fft(const float* __restrict__ rin, float2* __restrict__ C,
+__global__ __launch_bounds__(fft3_threads(L, G)) void k3_fft(float2* __restrict__ C,
                                                              float* __restrict__ rout, const float* __restrict__ radd,
                                                              const float2* __restrict__ twM,
                                                              const float2* __restrict__ twN,
@@ -390,20 +406,16 @@ __global__ __launch_bounds__(fft3_threads(L, G)) void k3_fft(const float* __rest
         const size_t o = addr(e, g, pos, kk);
         float2 v;
         if (axis == 2) {
-            // k-line g of P = 2L real samples as L complex ones z_n = x_2n + i x_2n+1
+            // mode 4: the inverse of k-line g (P = 2L real samples) as the
+            // L-point transform of Z_m = E_m + i O_m, E_m = X_m + conj X_L-m
+            // (2x the even samples' spectrum), O_m = (X_m - conj X_L-m) W_P^-m
             const size_t line = (size_t)(line0 + g);
-            if (mode == 0) {
-                v = *reinterpret_cast<const float2*>(rin + line * P + 2 * pos);
-            } else {
-                // mode 4: Z_m = E_m + i O_m with E_m = X_m + conj X_L-m (2x the
-                // even samples' spectrum) and O_m = (X_m - conj X_L-m) W_P^-m
-                const float2 xm = C[line * Hp + pos], xq = C[line * Hp + (L - pos)];
-                const float2 e = make_float2(xm.x + xq.x, xm.y - xq.y);
-                const float2 d = make_float2(xm.x - xq.x, xm.y + xq.y);
-                const float2 t = twP[pos];
-                const float2 o = make_float2(d.x * t.x + d.y * t.y, d.y * t.x - d.x * t.y);
-                v = make_float2(e.x - o.y, e.y + o.x);
-            }
+            const float2 xm = C[line * Hp + pos], xq = C[line * Hp + (L - pos)];
+            const float2 e = make_float2(xm.x + xq.x, xm.y - xq.y);
+            const float2 d = make_float2(xm.x - xq.x, xm.y + xq.y);
+            const float2 t = twP[pos];
+            const float2 o = make_float2(d.x * t.x + d.y * t.y, d.y * t.x - d.x * t.y);
+            v = make_float2(e.x - o.y, e.y + o.x);
         } else {
             v = kk < H ? C[o] : make_float2(0.0f, 0.0f);
         }
@@ -433,26 +445,53 @@ __global__ __launch_bounds__(fft3_threads(L, G)) void k3_fft(const float* __rest
         int gg, pos, kk;
         const size_t o = addr(e, gg, pos, kk);
         const float2 z = res[gg * LP + pos];
-        if (axis == 2) {
-            const size_t line = (size_t)(line0 + gg);
-            if (mode == 4) {   // z_n = P (x_2n + i x_2n+1) up to the other axes' factors
-                const size_t r = line * P + 2 * pos;
-                const float2 ad = *reinterpret_cast<const float2*>(radd + r);
-                *reinterpret_cast<float2*>(rout + r) = make_float2(ad.x + scale * z.x, ad.y + scale * z.y);
-            } else {
-                // X_m = E_m + W_P^m O_m (m = 0..L) from the spectra of the even
-                // and odd samples, E_m = (Z_m + conj Z_L-m) / 2 and
-                // O_m = (Z_m - conj Z_L-m) / 2i (indices mod L); X_L = E_0 - O_0
-                const float2 zq = res[gg * LP + ((L - pos) & (L - 1))];
-                const float2 e = make_float2(0.5f * (z.x + zq.x), 0.5f * (z.y - zq.y));
-                const float2 o = make_float2(0.5f * (z.y + zq.y), -0.5f * (z.x - zq.x));
-                const float2 wo = sr::cmul(twP[pos], o);
-                C[line * Hp + pos] = sr::cadd(e, wo);
-                if (pos == 0) C[line * Hp + L] = sr::csub(e, o);
-            }
+        if (axis == 2) {   // mode 4: z_n = P (x_2n + i x_2n+1) up to the other axes' factors
+            const size_t r = (size_t)(line0 + gg) * P + 2 * pos;
+            const float2 ad = *reinterpret_cast<const float2*>(radd + r);
+            *reinterpret_cast<float2*>(rout + r) = make_float2(ad.x + scale * z.x, ad.y + scale * z.y);
         } else if (kk < H) {
             C[o] = z;
         }
+    }
+}
+
+// The right-hand side (rhs_voxel) fused with the forward k transform: each
+// k-line's r is formed in registers, never stored, and transformed as in
+// k passes.  first: the outer iteration's first inner
+// step (forms D).
+template <int L, int G>
+__global__ __launch_bounds__(fft3_threads(L, G)) void k3_rhs_kfwd(const float* __restrict__ phi,
+                                                                  const float* __restrict__ W,
+                                                                  const float* __restrict__ B, float* __restrict__ D,
+                                                                  const float* __restrict__ g,
+                                                                  const float* __restrict__ V, float2* __restrict__ C,
+                                                                  const float2* __restrict__ twP, int M, int N, int P,
+                                                                  int Hp, int first, KParams kp) {
+    using S = FftShape3<L, G>;
+    extern __shared__ float2 lds3[];
+    constexpr int LP = L + 1;
+    float2* s0 = lds3;
+    float2* s1 = lds3 + G * LP;
+    float2* stw = lds3 + 2 * G * LP;
+    const int tid = threadIdx.x;
+    const int line0 = blockIdx.x * G;
+    for (int i = tid; i < L; i += S::T) stw[i] = twP[2 * i];
+    // consecutive threads on consecutive voxels of a line; voxel k of line
+    // gl is component k & 1 of element k / 2 of the line's complex input
+#pragma unroll
+    for (int m = 0; m < 2 * S::NE; ++m) {
+        const int e = tid + m * S::T;
+        const int gl = e / (2 * L), k = e - gl * (2 * L);
+        const int line = line0 + gl, i = line / N, j = line - i * N;
+        reinterpret_cast<float*>(s0 + gl * LP)[k] = rhs_voxel(phi, W, B, D, g, V, M, N, P, i, j, k, first, kp);
+    }
+    __syncthreads();
+    const float2* res = stockham<L, G>(s0, s1, stw, false);
+#pragma unroll
+    for (int m = 0; m < S::NE; ++m) {
+        const int e = tid + m * S::T;
+        const int gl = e / L, pos = e - gl * L;
+        store_k_half<L>(res + gl * LP, pos, C + (size_t)(line0 + gl) * Hp, twP);
     }
 }
 
@@ -474,7 +513,7 @@ bool pow2_in(int x) { return x >= 8 && x <= 256 && (x & (x - 1)) == 0; }
 int half_pitch(int P) { return (P / 2 + 1 + kStridedLines - 1) / kStridedLines * kStridedLines; }
 
 struct Layout3 {
-    size_t g, pa, pb, W, B, U, T, R, D, C, twM, twN, twP, total;
+    size_t g, pa, pb, W, B, U, T, D, C, twM, twN, twP, total;
 };
 
 Layout3 layout3(int M, int N, int P) {
@@ -489,7 +528,6 @@ Layout3 layout3(int M, int N, int P) {
     L.B = take(3 * pl);
     L.U = take(3 * pl);
     L.T = take(3 * pl);
-    L.R = take(pl);
     L.D = take(pl);
     L.C = take(sizeof(float2) * (size_t)M * N * half_pitch(P));
     L.twM = take(sizeof(float2) * M);
@@ -520,7 +558,7 @@ struct sr3_ctx {
     KParams kp;
     Gauss3 gauss;
     hipStream_t st;
-    float *g, *phi, *alt, *W, *B, *U, *T, *R, *D;   // D = div(b - w) of the current outer iteration
+    float *g, *phi, *alt, *W, *B, *U, *T, *D;   // D = div(b - w) of the current outer iteration
     float2 *C, *twM, *twN, *twP;
     float taumu;
     long long k = 0;
@@ -549,29 +587,40 @@ void disarm() { t_ev[0] = t_ev[1] = nullptr; }
 unsigned vblocks(size_t n) { return (unsigned)((n + kT - 1) / kT); }
 
 template <int L, int G>
-void fft_pass_g(sr3_ctx* c, int axis, int mode, const float* rin, float* rout, const float* radd) {
+void fft_pass_g(sr3_ctx* c, int axis, int mode, float* rout, const float* radd) {
     // the k pass: one line per (i, j); the strided passes: one line per k
     // slot of the half spectrum and (j, or i)
     const int Hp = half_pitch(c->P);
     const int lines = axis == 2 ? c->M * c->N : (axis == 1 ? c->M : c->N) * Hp;
     const float scale = 1.0f / (float)c->n;
     const size_t lds = sizeof(float2) * (2 * G * (L + 1) + L);
-    launch(k3_fft<L, G>, dim3(lines / G), dim3(FftShape3<L, G>::T), lds, c->st, rin, c->C, rout, radd, c->twM,
+    launch(k3_fft<L, G>, dim3(lines / G), dim3(FftShape3<L, G>::T), lds, c->st, c->C, rout, radd, c->twM,
            c->twN, c->twP, c->M, c->N, c->P, Hp, axis, mode, c->taumu, scale);
 }
 
 // L is the axis length; the k pass runs L/2-point transforms
 template <int L>
-void fft_pass_t(sr3_ctx* c, int axis, int mode, const float* rin, float* rout, const float* radd) {
+void fft_pass_t(sr3_ctx* c, int axis, int mode, float* rout, const float* radd) {
     if (axis == 2)
-        fft_pass_g<L / 2, kLines>(c, axis, mode, rin, rout, radd);
+        fft_pass_g<L / 2, kLines>(c, axis, mode, rout, radd);
     else
-        fft_pass_g<L, kStridedLines>(c, axis, mode, rin, rout, radd);
+        fft_pass_g<L, kStridedLines>(c, axis, mode, rout, radd);
+}
+
+// The rhs fused with the forward k transform (P = L real samples per line).
+template <int L>
+void rhs_kfwd_t(sr3_ctx* c, int first) {
+    constexpr int Q = L / 2, G = kLines;
+    const size_t lds = sizeof(float2) * (2 * G * (Q + 1) + Q);
+    launch(k3_rhs_kfwd<Q, G>, dim3(c->M * c->N / G), dim3(FftShape3<Q, G>::T), lds, c->st, c->phi, c->W, c->B,
+           c->D, c->g, c->T, c->C, c->twP, c->M, c->N, c->P, half_pitch(c->P), first, c->kp);
 }
 
 template <int L>
 void fft_attrs() {
     (void)hipFuncSetAttribute((const void*)k3_fft<L / 2, kLines>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)(sizeof(float2) * (2 * kLines * (L / 2 + 1) + L / 2)));
+    (void)hipFuncSetAttribute((const void*)k3_rhs_kfwd<L / 2, kLines>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)(sizeof(float2) * (2 * kLines * (L / 2 + 1) + L / 2)));
     (void)hipFuncSetAttribute((const void*)k3_fft<L, kStridedLines>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)(sizeof(float2) * (2 * kStridedLines * (L + 1) + L)));
@@ -581,27 +630,40 @@ void fft_attrs() {
 
 namespace {
 
-void fft_pass(sr3_ctx* c, int axis, int mode, const float* rin, float* rout, const float* radd) {
+void fft_pass(sr3_ctx* c, int axis, int mode, float* rout, const float* radd) {
     arm(c, 2);
     const int L = axis == 0 ? c->M : axis == 1 ? c->N : c->P;
     switch (L) {
-        case 8: fft_pass_t<8>(c, axis, mode, rin, rout, radd); break;
-        case 16: fft_pass_t<16>(c, axis, mode, rin, rout, radd); break;
-        case 32: fft_pass_t<32>(c, axis, mode, rin, rout, radd); break;
-        case 64: fft_pass_t<64>(c, axis, mode, rin, rout, radd); break;
-        case 128: fft_pass_t<128>(c, axis, mode, rin, rout, radd); break;
-        default: fft_pass_t<256>(c, axis, mode, rin, rout, radd); break;
+        case 8: fft_pass_t<8>(c, axis, mode, rout, radd); break;
+        case 16: fft_pass_t<16>(c, axis, mode, rout, radd); break;
+        case 32: fft_pass_t<32>(c, axis, mode, rout, radd); break;
+        case 64: fft_pass_t<64>(c, axis, mode, rout, radd); break;
+        case 128: fft_pass_t<128>(c, axis, mode, rout, radd); break;
+        default: fft_pass_t<256>(c, axis, mode, rout, radd); break;
     }
     disarm();
 }
 
-// phi_out = phi_in + u with (1 - tau mu Lap) u = r.
-void solve(sr3_ctx* c, const float* r, const float* phi_in, float* phi_out) {
-    fft_pass(c, 2, 0, r, nullptr, nullptr);
-    fft_pass(c, 1, 1, nullptr, nullptr, nullptr);
-    fft_pass(c, 0, 2, nullptr, nullptr, nullptr);
-    fft_pass(c, 1, 3, nullptr, nullptr, nullptr);
-    fft_pass(c, 2, 4, nullptr, phi_out, phi_in);
+// r (eq 37) and its forward k transform, one launch.
+void rhs_kfwd(sr3_ctx* c, int first) {
+    arm(c, 1);
+    switch (c->P) {
+        case 8: rhs_kfwd_t<8>(c, first); break;
+        case 16: rhs_kfwd_t<16>(c, first); break;
+        case 32: rhs_kfwd_t<32>(c, first); break;
+        case 64: rhs_kfwd_t<64>(c, first); break;
+        case 128: rhs_kfwd_t<128>(c, first); break;
+        default: rhs_kfwd_t<256>(c, first); break;
+    }
+    disarm();
+}
+
+// phi_out = phi_in + u with (1 - tau mu Lap) u = r, from r's k transform.
+void solve(sr3_ctx* c, const float* phi_in, float* phi_out) {
+    fft_pass(c, 1, 1, nullptr, nullptr);
+    fft_pass(c, 0, 2, nullptr, nullptr);
+    fft_pass(c, 1, 3, nullptr, nullptr);
+    fft_pass(c, 2, 4, phi_out, phi_in);
 }
 
 // V (in T) = cube window of u = W h(phi): the k pass forms u, then j, i.
@@ -626,11 +688,8 @@ void iteration(sr3_ctx* c) {
     const unsigned nb = vblocks(c->n);
     for (int s = 0; s < c->p.S; ++s) {
         window(c, c->phi);
-        arm(c, 1);
-        launch(k3_rhs, dim3(nb), dim3(kT), 0, c->st, c->phi, c->W, c->B, c->D, c->g, c->T, c->R, c->M, c->N, c->P,
-               s == 0 ? 1 : 0, c->kp);
-        disarm();
-        solve(c, c->R, c->phi, c->alt);
+        rhs_kfwd(c, s == 0 ? 1 : 0);
+        solve(c, c->phi, c->alt);
         float* t = c->phi;
         c->phi = c->alt;
         c->alt = t;
@@ -726,7 +785,6 @@ int sr3_create(sr3_ctx** out, int32_t M, int32_t N, int32_t P, const sr_params* 
     c->B = (float*)(base + L.B);
     c->U = (float*)(base + L.U);
     c->T = (float*)(base + L.T);
-    c->R = (float*)(base + L.R);
     c->D = (float*)(base + L.D);
     c->C = (float2*)(base + L.C);
     c->twM = (float2*)(base + L.twM);

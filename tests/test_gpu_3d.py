@@ -175,6 +175,7 @@ def test_profile_counts_3d(sr):
     s.set_image(_cuda(f), _cuda(phi0))
     prof = sr.sr3_profile(s.ctx, 3)
     assert prof["window"][1] == 3 * 3 * 3 and prof["rhs"][1] == 3 * 2
-    assert prof["fft"][1] == 3 * 2 * 5 and prof["w_step"][1] == 3
+    # the forward k transform runs inside the rhs launch: four FFT launches per solve
+    assert prof["fft"][1] == 3 * 2 * 4 and prof["w_step"][1] == 3
     assert all(v[0] > 0 for v in prof.values())
     assert s.step(1) == 4
