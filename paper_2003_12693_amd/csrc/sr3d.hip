@@ -456,9 +456,9 @@ __global__ __launch_bounds__(fft3_threads(L, G)) void k3_fft(float2* __restrict_
 }
 
 // The right-hand side (rhs_voxel) fused with the forward k transform: each
-// k-line's r is formed in registers, never stored, and transformed as in
-// k passes.  first: the outer iteration's first inner
-// step (forms D).
+// k-line's r goes straight into LDS as the transform's input, never to
+// memory; the half spectrum is stored as the inverse k pass expects it.
+// first: the outer iteration's first inner step (forms D).
 template <int L, int G>
 __global__ __launch_bounds__(fft3_threads(L, G)) void k3_rhs_kfwd(const float* __restrict__ phi,
                                                                   const float* __restrict__ W,
