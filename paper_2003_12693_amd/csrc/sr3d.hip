@@ -127,6 +127,7 @@ __global__ __launch_bounds__(kT) void k3_win_u(const float* __restrict__ W, cons
 constexpr int kWinTA = 16;
 constexpr int kWinKT = 64;
 
+static_assert((kWinTA + 2 * sr::kMaxR) * kWinKT % kT == 0, "whole load rounds");
 __global__ __launch_bounds__(kT) void k3_win_tile(const float* __restrict__ src, float* __restrict__ dst, int M,
                                                   int N, int P, int axis, KParams kp) {
     __shared__ float sv[3][(kWinTA + 2 * sr::kMaxR) * kWinKT];
@@ -140,12 +141,29 @@ __global__ __launch_bounds__(kT) void k3_win_tile(const float* __restrict__ src,
         return axis == 0 ? vox(a, other, k, N, P) : vox(other, a, k, N, P);
     };
     const int EH = TA + 2 * R;
-    for (int e = threadIdx.x; e < EH * KT; e += kT) {
-        const int ea = e / KT, ek = e - ea * KT;
-        const size_t o = at(wrp(a0 - R + ea, La), k0 + ek);
-        sv[0][e] = src[o];
-        sv[1][e] = src[n + o];
-        sv[2][e] = src[2 * n + o];
+    // every load of the tile is issued before the first is used (a runtime
+    // loop would wait for each round's loads before issuing the next)
+    constexpr int kRounds = (kWinTA + 2 * sr::kMaxR) * kWinKT / kT;
+    float t0[kRounds], t1[kRounds], t2[kRounds];
+#pragma unroll
+    for (int it = 0; it < kRounds; ++it) {
+        const int e = threadIdx.x + it * kT;
+        if (e < EH * KT) {
+            const int ea = e / KT, ek = e - ea * KT;
+            const size_t o = at(wrp(a0 - R + ea, La), k0 + ek);
+            t0[it] = src[o];
+            t1[it] = src[n + o];
+            t2[it] = src[2 * n + o];
+        }
+    }
+#pragma unroll
+    for (int it = 0; it < kRounds; ++it) {
+        const int e = threadIdx.x + it * kT;
+        if (e < EH * KT) {
+            sv[0][e] = t0[it];
+            sv[1][e] = t1[it];
+            sv[2][e] = t2[it];
+        }
     }
     __syncthreads();
     for (int e = threadIdx.x; e < TA * KT; e += kT) {
