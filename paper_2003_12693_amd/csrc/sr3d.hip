@@ -4,15 +4,15 @@
 //   S x [ the cube window of u = w h(phi_s) (3 components) as three
 //         separable passes (k, forming u in LDS; j; i),
 //         r = tau (N(phi_s) + mu div(b - w) + mu Lap phi_s) (eq 37 in
-//         increment form), the 3-D FFT solve (eqs 30-33):
-//         forward along k (real input), along j, along i with the division by
-//         the symbol and the inverse along i, inverse along j, inverse along
-//         k with phi_{s+1} = phi_s + Re / (M N P) ]
+//         increment form) formed inside the first pass of the 3-D FFT solve
+//         (eqs 30-33): forward along k (real input, half spectrum), along j,
+//         along i with the division by the symbol and the inverse along i,
+//         inverse along j, inverse along k with phi_{s+1} = phi_s + Re / (M N P) ]
 //   then u = w^k h(phi^{k+1}) and the window again, and the w step: B of
 //   eq (41), the eq (42) gate and the projection of eq (40) (B / |B|), b of
 //   eq (23), per voxel.
-// The Gaussian, edge, rhs and w-step kernels are per voxel; the window
-// passes and the FFTs stage lines or tiles in LDS.
+// The Gaussian, edge and w-step kernels are per voxel; the window passes and
+// the FFTs (the first with the rhs) stage lines or tiles in LDS.
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
@@ -383,18 +383,17 @@ __global__ __launch_bounds__(fft3_threads(L, G)) void k3_fft(float2* __restrict_
     const int line0 = blockIdx.x * G;
     const float2* tw = axis == 0 ? twM : axis == 1 ? twN : twP;
     // The stages read their twiddles from LDS: from memory, each stage would
-    // wait for an L2 round trip before its butterflies.
-    // (the k pass runs L = P/2-point transforms: every second entry of the
-    // P-point table)
+    // wait for an L2 round trip before its butterflies.  (The k pass runs
+    // L = P/2-point transforms: every second entry of the P-point table.)
     for (int i = tid; i < L; i += S::T) stw[i] = tw[axis == 2 ? 2 * i : i];
-    // mode 2 (axis 0): this thread's elements all lie on line line0 + tid % G
-    // (the thread count is a multiple of G); the j and k cosines of that line
-    // are loaded with the data
     // The spectrum C holds k frequencies 0..P/2 only (the rest follow from
     // those by conjugate symmetry, the volume being real), Hp >= P/2 + 1
     // slots per k-line.  Lines of the strided passes run over every slot;
     // those past P/2 carry zeros and are not stored.
     const int H = P / 2 + 1;
+    // mode 2 (axis 0): this thread's elements all lie on line line0 + tid % G
+    // (the thread count is a multiple of G); the j and k cosines of that line
+    // are loaded with the data
     float cj = 0.0f, ck = 0.0f;
     if (mode == 2) {
         const int l = line0 + tid % G, kk = l % Hp;
@@ -442,7 +441,7 @@ __global__ __launch_bounds__(fft3_threads(L, G)) void k3_fft(float2* __restrict_
     __syncthreads();
     float2* res = stockham<L, G>(s0, s1, stw, mode >= 3);
     if (mode == 2) {
-        // line l = j P + k holds frequencies (n, j, k): symbol
+        // line l = j Hp + k holds frequencies (n, j, k): symbol
         // 1 + tau mu (6 - 2 cos(2 pi n / M) - 2 cos(2 pi j / N) - 2 cos(2 pi k / P))
         float2* other = res == s0 ? s1 : s0;
 #pragma unroll
