@@ -91,7 +91,9 @@ def measured_traffic(workload, kernel, tile_rows, build_id):
     """HBM bytes per launch from the committed rocprofv3 counter summary,
     or None if it was taken on a library built from other sources.  The
     separate right-hand-side kernel's traffic depends on its tile height
-    (halo rows), so it is listed per height ("rhs_repulsion@16")."""
+    (halo rows), so it is listed per height ("rhs_repulsion@16").  A 3-D
+    kind that runs several kernels is listed as the mean over its launches
+    of one outer iteration."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     key = f"{kernel}@{tile_rows}" if kernel == "rhs_repulsion" else kernel
@@ -201,6 +203,8 @@ def volume_bench(S, steps, warmup, cpu):
     per_iter_ms = {k: v[0] * v[1] / 3 for k, v in prof.items()}
     dom = max(per_iter_ms, key=per_iter_ms.get)
     achieved = bytes_per_vox_3d(dom, S) * S ** 3 / (prof[dom][0] * 1e-3) / 1e9
+    build_id = sr.sr_build_id()
+    traffic = measured_traffic(f"balls3d-{S}", dom, None, build_id)
     out = {"metric": f"3-D SB megavoxel-iters/s at {S}^3", "value": round(value, 2), "unit": "MVox-it/s",
            "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": round((t1 - t0) * 1e3 / steps, 4),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
@@ -208,10 +212,14 @@ def volume_bench(S, steps, warmup, cpu):
                                   "weights (gamma 5, alpha 4, beta 0.2, mu 3, tau 0.05, eps 1, l 1, d 4, 5^3 window, "
                                   "S 5)"},
            "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                         "alg_bytes_per_launch": bytes_per_vox_3d(dom, S) * S ** 3},
            "kernels_ms": {k: round(v[0], 5) for k, v in prof.items()},
-           "iteration_ms_sum_of_kernels": round(sum(per_iter_ms.values()), 4)}
+           "iteration_ms_sum_of_kernels": round(sum(per_iter_ms.values()), 4),
+           "build_id": build_id}
+    if traffic is not None:   # bytes the counters saw move, over the same duration
+        out["roofline"]["achieved_by_counters"] = round(traffic / (prof[dom][0] * 1e-3) / 1e9, 1)
+        out["roofline"]["frac_by_counters"] = round(out["roofline"]["achieved_by_counters"] / HBM_PEAK_GBS, 4)
     if cpu:
         from oracle import sr_oracle as O
         from oracle import sr_oracle3d as O3
